@@ -1,0 +1,255 @@
+/*
+ * fvv.h -- C ABI of the MI355X (gfx950) coarse-to-fine visual-hull library.
+ *
+ * The library implements the reconstruction path of Chen et al., "A Fast
+ * Free-viewpoint Video Synthesis Algorithm for Sports Scenes":
+ *   1. sparse (coarse) volumetric visual hull over the whole volume  (Sec. II-B-1)
+ *   2. 26-adjacency connected components, the size filter of Eq. (1) and the
+ *      minimum 3-D bounding box (ROI) of each kept component         (Sec. II-B-2)
+ *   3. dense (fine) visual hull inside each ROI only                (Sec. II-B-3)
+ *   4. for every grid edge whose endpoints differ, the point where it
+ *      leaves the visual hull (the first exit over all cameras, the
+ *      minimum of Eq. (3)), which gives the mesh vertices             (Sec. II-C)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Camera    P is a row-major 3x4 float32 projection.  A world point (X,Y,Z)
+ *           maps to a = P0.X, b = P1.X, w = P2.X, each evaluated as the fused
+ *           chain fma(P[4r+2], Z, fma(P[4r+1], Y, fma(P[4r+0], X, P[4r+3]))).
+ *           The point is seen by the camera iff w > 0 and pixel
+ *           (floor(a/w), floor(b/w)) lies in [0,W) x [0,H), the floors taken of
+ *           the exact real quotient; pixel (x, y) covers [x,x+1) x [y,y+1).
+ * Silhouette bit-packed uint32 rows, layout [camera][H][wpr], wpr = ceil(W/32);
+ *           pixel x of a row is bit (x & 31) of word (x >> 5); pad bits are 0.
+ * Grid      a lattice {origin, h, lo, dims}.  Sample (i,j,k), 0 <= i < dims[0]
+ *           etc., has global index g = lo + (i,j,k) and world position
+ *           fma((float)g_axis, h, origin_axis) on each axis.  Buffers over a
+ *           grid are x-fastest: lin = i + dims[0]*(j + dims[1]*k).
+ * Occupancy a sample is occupied iff it is seen inside the silhouette of every
+ *           camera (Sec. II-B: a voxel falling outside a silhouette is
+ *           unoccupied).  Results are bit-exact: they do not depend on launch
+ *           shape, tile choice or camera order.
+ *
+ * Memory: every d_* pointer is device memory owned by the caller; host
+ * pointers are read before the call returns.  The library never frees caller
+ * memory.  A context owns all scratch, allocated once by fvv_create (all GPU
+ * memory is taken at start-up, as the paper's system does), on the device that
+ * is current at that time.  Use one context per concurrently used stream.
+ *
+ * Errors: argument checks run on the host before anything is enqueued and
+ * return FVV_EINVAL.  Launch failures return FVV_EDEVICE.  Overflow of an
+ * output capacity is detected on the device: the true count is still written,
+ * nothing is written past the capacity, and a sticky flag makes the next
+ * fvv_check return FVV_ECAPACITY.  Every call except fvv_create, fvv_destroy,
+ * fvv_check and the graph helpers is asynchronous on its stream, makes no host
+ * synchronisation, and can be captured into a HIP graph.
+ */
+#ifndef FVV_H
+#define FVV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FVV_MAX_CAMS 32
+#define FVV_MAX_STEPS 12
+
+typedef enum {
+    FVV_OK = 0,
+    FVV_EINVAL = -1,     /* bad argument, rejected before any work is enqueued */
+    FVV_ECAPACITY = -2,  /* an output capacity was exceeded (reported by fvv_check) */
+    FVV_EDEVICE = -3,    /* a HIP call failed */
+    FVV_ENOMEM = -4      /* fvv_create could not allocate its scratch */
+} fvv_status;
+
+typedef struct {
+    float P[12];          /* row-major 3x4 projection */
+    int32_t width, height;
+} fvv_camera;
+
+typedef struct {
+    float origin[3];      /* world position of global index 0 on each axis */
+    float h;              /* lattice spacing (metres) */
+    int32_t lo[3];        /* global index of sample (0,0,0) */
+    int32_t dims[3];      /* samples per axis, each >= 1 */
+} fvv_grid;
+
+typedef struct {
+    int32_t lo[3], hi[3]; /* inclusive bounding box, grid-local indices */
+    uint32_t count;       /* voxels in the component, N(S) of Eq. (1) */
+    uint32_t min_index;   /* smallest linear index in the component */
+} fvv_roi;
+
+/* One unit of batched fine carving: a lattice to carve with the cameras
+ * cams[cam_base .. cam_base+n_cams) of the camera table, whose silhouettes
+ * start at word sil_base of the silhouette buffer (layout [n_cams][height][wpr]),
+ * writing dims[0]*dims[1]*dims[2] bytes at byte out_offset of the output. */
+typedef struct {
+    fvv_grid grid;
+    int32_t cam_base, n_cams;
+    int32_t width, height;
+    int64_t sil_base;
+    int64_t out_offset;
+} fvv_job;
+
+typedef struct {
+    int32_t max_cams;     /* <= FVV_MAX_CAMS */
+    int32_t max_w, max_h; /* largest image */
+    int64_t max_coarse;   /* largest grid given to fvv_label / fvv_frame (< 2^31) */
+    int64_t max_fine;     /* largest total fine samples of one fvv_frame */
+    uint32_t max_rois;    /* largest number of ROIs fvv_frame carries to the fine stage */
+    uint32_t max_points;  /* largest number of crossing edges of one fvv_frame */
+    uint32_t max_jobs;    /* largest job table given to fvv_carve_batched */
+} fvv_limits;
+
+/* Tile of the fine/coarse carving kernels: tx*ty threads per workgroup
+ * (tx*ty == 256, tx in {16, 32, 64}), each carving tz samples stacked in z. */
+typedef struct {
+    int32_t tx, ty, tz;
+    int32_t persistent_blocks; /* workgroups of the persistent batched launch; 0 = auto */
+} fvv_tile;
+
+typedef struct fvv_ctx fvv_ctx;
+
+/* Create a context: allocates all device scratch for the given limits on the
+ * current device.  FVV_EINVAL for limits out of range, FVV_ENOMEM if the
+ * allocation fails.  *out is NULL on failure. */
+fvv_status fvv_create(fvv_ctx **out, const fvv_limits *limits);
+
+/* Free a context's scratch (synchronises the device first).  NULL is a no-op. */
+void fvv_destroy(fvv_ctx *ctx);
+
+/* Static text for a status code. */
+const char *fvv_status_str(fvv_status s);
+
+/* Wait for `stream`, then report and clear the context's sticky device flags:
+ * FVV_ECAPACITY if a capacity was exceeded since the last check, else FVV_OK. */
+fvv_status fvv_check(fvv_ctx *ctx, hipStream_t stream);
+
+/* Pack n silhouettes, uint8 [n][height][width] (non-zero = foreground, the
+ * binary silhouette of Sec. II-A), into d_sils [n][height][wpr]. */
+fvv_status fvv_pack_silhouettes(fvv_ctx *ctx, int32_t n, int32_t width, int32_t height,
+                                const uint8_t *d_masks, uint32_t *d_sils, hipStream_t stream);
+
+/* Volumetric visual hull on one lattice (Sec. II-B-1 for the whole volume,
+ * Sec. II-B-3 for an ROI): d_occ[lin] = 1 if the sample is occupied, else 0.
+ * cams: host array of n_cams (1..max_cams) cameras with identical width and
+ * height; d_sils: their silhouettes.  EINVAL on NULL pointers, bad counts,
+ * mismatched or oversized images, non-finite P, dims < 1, more than 2^31-1
+ * samples, or |global index| >= 2^24. */
+fvv_status fvv_carve(fvv_ctx *ctx, int32_t n_cams, const fvv_camera *cams,
+                     const uint32_t *d_sils, const fvv_grid *grid, const fvv_tile *tile,
+                     uint8_t *d_occ, hipStream_t stream);
+
+/* Connected components and ROIs (Sec. II-B-2).  d_occ (in: occupancy of
+ * `grid`, out: occupancy with removed components switched OFF), d_labels
+ * (out, int32 per sample): components are maximal sets of ON samples linked by
+ * 26-adjacency; a component S is kept iff t_np <= N(S) <= t_nb (Eq. (1), read
+ * as the sentence after it states); kept components are numbered 1..K in
+ * ascending order of their smallest linear index, labels are 0 elsewhere.
+ * d_rois[t-1] (t <= max_rois) receives component t's box; *d_n_rois receives
+ * K (device).  K > max_rois sets the ECAPACITY flag.  EINVAL if the grid
+ * exceeds max_coarse, pointers are NULL or t_np > t_nb. */
+fvv_status fvv_label(fvv_ctx *ctx, const fvv_grid *grid, uint8_t *d_occ, int32_t *d_labels,
+                     uint32_t t_np, uint32_t t_nb, fvv_roi *d_rois, uint32_t max_rois,
+                     uint32_t *d_n_rois, hipStream_t stream);
+
+/* Fine lattice of each ROI (Sec. II-B-3: each ROI is carved as its own
+ * volume).  Host-only, pure integer arithmetic.  Lattices share the coarse
+ * origin; spacings are integer micrometres hc_um (coarse) and hf_um (fine)
+ * and the fine spacing is h = (float)((double)hf_um * 1e-6).  Per axis, with
+ * A = coarse.lo + roi.lo and B = coarse.lo + roi.hi (global coarse indices):
+ * fine indices [floor((A-1) hc/hf), ceil((B+1) hc/hf)], clamped to the fine
+ * samples inside the coarse lattice's extent, i.e. the box dilated by one
+ * coarse cell.  EINVAL on NULL pointers or non-positive spacings. */
+fvv_status fvv_roi_grids(const fvv_grid *coarse, int64_t hc_um, int64_t hf_um,
+                         const fvv_roi *rois, uint32_t n, fvv_grid *out);
+
+/* Exit points of one carved ROI (Sec. II-C).  d_occ_fine: occupancy of `roi`.
+ * Every lattice edge (p, p+e_axis) with both ends in the grid and
+ * occ(p) != occ(p+e_axis) is a crossing edge with key 3*lin(p)+axis; keys are
+ * written to d_keys in ascending order.  For each, n_steps (1..12) bisection
+ * steps on the edge parameter t (0 at the ON end, 1 at the OFF end) test the
+ * midpoint with the occupancy test above; the vertex is the final bracket's
+ * midpoint t* = (lo+hi)/2, d_xyz[3e..3e+2] its world position (axis
+ * coordinate fma(g_on + d*t*, h, origin), d = +1 or -1 toward the OFF end).
+ * *d_n_points receives the edge count E; E > max_points sets ECAPACITY and
+ * only the first max_points are written.  EINVAL as fvv_carve, plus n_steps
+ * out of range or |global index| >= 2^(23 - n_steps). */
+fvv_status fvv_surface(fvv_ctx *ctx, const fvv_grid *roi, const uint8_t *d_occ_fine,
+                       int32_t n_cams, const fvv_camera *cams, const uint32_t *d_sils,
+                       int32_t n_steps, uint32_t *d_keys, float *d_xyz, uint32_t max_points,
+                       uint32_t *d_n_points, hipStream_t stream);
+
+/* Batched fine carving (Sec. II-B-3 over many ROIs, of one or many frames) in
+ * ONE persistent launch: workgroups take (job, tile) work items from a device
+ * counter until none are left.  d_jobs: n_jobs jobs (device, <= max_jobs);
+ * d_cams: device camera table; output bytes as each job states.  The output
+ * is byte-identical to carving each job with fvv_carve.  tile may be NULL
+ * (default tile). */
+fvv_status fvv_carve_batched(fvv_ctx *ctx, const fvv_job *d_jobs, uint32_t n_jobs,
+                             const fvv_camera *d_cams, const uint32_t *d_sils,
+                             uint8_t *d_occ_out, const fvv_tile *tile, hipStream_t stream);
+
+/* ---------------------------------------------------------------- one frame
+ * The whole path for one frame with every intermediate on the device, so it
+ * can run as a single HIP graph: carve the coarse grid, label it, turn each
+ * kept ROI into a fine job (fvv_roi_grids' arithmetic, on the device), carve
+ * all ROIs in one persistent launch, and find the exit points of every ROI's
+ * crossing edges.  Outputs (device, caller-owned):
+ *   d_occ_coarse  [coarse samples]       filtered coarse occupancy
+ *   d_labels      [coarse samples]       component labels
+ *   d_rois        [max_rois]             ROI boxes; counts[0] = K
+ *   d_jobs        [max_rois]             fine lattice of each ROI (as fvv_job)
+ *   d_occ_fine    [max_fine]             fine occupancy, ROI t at d_jobs[t].out_offset
+ *   d_keys/d_xyz  [max_points]           crossing edges of all ROIs, ROI-major
+ *   d_point_off   [max_rois + 1]         first edge of each ROI
+ *   d_counts      [4]                    K, fine samples, edges, ROIs carried
+ * ROIs whose fine lattices do not fit max_fine are not carried (ECAPACITY). */
+typedef struct {
+    int32_t n_cams;
+    fvv_camera cams[FVV_MAX_CAMS];
+    fvv_grid coarse;
+    int64_t hc_um, hf_um;
+    uint32_t t_np, t_nb;
+    int32_t n_steps;
+    fvv_tile coarse_tile, fine_tile;
+} fvv_frame_params;
+
+typedef struct {
+    uint8_t *d_occ_coarse;
+    int32_t *d_labels;
+    fvv_roi *d_rois;
+    fvv_job *d_jobs;
+    uint8_t *d_occ_fine;
+    uint32_t *d_keys;
+    float *d_xyz;
+    uint32_t *d_point_off;
+    uint32_t *d_counts;
+    uint32_t max_rois;
+    int64_t max_fine;
+    uint32_t max_points;
+} fvv_frame_out;
+
+/* Enqueue the whole frame on `stream`.  d_sils: the frame's packed
+ * silhouettes.  EINVAL as the individual calls. */
+fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint32_t *d_sils,
+                     const fvv_frame_out *out, hipStream_t stream);
+
+/* Capture fvv_frame (with fixed arguments) into an executable HIP graph.
+ * The capture runs on an internal stream; the graph replays the frame with the
+ * same pointers.  Release with fvv_graph_destroy. */
+typedef struct fvv_graph fvv_graph;
+fvv_status fvv_frame_graph_create(fvv_ctx *ctx, const fvv_frame_params *params,
+                                  const uint32_t *d_sils, const fvv_frame_out *out,
+                                  fvv_graph **graph);
+fvv_status fvv_graph_launch(fvv_graph *graph, hipStream_t stream);
+void fvv_graph_destroy(fvv_graph *graph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVV_H */

@@ -1,0 +1,394 @@
+"""Python binding of the gfx950 coarse-to-fine visual-hull library (libfvv.so).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C ABI
+declared in ``include/fvv.h``.  torch supplies device memory and streams.  The
+binding has no CPU path: importing it without the built library, or calling it
+without a GPU, raises.
+
+Names follow the C ABI: ``pack_silhouettes``, ``carve``, ``label``,
+``roi_grids``, ``surface``, ``carve_batched``, ``frame`` and ``frame_graph``,
+as methods of :class:`Context` (which owns the library's device scratch).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfvv.so")
+MAX_CAMS = 32
+MAX_STEPS = 12
+
+FVV_OK, FVV_EINVAL, FVV_ECAPACITY, FVV_EDEVICE, FVV_ENOMEM = 0, -1, -2, -3, -4
+
+
+class FvvError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+# ------------------------------------------------------------------ C structs (layout of fvv.h)
+class Camera(C.Structure):
+    _fields_ = [("P", C.c_float * 12), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class GridC(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("h", C.c_float), ("lo", C.c_int32 * 3),
+                ("dims", C.c_int32 * 3)]
+
+
+class Roi(C.Structure):
+    _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("count", C.c_uint32),
+                ("min_index", C.c_uint32)]
+
+
+class Job(C.Structure):
+    _fields_ = [("grid", GridC), ("cam_base", C.c_int32), ("n_cams", C.c_int32),
+                ("width", C.c_int32), ("height", C.c_int32), ("sil_base", C.c_int64),
+                ("out_offset", C.c_int64)]
+
+
+class Limits(C.Structure):
+    _fields_ = [("max_cams", C.c_int32), ("max_w", C.c_int32), ("max_h", C.c_int32),
+                ("max_coarse", C.c_int64), ("max_fine", C.c_int64), ("max_rois", C.c_uint32),
+                ("max_points", C.c_uint32), ("max_jobs", C.c_uint32)]
+
+
+class Tile(C.Structure):
+    _fields_ = [("tx", C.c_int32), ("ty", C.c_int32), ("tz", C.c_int32),
+                ("persistent_blocks", C.c_int32)]
+
+
+class FrameParams(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("cams", Camera * MAX_CAMS), ("coarse", GridC),
+                ("hc_um", C.c_int64), ("hf_um", C.c_int64), ("t_np", C.c_uint32),
+                ("t_nb", C.c_uint32), ("n_steps", C.c_int32), ("coarse_tile", Tile),
+                ("fine_tile", Tile)]
+
+
+class FrameOut(C.Structure):
+    _fields_ = [("d_occ_coarse", C.c_void_p), ("d_labels", C.c_void_p), ("d_rois", C.c_void_p),
+                ("d_jobs", C.c_void_p), ("d_occ_fine", C.c_void_p), ("d_keys", C.c_void_p),
+                ("d_xyz", C.c_void_p), ("d_point_off", C.c_void_p), ("d_counts", C.c_void_p),
+                ("max_rois", C.c_uint32), ("max_fine", C.c_int64), ("max_points", C.c_uint32)]
+
+
+ROI_DTYPE = np.dtype([("lo", "<i4", 3), ("hi", "<i4", 3), ("count", "<u4"), ("min_index", "<u4")])
+JOB_DTYPE = np.dtype({"names": ["origin", "h", "lo", "dims", "cam_base", "n_cams", "width",
+                                "height", "sil_base", "out_offset"],
+                      "formats": [("<f4", 3), "<f4", ("<i4", 3), ("<i4", 3), "<i4", "<i4", "<i4",
+                                  "<i4", "<i8", "<i8"],
+                      "offsets": [0, 12, 16, 28, 40, 44, 48, 52, 56, 64], "itemsize": 72})
+CAMERA_DTYPE = np.dtype({"names": ["P", "width", "height"], "formats": [("<f4", 12), "<i4", "<i4"],
+                         "offsets": [0, 48, 52], "itemsize": 56})
+assert C.sizeof(Job) == JOB_DTYPE.itemsize and C.sizeof(Roi) == ROI_DTYPE.itemsize
+assert C.sizeof(Camera) == CAMERA_DTYPE.itemsize
+
+
+# ------------------------------------------------------------------ library
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads torch's HIP runtime first, which the library then shares)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1903_11785_amd.build.build()")
+    L = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
+    P, i32, u32, i64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_int64
+    sigs = {
+        "fvv_create": ([C.POINTER(P), C.POINTER(Limits)], i32),
+        "fvv_destroy": ([P], None),
+        "fvv_status_str": ([i32], C.c_char_p),
+        "fvv_check": ([P, P], i32),
+        "fvv_pack_silhouettes": ([P, i32, i32, i32, P, P, P], i32),
+        "fvv_carve": ([P, i32, C.POINTER(Camera), P, C.POINTER(GridC), C.POINTER(Tile), P, P], i32),
+        "fvv_label": ([P, C.POINTER(GridC), P, P, u32, u32, P, u32, P, P], i32),
+        "fvv_roi_grids": ([C.POINTER(GridC), i64, i64, C.POINTER(Roi), u32, C.POINTER(GridC)], i32),
+        "fvv_surface": ([P, C.POINTER(GridC), P, i32, C.POINTER(Camera), P, i32, P, P, u32, P, P],
+                        i32),
+        "fvv_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), P], i32),
+        "fvv_frame": ([P, C.POINTER(FrameParams), P, C.POINTER(FrameOut), P], i32),
+        "fvv_frame_graph_create": ([P, C.POINTER(FrameParams), P, C.POINTER(FrameOut),
+                                    C.POINTER(P)], i32),
+        "fvv_graph_launch": ([P, P], i32),
+        "fvv_graph_destroy": ([P], None),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def library():
+    """The loaded ctypes library (raises ImportError when not built)."""
+    return _load()
+
+
+def status_str(s: int) -> str:
+    return _load().fvv_status_str(int(s)).decode()
+
+
+def _ok(s: int, what: str):
+    if s != FVV_OK:
+        raise FvvError(int(s), what)
+
+
+# ------------------------------------------------------------------ value types
+@dataclass
+class Grid:
+    origin: Tuple[float, float, float]
+    h: float
+    lo: Tuple[int, int, int]
+    dims: Tuple[int, int, int]
+
+    def c(self) -> GridC:
+        g = GridC()
+        for a in range(3):
+            g.origin[a] = float(np.float32(self.origin[a]))
+            g.lo[a] = int(self.lo[a])
+            g.dims[a] = int(self.dims[a])
+        g.h = float(np.float32(self.h))
+        return g
+
+    @staticmethod
+    def from_c(g: GridC) -> "Grid":
+        return Grid(origin=tuple(np.float32(v) for v in g.origin), h=np.float32(g.h),
+                    lo=tuple(int(v) for v in g.lo), dims=tuple(int(v) for v in g.dims))
+
+    @property
+    def size(self) -> int:
+        return int(np.prod(self.dims, dtype=np.int64))
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        return (int(self.dims[2]), int(self.dims[1]), int(self.dims[0]))
+
+
+def make_cameras(P: np.ndarray, W: int, H: int):
+    P = np.asarray(P, np.float32).reshape(-1, 12)
+    arr = (Camera * P.shape[0])()
+    for c in range(P.shape[0]):
+        for e in range(12):
+            arr[c].P[e] = float(P[c, e])
+        arr[c].width = int(W)
+        arr[c].height = int(H)
+    return arr
+
+
+def tile(tx: int = 64, tz: int = 4, persistent_blocks: int = 0) -> Tile:
+    return Tile(tx, 256 // tx, tz, persistent_blocks)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def roi_grids(coarse: Grid, hc_um: int, hf_um: int, rois: np.ndarray) -> List[Grid]:
+    """Host-side fine lattice of each ROI (rows of ROI_DTYPE or int32 [K][8])."""
+    rois = np.ascontiguousarray(rois)
+    if rois.dtype != ROI_DTYPE:
+        rois = np.ascontiguousarray(rois.astype(np.int32).reshape(-1, 8)).view(ROI_DTYPE).reshape(-1)
+    n = rois.shape[0]
+    out = (GridC * max(n, 1))()
+    src = rois.ctypes.data_as(C.POINTER(Roi)) if n else None
+    _ok(_load().fvv_roi_grids(C.byref(coarse.c()), int(hc_um), int(hf_um), src, n, out),
+        "fvv_roi_grids")
+    return [Grid.from_c(out[t]) for t in range(n)]
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """Owns the library's device scratch (all allocated up front)."""
+
+    def __init__(self, max_cams: int = 32, max_w: int = 3840, max_h: int = 2160,
+                 max_coarse: int = 1 << 23, max_fine: int = 1 << 28, max_rois: int = 4096,
+                 max_points: int = 1 << 23, max_jobs: int = 4096):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1903_11785_amd needs a ROCm GPU; there is no CPU path")
+        self.L = _load()
+        self.limits = Limits(max_cams, max_w, max_h, max_coarse, max_fine, max_rois, max_points,
+                             max_jobs)
+        h = C.c_void_p()
+        _ok(self.L.fvv_create(C.byref(h), C.byref(self.limits)), "fvv_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.fvv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, stream=None) -> int:
+        """Synchronise and return the sticky device status (FVV_OK / FVV_ECAPACITY)."""
+        return int(self.L.fvv_check(self.h, C.c_void_p(_stream(stream))))
+
+    # -------------------------------------------------------------- calls
+    def pack_silhouettes(self, masks, out=None, stream=None):
+        import torch
+        assert masks.is_cuda and masks.dtype == torch.uint8 and masks.is_contiguous()
+        N, H, W = masks.shape
+        wpr = (W + 31) // 32
+        if out is None:
+            out = torch.empty((N, H, wpr), dtype=torch.int32, device=masks.device)
+        _ok(self.L.fvv_pack_silhouettes(self.h, N, W, H, _ptr(masks), _ptr(out),
+                                        C.c_void_p(_stream(stream))), "fvv_pack_silhouettes")
+        return out
+
+    def carve(self, P: np.ndarray, W: int, H: int, sils, grid: Grid, tile_: Optional[Tile] = None,
+              out=None, stream=None):
+        import torch
+        cams = make_cameras(P, W, H)
+        if out is None:
+            out = torch.empty(grid.shape, dtype=torch.uint8, device=sils.device)
+        _ok(self.L.fvv_carve(self.h, len(cams), cams, _ptr(sils), C.byref(grid.c()),
+                             C.byref(tile_) if tile_ is not None else None, _ptr(out),
+                             C.c_void_p(_stream(stream))), "fvv_carve")
+        return out
+
+    def label(self, grid: Grid, occ, t_np: int = 8, t_nb: int = 0xFFFFFFFF, max_rois: int = 4096,
+              labels=None, rois=None, n_rois=None, stream=None):
+        """In place on occ; returns (labels int32, rois int32 [max_rois][8], n_rois int32 [1])."""
+        import torch
+        dev = occ.device
+        if labels is None:
+            labels = torch.empty(grid.shape, dtype=torch.int32, device=dev)
+        if rois is None:
+            rois = torch.zeros((max_rois, 8), dtype=torch.int32, device=dev)
+        if n_rois is None:
+            n_rois = torch.zeros(1, dtype=torch.int32, device=dev)
+        _ok(self.L.fvv_label(self.h, C.byref(grid.c()), _ptr(occ), _ptr(labels), int(t_np),
+                             int(t_nb), _ptr(rois), int(max_rois), _ptr(n_rois),
+                             C.c_void_p(_stream(stream))), "fvv_label")
+        return labels, rois, n_rois
+
+    def surface(self, roi: Grid, occ_fine, P: np.ndarray, W: int, H: int, sils, n_steps: int = 8,
+                max_points: int = 1 << 22, keys=None, xyz=None, n_points=None, stream=None):
+        import torch
+        dev = occ_fine.device
+        cams = make_cameras(P, W, H)
+        if keys is None:
+            keys = torch.empty(max_points, dtype=torch.int32, device=dev)
+        if xyz is None:
+            xyz = torch.empty((max_points, 3), dtype=torch.float32, device=dev)
+        if n_points is None:
+            n_points = torch.zeros(1, dtype=torch.int32, device=dev)
+        _ok(self.L.fvv_surface(self.h, C.byref(roi.c()), _ptr(occ_fine), len(cams), cams,
+                               _ptr(sils), int(n_steps), _ptr(keys), _ptr(xyz), int(max_points),
+                               _ptr(n_points), C.c_void_p(_stream(stream))), "fvv_surface")
+        return keys, xyz, n_points
+
+    def carve_batched(self, jobs_dev, n_jobs: int, cams_dev, sils, out, tile_: Optional[Tile] = None,
+                      stream=None):
+        _ok(self.L.fvv_carve_batched(self.h, _ptr(jobs_dev), int(n_jobs), _ptr(cams_dev),
+                                     _ptr(sils), _ptr(out),
+                                     C.byref(tile_) if tile_ is not None else None,
+                                     C.c_void_p(_stream(stream))), "fvv_carve_batched")
+        return out
+
+    def frame(self, params: FrameParams, sils, out: "FrameBuffers", stream=None):
+        _ok(self.L.fvv_frame(self.h, C.byref(params), _ptr(sils), C.byref(out.c),
+                             C.c_void_p(_stream(stream))), "fvv_frame")
+
+    def frame_graph(self, params: FrameParams, sils, out: "FrameBuffers") -> "FrameGraph":
+        g = C.c_void_p()
+        _ok(self.L.fvv_frame_graph_create(self.h, C.byref(params), _ptr(sils), C.byref(out.c),
+                                          C.byref(g)), "fvv_frame_graph_create")
+        return FrameGraph(self.L, g)
+
+
+class FrameGraph:
+    def __init__(self, L, g):
+        self.L, self.g = L, g
+
+    def launch(self, stream=None):
+        _ok(self.L.fvv_graph_launch(self.g, C.c_void_p(_stream(stream))), "fvv_graph_launch")
+
+    def close(self):
+        if self.g:
+            self.L.fvv_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def frame_params(P: np.ndarray, W: int, H: int, coarse: Grid, hc_um: int, hf_um: int,
+                 t_np: int = 8, t_nb: int = 0xFFFFFFFF, n_steps: int = 8,
+                 coarse_tile: Optional[Tile] = None, fine_tile: Optional[Tile] = None) -> FrameParams:
+    p = FrameParams()
+    cams = make_cameras(P, W, H)
+    p.n_cams = len(cams)
+    for c in range(len(cams)):
+        p.cams[c] = cams[c]
+    p.coarse = coarse.c()
+    p.hc_um, p.hf_um = int(hc_um), int(hf_um)
+    p.t_np, p.t_nb, p.n_steps = int(t_np), int(t_nb), int(n_steps)
+    p.coarse_tile = coarse_tile if coarse_tile is not None else tile(64, 1)
+    p.fine_tile = fine_tile if fine_tile is not None else tile(64, 4)
+    return p
+
+
+class FrameBuffers:
+    """Device outputs of one frame (caller-owned torch tensors)."""
+
+    def __init__(self, coarse: Grid, max_rois: int = 256, max_fine: int = 1 << 26,
+                 max_points: int = 1 << 22, device: str = "cuda"):
+        import torch
+        z = lambda shape, dt: torch.zeros(shape, dtype=dt, device=device)
+        self.occ_coarse = z(coarse.shape, torch.uint8)
+        self.labels = z(coarse.shape, torch.int32)
+        self.rois = z((max_rois, 8), torch.int32)
+        self.jobs = z((max_rois, JOB_DTYPE.itemsize), torch.uint8)
+        self.occ_fine = z(max_fine, torch.uint8)
+        self.keys = z(max_points, torch.int32)
+        self.xyz = z((max_points, 3), torch.float32)
+        self.point_off = z(max_rois + 1, torch.int32)
+        self.counts = z(4, torch.int32)
+        self.max_rois, self.max_fine, self.max_points = max_rois, max_fine, max_points
+        self.c = FrameOut(_ptr(self.occ_coarse), _ptr(self.labels), _ptr(self.rois),
+                          _ptr(self.jobs), _ptr(self.occ_fine), _ptr(self.keys), _ptr(self.xyz),
+                          _ptr(self.point_off), _ptr(self.counts), max_rois, max_fine, max_points)
+
+    def jobs_host(self, n: int) -> np.ndarray:
+        return self.jobs[:n].cpu().numpy().reshape(-1).view(JOB_DTYPE)
+
+
+def jobs_to_device(jobs: np.ndarray, device="cuda"):
+    import torch
+    jobs = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
+    return torch.from_numpy(jobs.view(np.uint8).reshape(-1, JOB_DTYPE.itemsize).copy()).to(device)
+
+
+def cameras_to_device(P: np.ndarray, W: int, H: int, device="cuda"):
+    import torch
+    P = np.asarray(P, np.float32).reshape(-1, 12)
+    arr = np.zeros(P.shape[0], CAMERA_DTYPE)
+    arr["P"] = P
+    arr["width"] = W
+    arr["height"] = H
+    return torch.from_numpy(arr.view(np.uint8).reshape(-1, CAMERA_DTYPE.itemsize).copy()).to(device)

@@ -1,0 +1,420 @@
+// C ABI of the gfx950 visual-hull library: argument checks, the context's
+// start-up allocation, and the launch sequence of each call.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "fvv_internal.h"
+
+using namespace fvv;
+
+namespace {
+
+constexpr int64_t kMaxSamples = 0x7fffffffLL;
+constexpr int32_t kMaxIndex = 1 << 24;  // (float)g is exact below this
+
+bool finite3(const float* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+int64_t grid_samples(const fvv_grid& g) {
+    return (int64_t)g.dims[0] * (int64_t)g.dims[1] * (int64_t)g.dims[2];
+}
+
+bool grid_ok(const fvv_grid* g, int32_t index_limit) {
+    if (!g)
+        return false;
+    if (!finite3(g->origin) || !isfinite(g->h) || !(g->h > 0.0f))
+        return false;
+    for (int a = 0; a < 3; ++a) {
+        if (g->dims[a] < 1)
+            return false;
+        const int64_t lo = g->lo[a], hi = (int64_t)g->lo[a] + g->dims[a];
+        if (lo <= -index_limit || hi >= index_limit)
+            return false;
+    }
+    return grid_samples(*g) <= kMaxSamples;
+}
+
+bool cams_ok(const fvv_ctx* ctx, int32_t n, const fvv_camera* cams) {
+    if (!cams || n < 1 || n > FVV_MAX_CAMS || n > ctx->lim.max_cams)
+        return false;
+    const int32_t W = cams[0].width, H = cams[0].height;
+    if (W < 1 || H < 1 || W > ctx->lim.max_w || H > ctx->lim.max_h)
+        return false;
+    for (int c = 0; c < n; ++c) {
+        if (cams[c].width != W || cams[c].height != H)
+            return false;
+        for (int e = 0; e < 12; ++e)
+            if (!isfinite(cams[c].P[e]))
+                return false;
+    }
+    return true;
+}
+
+CamSet make_camset(int32_t n, const fvv_camera* cams) {
+    CamSet cs;
+    memset(&cs, 0, sizeof(cs));
+    cs.n = n;
+    cs.W = cams[0].width;
+    cs.H = cams[0].height;
+    cs.wpr = (cs.W + 31) / 32;
+    for (int c = 0; c < n; ++c)
+        for (int e = 0; e < 12; ++e)
+            cs.P[c][e] = cams[c].P[e];
+    return cs;
+}
+
+bool tile_ok(const fvv_tile* t) {
+    if (!t)
+        return true;
+    if (!((t->tx == 64 && t->ty == 4) || (t->tx == 32 && t->ty == 8) ||
+          (t->tx == 16 && t->ty == 16)))
+        return false;
+    if (!(t->tz == 1 || t->tz == 2 || t->tz == 4 || t->tz == 8))
+        return false;
+    return t->persistent_blocks >= 0 && t->persistent_blocks <= (1 << 20);
+}
+
+TileShape tile_of(const fvv_tile* t) {
+    if (!t)
+        return TileShape{64, 4, 4};
+    return TileShape{t->tx, t->ty, t->tz};
+}
+
+int persistent_blocks(const fvv_ctx* ctx, const fvv_tile* t) {
+    if (t && t->persistent_blocks > 0)
+        return t->persistent_blocks;
+    return ctx->n_cus * 8;
+}
+
+fvv_status dev(hipError_t e) { return e == hipSuccess ? FVV_OK : FVV_EDEVICE; }
+
+int64_t floor_div64(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0)))
+        q -= 1;
+    return q;
+}
+
+int64_t ceil_div64(int64_t a, int64_t b) { return -floor_div64(-a, b); }
+
+template <typename T>
+hipError_t alloc(T** p, int64_t count) {
+    if (count < 1)
+        count = 1;
+    return hipMalloc((void**)p, (size_t)count * sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fvv_status_str(fvv_status s) {
+    switch (s) {
+    case FVV_OK: return "ok";
+    case FVV_EINVAL: return "invalid argument";
+    case FVV_ECAPACITY: return "output capacity exceeded";
+    case FVV_EDEVICE: return "device error";
+    case FVV_ENOMEM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+void fvv_destroy(fvv_ctx* ctx) {
+    if (!ctx)
+        return;
+    hipDeviceSynchronize();
+    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_parent, ctx->d_rid, ctx->d_rootbits,
+                    ctx->d_blk_cnt, ctx->d_n_roots, ctx->d_stats, ctx->d_keep, ctx->d_prefix,
+                    ctx->d_job_single, ctx->d_cams, ctx->d_item_cnt, ctx->d_item_base,
+                    ctx->d_point_off_single, ctx->d_counts_single};
+    for (void* p : ptrs)
+        if (p)
+            hipFree(p);
+    delete ctx;
+}
+
+fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
+    if (!out)
+        return FVV_EINVAL;
+    *out = nullptr;
+    if (!lim || lim->max_cams < 1 || lim->max_cams > FVV_MAX_CAMS || lim->max_w < 1 ||
+        lim->max_h < 1 || lim->max_w > (1 << 16) || lim->max_h > (1 << 16) ||
+        lim->max_coarse < 1 || lim->max_coarse > kMaxSamples || lim->max_fine < 1 ||
+        lim->max_fine > ((int64_t)1 << 40) || lim->max_rois < 1 || lim->max_points < 1 ||
+        lim->max_jobs < 1)
+        return FVV_EINVAL;
+    fvv_ctx* c = new (std::nothrow) fvv_ctx;
+    if (!c)
+        return FVV_ENOMEM;
+    memset(c, 0, sizeof(*c));
+    c->lim = *lim;
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->n_cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess) {
+        delete c;
+        return FVV_EDEVICE;
+    }
+    const int64_t V = lim->max_coarse;
+    const int64_t chunks = (V + kRootChunk - 1) / kRootChunk;
+    c->root_cap = V;
+    c->job_cap = (int64_t)(lim->max_jobs > lim->max_rois ? lim->max_jobs : lim->max_rois) + 2;
+    c->item_cap = lim->max_fine / kEdgeChunk + (int64_t)lim->max_rois + 2;
+    hipError_t e = hipSuccess;
+#define A(ptr, n)                  \
+    if (e == hipSuccess)           \
+        e = alloc(&c->ptr, (n));
+    A(d_status, 1)
+    A(d_counter, 4)
+    A(d_parent, V)
+    A(d_rid, V)
+    A(d_rootbits, chunks * (kRootChunk / 64))
+    A(d_blk_cnt, chunks)
+    A(d_n_roots, 1)
+    A(d_stats, 8 * V)
+    A(d_keep, V)
+    A(d_prefix, c->job_cap)
+    A(d_job_single, 1)
+    A(d_cams, FVV_MAX_CAMS)
+    A(d_item_cnt, c->item_cap)
+    A(d_item_base, c->item_cap)
+    A(d_point_off_single, 2)
+    A(d_counts_single, 4)
+#undef A
+    if (e == hipSuccess)
+        e = hipMemset(c->d_status, 0, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        fvv_destroy(c);
+        return e == hipErrorOutOfMemory ? FVV_ENOMEM : FVV_EDEVICE;
+    }
+    *out = c;
+    return FVV_OK;
+}
+
+fvv_status fvv_check(fvv_ctx* ctx, hipStream_t stream) {
+    if (!ctx)
+        return FVV_EINVAL;
+    if (hipStreamSynchronize(stream) != hipSuccess)
+        return FVV_EDEVICE;
+    uint32_t flags = 0;
+    if (hipMemcpy(&flags, ctx->d_status, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess)
+        return FVV_EDEVICE;
+    if (flags) {
+        if (hipMemset(ctx->d_status, 0, sizeof(uint32_t)) != hipSuccess)
+            return FVV_EDEVICE;
+        if (hipDeviceSynchronize() != hipSuccess)
+            return FVV_EDEVICE;
+    }
+    return (flags & kFlagCapacity) ? FVV_ECAPACITY : FVV_OK;
+}
+
+fvv_status fvv_pack_silhouettes(fvv_ctx* ctx, int32_t n, int32_t width, int32_t height,
+                                const uint8_t* d_masks, uint32_t* d_sils, hipStream_t stream) {
+    if (!ctx || !d_masks || !d_sils || n < 1 || width < 1 || height < 1 ||
+        width > ctx->lim.max_w || height > ctx->lim.max_h || n > ctx->lim.max_cams)
+        return FVV_EINVAL;
+    return dev(launch_pack(n, width, height, d_masks, d_sils, stream));
+}
+
+fvv_status fvv_carve(fvv_ctx* ctx, int32_t n_cams, const fvv_camera* cams, const uint32_t* d_sils,
+                     const fvv_grid* grid, const fvv_tile* tile, uint8_t* d_occ,
+                     hipStream_t stream) {
+    if (!ctx || !d_sils || !d_occ || !cams_ok(ctx, n_cams, cams) || !grid_ok(grid, kMaxIndex) ||
+        !tile_ok(tile))
+        return FVV_EINVAL;
+    const CamSet cs = make_camset(n_cams, cams);
+    return dev(launch_carve(cs, d_sils, *grid, tile_of(tile), d_occ, stream));
+}
+
+fvv_status fvv_label(fvv_ctx* ctx, const fvv_grid* grid, uint8_t* d_occ, int32_t* d_labels,
+                     uint32_t t_np, uint32_t t_nb, fvv_roi* d_rois, uint32_t max_rois,
+                     uint32_t* d_n_rois, hipStream_t stream) {
+    if (!ctx || !grid || !d_occ || !d_labels || !d_rois || !d_n_rois || max_rois < 1 ||
+        t_np > t_nb)
+        return FVV_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (grid->dims[a] < 1)
+            return FVV_EINVAL;
+    if (grid_samples(*grid) > ctx->lim.max_coarse)
+        return FVV_EINVAL;
+    return dev(launch_label(ctx, *grid, d_occ, d_labels, t_np, t_nb, d_rois, max_rois, d_n_rois,
+                            stream));
+}
+
+fvv_status fvv_roi_grids(const fvv_grid* coarse, int64_t hc_um, int64_t hf_um,
+                         const fvv_roi* rois, uint32_t n, fvv_grid* out) {
+    if (!coarse || (n > 0 && (!rois || !out)) || hc_um < 1 || hf_um < 1)
+        return FVV_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (coarse->dims[a] < 1)
+            return FVV_EINVAL;
+    const float h = (float)((double)hf_um * 1e-6);
+    for (uint32_t t = 0; t < n; ++t) {
+        fvv_grid g;
+        for (int a = 0; a < 3; ++a) {
+            if (rois[t].lo[a] < 0 || rois[t].hi[a] < rois[t].lo[a] ||
+                rois[t].hi[a] >= coarse->dims[a])
+                return FVV_EINVAL;
+            const int64_t A = (int64_t)coarse->lo[a] + rois[t].lo[a] - 1;
+            const int64_t B = (int64_t)coarse->lo[a] + rois[t].hi[a] + 1;
+            int64_t f0 = floor_div64(A * hc_um, hf_um);
+            int64_t f1 = ceil_div64(B * hc_um, hf_um);
+            const int64_t fmin = ceil_div64((int64_t)coarse->lo[a] * hc_um, hf_um);
+            const int64_t fmax =
+                floor_div64(((int64_t)coarse->lo[a] + coarse->dims[a] - 1) * hc_um, hf_um);
+            if (f0 < fmin)
+                f0 = fmin;
+            if (f1 > fmax)
+                f1 = fmax;
+            g.origin[a] = coarse->origin[a];
+            g.lo[a] = (int32_t)f0;
+            g.dims[a] = (int32_t)(f1 - f0 + 1);
+        }
+        g.h = h;
+        out[t] = g;
+    }
+    return FVV_OK;
+}
+
+fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_fine,
+                       int32_t n_cams, const fvv_camera* cams, const uint32_t* d_sils,
+                       int32_t n_steps, uint32_t* d_keys, float* d_xyz, uint32_t max_points,
+                       uint32_t* d_n_points, hipStream_t stream) {
+    if (!ctx || !d_occ_fine || !d_sils || !d_keys || !d_xyz || !d_n_points || max_points < 1 ||
+        n_steps < 1 || n_steps > FVV_MAX_STEPS || !cams_ok(ctx, n_cams, cams) ||
+        !grid_ok(roi, 1 << (23 - n_steps)))
+        return FVV_EINVAL;
+    if (grid_samples(*roi) > ctx->lim.max_fine || grid_samples(*roi) > 1431655765LL)
+        return FVV_EINVAL;
+    const CamSet cs = make_camset(n_cams, cams);
+    fvv_job job;
+    memset(&job, 0, sizeof(job));
+    job.grid = *roi;
+    job.n_cams = n_cams;
+    job.width = cs.W;
+    job.height = cs.H;
+    hipError_t e = launch_surface_prepare_single(ctx, job, stream);
+    if (e == hipSuccess)
+        e = launch_surface(ctx, ctx->d_job_single, ctx->d_counts_single + 3, 1, d_occ_fine, cs,
+                           d_sils, n_steps, d_keys, d_xyz, max_points, ctx->d_point_off_single,
+                           d_n_points, stream);
+    return dev(e);
+}
+
+fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_jobs,
+                             const fvv_camera* d_cams, const uint32_t* d_sils,
+                             uint8_t* d_occ_out, const fvv_tile* tile, hipStream_t stream) {
+    if (!ctx || !d_jobs || !d_cams || !d_sils || !d_occ_out || n_jobs < 1 ||
+        n_jobs > ctx->lim.max_jobs || !tile_ok(tile))
+        return FVV_EINVAL;
+    return dev(launch_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out,
+                                    tile_of(tile), persistent_blocks(ctx, tile), false, stream));
+}
+
+fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint32_t* d_sils,
+                     const fvv_frame_out* o, hipStream_t stream) {
+    if (!ctx || !p || !o || !d_sils || !cams_ok(ctx, p->n_cams, p->cams) ||
+        !grid_ok(&p->coarse, kMaxIndex) || p->hc_um < 1 || p->hf_um < 1 || p->t_np > p->t_nb ||
+        p->n_steps < 1 || p->n_steps > FVV_MAX_STEPS || !tile_ok(&p->coarse_tile) ||
+        !tile_ok(&p->fine_tile))
+        return FVV_EINVAL;
+    if (!o->d_occ_coarse || !o->d_labels || !o->d_rois || !o->d_jobs || !o->d_occ_fine ||
+        !o->d_keys || !o->d_xyz || !o->d_point_off || !o->d_counts || o->max_rois < 1 ||
+        o->max_rois > ctx->lim.max_rois || o->max_fine < 1 || o->max_fine > ctx->lim.max_fine ||
+        o->max_points < 1)
+        return FVV_EINVAL;
+    if (grid_samples(p->coarse) > ctx->lim.max_coarse)
+        return FVV_EINVAL;
+    // every fine index must stay exact through the bisection
+    for (int a = 0; a < 3; ++a) {
+        const int64_t hi = ((int64_t)p->coarse.lo[a] + p->coarse.dims[a]) * p->hc_um / p->hf_um + 2;
+        const int64_t lo = (int64_t)p->coarse.lo[a] * p->hc_um / p->hf_um - 2;
+        const int64_t lim = (int64_t)1 << (23 - p->n_steps);
+        if (hi >= lim || lo <= -lim)
+            return FVV_EINVAL;
+    }
+    const CamSet cs = make_camset(p->n_cams, p->cams);
+    const float h_fine = (float)((double)p->hf_um * 1e-6);
+    const TileShape ct = tile_of(&p->coarse_tile), ft = tile_of(&p->fine_tile);
+    const int blocks = persistent_blocks(ctx, &p->fine_tile);
+    hipError_t e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, stream);
+    if (e == hipSuccess)
+        e = launch_label(ctx, p->coarse, o->d_occ_coarse, o->d_labels, p->t_np, p->t_nb, o->d_rois,
+                         o->max_rois, o->d_counts + 0, stream);
+    if (e == hipSuccess)
+        e = launch_frame_jobs(ctx, cs, p->coarse, p->hc_um, p->hf_um, h_fine, o->d_rois,
+                              o->d_counts + 0, o->max_rois, o->d_jobs, o->max_fine, o->d_counts,
+                              ft, blocks, stream);
+    if (e == hipSuccess)
+        e = launch_carve_batched(ctx, o->d_jobs, 0, ctx->d_cams, d_sils, o->d_occ_fine, ft, blocks,
+                                 true, stream);
+    if (e == hipSuccess)
+        e = launch_surface(ctx, o->d_jobs, o->d_counts + 3, o->max_rois, o->d_occ_fine, cs, d_sils,
+                           p->n_steps, o->d_keys, o->d_xyz, o->max_points, o->d_point_off,
+                           o->d_counts + 2, stream);
+    return dev(e);
+}
+
+struct fvv_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+fvv_status fvv_frame_graph_create(fvv_ctx* ctx, const fvv_frame_params* p, const uint32_t* d_sils,
+                                  const fvv_frame_out* o, fvv_graph** out) {
+    if (!out)
+        return FVV_EINVAL;
+    *out = nullptr;
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return FVV_EDEVICE;
+    fvv_status st = FVV_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamDestroy(s);
+        return FVV_EDEVICE;
+    }
+    st = fvv_frame(ctx, p, d_sils, o, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    hipStreamDestroy(s);
+    if (st != FVV_OK) {
+        if (g)
+            hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess || !g)
+        return FVV_EDEVICE;
+    hipGraphExec_t ex;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return FVV_EDEVICE;
+    }
+    fvv_graph* r = new (std::nothrow) fvv_graph;
+    if (!r) {
+        hipGraphExecDestroy(ex);
+        hipGraphDestroy(g);
+        return FVV_ENOMEM;
+    }
+    r->graph = g;
+    r->exec = ex;
+    *out = r;
+    return FVV_OK;
+}
+
+fvv_status fvv_graph_launch(fvv_graph* g, hipStream_t stream) {
+    if (!g)
+        return FVV_EINVAL;
+    return dev(hipGraphLaunch(g->exec, stream));
+}
+
+void fvv_graph_destroy(fvv_graph* g) {
+    if (!g)
+        return;
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

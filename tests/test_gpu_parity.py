@@ -1,0 +1,417 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by
+element on the same seeded inputs.  Occupancy, labels, ROI boxes and edge keys
+must be bit-exact (0 mismatches); exit points must agree within 1e-4 of the
+fine voxel edge (both sides compute the same dyadic parameter, so they are
+expected to agree exactly).  Sizes span several tiles with ragged tails, up to
+the full volleyball and judo frames."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(tx, tz) for tx in (64, 32, 16) for tz in (1, 2, 4, 8)]
+
+
+@pytest.fixture(scope="module")
+def fvv():
+    import paper_1903_11785_amd as fvv
+    return fvv
+
+
+@pytest.fixture(scope="module")
+def ctx(fvv):
+    c = fvv.Context(max_coarse=5_000_000, max_fine=1 << 28, max_rois=4096, max_points=1 << 23,
+                    max_jobs=4096)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def sils_dev(ctx, masks):
+    s = ctx.pack_silhouettes(dev(masks))
+    return s
+
+
+def grid_of(fvv, lat):
+    return fvv.Grid(origin=tuple(np.float32(lat.origin)), h=np.float32(lat.h), lo=tuple(lat.lo),
+                    dims=tuple(lat.dims))
+
+
+def coarse_lat(sc):
+    return oracle.Lattice(origin=sc.origin, h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
+
+
+# ------------------------------------------------------------------ packing
+@pytest.mark.parametrize("shape", [(4, 240, 320), (3, 7, 33), (2, 5, 31), (1, 3, 64), (5, 9, 100)])
+def test_pack(ctx, shape):
+    rng = np.random.default_rng(sum(shape))
+    masks = (rng.uniform(size=shape) < 0.5).astype(np.uint8) * rng.integers(1, 255, size=shape).astype(np.uint8)
+    got = host(ctx.pack_silhouettes(dev(masks))).view(np.uint32)
+    np.testing.assert_array_equal(got, oracle.pack(masks))
+
+
+def test_pack_full_frames(ctx, scene_cache):
+    for cfg in (2, 3):
+        sc = scene_cache(cfg, 0)
+        got = host(ctx.pack_silhouettes(dev(sc.masks))).view(np.uint32)
+        np.testing.assert_array_equal(got, oracle.pack(sc.masks))
+
+
+# ------------------------------------------------------------------ carving
+@pytest.mark.parametrize("tx,tz", TILES)
+def test_carve_tiny_coarse_every_tile(fvv, ctx, scene_cache, tx, tz):
+    sc = scene_cache(1, 0)
+    lat = coarse_lat(sc)
+    ref, _ = oracle.carve(sc.P32, oracle.pack(sc.masks), sc.W, sc.H, lat)
+    got = host(ctx.carve(sc.P32, sc.W, sc.H, sils_dev(ctx, sc.masks), grid_of(fvv, lat),
+                         fvv.tile(tx, tz)))
+    assert int((got != ref).sum()) == 0
+
+
+@pytest.mark.parametrize("seed", range(1, 7))
+def test_carve_tiny_coarse_and_fine(fvv, ctx, scene_cache, seed):
+    sc = scene_cache(1, seed)
+    sils = sils_dev(ctx, sc.masks)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, surface=False)
+    got = host(ctx.carve(sc.P32, sc.W, sc.H, sils, grid_of(fvv, res.coarse)))
+    assert int((got != res.occ_coarse).sum()) == 0
+    for lat, ref in zip(res.fine, res.occ_fine):
+        got = host(ctx.carve(sc.P32, sc.W, sc.H, sils, grid_of(fvv, lat), fvv.tile(32, 2)))
+        assert int((got != ref).sum()) == 0
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_carve_full_size_coarse(fvv, ctx, scene_cache, cfg):
+    sc = scene_cache(cfg, 0)
+    lat = coarse_lat(sc)
+    ref, _ = oracle.carve(sc.P32, oracle.pack(sc.masks), sc.W, sc.H, lat)
+    got = host(ctx.carve(sc.P32, sc.W, sc.H, sils_dev(ctx, sc.masks), grid_of(fvv, lat),
+                         fvv.tile(64, 1)))
+    assert int((got != ref).sum()) == 0
+
+
+def test_carve_integer_quotients(fvv, ctx):
+    """Projections that land exactly on pixel edges (a/w integral), where a
+    rounded quotient floors to the wrong pixel unless corrected exactly."""
+    rng = np.random.default_rng(5)
+    W = H = 160
+    for scale in (3.0, 0.1, 7.0, 1.0 / 3.0, 13.0):
+        s = np.float32(scale)
+        P = np.array([[[s, 0, 0, 0], [0, s, 0, 0], [0, 0, 0, s]],
+                      [[0, s, 0, s], [0, 0, s, 0], [0, 0, 0, s]]], np.float32)
+        masks = (rng.uniform(size=(2, H, W)) < 0.7).astype(np.uint8)
+        lat = oracle.Lattice(origin=np.float32([-1, -1, 0]), h=np.float32(0.25), lo=(0, 0, 0),
+                             dims=(300, 7, 300))
+        ref, _ = oracle.carve(P, oracle.pack(masks), W, H, lat)
+        got = host(ctx.carve(P, W, H, sils_dev(ctx, masks), grid_of(fvv, lat), fvv.tile(64, 4)))
+        assert int((got != ref).sum()) == 0
+        assert 0 < ref.sum() < ref.size
+
+
+def test_carve_behind_and_off_image(fvv, ctx, scene_cache):
+    sc = scene_cache(1, 0)
+    away = scenes.look_at([3.0, 0.0, 0.0], [16.0, 0.0, 0.0], 300.0, 320, 240)
+    P = np.concatenate([sc.P32, away.P32[None]], 0)
+    masks = np.concatenate([sc.masks, np.ones((1, 240, 320), np.uint8)], 0)
+    lat = oracle.Lattice(origin=np.float32([-7, -7, -4]), h=np.float32(0.125), lo=(0, 0, 0),
+                         dims=(112, 112, 64))
+    for cams in (slice(0, 4), slice(0, 5), slice(4, 5)):
+        ref, _ = oracle.carve(P[cams], oracle.pack(masks[cams]), 320, 240, lat)
+        got = host(ctx.carve(P[cams], 320, 240, sils_dev(ctx, masks[cams]), grid_of(fvv, lat)))
+        assert int((got != ref).sum()) == 0
+
+
+def test_carve_negative_lattice_indices_and_ragged(fvv, ctx, scene_cache):
+    sc = scene_cache(1, 3)
+    sils = sils_dev(ctx, sc.masks)
+    for lo, dims in [((-37, -20, -9), (131, 61, 47)), ((3, -50, 1), (65, 129, 3)),
+                     ((0, 0, 0), (1, 1, 1)), ((-100, -100, -50), (1, 257, 9))]:
+        lat = oracle.Lattice(origin=np.float32([0.3, -0.2, 0.1]), h=np.float32(0.02), lo=lo,
+                             dims=dims)
+        ref, _ = oracle.carve(sc.P32, oracle.pack(sc.masks), sc.W, sc.H, lat)
+        for tx, tz in ((64, 4), (16, 8), (32, 1)):
+            got = host(ctx.carve(sc.P32, sc.W, sc.H, sils, grid_of(fvv, lat), fvv.tile(tx, tz)))
+            assert int((got != ref).sum()) == 0
+
+
+# ------------------------------------------------------------------ labelling
+def check_label(fvv, ctx, occ, t_np=1, t_nb=0xFFFFFFFF, max_rois=4096):
+    nz, ny, nx = occ.shape
+    g = fvv.Grid(origin=(0, 0, 0), h=1.0, lo=(0, 0, 0), dims=(nx, ny, nz))
+    occ_d = dev(occ.astype(np.uint8))
+    labels, rois, n = ctx.label(g, occ_d, t_np, t_nb, max_rois)
+    ref_occ, ref_lab, ref_rois, K = oracle.label(occ, t_np, t_nb)
+    assert int(host(n)[0]) == K
+    np.testing.assert_array_equal(host(labels), ref_lab)
+    np.testing.assert_array_equal(host(occ_d), ref_occ)
+    k = min(K, max_rois)
+    np.testing.assert_array_equal(host(rois)[:k], ref_rois[:k])
+    return K
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_label_random(fvv, ctx, seed):
+    rng = np.random.default_rng(100 + seed)
+    shape = tuple(int(v) for v in rng.integers(5, 70, size=3))
+    dens = [0.03, 0.1, 0.2, 0.35, 0.5][seed % 5]
+    occ = (rng.uniform(size=shape) < dens).astype(np.uint8)
+    check_label(fvv, ctx, occ)
+    check_label(fvv, ctx, occ, t_np=3, t_nb=50)
+
+
+def test_label_adversarial_shapes(fvv, ctx):
+    occ = np.zeros((37, 41, 45), np.uint8)
+    for t in range(37):
+        occ[t, t, t] = 1                      # diagonal through many blocks, vertex contacts only
+    occ[0, 40, 0:45:2] = 1                    # isolated voxels along a row
+    k, j, i = np.indices((20, 20, 40))
+    cb = ((i + j + k) % 2 == 0).astype(np.uint8)
+    spiral = np.zeros((8, 64, 64), np.uint8)
+    y, x = 32, 32
+    for s in range(1, 60):
+        for _ in range(s):
+            x += 1 if s % 2 else -1
+            if 0 <= x < 64:
+                spiral[s % 8, y, x] = 1
+        for _ in range(s):
+            y += 1 if s % 2 else -1
+            if 0 <= y < 64 and 0 <= x < 64:
+                spiral[s % 8, y, x] = 1
+    for g in (occ, cb, spiral, np.ones((9, 10, 33), np.uint8), np.zeros((3, 4, 5), np.uint8)):
+        check_label(fvv, ctx, g)
+
+
+def test_label_filter_bounds(fvv, ctx):
+    occ = np.zeros((10, 10, 30), np.uint8)
+    occ[1, 1, 0:3] = 1
+    occ[5, 5, 0:4] = 1
+    occ[8, 8, 10:15] = 1
+    occ[1, 8, 20:26] = 1
+    for t_np, t_nb in [(4, 5), (3, 6), (5, 5), (7, 0xFFFFFFFF), (1, 3)]:
+        check_label(fvv, ctx, occ, t_np, t_nb)
+
+
+def test_label_capacity_overflow(fvv, ctx):
+    occ = np.zeros((6, 6, 12), np.uint8)
+    occ[0, 0, 0] = occ[3, 3, 3] = occ[5, 5, 8] = 1
+    assert ctx.check() == fvv.FVV_OK
+    K = check_label(fvv, ctx, occ, max_rois=2)
+    assert K == 3
+    assert ctx.check() == fvv.FVV_ECAPACITY
+    assert ctx.check() == fvv.FVV_OK
+
+
+@pytest.mark.parametrize("cfg,frame", [(1, 0), (1, 4), (2, 0), (3, 0)])
+def test_label_scene_coarse(fvv, ctx, scene_cache, cfg, frame):
+    sc = scene_cache(cfg, frame)
+    occ, _ = oracle.carve(sc.P32, oracle.pack(sc.masks), sc.W, sc.H, coarse_lat(sc))
+    check_label(fvv, ctx, occ, sc.t_np, sc.t_nb)
+
+
+# ------------------------------------------------------------------ surface
+def check_surface(fvv, ctx, sc, lat, occ, sils, steps=8, max_points=1 << 22):
+    keys_ref = oracle.edges(occ)
+    xyz_ref, _ = oracle.bisect(sc.P32, oracle.pack(sc.masks), sc.W, sc.H, lat, occ, keys_ref, steps)
+    keys, xyz, n = ctx.surface(grid_of(fvv, lat), dev(occ), sc.P32, sc.W, sc.H, sils, steps,
+                               max_points)
+    E = int(host(n)[0])
+    assert E == keys_ref.size
+    k = min(E, max_points)
+    np.testing.assert_array_equal(host(keys)[:k].view(np.uint32), keys_ref[:k])
+    err = np.abs(host(xyz)[:k].astype(np.float64) - xyz_ref[:k].astype(np.float64)).max(initial=0)
+    assert err <= 1e-4 * float(lat.h)
+    return E, err
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_surface_tiny(fvv, ctx, scene_cache, seed):
+    sc = scene_cache(1, seed)
+    sils = sils_dev(ctx, sc.masks)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, surface=False)
+    for lat, occ in zip(res.fine, res.occ_fine):
+        for steps in (8, 1, 12):
+            E, err = check_surface(fvv, ctx, sc, lat, occ, sils, steps)
+            assert E > 0 and err == 0.0
+
+
+def test_surface_degenerate_and_capacity(fvv, ctx, scene_cache):
+    sc = scene_cache(1, 0)
+    sils = sils_dev(ctx, sc.masks)
+    lat = oracle.Lattice(origin=sc.origin, h=sc.hf, lo=(90, 90, 40), dims=(1, 1, 1))
+    E, _ = check_surface(fvv, ctx, sc, lat, np.zeros((1, 1, 1), np.uint8), sils)
+    assert E == 0
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, surface=False)
+    lat, occ = res.fine[0], res.occ_fine[0]
+    assert ctx.check() == fvv.FVV_OK
+    E, _ = check_surface(fvv, ctx, sc, lat, occ, sils, max_points=1000)
+    assert E > 1000
+    assert ctx.check() == fvv.FVV_ECAPACITY
+
+
+# ------------------------------------------------------------------ batched carve
+def batched_case(n_frames=3, rois_per_frame=4, scale=0.35):
+    sc_list, boxes = scenes.batched_rois(n_frames, rois_per_frame, hf_um=20000,
+                                         edge_lo=0.6 * scale * 2, edge_hi=2.5 * scale * 2)
+    return sc_list, boxes
+
+
+def test_batched_equals_per_roi_and_oracle(fvv, ctx):
+    import torch
+    scs, boxes = batched_case()
+    W, H = scs[0].W, scs[0].H
+    N = scs[0].P32.shape[0]
+    P_all = np.concatenate([s.P32 for s in scs], 0)
+    masks_all = np.concatenate([s.masks for s in scs], 0)
+    sils = sils_dev(ctx, masks_all)
+    cams_dev = fvv.cameras_to_device(P_all, W, H)
+    wpr = (W + 31) // 32
+    jobs = np.zeros(len(boxes), fvv.JOB_DTYPE)
+    off = 0
+    for t, b in enumerate(boxes):
+        jobs[t]["origin"] = scs[b.frame].origin
+        jobs[t]["h"] = scs[b.frame].hf
+        jobs[t]["lo"] = b.lo
+        jobs[t]["dims"] = b.dims
+        jobs[t]["cam_base"] = b.frame * N
+        jobs[t]["n_cams"] = N
+        jobs[t]["width"], jobs[t]["height"] = W, H
+        jobs[t]["sil_base"] = b.frame * N * H * wpr
+        jobs[t]["out_offset"] = off
+        off += int(np.prod(b.dims))
+    jobs_d = fvv.jobs_to_device(jobs)
+    outs = []
+    for (tx, tz, blocks) in [(64, 4, 0), (32, 2, 7), (16, 8, 1), (64, 1, 3000)]:
+        out = torch.full((off,), 7, dtype=torch.uint8, device="cuda")
+        ctx.carve_batched(jobs_d, len(boxes), cams_dev, sils, out, fvv.tile(tx, tz, blocks))
+        outs.append(host(out))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    for t, b in enumerate(boxes):
+        s = scs[b.frame]
+        lat = oracle.Lattice(origin=s.origin, h=s.hf, lo=b.lo, dims=b.dims)
+        ref, _ = oracle.carve(s.P32, oracle.pack(s.masks), W, H, lat)
+        seg = outs[0][int(jobs[t]["out_offset"]):int(jobs[t]["out_offset"]) + lat.size]
+        assert int((seg.reshape(ref.shape) != ref).sum()) == 0
+        per = host(ctx.carve(s.P32, W, H, sils_dev(ctx, s.masks), grid_of(fvv, lat)))
+        np.testing.assert_array_equal(per, ref)
+
+
+# ------------------------------------------------------------------ whole frame
+def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, graph=False):
+    coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
+    params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
+                              sc.n_steps)
+    bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
+    masks = dev(sc.masks)
+    sils = ctx.pack_silhouettes(masks)
+    if graph:
+        g = ctx.frame_graph(params, sils, bufs)
+        return g, bufs, sils
+    ctx.frame(params, sils, bufs)
+    return None, bufs, sils
+
+
+def compare_frame(fvv, sc, bufs, res):
+    counts = host(bufs.counts)
+    K = len(res.rois)
+    assert int(counts[0]) == K and int(counts[3]) == K
+    np.testing.assert_array_equal(host(bufs.occ_coarse), res.occ_filtered)
+    np.testing.assert_array_equal(host(bufs.labels), res.labels)
+    np.testing.assert_array_equal(host(bufs.rois)[:K], res.rois)
+    jobs = bufs.jobs_host(K)
+    occ_fine = host(bufs.occ_fine)
+    keys = host(bufs.keys).view(np.uint32)
+    xyz = host(bufs.xyz)
+    poff = host(bufs.point_off)
+    assert int(counts[1]) == res.fine_voxels
+    assert int(counts[2]) == sum(k.size for k in res.keys)
+    for t, lat in enumerate(res.fine):
+        assert tuple(jobs[t]["lo"]) == lat.lo and tuple(jobs[t]["dims"]) == lat.dims
+        assert np.float32(jobs[t]["h"]) == lat.h
+        o = int(jobs[t]["out_offset"])
+        seg = occ_fine[o:o + lat.size].reshape(res.occ_fine[t].shape)
+        assert int((seg != res.occ_fine[t]).sum()) == 0
+        a, b = int(poff[t]), int(poff[t + 1])
+        np.testing.assert_array_equal(keys[a:b], res.keys[t])
+        err = np.abs(xyz[a:b].astype(np.float64) - res.xyz[t].astype(np.float64)).max(initial=0)
+        assert err <= 1e-4 * float(lat.h)
+
+
+@pytest.mark.parametrize("cfg,frame", [(1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (3, 0)])
+def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
+    sc = scene_cache(cfg, frame)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    _, bufs, _ = run_frame(fvv, ctx, sc)
+    assert ctx.check() == fvv.FVV_OK
+    compare_frame(fvv, sc, bufs, res)
+
+
+def test_frame_graph_replays(fvv, ctx, scene_cache):
+    import torch
+    sc = scene_cache(2, 0)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims)
+    g, bufs, sils = run_frame(fvv, ctx, sc, graph=True)
+    for rep in range(4):
+        for t in (bufs.occ_fine, bufs.keys, bufs.xyz, bufs.labels, bufs.counts):
+            t.fill_(0 if rep % 2 else 3)
+        g.launch()
+        torch.cuda.synchronize()
+        x = torch.randn(1000, device="cuda").sum()          # eager work between replays
+        torch.cuda.synchronize()
+        compare_frame(fvv, sc, bufs, res)
+    g.close()
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_frame_capacity_limits(fvv, ctx, scene_cache):
+    sc = scene_cache(2, 0)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims)
+    sizes = [l.size for l in res.fine]
+    cap = sum(sizes[:3]) + sizes[3] // 2              # room for three ROIs only
+    _, bufs, _ = run_frame(fvv, ctx, sc, max_fine=cap)
+    counts = host(bufs.counts)
+    assert int(counts[0]) == len(res.rois) and int(counts[3]) == 3
+    assert int(counts[1]) == sum(sizes[:3])
+    assert ctx.check() == fvv.FVV_ECAPACITY
+    _, bufs, _ = run_frame(fvv, ctx, sc, max_rois=5)
+    counts = host(bufs.counts)
+    assert int(counts[0]) == len(res.rois) and int(counts[3]) == 5
+    assert ctx.check() == fvv.FVV_ECAPACITY
+
+
+def test_invalid_arguments_are_rejected(fvv, ctx, scene_cache):
+    sc = scene_cache(1, 0)
+    sils = sils_dev(ctx, sc.masks)
+    bad = [
+        fvv.Grid(origin=(0, 0, 0), h=0.1, lo=(0, 0, 0), dims=(0, 4, 4)),
+        fvv.Grid(origin=(0, 0, 0), h=-0.1, lo=(0, 0, 0), dims=(4, 4, 4)),
+        fvv.Grid(origin=(0, 0, 0), h=0.1, lo=(1 << 24, 0, 0), dims=(4, 4, 4)),
+        fvv.Grid(origin=(0, 0, 0), h=0.1, lo=(0, 0, 0), dims=(1 << 16, 1 << 16, 1)),
+    ]
+    for g in bad:
+        with pytest.raises(fvv.FvvError) as e:
+            ctx.carve(sc.P32, sc.W, sc.H, sils, g, out=dev(np.zeros(1, np.uint8)))
+        assert e.value.status == fvv.FVV_EINVAL
+    good = fvv.Grid(origin=(0, 0, 0), h=0.1, lo=(0, 0, 0), dims=(4, 4, 4))
+    P = sc.P32.copy()
+    P[1, 0, 0] = np.nan
+    with pytest.raises(fvv.FvvError):
+        ctx.carve(P, sc.W, sc.H, sils, good)
+    with pytest.raises(fvv.FvvError):
+        ctx.carve(np.zeros((33, 3, 4), np.float32), sc.W, sc.H, sils, good)
+    with pytest.raises(fvv.FvvError):
+        ctx.surface(good, dev(np.zeros((4, 4, 4), np.uint8)), sc.P32, sc.W, sc.H, sils, n_steps=13)
+    with pytest.raises(fvv.FvvError):
+        ctx.label(good, dev(np.zeros((4, 4, 4), np.uint8)), t_np=9, t_nb=8)
