@@ -234,18 +234,24 @@ typedef struct {
     uint32_t max_points;
 } fvv_frame_out;
 
-/* Enqueue the whole frame on `stream`.  d_sils: the frame's packed
- * silhouettes.  EINVAL as the individual calls. */
-fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint32_t *d_sils,
-                     const fvv_frame_out *out, hipStream_t stream);
+/* Enqueue the whole frame on `stream`.  d_masks: the frame's uint8
+ * silhouettes [n_cams][H][W], packed into d_sils first; or NULL when d_sils
+ * already holds the packed silhouettes.  events: NULL, or FVV_FRAME_EVENTS
+ * HIP events recorded on `stream` at the start and after each stage (pack,
+ * coarse carve, labelling, fine jobs + fine carve, crossing edges, exit
+ * points) -- a per-stage timing of the frame.  EINVAL as the individual calls. */
+#define FVV_FRAME_EVENTS 7
+fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint8_t *d_masks,
+                     uint32_t *d_sils, const fvv_frame_out *out, hipEvent_t *events,
+                     hipStream_t stream);
 
-/* Capture fvv_frame (with fixed arguments) into an executable HIP graph.
- * The capture runs on an internal stream; the graph replays the frame with the
- * same pointers.  Release with fvv_graph_destroy. */
+/* Capture fvv_frame (with fixed arguments, no events) into an executable HIP
+ * graph.  The capture runs on an internal stream; the graph replays the frame
+ * with the same pointers.  Release with fvv_graph_destroy. */
 typedef struct fvv_graph fvv_graph;
 fvv_status fvv_frame_graph_create(fvv_ctx *ctx, const fvv_frame_params *params,
-                                  const uint32_t *d_sils, const fvv_frame_out *out,
-                                  fvv_graph **graph);
+                                  const uint8_t *d_masks, uint32_t *d_sils,
+                                  const fvv_frame_out *out, fvv_graph **graph);
 fvv_status fvv_graph_launch(fvv_graph *graph, hipStream_t stream);
 void fvv_graph_destroy(fvv_graph *graph);
 

@@ -62,6 +62,7 @@ def lib():
                                  C.c_int, p, p]
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
+        L.orc_threads.restype = i32
         _lib = L
     return _lib
 
@@ -77,6 +78,11 @@ def _i3(v) -> np.ndarray:
 
 def _f3(v) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(v, dtype=np.float32).reshape(3))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def floor_div(a: float, w: float) -> int:

@@ -399,3 +399,16 @@ int32_t orc_point_inside(int ncam, const float *P, int W, int H, const uint32_t 
     int nt = 0;
     return point_inside(ncam, P, W, H, sils, X, Y, Z, &nt);
 }
+
+/* Threads the OpenMP loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int32_t orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

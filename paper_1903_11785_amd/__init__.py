@@ -22,6 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfvv.so")
 MAX_CAMS = 32
 MAX_STEPS = 12
+FRAME_EVENTS = 7
+STAGES = ("pack", "coarse_carve", "label", "fine_carve", "edges", "exit_points")
 
 FVV_OK, FVV_EINVAL, FVV_ECAPACITY, FVV_EDEVICE, FVV_ENOMEM = 0, -1, -2, -3, -4
 
@@ -115,8 +117,8 @@ def _load():
         "fvv_surface": ([P, C.POINTER(GridC), P, i32, C.POINTER(Camera), P, i32, P, P, u32, P, P],
                         i32),
         "fvv_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), P], i32),
-        "fvv_frame": ([P, C.POINTER(FrameParams), P, C.POINTER(FrameOut), P], i32),
-        "fvv_frame_graph_create": ([P, C.POINTER(FrameParams), P, C.POINTER(FrameOut),
+        "fvv_frame": ([P, C.POINTER(FrameParams), P, P, C.POINTER(FrameOut), P, P], i32),
+        "fvv_frame_graph_create": ([P, C.POINTER(FrameParams), P, P, C.POINTER(FrameOut),
                                     C.POINTER(P)], i32),
         "fvv_graph_launch": ([P, P], i32),
         "fvv_graph_destroy": ([P], None),
@@ -191,6 +193,15 @@ def tile(tx: int = 64, tz: int = 4, persistent_blocks: int = 0) -> Tile:
 
 def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
+
+
+def _event_handle(ev) -> int:
+    """hipEvent_t of a torch.cuda.Event (created on first use)."""
+    import torch
+    if ev.cuda_event == 0:                  # torch creates events lazily
+        ev.record(torch.cuda.current_stream())
+        torch.cuda.current_stream().synchronize()
+    return int(ev.cuda_event)
 
 
 def _stream(stream=None) -> int:
@@ -307,14 +318,22 @@ class Context:
                                      C.c_void_p(_stream(stream))), "fvv_carve_batched")
         return out
 
-    def frame(self, params: FrameParams, sils, out: "FrameBuffers", stream=None):
-        _ok(self.L.fvv_frame(self.h, C.byref(params), _ptr(sils), C.byref(out.c),
+    def frame(self, params: FrameParams, sils, out: "FrameBuffers", masks=None, events=None,
+              stream=None):
+        """The whole path for one frame.  masks (uint8 [N][H][W], optional) are
+        packed into sils first.  events: optional list of FRAME_EVENTS
+        torch.cuda.Event(enable_timing=True), recorded between the stages."""
+        ev = None
+        if events is not None:
+            assert len(events) == FRAME_EVENTS
+            ev = (C.c_void_p * FRAME_EVENTS)(*[_event_handle(e) for e in events])
+        _ok(self.L.fvv_frame(self.h, C.byref(params), _ptr(masks), _ptr(sils), C.byref(out.c), ev,
                              C.c_void_p(_stream(stream))), "fvv_frame")
 
-    def frame_graph(self, params: FrameParams, sils, out: "FrameBuffers") -> "FrameGraph":
+    def frame_graph(self, params: FrameParams, sils, out: "FrameBuffers", masks=None) -> "FrameGraph":
         g = C.c_void_p()
-        _ok(self.L.fvv_frame_graph_create(self.h, C.byref(params), _ptr(sils), C.byref(out.c),
-                                          C.byref(g)), "fvv_frame_graph_create")
+        _ok(self.L.fvv_frame_graph_create(self.h, C.byref(params), _ptr(masks), _ptr(sils),
+                                          C.byref(out.c), C.byref(g)), "fvv_frame_graph_create")
         return FrameGraph(self.L, g)
 
 

@@ -299,7 +299,7 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
     if (e == hipSuccess)
         e = launch_surface(ctx, ctx->d_job_single, ctx->d_counts_single + 3, 1, d_occ_fine, cs,
                            d_sils, n_steps, d_keys, d_xyz, max_points, ctx->d_point_off_single,
-                           d_n_points, stream);
+                           d_n_points, nullptr, stream);
     return dev(e);
 }
 
@@ -313,8 +313,9 @@ fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_job
                                     tile_of(tile), persistent_blocks(ctx, tile), false, stream));
 }
 
-fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint32_t* d_sils,
-                     const fvv_frame_out* o, hipStream_t stream) {
+fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_masks,
+                     uint32_t* d_sils, const fvv_frame_out* o, hipEvent_t* events,
+                     hipStream_t stream) {
     if (!ctx || !p || !o || !d_sils || !cams_ok(ctx, p->n_cams, p->cams) ||
         !grid_ok(&p->coarse, kMaxIndex) || p->hc_um < 1 || p->hf_um < 1 || p->t_np > p->t_nb ||
         p->n_steps < 1 || p->n_steps > FVV_MAX_STEPS || !tile_ok(&p->coarse_tile) ||
@@ -335,14 +336,30 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint32_t* d_
         if (hi >= lim || lo <= -lim)
             return FVV_EINVAL;
     }
+    if (events)
+        for (int i = 0; i < FVV_FRAME_EVENTS; ++i)
+            if (!events[i])
+                return FVV_EINVAL;
     const CamSet cs = make_camset(p->n_cams, p->cams);
     const float h_fine = (float)((double)p->hf_um * 1e-6);
     const TileShape ct = tile_of(&p->coarse_tile), ft = tile_of(&p->fine_tile);
     const int blocks = persistent_blocks(ctx, &p->fine_tile);
-    hipError_t e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, stream);
+    auto mark = [&](int i) {
+        if (events)
+            (void)hipEventRecord(events[i], stream);
+    };
+    hipError_t e = hipSuccess;
+    mark(0);
+    if (d_masks)
+        e = launch_pack(p->n_cams, cs.W, cs.H, d_masks, d_sils, stream);
+    mark(1);
+    if (e == hipSuccess)
+        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, stream);
+    mark(2);
     if (e == hipSuccess)
         e = launch_label(ctx, p->coarse, o->d_occ_coarse, o->d_labels, p->t_np, p->t_nb, o->d_rois,
                          o->max_rois, o->d_counts + 0, stream);
+    mark(3);
     if (e == hipSuccess)
         e = launch_frame_jobs(ctx, cs, p->coarse, p->hc_um, p->hf_um, h_fine, o->d_rois,
                               o->d_counts + 0, o->max_rois, o->d_jobs, o->max_fine, o->d_counts,
@@ -350,10 +367,12 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint32_t* d_
     if (e == hipSuccess)
         e = launch_carve_batched(ctx, o->d_jobs, 0, ctx->d_cams, d_sils, o->d_occ_fine, ft, blocks,
                                  true, stream);
+    mark(4);
     if (e == hipSuccess)
         e = launch_surface(ctx, o->d_jobs, o->d_counts + 3, o->max_rois, o->d_occ_fine, cs, d_sils,
                            p->n_steps, o->d_keys, o->d_xyz, o->max_points, o->d_point_off,
-                           o->d_counts + 2, stream);
+                           o->d_counts + 2, events ? events[5] : nullptr, stream);
+    mark(6);
     return dev(e);
 }
 
@@ -362,7 +381,8 @@ struct fvv_graph {
     hipGraphExec_t exec;
 };
 
-fvv_status fvv_frame_graph_create(fvv_ctx* ctx, const fvv_frame_params* p, const uint32_t* d_sils,
+fvv_status fvv_frame_graph_create(fvv_ctx* ctx, const fvv_frame_params* p,
+                                  const uint8_t* d_masks, uint32_t* d_sils,
                                   const fvv_frame_out* o, fvv_graph** out) {
     if (!out)
         return FVV_EINVAL;
@@ -376,7 +396,7 @@ fvv_status fvv_frame_graph_create(fvv_ctx* ctx, const fvv_frame_params* p, const
         hipStreamDestroy(s);
         return FVV_EDEVICE;
     }
-    st = fvv_frame(ctx, p, d_sils, o, s);
+    st = fvv_frame(ctx, p, d_masks, d_sils, o, nullptr, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     hipStreamDestroy(s);
     if (st != FVV_OK) {

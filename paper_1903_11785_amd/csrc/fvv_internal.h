@@ -238,7 +238,7 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                           uint32_t max_jobs, const uint8_t* occ_fine, const CamSet& cams,
                           const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,
                           uint32_t max_points, uint32_t* point_off, uint32_t* n_points,
-                          hipStream_t s);
+                          hipEvent_t edges_done, hipStream_t s);
 hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, hipStream_t s);
 
 }  // namespace fvv

@@ -356,7 +356,7 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                           uint32_t max_jobs, const uint8_t* occ_fine, const CamSet& cams,
                           const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,
                           uint32_t max_points, uint32_t* point_off, uint32_t* n_points,
-                          hipStream_t s) {
+                          hipEvent_t edges_done, hipStream_t s) {
     (void)max_jobs;
     const unsigned blocks = (unsigned)(ctx->n_cus * 8);
     hipLaunchKernelGGL(edge_count_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
@@ -366,6 +366,8 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                        ctx->d_status);
     hipLaunchKernelGGL(edge_write_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
                        n_jobs_dev, occ_fine, ctx->d_item_base, keys, max_points);
+    if (edges_done)
+        (void)hipEventRecord(edges_done, s);
     hipLaunchKernelGGL(bisect_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, n_jobs_dev,
                        point_off, occ_fine, cams, sils, n_steps, keys, xyz, max_points);
     return hipGetLastError();

@@ -24,6 +24,8 @@ are in its experiments section):
 
 Random streams: ``numpy.random.Generator(PCG64(SeedSequence([cfg, frame,
 purpose])))`` with purpose 0 = cameras, 1 = objects, 2 = noise, 3 = ROI boxes.
+The court rigs are static (drawn with frame 0 for every frame): the paper's
+cameras do not move and are calibrated once.
 
 Conventions (shared by specification with the consumers, not by code):
 camera rows are R = [right; down; forward] with world z up, intrinsics
@@ -361,7 +363,7 @@ def _place_players(rng, n_per_half: int, x_rng, y_rng, spacing: float):
 
 def scene_volleyball(frame: int) -> Scene:
     lo, hi = np.array([-9.0, -4.5, 0.0]), np.array([9.0, 4.5, 4.0])
-    cams = _court_rig(CFG_VOLLEYBALL, frame, 16, 1920, 1080, 1800.0, 2400.0, lo, hi)
+    cams = _court_rig(CFG_VOLLEYBALL, 0, 16, 1920, 1080, 1800.0, 2400.0, lo, hi)   # static rig
     rng = rng_for(CFG_VOLLEYBALL, frame, 1)
     ells, groups = [], []
     for p in _place_players(rng, 6, (0.8, 8.2), (-3.8, 3.8), 1.0):
@@ -380,7 +382,7 @@ def scene_volleyball(frame: int) -> Scene:
 
 def scene_judo(frame: int) -> Scene:
     lo, hi = np.array([-5.0, -5.0, 0.0]), np.array([5.0, 5.0, 3.0])
-    cams = _court_rig(CFG_JUDO, frame, 24, 3840, 2160, 3600.0, 4800.0, lo, hi)
+    cams = _court_rig(CFG_JUDO, 0, 24, 3840, 2160, 3600.0, 4800.0, lo, hi)   # static rig
     rng = rng_for(CFG_JUDO, frame, 1)
     n_pairs = int(rng.integers(1, 3))          # 2-4 players in touching pairs
     ells, groups = [], []

@@ -308,17 +308,27 @@ def test_batched_equals_per_roi_and_oracle(fvv, ctx):
 
 
 # ------------------------------------------------------------------ whole frame
-def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, graph=False):
+def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, graph=False,
+              pack_first=False):
     coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
     params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
                               sc.n_steps)
     bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
+    import torch
     masks = dev(sc.masks)
-    sils = ctx.pack_silhouettes(masks)
-    if graph:
-        g = ctx.frame_graph(params, sils, bufs)
+    N, H, W = sc.masks.shape
+    sils = torch.zeros((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+    if graph:                                  # packing inside the graph
+        g = ctx.frame_graph(params, sils, bufs, masks=masks)
         return g, bufs, sils
-    ctx.frame(params, sils, bufs)
+    if pack_first:                             # packed by a separate call
+        ctx.pack_silhouettes(masks, out=sils)
+        ctx.frame(params, sils, bufs)
+    else:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(fvv.FRAME_EVENTS)]
+        ctx.frame(params, sils, bufs, masks=masks, events=ev)
+        torch.cuda.synchronize()
+        assert all(ev[i].elapsed_time(ev[i + 1]) >= 0 for i in range(fvv.FRAME_EVENTS - 1))
     return None, bufs, sils
 
 
@@ -353,7 +363,7 @@ def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
     sc = scene_cache(cfg, frame)
     res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
                        sc.t_nb, sc.n_steps)
-    _, bufs, _ = run_frame(fvv, ctx, sc)
+    _, bufs, _ = run_frame(fvv, ctx, sc, pack_first=(frame % 2 == 1))
     assert ctx.check() == fvv.FVV_OK
     compare_frame(fvv, sc, bufs, res)
 
