@@ -1,6 +1,8 @@
 // C ABI of the gfx950 visual-hull library: argument checks, the context's
 // start-up allocation, and the launch sequence of each call.
 #include <math.h>
+
+#include <cmath>
 #include <string.h>
 
 #include <new>
@@ -51,16 +53,67 @@ bool cams_ok(const fvv_ctx* ctx, int32_t n, const fvv_camera* cams) {
     return true;
 }
 
-CamSet make_camset(int32_t n, const fvv_camera* cams) {
+// World box of the samples of g (corner samples, as the kernels compute them).
+void grid_box(const fvv_grid& g, double lo[3], double hi[3]) {
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (double)fmaf((float)g.lo[a], g.h, g.origin[a]);
+        hi[a] = (double)fmaf((float)(g.lo[a] + g.dims[a] - 1), g.h, g.origin[a]);
+    }
+}
+
+// Rounding pad of camera P over the world box [lo, hi] (see CamSet::pad).
+// Each projection row is a chain of three fmas, so its rounded value is within
+// 3u(1+u)^2 < 4u of S = sum |P_k||X_k| + |P_3| (u = 2^-24); the quotient of the
+// rounded rows is then within d = (4u S_ab + M 4u S_w) / (w_min - 4u S_w) of the
+// real projection wherever |a/w| <= M, and a quotient formed with rcp adds at
+// most M 2^-22.  The pad covers a point's rounded quotient against the rcp
+// quotients of two other points: 2d + M 2^-21, plus slack.
+float rounding_pad(const float* P, int W, int H, const double lo[3], const double hi[3]) {
+    const double u = std::ldexp(1.0, -24);
+    double s[3] = {0, 0, 0}, wmin = INFINITY;
+    for (int corner = 0; corner < 8; ++corner) {
+        const double X[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1],
+                             (corner & 4) ? hi[2] : lo[2]};
+        for (int r = 0; r < 3; ++r) {
+            double acc = std::fabs((double)P[4 * r + 3]);
+            for (int k = 0; k < 3; ++k)
+                acc += std::fabs((double)P[4 * r + k]) * std::fabs(X[k]);
+            s[r] = std::fmax(s[r], acc);
+        }
+        double w = (double)P[11];
+        for (int k = 0; k < 3; ++k)
+            w += (double)P[8 + k] * X[k];
+        wmin = std::fmin(wmin, w);
+    }
+    const double M = 4.0 * (double)(W > H ? W : H);
+    const double ew = 4.0 * u * s[2];
+    if (!(wmin - ew > 0.0))
+        return INFINITY;
+    const double d = (4.0 * u * std::fmax(s[0], s[1]) + M * ew) / (wmin - ew);
+    const double pad = 2.0 * d + M * std::ldexp(1.0, -21) + std::ldexp(1.0, -10);
+    if (!(pad < 0.25))
+        return INFINITY;       // too coarse to be useful
+    return (float)pad * (1.0f + 0x1p-20f);
+}
+
+CamSet make_camset(int32_t n, const fvv_camera* cams, const fvv_grid* box = nullptr) {
     CamSet cs;
     memset(&cs, 0, sizeof(cs));
     cs.n = n;
     cs.W = cams[0].width;
     cs.H = cams[0].height;
     cs.wpr = (cs.W + 31) / 32;
-    for (int c = 0; c < n; ++c)
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    if (box)
+        grid_box(*box, lo, hi);
+    for (int c = 0; c < FVV_MAX_CAMS; ++c)
+        cs.pad[c] = INFINITY;
+    for (int c = 0; c < n; ++c) {
         for (int e = 0; e < 12; ++e)
             cs.P[c][e] = cams[c].P[e];
+        if (box)
+            cs.pad[c] = rounding_pad(cams[c].P, cs.W, cs.H, lo, hi);
+    }
     return cs;
 }
 
@@ -124,13 +177,20 @@ void fvv_destroy(fvv_ctx* ctx) {
     if (!ctx)
         return;
     hipDeviceSynchronize();
-    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_parent, ctx->d_rid, ctx->d_rootbits,
-                    ctx->d_blk_cnt, ctx->d_n_roots, ctx->d_stats, ctx->d_keep, ctx->d_prefix,
+    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_parent, ctx->d_stats, ctx->d_list,
+                    ctx->d_slot, ctx->d_list_count, ctx->d_bits0, ctx->d_bits1, ctx->d_words,
+                    ctx->d_prefix,
                     ctx->d_job_single, ctx->d_cams, ctx->d_item_cnt, ctx->d_item_base,
                     ctx->d_point_off_single, ctx->d_counts_single};
     for (void* p : ptrs)
         if (p)
             hipFree(p);
+    if (ctx->ev_fork)
+        hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join)
+        hipEventDestroy(ctx->ev_join);
+    if (ctx->side)
+        hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -156,8 +216,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         return FVV_EDEVICE;
     }
     const int64_t V = lim->max_coarse;
-    const int64_t chunks = (V + kRootChunk - 1) / kRootChunk;
-    c->root_cap = V;
+    const int64_t w0 = (V + 63) / 64 + 1, w1 = (V + 4095) / 4096 + 1;
     c->job_cap = (int64_t)(lim->max_jobs > lim->max_rois ? lim->max_jobs : lim->max_rois) + 2;
     c->item_cap = lim->max_fine / kEdgeChunk + (int64_t)lim->max_rois + 2;
     hipError_t e = hipSuccess;
@@ -167,12 +226,13 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_status, 1)
     A(d_counter, 4)
     A(d_parent, V)
-    A(d_rid, V)
-    A(d_rootbits, chunks * (kRootChunk / 64))
-    A(d_blk_cnt, chunks)
-    A(d_n_roots, 1)
-    A(d_stats, 8 * V)
-    A(d_keep, V)
+    A(d_stats, (int64_t)kStatsRow * V)
+    A(d_list, V)
+    A(d_slot, V)
+    A(d_list_count, 1)
+    A(d_bits0, w0)
+    A(d_bits1, w1)
+    A(d_words, w0)
     A(d_prefix, c->job_cap)
     A(d_job_single, 1)
     A(d_cams, FVV_MAX_CAMS)
@@ -182,7 +242,20 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_counts_single, 4)
 #undef A
     if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    // scratch the kernels expect cleared (they clear it again after use)
+    if (e == hipSuccess)
         e = hipMemset(c->d_status, 0, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(c->d_list_count, 0, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(c->d_bits0, 0, (size_t)w0 * sizeof(uint64_t));
+    if (e == hipSuccess)
+        e = hipMemset(c->d_bits1, 0, (size_t)w1 * sizeof(uint64_t));
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -225,7 +298,7 @@ fvv_status fvv_carve(fvv_ctx* ctx, int32_t n_cams, const fvv_camera* cams, const
         !tile_ok(tile))
         return FVV_EINVAL;
     const CamSet cs = make_camset(n_cams, cams);
-    return dev(launch_carve(cs, d_sils, *grid, tile_of(tile), d_occ, stream));
+    return dev(launch_carve(cs, d_sils, *grid, tile_of(tile), d_occ, nullptr, stream));
 }
 
 fvv_status fvv_label(fvv_ctx* ctx, const fvv_grid* grid, uint8_t* d_occ, int32_t* d_labels,
@@ -240,7 +313,7 @@ fvv_status fvv_label(fvv_ctx* ctx, const fvv_grid* grid, uint8_t* d_occ, int32_t
     if (grid_samples(*grid) > ctx->lim.max_coarse)
         return FVV_EINVAL;
     return dev(launch_label(ctx, *grid, d_occ, d_labels, t_np, t_nb, d_rois, max_rois, d_n_rois,
-                            stream));
+                            false, nullptr, stream));
 }
 
 fvv_status fvv_roi_grids(const fvv_grid* coarse, int64_t hc_um, int64_t hf_um,
@@ -288,7 +361,7 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
         return FVV_EINVAL;
     if (grid_samples(*roi) > ctx->lim.max_fine || grid_samples(*roi) > 1431655765LL)
         return FVV_EINVAL;
-    const CamSet cs = make_camset(n_cams, cams);
+    const CamSet cs = make_camset(n_cams, cams, roi);
     fvv_job job;
     memset(&job, 0, sizeof(job));
     job.grid = *roi;
@@ -340,7 +413,14 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         for (int i = 0; i < FVV_FRAME_EVENTS; ++i)
             if (!events[i])
                 return FVV_EINVAL;
-    const CamSet cs = make_camset(p->n_cams, p->cams);
+    // every fine sample of the frame lies in the coarse lattice's box (widened
+    // by one cell against the rounding of the fine coordinates)
+    fvv_grid wide = p->coarse;
+    for (int a = 0; a < 3; ++a) {
+        wide.lo[a] -= 1;
+        wide.dims[a] += 2;
+    }
+    const CamSet cs = make_camset(p->n_cams, p->cams, &wide);
     const float h_fine = (float)((double)p->hf_um * 1e-6);
     const TileShape ct = tile_of(&p->coarse_tile), ft = tile_of(&p->fine_tile);
     const int blocks = persistent_blocks(ctx, &p->fine_tile);
@@ -353,17 +433,38 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (d_masks)
         e = launch_pack(p->n_cams, cs.W, cs.H, d_masks, d_sils, stream);
     mark(1);
+    // the coarse carve seeds the labelling with its occupied samples
+    const LabelSeed seed = label_seed(ctx);
     if (e == hipSuccess)
-        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, stream);
+        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, &seed, stream);
     mark(2);
+    // labelling; its selection kernel also lays out the fine jobs of the ROIs
+    FrameJobs fj;
+    fj.cams = cs;
+    fj.coarse = p->coarse;
+    fj.hc_um = p->hc_um;
+    fj.hf_um = p->hf_um;
+    fj.h_fine = h_fine;
+    fj.jobs = o->d_jobs;
+    fj.max_fine = o->max_fine;
+    fj.counts = o->d_counts;
+    fj.tile_x = ft.tx;
+    fj.tile_z = ft.tz;
+    fj.blocks = (uint32_t)blocks;
     if (e == hipSuccess)
-        e = launch_label(ctx, p->coarse, o->d_occ_coarse, o->d_labels, p->t_np, p->t_nb, o->d_rois,
-                         o->max_rois, o->d_counts + 0, stream);
+        e = launch_label(ctx, p->coarse, o->d_occ_coarse, nullptr, p->t_np, p->t_nb, o->d_rois,
+                         o->max_rois, o->d_counts + 0, true, &fj, stream);
     mark(3);
+    // the grid pass writing labels and the filtered coarse occupancy runs on a
+    // side branch, beside the fine stage, which needs only the ROI table
     if (e == hipSuccess)
-        e = launch_frame_jobs(ctx, cs, p->coarse, p->hc_um, p->hf_um, h_fine, o->d_rois,
-                              o->d_counts + 0, o->max_rois, o->d_jobs, o->max_fine, o->d_counts,
-                              ft, blocks, stream);
+        e = hipEventRecord(ctx->ev_fork, stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+    if (e == hipSuccess)
+        e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, ctx->side);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_join, ctx->side);
     if (e == hipSuccess)
         e = launch_carve_batched(ctx, o->d_jobs, 0, ctx->d_cams, d_sils, o->d_occ_fine, ft, blocks,
                                  true, stream);
@@ -372,6 +473,8 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = launch_surface(ctx, o->d_jobs, o->d_counts + 3, o->max_rois, o->d_occ_fine, cs, d_sils,
                            p->n_steps, o->d_keys, o->d_xyz, o->max_points, o->d_point_off,
                            o->d_counts + 2, events ? events[5] : nullptr, stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(stream, ctx->ev_join, 0);
     mark(6);
     return dev(e);
 }

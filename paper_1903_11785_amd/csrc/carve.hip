@@ -1,17 +1,23 @@
 // Silhouette packing and volumetric visual-hull carving (Sec. II-B-1 over the
 // whole volume, Sec. II-B-3 inside ROIs) for gfx950.
 //
-// Carving is one sample per lane: a workgroup of 256 threads owns a tile of
-// TX x TY x TZ samples, TX consecutive x-samples per row so each wave writes
-// contiguous occupancy bytes, and each thread carries TZ samples stacked in z.
-// The two inner fma terms of each projection row (P0*X + P3, then + P1*Y) do
-// not depend on z, so they are computed once per thread and camera; the same
-// fused chain in the same order as a per-sample evaluation, hence bit-equal.
-// Cameras are tested in index order and a wave stops as soon as none of its
-// samples is still inside every camera tested so far.
+// A workgroup of 256 threads carves a tile of TX x TY x TZ lattice samples
+// (TX * TY = 256).  The tile keeps, in LDS, the list of its samples that are
+// still inside every camera tested so far.  Each pass tests the listed samples
+// against the next kCamGroup cameras (independent loads, one memory round trip
+// per pass) and appends the survivors to the other list, so every lane of a
+// pass works on a live sample: samples outside the lattice never enter the
+// list and rejected ones leave it at once.  The tile is done when a pass
+// leaves no survivor or the cameras run out; the survivors are the occupied
+// samples.  The occupancy is the AND over all cameras, so neither the passes
+// nor the order in which samples are listed change a result.  Each test
+// evaluates the full fused projection chain of the sample, bit-equal to the
+// definition.
 #include "fvv_internal.h"
 
 namespace fvv {
+
+constexpr int kCamGroup = 2;
 
 // ------------------------------------------------------------------ packing
 // One lane per 32-pixel word.  Fast path: rows of a multiple of 32 pixels
@@ -60,90 +66,144 @@ hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils
 }
 
 // ------------------------------------------------------------------ carving tile
+constexpr int log2_of(int v) { return v <= 1 ? 0 : 1 + log2_of(v / 2); }
+
+// Append val to an LDS list for the lanes where pred holds (one LDS atomic
+// per wave).
+__device__ __forceinline__ void lds_append(bool pred, uint16_t val, uint16_t* list,
+                                           uint32_t* count) {
+    const uint64_t m = __ballot(pred);
+    if (m == 0)
+        return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader)
+        base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, kWave);
+    if (pred)
+        list[base + lane_rank(m)] = val;
+}
+
 // Carve tile `tile` of lattice g.  getP(c) returns camera c's 12 floats (a
-// wave-uniform address); sil_of(c) its silhouette rows.
-template <int TX, int TZ, typename GetP, typename GetSil>
+// wave-uniform address); sil_of(c) its silhouette rows.  With kSeed, every
+// occupied sample is also handed to the labelling stage (LabelSeed).
+template <int TX, int TZ, bool kSeed, typename GetP, typename GetSil>
 __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, int W, int H,
                                            int wpr, const fvv_grid& g, uint64_t tile,
-                                           uint8_t* __restrict__ out) {
+                                           uint8_t* __restrict__ out, const LabelSeed& seed) {
     constexpr int TY = kBlock / TX;
+    constexpr int TV = TX * TY * TZ;
+    constexpr int LX = log2_of(TX), LY = log2_of(TY);
+    __shared__ uint16_t s_list[2][TV];
+    __shared__ uint32_t s_cnt[3];
+    __shared__ uint32_t s_alive[TV / 32];
+
     const int ntx = (g.dims[0] + TX - 1) / TX;
     const int nty = (g.dims[1] + TY - 1) / TY;
     const int bx = (int)(tile % (uint64_t)ntx);
     const uint64_t r = tile / (uint64_t)ntx;
     const int by = (int)(r % (uint64_t)nty);
     const int bz = (int)(r / (uint64_t)nty);
-    const int i = bx * TX + (int)(threadIdx.x % TX);
-    const int j = by * TY + (int)(threadIdx.x / TX);
-    const int k0 = bz * TZ;
-    const bool in_xy = i < g.dims[0] && j < g.dims[1];
+    const int i0 = bx * TX, j0 = by * TY, k0 = bz * TZ;
 
-    const float X = lattice_coord(g.lo[0] + i, g.h, g.origin[0]);
-    const float Y = lattice_coord(g.lo[1] + j, g.h, g.origin[1]);
-    float Z[TZ];
-    uint32_t alive = 0;
+    __syncthreads();   // the previous tile of this workgroup is done with the LDS
+    if (threadIdx.x < 3)
+        s_cnt[threadIdx.x] = 0;
+    for (int w = threadIdx.x; w < TV / 32; w += kBlock)
+        s_alive[w] = 0;
+    __syncthreads();
 #pragma unroll
-    for (int z = 0; z < TZ; ++z) {
-        Z[z] = lattice_coord(g.lo[2] + k0 + z, g.h, g.origin[2]);
-        if (in_xy && k0 + z < g.dims[2])
-            alive |= 1u << z;
+    for (int rr = 0; rr < TZ; ++rr) {
+        const int s = rr * kBlock + (int)threadIdx.x;
+        const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
+        const bool valid = i0 + lx < g.dims[0] && j0 + ly < g.dims[1] && k0 + lz < g.dims[2];
+        lds_append(valid, (uint16_t)s, s_list[0], &s_cnt[0]);
+    }
+    __syncthreads();
+
+    int cur = 0;
+    for (int c0 = 0; c0 < ncam; c0 += kCamGroup) {
+        const uint32_t n = s_cnt[cur % 3];
+        if (n == 0)
+            break;
+        if (threadIdx.x == 0)
+            s_cnt[(cur + 2) % 3] = 0;   // last read a pass ago, next appended to a pass on
+        const float* __restrict__ P[kCamGroup];
+        const uint32_t* sil[kCamGroup];
+#pragma unroll
+        for (int q = 0; q < kCamGroup; ++q) {
+            const int c = c0 + q < ncam ? c0 + q : c0;   // wave-uniform
+            P[q] = getP(c);
+            sil[q] = sil_of(c);
+        }
+        const uint16_t* src = s_list[cur & 1];
+        uint16_t* dst = s_list[(cur + 1) & 1];
+        uint32_t* dcnt = &s_cnt[(cur + 1) % 3];
+        for (uint32_t base = 0; base < n; base += kBlock) {
+            const uint32_t idx = base + threadIdx.x;
+            const bool act = idx < n;
+            const int s = act ? src[idx] : 0;
+            const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
+            const float X = lattice_coord(g.lo[0] + i0 + lx, g.h, g.origin[0]);
+            const float Y = lattice_coord(g.lo[1] + j0 + ly, g.h, g.origin[1]);
+            const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
+            bool ok = act;
+#pragma unroll
+            for (int q = 0; q < kCamGroup; ++q)
+                if (c0 + q < ncam)
+                    ok &= seen_inside(P[q], X, Y, Z, sil[q], W, H, wpr);
+            lds_append(ok, (uint16_t)s, dst, dcnt);
+        }
+        __syncthreads();
+        ++cur;
     }
 
-    for (int c = 0; c < ncam; ++c) {
-        if (__ballot(alive != 0) == 0)
-            break;
-        const float* __restrict__ P = getP(c);
-        const float p0 = P[0], p1 = P[1], p2 = P[2], p3 = P[3];
-        const float p4 = P[4], p5 = P[5], p6 = P[6], p7 = P[7];
-        const float p8 = P[8], p9 = P[9], p10 = P[10], p11 = P[11];
-        const float ba = __builtin_fmaf(p1, Y, __builtin_fmaf(p0, X, p3));
-        const float bb = __builtin_fmaf(p5, Y, __builtin_fmaf(p4, X, p7));
-        const float bw = __builtin_fmaf(p9, Y, __builtin_fmaf(p8, X, p11));
-        const uint32_t* __restrict__ sil = sil_of(c);
-#pragma unroll
-        for (int z = 0; z < TZ; ++z) {
-            if (alive & (1u << z)) {
-                const float a = __builtin_fmaf(p2, Z[z], ba);
-                const float b = __builtin_fmaf(p6, Z[z], bb);
-                const float w = __builtin_fmaf(p10, Z[z], bw);
-                bool ok = w > 0.0f;
-                const int px = pixel_index(a, w, W);
-                const int py = pixel_index(b, w, H);
-                ok = ok && (px | py) >= 0;
-                const uint32_t word = sil[ok ? py * wpr + (px >> 5) : 0];
-                ok = ok && ((word >> (px & 31)) & 1u);
-                if (!ok)
-                    alive &= ~(1u << z);
+    const uint32_t n_in = s_cnt[cur % 3];
+    const uint16_t* surv = s_list[cur & 1];
+    for (uint32_t base = 0; base < n_in; base += kBlock) {
+        const uint32_t idx = base + threadIdx.x;
+        const bool act = idx < n_in;
+        const int s = act ? surv[idx] : 0;
+        if (act)
+            atomicOr(&s_alive[s >> 5], 1u << (s & 31));
+        if (kSeed) {
+            const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
+            const int32_t lin = (i0 + lx) + g.dims[0] * ((j0 + ly) + g.dims[1] * (k0 + lz));
+            const uint64_t m = __ballot(act);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                uint32_t sbase = 0;
+                if (lane_id() == leader)
+                    sbase = atomicAdd(seed.count, (uint32_t)__popcll(m));
+                sbase = __shfl(sbase, leader, kWave);
+                if (act)
+                    seed_sample(seed, lin, sbase + lane_rank(m));
             }
         }
     }
-
-    if (in_xy) {
-        const uint64_t plane = (uint64_t)g.dims[0] * (uint64_t)g.dims[1];
-        uint8_t* o = out + (uint64_t)j * g.dims[0] + i;
+    __syncthreads();
+    const uint64_t plane = (uint64_t)g.dims[0] * (uint64_t)g.dims[1];
 #pragma unroll
-        for (int z = 0; z < TZ; ++z)
-            if (k0 + z < g.dims[2])
-                o[(uint64_t)(k0 + z) * plane] = (uint8_t)((alive >> z) & 1u);
+    for (int rr = 0; rr < TZ; ++rr) {
+        const int s = rr * kBlock + (int)threadIdx.x;
+        const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
+        const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
+        if (i < g.dims[0] && j < g.dims[1] && k < g.dims[2])
+            out[(uint64_t)k * plane + (uint64_t)j * g.dims[0] + i] =
+                (uint8_t)((s_alive[s >> 5] >> (s & 31)) & 1u);
     }
 }
 
-template <int TX, int TZ>
-__device__ __forceinline__ uint64_t tiles_of(const fvv_grid& g) {
-    constexpr int TY = kBlock / TX;
-    return (uint64_t)((g.dims[0] + TX - 1) / TX) * (uint64_t)((g.dims[1] + TY - 1) / TY) *
-           (uint64_t)((g.dims[2] + TZ - 1) / TZ);
-}
-
 // ------------------------------------------------------------------ one lattice
-template <int TX, int TZ>
+template <int TX, int TZ, bool kSeed>
 __global__ __launch_bounds__(kBlock) void carve_kernel(const CamSet cams,
                                                        const uint32_t* __restrict__ sils,
-                                                       const fvv_grid g, uint8_t* __restrict__ occ) {
+                                                       const fvv_grid g, uint8_t* __restrict__ occ,
+                                                       const LabelSeed seed) {
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-    carve_tile<TX, TZ>([&](int c) { return &cams.P[c][0]; },
-                       [&](int c) { return sils + c * cam_words; }, cams.n, cams.W, cams.H,
-                       cams.wpr, g, blockIdx.x, occ);
+    carve_tile<TX, TZ, kSeed>([&](int c) { return &cams.P[c][0]; },
+                              [&](int c) { return sils + c * cam_words; }, cams.n, cams.W, cams.H,
+                              cams.wpr, g, blockIdx.x, occ, seed);
 }
 
 // ------------------------------------------------------------------ batched, persistent
@@ -162,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* 
     __syncthreads();
     for (uint32_t base = 0; base < n_jobs; base += kBlock) {
         uint32_t j = base + threadIdx.x;
-        uint64_t t = j < n_jobs ? tiles_of<TX, TZ>(jobs[j].grid) : 0;
+        uint64_t t = j < n_jobs ? tiles_of_grid(jobs[j].grid, TX, TZ) : 0;
         uint64_t tot;
         uint64_t ex = block_exclusive_sum64<kBlock>(t, scratch, &tot);
         uint64_t c0 = carry;
@@ -176,9 +236,8 @@ __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* 
     if (threadIdx.x == 0) {
         uint64_t total = carry;
         pre[n_jobs].tile_off = total;
-        uint64_t per = (total + (uint64_t)blocks * 8 - 1) / ((uint64_t)blocks * 8);
         counter[0] = 0;
-        counter[1] = (uint32_t)(per < 1 ? 1 : per);
+        counter[1] = grab_size(total, blocks);
         counter[2] = n_jobs;
     }
 }
@@ -192,6 +251,7 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
     const uint32_t nj = counter[2];
     const uint64_t per = counter[1];
     const uint64_t total = pre[nj].tile_off;
+    const LabelSeed no_seed{};
     for (;;) {
         if (threadIdx.x == 0)
             s_item = atomicAdd(&counter[0], 1u);
@@ -208,10 +268,10 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
             const int64_t cam_words = (int64_t)job.height * wpr;
             const fvv_camera* jc = cams + job.cam_base;
             const uint32_t* js = sils + job.sil_base;
-            carve_tile<TX, TZ>([&](int c) { return &jc[c].P[0]; },
-                               [&](int c) { return js + c * cam_words; }, job.n_cams, job.width,
-                               job.height, wpr, job.grid, t - pre[jb].tile_off,
-                               out + job.out_offset);
+            carve_tile<TX, TZ, false>([&](int c) { return &jc[c].P[0]; },
+                                      [&](int c) { return js + c * cam_words; }, job.n_cams,
+                                      job.width, job.height, wpr, job.grid, t - pre[jb].tile_off,
+                                      out + job.out_offset, no_seed);
         }
     }
 }
@@ -221,22 +281,22 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
     X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(32, 1) X(32, 2) X(32, 4) X(32, 8) X(16, 1)     \
     X(16, 2) X(16, 4) X(16, 8)
 
-static inline uint64_t host_tiles(const fvv_grid& g, TileShape t) {
-    return (uint64_t)((g.dims[0] + t.tx - 1) / t.tx) * (uint64_t)((g.dims[1] + t.ty - 1) / t.ty) *
-           (uint64_t)((g.dims[2] + t.tz - 1) / t.tz);
-}
-
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g, TileShape t,
-                        uint8_t* occ, hipStream_t s) {
-    uint64_t tiles = host_tiles(g, t);
+                        uint8_t* occ, const LabelSeed* seed, hipStream_t s) {
+    const uint64_t tiles = tiles_of_grid(g, t.tx, t.tz);
     if (tiles == 0)
         return hipSuccess;
     if (tiles > 0x7fffffffull)
         return hipErrorInvalidValue;
+    const LabelSeed sd = seed ? *seed : LabelSeed{};
 #define X(TXV, TZV)                                                                           \
     if (t.tx == TXV && t.tz == TZV) {                                                         \
-        hipLaunchKernelGGL((carve_kernel<TXV, TZV>), dim3((unsigned)tiles), dim3(kBlock), 0, s, \
-                           cams, sils, g, occ);                                               \
+        if (seed)                                                                             \
+            hipLaunchKernelGGL((carve_kernel<TXV, TZV, true>), dim3((unsigned)tiles),         \
+                               dim3(kBlock), 0, s, cams, sils, g, occ, sd);                   \
+        else                                                                                  \
+            hipLaunchKernelGGL((carve_kernel<TXV, TZV, false>), dim3((unsigned)tiles),        \
+                               dim3(kBlock), 0, s, cams, sils, g, occ, sd);                   \
         return hipGetLastError();                                                             \
     }
     FVV_TILE_CASES(X)

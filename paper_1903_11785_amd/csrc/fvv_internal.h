@@ -17,8 +17,12 @@ constexpr int kRootChunk = 16384;        // coarse samples per root-numbering bl
 constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits
 
 // Projections of a camera rig passed by value in the kernel arguments.
+// pad[c] bounds, for every point of the lattice box the call works in, how far
+// the quotients the occupancy test floors can be from the real projection
+// (plus the error of an rcp-based quotient); +inf where no bound holds.
 struct CamSet {
     float P[FVV_MAX_CAMS][12];
+    float pad[FVV_MAX_CAMS];
     int32_t n, W, H, wpr;
 };
 
@@ -28,22 +32,46 @@ struct TileShape {
 };
 
 // ------------------------------------------------------------------ pixel test
-// Index of the pixel holding the image coordinate a/w along an axis of `dim`
-// pixels, or -1 when outside [0, dim).  Requires w > 0 and finite a, w.
-// q = a * rcp(w) is within a few ulp of the real quotient, so floor(q) is the
-// exact floor or off by one; the sign of the residual a - n*w, which a single
-// fma rounds without changing, decides which.  The result is the floor of the
-// real quotient whatever the rounding of q.  The IEEE division serves the
-// (never seen) w below 2^-64, where rcp could overflow.
-__device__ __forceinline__ int pixel_index(float a, float w, int dim) {
-    float q = (w >= 0x1p-64f) ? a * __builtin_amdgcn_rcpf(w) : a / w;
+// Floor of the real quotient a/w (w > 0) from an approximation q of it that is
+// within 1 of it.  floor(q) is then the exact floor or off by one, and the
+// signs of the residuals a - n*w and a - (n+1)*w, which a single fma rounds
+// without changing, decide which.  Branch-free.
+__device__ __forceinline__ int exact_floor(float a, float w, float q) {
     int n = (int)__builtin_floorf(q);
-    float nf = (float)n;
-    if (__builtin_fmaf(-nf, w, a) < 0.0f)
-        n -= 1;
-    else if (__builtin_fmaf(-(nf + 1.0f), w, a) >= 0.0f)
-        n += 1;
-    return ((unsigned)n < (unsigned)dim) ? n : -1;
+    const float nf = (float)n;
+    const float r0 = __builtin_fmaf(-nf, w, a);
+    const float r1 = __builtin_fmaf(-(nf + 1.0f), w, a);
+    n -= (r0 < 0.0f) ? 1 : 0;
+    n += (r1 >= 0.0f) ? 1 : 0;
+    return n;
+}
+
+// Occupancy test of one projected sample (a, b, w) in one camera: w > 0 and
+// pixel (floor(a/w), floor(b/w)) inside the W x H image and foreground in
+// `sil` (this camera's [H][wpr] rows).  The quotients come from rcp(w),
+// clamped to [-4, dim + 4] so the floor stays exact inside the image and the
+// classification right outside it; a positive w below 2^-64 (where rcp would
+// overflow; never met in practice) takes the IEEE division instead, behind a
+// wave-uniform branch.
+__device__ __forceinline__ bool sil_test(float a, float b, float w,
+                                         const uint32_t* __restrict__ sil, int W, int H,
+                                         int wpr) {
+    const float r = __builtin_amdgcn_rcpf(w);
+    float qa = a * r, qb = b * r;
+    const bool tiny = w > 0.0f && w < 0x1p-64f;
+    if (__builtin_expect(__ballot(tiny) != 0, 0)) {
+        if (tiny) {
+            qa = a / w;
+            qb = b / w;
+        }
+    }
+    qa = __builtin_amdgcn_fmed3f(qa, -4.0f, (float)W + 4.0f);
+    qb = __builtin_amdgcn_fmed3f(qb, -4.0f, (float)H + 4.0f);
+    const int px = exact_floor(a, w, qa);
+    const int py = exact_floor(b, w, qb);
+    const bool ok = (w > 0.0f) & ((unsigned)px < (unsigned)W) & ((unsigned)py < (unsigned)H);
+    const uint32_t word = sil[ok ? py * wpr + (px >> 5) : 0];
+    return ok & (((word >> (px & 31)) & 1u) != 0u);
 }
 
 // World coordinate of global lattice index g on one axis.
@@ -51,22 +79,15 @@ __device__ __forceinline__ float lattice_coord(int g, float h, float o) {
     return __builtin_fmaf((float)g, h, o);
 }
 
-// Test of one sample against camera P (12 floats): 1 if it projects into a
-// foreground pixel of `sil` (this camera's [H][wpr] rows), else 0.
+// Test of one world point against camera P (12 floats).
 __device__ __forceinline__ bool seen_inside(const float* __restrict__ P, float X, float Y, float Z,
                                             const uint32_t* __restrict__ sil, int W, int H,
                                             int wpr) {
-    float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
-    float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
-    float w = __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
-    if (!(w > 0.0f))
-        return false;
-    int px = pixel_index(a, w, W);
-    int py = pixel_index(b, w, H);
-    if ((px | py) < 0)
-        return false;
-    uint32_t word = sil[py * wpr + (px >> 5)];
-    return (word >> (px & 31)) & 1u;
+    const float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
+    const float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
+    const float w =
+        __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
+    return sil_test(a, b, w, sil, W, H, wpr);
 }
 
 // ------------------------------------------------------------------ wave/block helpers
@@ -163,6 +184,43 @@ __host__ __device__ inline uint64_t tiles_of_grid(const fvv_grid& g, int tx, int
            (uint64_t)((g.dims[2] + tz - 1) / tz);
 }
 
+// Rank of this lane among the set lanes of `mask` below it.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Work items a persistent workgroup grabs at a time: about 8 grabs per
+// workgroup over the whole launch.
+__host__ __device__ inline uint32_t grab_size(uint64_t total_tiles, uint32_t blocks) {
+    const uint64_t per = (total_tiles + (uint64_t)blocks * 8 - 1) / ((uint64_t)blocks * 8);
+    return (uint32_t)(per < 1 ? 1 : (per > 0xffffffffull ? 0xffffffffull : per));
+}
+
+// ------------------------------------------------------------------ labelling seeds
+// Where the labelling stage starts: the list of occupied samples, and per
+// sample a union-find parent and a stats row (count, lo[3], hi[3], label).
+// The coarse carve of a frame fills these as it writes the occupancy.
+struct LabelSeed {
+    int32_t* parent;
+    int32_t* stats;
+    int32_t* list;
+    int32_t* slot;       // position of each occupied sample in the list
+    uint32_t* count;
+};
+
+constexpr int kStatsRow = 8;
+
+// Append occupied sample lin at list position pos.
+__device__ __forceinline__ void seed_sample(const LabelSeed& s, int32_t lin, uint32_t pos) {
+    s.list[pos] = lin;
+    s.slot[lin] = (int32_t)pos;
+    s.parent[lin] = lin;
+    int4* row = reinterpret_cast<int4*>(s.stats + (int64_t)kStatsRow * lin);
+    row[0] = make_int4(0, 0x7fffffff, 0x7fffffff, 0x7fffffff);
+    row[1] = make_int4(-1, -1, -1, 0);
+}
+
 // ------------------------------------------------------------------ device-side job prefix data
 // Per job of a batched carve / surface: first carving tile and first
 // crossing-edge work item (exclusive prefix sums over the job table).
@@ -194,16 +252,16 @@ struct fvv_ctx {
     int device;
     // status and counters
     uint32_t* d_status;          // sticky flags
-    uint32_t* d_counter;         // persistent-kernel work counter [0] and grab size [1]
+    uint32_t* d_counter;         // persistent carve: [0] next item, [1] grab size, [2] jobs
     // labelling
-    int32_t* d_parent;           // union-find forest over coarse samples
-    int32_t* d_rid;              // root number of each root sample
-    uint64_t* d_rootbits;        // root flags, one bit per sample
-    uint32_t* d_blk_cnt;         // roots per numbering block
-    uint32_t* d_n_roots;         // number of components
-    int32_t* d_stats;            // per root: count, lo[3], hi[3], root index
-    int32_t* d_keep;             // per root: final label or 0
-    int64_t root_cap;
+    int32_t* d_parent;           // union-find forest over the occupied coarse samples
+    int32_t* d_stats;            // per sample (used at roots): count, lo[3], hi[3], label
+    int32_t* d_list;             // occupied coarse samples
+    int32_t* d_slot;             // list position of each occupied coarse sample
+    uint32_t* d_list_count;      // their number (reset by the selection kernel)
+    uint64_t* d_bits0;           // root flags, one bit per coarse sample
+    uint64_t* d_bits1;           // one bit per non-zero word of d_bits0
+    uint32_t* d_words;           // non-zero d_bits0 words in ascending order
     // batched carve / frame
     fvv::JobPrefix* d_prefix;    // per job (max(max_jobs, max_rois) + 1)
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
@@ -215,25 +273,42 @@ struct fvv_ctx {
     int64_t item_cap;
     int64_t job_cap;
     int n_cus;
+    // side branch of a frame (work off the critical path), default priority
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
 };
 
 namespace fvv {
 
+// What the selection kernel of a frame also builds once the ROIs are known:
+// the fine lattice job of every carried ROI (Sec. II-B-3) and the prefixes of
+// the batched carve and the surface passes.
+struct FrameJobs {
+    CamSet cams;
+    fvv_grid coarse;
+    int64_t hc_um, hf_um;
+    float h_fine;
+    fvv_job* jobs;
+    int64_t max_fine;
+    uint32_t* counts;
+    int tile_x, tile_z;
+    uint32_t blocks;
+};
+
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils, hipStream_t s);
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g,
-                        TileShape t, uint8_t* occ, hipStream_t s);
+                        TileShape t, uint8_t* occ, const LabelSeed* seed, hipStream_t s);
 hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jobs,
                                 const fvv_camera* cams, const uint32_t* sils, uint8_t* out,
                                 TileShape t, int blocks, bool jobs_prepared, hipStream_t s);
+LabelSeed label_seed(fvv_ctx* ctx);
+// labels == nullptr: stop before the grid pass (launch_label_write does it).
 hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                         uint32_t t_np, uint32_t t_nb, fvv_roi* rois, uint32_t max_rois,
-                        uint32_t* n_rois, hipStream_t s);
-hipError_t launch_frame_jobs(fvv_ctx* ctx, const CamSet& cams, const fvv_grid& coarse,
-                             int64_t hc_um, int64_t hf_um, float h_fine, const fvv_roi* rois,
-                             const uint32_t* n_rois, uint32_t max_rois, fvv_job* jobs,
-                             int64_t max_fine, uint32_t* counts, TileShape fine_tile, int blocks,
-                             hipStream_t s);
+                        uint32_t* n_rois, bool seeded, const FrameJobs* frame, hipStream_t s);
+hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
+                              hipStream_t s);
 hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                           uint32_t max_jobs, const uint8_t* occ_fine, const CamSet& cams,
                           const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,

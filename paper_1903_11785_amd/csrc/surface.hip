@@ -1,151 +1,15 @@
-// ROI -> fine lattices (Sec. II-B-3), crossing-edge compaction and exit-point
-// bisection (Sec. II-C) for gfx950.
+// Crossing-edge compaction and exit-point bisection (Sec. II-C) for gfx950.
 //
 // Crossing edges: work items are chunks of kEdgeChunk consecutive samples of
-// one ROI.  A first pass counts each item's edges, one workgroup scans the
-// counts, and a second pass writes keys 3*lin+axis in ascending order: within
-// an item a workgroup walks its samples in 8 passes of 256, and a block scan
-// of the per-lane counts (0..3 axes each) places every key.  Exit points: one
-// edge per lane, n_steps bisection steps, each testing all cameras with the
-// same occupancy test as carving.
+// one ROI, eight consecutive samples per thread.  A first pass counts each
+// item's edges, one workgroup scans the counts, and a second pass writes keys
+// 3*lin+axis in ascending order (a thread's keys are in order, and a block
+// scan orders the threads).  Exit points: one edge per lane; a first pass
+// finds the cameras that can reject some point of the edge at all, and the
+// n_steps bisection steps test only those at each bracket midpoint.
 #include "fvv_internal.h"
 
 namespace fvv {
-
-// ------------------------------------------------------------------ fine jobs of a frame
-// One workgroup: map each kept ROI to its fine lattice (integer micrometres,
-// one-coarse-cell dilation, clamped to the coarse lattice's extent), lay the
-// carried ROIs out back to back in the fine occupancy buffer, and build the
-// tile and work-item prefixes of the batched carve and the surface passes.
-__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
-    int64_t q = a / b;
-    if ((a % b != 0) && ((a < 0) != (b < 0)))
-        q -= 1;
-    return q;
-}
-
-__device__ __forceinline__ int64_t ceil_div64(int64_t a, int64_t b) { return -floor_div64(-a, b); }
-
-constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
-
-__global__ __launch_bounds__(kBlock) void frame_jobs_kernel(
-    const CamSet cams, const fvv_grid coarse, int64_t hc_um, int64_t hf_um, float h_fine,
-    const fvv_roi* __restrict__ rois, const uint32_t* __restrict__ n_rois, uint32_t max_rois,
-    fvv_job* __restrict__ jobs, int64_t max_fine, uint32_t* __restrict__ counts, int tile_x,
-    int tile_z, JobPrefix* __restrict__ pre, uint32_t* __restrict__ counter, uint32_t blocks,
-    fvv_camera* __restrict__ dcams, uint32_t* __restrict__ status) {
-    __shared__ uint64_t scratch[kBlock / kWave];
-    __shared__ uint64_t c_vox, c_tiles, c_items;
-    __shared__ uint32_t carried;
-    for (int c = threadIdx.x; c < cams.n; c += kBlock) {
-        fvv_camera cam;
-        for (int e = 0; e < 12; ++e)
-            cam.P[e] = cams.P[c][e];
-        cam.width = cams.W;
-        cam.height = cams.H;
-        dcams[c] = cam;
-    }
-    const uint32_t K_all = *n_rois;
-    const uint32_t K = K_all < max_rois ? K_all : max_rois;
-    if (threadIdx.x == 0) {
-        c_vox = c_tiles = c_items = 0;
-        carried = K;
-    }
-    __syncthreads();
-    for (uint32_t base = 0; base < K; base += kBlock) {
-        const uint32_t t = base + threadIdx.x;
-        fvv_grid fg;
-        int64_t V = 0;
-        if (t < K) {
-            const fvv_roi r = rois[t];
-            V = 1;
-            for (int a = 0; a < 3; ++a) {
-                const int64_t A = (int64_t)coarse.lo[a] + r.lo[a] - 1;
-                const int64_t B = (int64_t)coarse.lo[a] + r.hi[a] + 1;
-                int64_t f0 = floor_div64(A * hc_um, hf_um);
-                int64_t f1 = ceil_div64(B * hc_um, hf_um);
-                const int64_t fmin = ceil_div64((int64_t)coarse.lo[a] * hc_um, hf_um);
-                const int64_t fmax =
-                    floor_div64(((int64_t)coarse.lo[a] + coarse.dims[a] - 1) * hc_um, hf_um);
-                f0 = f0 < fmin ? fmin : f0;
-                f1 = f1 > fmax ? fmax : f1;
-                fg.origin[a] = coarse.origin[a];
-                fg.lo[a] = (int32_t)f0;
-                fg.dims[a] = (int32_t)(f1 - f0 + 1);
-                V *= (f1 - f0 + 1);
-            }
-            fg.h = h_fine;
-        }
-        uint64_t tot_v;
-        const uint64_t ex_v = block_exclusive_sum64<kBlock>((uint64_t)V, scratch, &tot_v);
-        const uint64_t off = c_vox + ex_v;
-        const bool fits = t < K && off + (uint64_t)V <= (uint64_t)max_fine && V <= kMaxKeyedSamples &&
-                          t < carried;
-        const uint64_t tiles = fits ? tiles_of_grid(fg, tile_x, tile_z) : 0;
-        const uint64_t items = fits ? ((uint64_t)V + kEdgeChunk - 1) / kEdgeChunk : 0;
-        uint64_t tot_t, tot_i;
-        const uint64_t ex_t = block_exclusive_sum64<kBlock>(tiles, scratch, &tot_t);
-        const uint64_t ex_i = block_exclusive_sum64<kBlock>(items, scratch, &tot_i);
-        if (fits) {
-            fvv_job j;
-            j.grid = fg;
-            j.cam_base = 0;
-            j.n_cams = cams.n;
-            j.width = cams.W;
-            j.height = cams.H;
-            j.sil_base = 0;
-            j.out_offset = (int64_t)off;
-            jobs[t] = j;
-            pre[t].tile_off = c_tiles + ex_t;
-            pre[t].item_off = (uint32_t)(c_items + ex_i);
-        }
-        // the carried ROIs are the prefix that fits: the first misfit ends it
-        if (t < K && !fits)
-            atomicMin(&carried, t);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            c_vox += tot_v;
-            c_tiles += tot_t;
-            c_items += tot_i;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const uint32_t n = carried;
-        // totals over the carried prefix only
-        uint64_t vox = 0, tiles = 0, items = 0;
-        if (n > 0) {
-            const fvv_job& last = jobs[n - 1];
-            const uint64_t Vl = (uint64_t)last.grid.dims[0] * last.grid.dims[1] * last.grid.dims[2];
-            vox = (uint64_t)last.out_offset + Vl;
-            tiles = pre[n - 1].tile_off + tiles_of_grid(last.grid, tile_x, tile_z);
-            items = pre[n - 1].item_off + (Vl + kEdgeChunk - 1) / kEdgeChunk;
-        }
-        pre[n].tile_off = tiles;
-        pre[n].item_off = (uint32_t)items;
-        counts[0] = K_all;
-        counts[1] = (uint32_t)(vox > 0xffffffffull ? 0xffffffffull : vox);
-        counts[3] = n;
-        const uint64_t per = (tiles + (uint64_t)blocks * 8 - 1) / ((uint64_t)blocks * 8);
-        counter[0] = 0;
-        counter[1] = (uint32_t)(per < 1 ? 1 : per);
-        counter[2] = n;
-        if (n < K_all)
-            atomicOr(status, kFlagCapacity);
-    }
-}
-
-hipError_t launch_frame_jobs(fvv_ctx* ctx, const CamSet& cams, const fvv_grid& coarse,
-                             int64_t hc_um, int64_t hf_um, float h_fine, const fvv_roi* rois,
-                             const uint32_t* n_rois, uint32_t max_rois, fvv_job* jobs,
-                             int64_t max_fine, uint32_t* counts, TileShape fine_tile, int blocks,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(frame_jobs_kernel, dim3(1), dim3(kBlock), 0, s, cams, coarse, hc_um, hf_um,
-                       h_fine, rois, n_rois, max_rois, jobs, max_fine, counts, fine_tile.tx,
-                       fine_tile.tz, ctx->d_prefix, ctx->d_counter, (uint32_t)blocks, ctx->d_cams,
-                       ctx->d_status);
-    return hipGetLastError();
-}
 
 // The single job of fvv_surface, from the kernel arguments.
 __global__ void surface_single_kernel(const fvv_job job, fvv_job* __restrict__ dst,
@@ -166,23 +30,7 @@ hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, hipSt
 }
 
 // ------------------------------------------------------------------ crossing edges
-// Bits 0..2: the edges along x, y, z from sample lin of a dims lattice.
-__device__ __forceinline__ uint32_t crossing_bits(const uint8_t* __restrict__ occ, uint32_t lin,
-                                                  int dx, int dy, int dz) {
-    const uint32_t i = lin % (uint32_t)dx;
-    const uint32_t r = lin / (uint32_t)dx;
-    const uint32_t j = r % (uint32_t)dy;
-    const uint32_t k = r / (uint32_t)dy;
-    const bool o = occ[lin] != 0;
-    uint32_t bits = 0;
-    if (i + 1 < (uint32_t)dx && (occ[lin + 1] != 0) != o)
-        bits |= 1u;
-    if (j + 1 < (uint32_t)dy && (occ[lin + dx] != 0) != o)
-        bits |= 2u;
-    if (k + 1 < (uint32_t)dz && (occ[lin + (uint32_t)dx * dy] != 0) != o)
-        bits |= 4u;
-    return bits;
-}
+constexpr int kEdgeRun = kEdgeChunk / kBlock;   // consecutive samples per thread
 
 struct ItemRef {
     int job;
@@ -193,6 +41,49 @@ __device__ __forceinline__ ItemRef locate_item(const JobPrefix* __restrict__ pre
                                                uint32_t item) {
     const int jb = upper_job([&](int m) { return (uint64_t)pre[m].item_off; }, nj, item);
     return {jb, (item - pre[jb].item_off) * (uint32_t)kEdgeChunk};
+}
+
+// Crossing bits (x, y, z in bits 3s, 3s+1, 3s+2) of this thread's kEdgeRun
+// consecutive samples starting at lin; samples at or past V give 0.
+__device__ __forceinline__ uint32_t run_bits(const uint8_t* __restrict__ occ, uint32_t lin,
+                                             uint32_t V, int dx, int dy, int dz) {
+    if (lin >= V)
+        return 0;
+    const uint32_t sx = (uint32_t)dx, sxy = (uint32_t)dx * (uint32_t)dy;
+    uint32_t i = lin % sx;
+    const uint32_t r = lin / sx;
+    uint32_t j = r % (uint32_t)dy;
+    uint32_t k = r / (uint32_t)dy;
+    uint8_t o[kEdgeRun + 1], oy[kEdgeRun], oz[kEdgeRun];
+#pragma unroll
+    for (int s = 0; s <= kEdgeRun; ++s)
+        o[s] = lin + s < V ? occ[lin + s] : 0;
+#pragma unroll
+    for (int s = 0; s < kEdgeRun; ++s) {
+        oy[s] = lin + s + sx < V ? occ[lin + s + sx] : 0;
+        oz[s] = lin + s + sxy < V ? occ[lin + s + sxy] : 0;
+    }
+    uint32_t bits = 0;
+#pragma unroll
+    for (int s = 0; s < kEdgeRun; ++s) {
+        if (lin + s < V) {
+            const bool c = o[s] != 0;
+            if (i + 1 < sx && (o[s + 1] != 0) != c)
+                bits |= 1u << (3 * s);
+            if (j + 1 < (uint32_t)dy && (oy[s] != 0) != c)
+                bits |= 2u << (3 * s);
+            if (k + 1 < (uint32_t)dz && (oz[s] != 0) != c)
+                bits |= 4u << (3 * s);
+        }
+        if (++i == sx) {
+            i = 0;
+            if (++j == (uint32_t)dy) {
+                j = 0;
+                ++k;
+            }
+        }
+    }
+    return bits;
 }
 
 __global__ __launch_bounds__(kBlock) void edge_count_kernel(const fvv_job* __restrict__ jobs,
@@ -207,16 +98,10 @@ __global__ __launch_bounds__(kBlock) void edge_count_kernel(const fvv_job* __res
         const ItemRef ref = locate_item(pre, nj, item);
         const fvv_job job = jobs[ref.job];
         const uint32_t V = (uint32_t)job.grid.dims[0] * job.grid.dims[1] * job.grid.dims[2];
-        const uint8_t* occ = occ_base + job.out_offset;
-        uint32_t cnt = 0;
-        for (int it = 0; it < kEdgeChunk / kBlock; ++it) {
-            const uint32_t lin = ref.lin0 + it * kBlock + threadIdx.x;
-            if (lin < V)
-                cnt += __popc(crossing_bits(occ, lin, job.grid.dims[0], job.grid.dims[1],
-                                            job.grid.dims[2]));
-        }
+        const uint32_t bits = run_bits(occ_base + job.out_offset, ref.lin0 + threadIdx.x * kEdgeRun,
+                                       V, job.grid.dims[0], job.grid.dims[1], job.grid.dims[2]);
         uint32_t total;
-        block_exclusive_sum<kBlock>(cnt, scratch, &total);
+        block_exclusive_sum<kBlock>((uint32_t)__popc(bits), scratch, &total);
         if (threadIdx.x == 0)
             item_cnt[item] = total;
     }
@@ -271,29 +156,77 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
         const ItemRef ref = locate_item(pre, nj, item);
         const fvv_job job = jobs[ref.job];
         const uint32_t V = (uint32_t)job.grid.dims[0] * job.grid.dims[1] * job.grid.dims[2];
-        const uint8_t* occ = occ_base + job.out_offset;
-        uint32_t running = item_base[item];
-        for (int it = 0; it < kEdgeChunk / kBlock; ++it) {
-            const uint32_t lin = ref.lin0 + it * kBlock + threadIdx.x;
-            const uint32_t bits = lin < V ? crossing_bits(occ, lin, job.grid.dims[0],
-                                                          job.grid.dims[1], job.grid.dims[2])
-                                          : 0u;
-            uint32_t total;
-            uint32_t pos = running + block_exclusive_sum<kBlock>(__popc(bits), scratch, &total);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (bits & (1u << a)) {
-                    if (pos < max_points)
-                        keys[pos] = 3u * lin + (uint32_t)a;
-                    ++pos;
-                }
-            }
-            running += total;
+        const uint32_t lin = ref.lin0 + threadIdx.x * kEdgeRun;
+        uint32_t bits = run_bits(occ_base + job.out_offset, lin, V, job.grid.dims[0],
+                                 job.grid.dims[1], job.grid.dims[2]);
+        uint32_t total;
+        uint32_t pos = item_base[item] + block_exclusive_sum<kBlock>((uint32_t)__popc(bits),
+                                                                     scratch, &total);
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (pos < max_points)
+                keys[pos] = 3u * (lin + (uint32_t)(b / 3)) + (uint32_t)(b % 3);
+            ++pos;
         }
     }
 }
 
 // ------------------------------------------------------------------ exit points
+// Cameras that can reject some point of a crossing edge.  Camera c cannot when
+// the pixel rectangle of the edge's projection, widened by cams.pad[c], is
+// inside the image and entirely foreground: the projection of a segment is a
+// segment between the projections of its ends, and pad[c] bounds the distance
+// between the real quotient of any point of the lattice's box and the
+// rounded quotient the occupancy test floors (the ends' quotients here come
+// from rcp, whose error pad[c] also covers).  Such a camera accepts every
+// point of the edge, so leaving it out of the bisection changes no decision.
+__device__ __forceinline__ uint32_t cameras_that_matter(const CamSet& cams,
+                                                        const uint32_t* __restrict__ sils,
+                                                        int64_t cam_words, const float* X0,
+                                                        const float* X1) {
+    uint32_t mask = 0;
+    for (int c = 0; c < cams.n; ++c) {
+        const float* P = &cams.P[c][0];
+        const float pad = cams.pad[c];
+        float x[2], y[2];
+        bool front = true;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float* X = e ? X1 : X0;
+            const float a = __builtin_fmaf(P[2], X[2], __builtin_fmaf(P[1], X[1], __builtin_fmaf(P[0], X[0], P[3])));
+            const float b = __builtin_fmaf(P[6], X[2], __builtin_fmaf(P[5], X[1], __builtin_fmaf(P[4], X[0], P[7])));
+            const float w = __builtin_fmaf(P[10], X[2], __builtin_fmaf(P[9], X[1], __builtin_fmaf(P[8], X[0], P[11])));
+            const float r = __builtin_amdgcn_rcpf(w);
+            front = front && w > 0.0f;
+            x[e] = a * r;
+            y[e] = b * r;
+        }
+        const float fx0 = __builtin_floorf(fminf(x[0], x[1]) - pad);
+        const float fx1 = __builtin_floorf(fmaxf(x[0], x[1]) + pad);
+        const float fy0 = __builtin_floorf(fminf(y[0], y[1]) - pad);
+        const float fy1 = __builtin_floorf(fmaxf(y[0], y[1]) + pad);
+        bool safe = front && fx0 >= 0.0f && fy0 >= 0.0f && fx1 < (float)cams.W &&
+                    fy1 < (float)cams.H && fx1 - fx0 <= 31.0f && fy1 - fy0 <= 3.0f;
+        if (safe) {
+            const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+            const int w0 = x0 >> 5, w1 = x1 >> 5;
+            const uint32_t m0 = w0 == w1 ? (2u << (x1 & 31)) - (1u << (x0 & 31))
+                                         : 0u - (1u << (x0 & 31));
+            const uint32_t m1 = (2u << (x1 & 31)) - 1u;
+            const uint32_t* sil = sils + c * cam_words;
+            for (int yy = y0; yy <= y1; ++yy) {
+                const uint32_t* row = sil + yy * cams.wpr;
+                safe = safe && (row[w0] & m0) == m0;
+                if (w1 != w0)
+                    safe = safe && (row[w1] & m1) == m1;
+            }
+        }
+        mask |= (safe ? 0u : 1u) << c;
+    }
+    return mask;
+}
+
 __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ n_jobs_p,
                                                         const uint32_t* __restrict__ point_off,
@@ -310,8 +243,8 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < E; e += gridDim.x * kBlock) {
         const int jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, e);
-        const fvv_job& job = jobs[jb];
-        const fvv_grid g = job.grid;
+        const fvv_grid g = jobs[jb].grid;
+        const int64_t out_offset = jobs[jb].out_offset;
         const uint32_t key = keys[e];
         const uint32_t lin = key / 3u;
         const int axis = (int)(key - 3u * lin);
@@ -320,12 +253,16 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
         const uint32_t j = r % (uint32_t)g.dims[1];
         const uint32_t k = r / (uint32_t)g.dims[1];
         const int gidx[3] = {g.lo[0] + (int)i, g.lo[1] + (int)j, g.lo[2] + (int)k};
-        const bool p_on = occ_base[job.out_offset + lin] != 0;
+        const bool p_on = occ_base[out_offset + lin] != 0;
         const int g_on = gidx[axis] + (p_on ? 0 : 1);
         const float d = p_on ? 1.0f : -1.0f;
         float c[3] = {lattice_coord(gidx[0], g.h, g.origin[0]),
                       lattice_coord(gidx[1], g.h, g.origin[1]),
                       lattice_coord(gidx[2], g.h, g.origin[2])};
+        float X0[3] = {c[0], c[1], c[2]}, X1[3] = {c[0], c[1], c[2]};
+        X0[axis] = lattice_coord(gidx[axis], g.h, g.origin[axis]);
+        X1[axis] = lattice_coord(gidx[axis] + 1, g.h, g.origin[axis]);
+        const uint32_t active = cameras_that_matter(cams, sils, cam_words, X0, X1);
         float lo = 0.0f, hi = 1.0f;
         for (int s = 0; s < n_steps; ++s) {
             const float m = 0.5f * (lo + hi);
@@ -335,9 +272,11 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
             const float Y = axis == 1 ? ax : c[1];
             const float Z = axis == 2 ? ax : c[2];
             bool in = true;
-            for (int cam = 0; cam < cams.n && in; ++cam)
+            for (uint32_t rest = active; rest && in; rest &= rest - 1) {
+                const int cam = __ffs(rest) - 1;
                 in = seen_inside(&cams.P[cam][0], X, Y, Z, sils + cam * cam_words, cams.W, cams.H,
                                  cams.wpr);
+            }
             if (in)
                 lo = m;
             else

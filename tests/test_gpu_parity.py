@@ -368,6 +368,21 @@ def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
     compare_frame(fvv, sc, bufs, res)
 
 
+def test_frame_dense_coarse_hull(fvv, ctx, scene_cache):
+    """All-foreground silhouettes: every coarse sample is occupied, far more
+    than one workgroup's LDS forest holds, so the frame labels in global memory."""
+    import copy
+    sc = copy.copy(scene_cache(1, 0))
+    sc.masks = np.ones_like(sc.masks)
+    sc.masks[0, :, 150:154] = 0                # a thin empty band: two halves, crossing edges
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    assert res.occ_coarse.sum() > 10000
+    _, bufs, _ = run_frame(fvv, ctx, sc)
+    assert ctx.check() == fvv.FVV_OK
+    compare_frame(fvv, sc, bufs, res)
+
+
 def test_frame_graph_replays(fvv, ctx, scene_cache):
     import torch
     sc = scene_cache(2, 0)
