@@ -79,7 +79,7 @@ __device__ __forceinline__ void lds_append(bool pred, uint16_t val, uint16_t* li
     uint32_t base = 0;
     if (lane_id() == leader)
         base = atomicAdd(count, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, kWave);
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
     if (pred)
         list[base + lane_rank(m)] = val;
 }
@@ -128,7 +128,7 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
             break;
         if (threadIdx.x == 0)
             s_cnt[(cur + 2) % 3] = 0;   // last read a pass ago, next appended to a pass on
-        const float* __restrict__ P[kCamGroup];
+        const float* P[kCamGroup];
         const uint32_t* sil[kCamGroup];
 #pragma unroll
         for (int q = 0; q < kCamGroup; ++q) {
@@ -139,20 +139,22 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
         const uint16_t* src = s_list[cur & 1];
         uint16_t* dst = s_list[(cur + 1) & 1];
         uint32_t* dcnt = &s_cnt[(cur + 1) % 3];
-        for (uint32_t base = 0; base < n; base += kBlock) {
-            const uint32_t idx = base + threadIdx.x;
+        // each wave takes 64 consecutive entries per round and stops as soon
+        // as its next slice starts past the end of the list
+        const uint32_t wave0 = (threadIdx.x / kWave) * kWave;
+        for (uint32_t base = wave0; base < n; base += kBlock) {
+            const uint32_t idx = base + lane_id();
             const bool act = idx < n;
             const int s = act ? src[idx] : 0;
             const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
             const float X = lattice_coord(g.lo[0] + i0 + lx, g.h, g.origin[0]);
             const float Y = lattice_coord(g.lo[1] + j0 + ly, g.h, g.origin[1]);
             const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
-            bool ok = act;
-#pragma unroll
-            for (int q = 0; q < kCamGroup; ++q)
-                if (c0 + q < ncam)
-                    ok &= seen_inside(P[q], X, Y, Z, sil[q], W, H, wpr);
-            lds_append(ok, (uint16_t)s, dst, dcnt);
+            // all tests of the group are issued unconditionally (a camera past
+            // the last one repeats camera c0 and cannot change the result), so
+            // their silhouette loads are in flight together
+            const bool in = group_inside<kCamGroup>(P, X, Y, Z, sil, W, H, wpr);
+            lds_append(act && in, (uint16_t)s, dst, dcnt);
         }
         __syncthreads();
         ++cur;
@@ -175,7 +177,7 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
                 uint32_t sbase = 0;
                 if (lane_id() == leader)
                     sbase = atomicAdd(seed.count, (uint32_t)__popcll(m));
-                sbase = __shfl(sbase, leader, kWave);
+                sbase = (uint32_t)__builtin_amdgcn_readlane((int)sbase, leader);
                 if (act)
                     seed_sample(seed, lin, sbase + lane_rank(m));
             }

@@ -148,6 +148,13 @@ __device__ __forceinline__ void accumulate_stats(int32_t* __restrict__ stats, bo
     }
 }
 
+// Load of a value other waves produced with device atomics, from L2 (not a
+// possibly stale L1 line).
+template <typename T>
+__device__ __forceinline__ T coherent_load(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void flag_root(uint64_t* __restrict__ bits0, uint64_t* __restrict__ bits1,
                                           uint32_t v) {
     atomicOr((unsigned long long*)&bits0[v >> 6], 1ull << (v & 63));
@@ -306,7 +313,7 @@ __device__ __forceinline__ void select_roots(const SelectArgs& a, const FrameJob
         const uint32_t i = base + threadIdx.x;
         uint64_t w1 = 0;
         if (i < n1) {
-            w1 = a.bits1[i];
+            w1 = coherent_load(&a.bits1[i]);
             if (w1)
                 a.bits1[i] = 0;
         }
@@ -327,13 +334,13 @@ __device__ __forceinline__ void select_roots(const SelectArgs& a, const FrameJob
         uint32_t wi = 0;
         if (j < nw) {
             wi = a.words[j];
-            w0 = a.bits0[wi];
+            w0 = coherent_load(&a.bits0[wi]);
             a.bits0[wi] = 0;
         }
         uint32_t kc = 0;
         for (uint64_t m = w0; m; m &= m - 1) {
             const uint32_t v = wi * 64 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
-            const uint32_t cnt = (uint32_t)a.stats[(int64_t)kStatsRow * v];
+            const uint32_t cnt = (uint32_t)coherent_load(&a.stats[(int64_t)kStatsRow * v]);
             kc += (a.t_np <= cnt && cnt <= a.t_nb) ? 1u : 0u;
         }
         uint32_t total;
@@ -341,18 +348,18 @@ __device__ __forceinline__ void select_roots(const SelectArgs& a, const FrameJob
         for (uint64_t m = w0; m; m &= m - 1) {
             const uint32_t v = wi * 64 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
             int32_t* s = a.stats + (int64_t)kStatsRow * v;
-            const uint32_t cnt = (uint32_t)s[0];
+            const uint32_t cnt = (uint32_t)coherent_load(&s[0]);
             if (a.t_np <= cnt && cnt <= a.t_nb) {
                 ++lab;
                 s[7] = (int32_t)lab;
                 if (lab <= a.max_rois) {
                     fvv_roi r;
-                    r.lo[0] = s[1];
-                    r.lo[1] = s[2];
-                    r.lo[2] = s[3];
-                    r.hi[0] = s[4];
-                    r.hi[1] = s[5];
-                    r.hi[2] = s[6];
+                    r.lo[0] = coherent_load(&s[1]);
+                    r.lo[1] = coherent_load(&s[2]);
+                    r.lo[2] = coherent_load(&s[3]);
+                    r.hi[0] = coherent_load(&s[4]);
+                    r.hi[1] = coherent_load(&s[5]);
+                    r.hi[2] = coherent_load(&s[6]);
                     r.count = cnt;
                     r.min_index = v;
                     a.rois[lab - 1] = r;
@@ -385,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void ccl_seed_kernel(const uint8_t* __restr
     uint32_t base = 0;
     if (lane_id() == leader)
         base = atomicAdd(seed.count, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, kWave);
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
     if (on)
         seed_sample(seed, (int32_t)v, base + lane_rank(m));
 }
@@ -504,7 +511,8 @@ __global__ __launch_bounds__(kSmallThreads) void ccl_small_kernel(
         coords_of(v, nx, ny, i, j, k);
         accumulate_stats(sa.stats, act, r, i, j, k);
     }
-    __threadfence();
+    // one workgroup: the barrier orders the atomics above before the
+    // selection's (L2-coherent) loads of their results
     __syncthreads();
     select_roots<kSmallThreads, kJobs>(sa, fj);
 }

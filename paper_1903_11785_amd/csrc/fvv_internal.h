@@ -74,6 +74,53 @@ __device__ __forceinline__ bool sil_test(float a, float b, float w,
     return ok & (((word >> (px & 31)) & 1u) != 0u);
 }
 
+// Occupancy test of one world point against G cameras at once (AND of the
+// single-camera tests), phased so that the G silhouette loads are issued
+// together: all projections first, one wave-uniform check for the rare tiny
+// w, then all floors and loads, then the bits.
+template <int G>
+__device__ __forceinline__ bool group_inside(const float* const* __restrict__ P, float X, float Y,
+                                             float Z, const uint32_t* const* __restrict__ sil,
+                                             int W, int H, int wpr) {
+    float a[G], b[G], w[G], qa[G], qb[G];
+    bool tiny_any = false;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const float* p = P[q];
+        a[q] = __builtin_fmaf(p[2], Z, __builtin_fmaf(p[1], Y, __builtin_fmaf(p[0], X, p[3])));
+        b[q] = __builtin_fmaf(p[6], Z, __builtin_fmaf(p[5], Y, __builtin_fmaf(p[4], X, p[7])));
+        w[q] = __builtin_fmaf(p[10], Z, __builtin_fmaf(p[9], Y, __builtin_fmaf(p[8], X, p[11])));
+        const float r = __builtin_amdgcn_rcpf(w[q]);
+        qa[q] = a[q] * r;
+        qb[q] = b[q] * r;
+        tiny_any |= w[q] > 0.0f && w[q] < 0x1p-64f;
+    }
+    if (__builtin_expect(__ballot(tiny_any) != 0, 0)) {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (w[q] > 0.0f && w[q] < 0x1p-64f) {
+                qa[q] = a[q] / w[q];
+                qb[q] = b[q] / w[q];
+            }
+    }
+    uint32_t word[G];
+    int px[G];
+    bool ok[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        px[q] = exact_floor(a[q], w[q], __builtin_amdgcn_fmed3f(qa[q], -4.0f, (float)W + 4.0f));
+        const int py =
+            exact_floor(b[q], w[q], __builtin_amdgcn_fmed3f(qb[q], -4.0f, (float)H + 4.0f));
+        ok[q] = (w[q] > 0.0f) & ((unsigned)px[q] < (unsigned)W) & ((unsigned)py < (unsigned)H);
+        word[q] = sil[q][ok[q] ? py * wpr + (px[q] >> 5) : 0];
+    }
+    bool in = true;
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+        in &= ok[q] & (((word[q] >> (px[q] & 31)) & 1u) != 0u);
+    return in;
+}
+
 // World coordinate of global lattice index g on one axis.
 __device__ __forceinline__ float lattice_coord(int g, float h, float o) {
     return __builtin_fmaf((float)g, h, o);

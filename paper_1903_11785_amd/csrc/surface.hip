@@ -4,9 +4,10 @@
 // one ROI, eight consecutive samples per thread.  A first pass counts each
 // item's edges, one workgroup scans the counts, and a second pass writes keys
 // 3*lin+axis in ascending order (a thread's keys are in order, and a block
-// scan orders the threads).  Exit points: one edge per lane; a first pass
-// finds the cameras that can reject some point of the edge at all, and the
-// n_steps bisection steps test only those at each bracket midpoint.
+// scan orders the threads).  Exit points: a group of four lanes per edge, each
+// owning a quarter of the cameras; a first pass keeps the cameras that can
+// reject some point of the edge at all, and the n_steps bisection steps test
+// only those at each bracket midpoint.
 #include "fvv_internal.h"
 
 namespace fvv {
@@ -173,60 +174,57 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
 }
 
 // ------------------------------------------------------------------ exit points
-// Cameras that can reject some point of a crossing edge.  Camera c cannot when
-// the pixel rectangle of the edge's projection, widened by cams.pad[c], is
-// inside the image and entirely foreground: the projection of a segment is a
-// segment between the projections of its ends, and pad[c] bounds the distance
-// between the real quotient of any point of the lattice's box and the
-// rounded quotient the occupancy test floors (the ends' quotients here come
-// from rcp, whose error pad[c] also covers).  Such a camera accepts every
-// point of the edge, so leaving it out of the bisection changes no decision.
-__device__ __forceinline__ uint32_t cameras_that_matter(const CamSet& cams,
-                                                        const uint32_t* __restrict__ sils,
-                                                        int64_t cam_words, const float* X0,
-                                                        const float* X1) {
-    uint32_t mask = 0;
-    for (int c = 0; c < cams.n; ++c) {
-        const float* P = &cams.P[c][0];
-        const float pad = cams.pad[c];
-        float x[2], y[2];
-        bool front = true;
+constexpr int kLanesPerEdge = 4;
+
+// Whether camera c accepts every point of the edge X0-X1: the pixel rectangle
+// of the edge's projection, widened by cams.pad[c], lies inside the image and
+// is entirely foreground.  The projection of a segment is the segment between
+// the projections of its ends, and pad[c] bounds the distance between the real
+// quotient of any point of the lattice's box and the rounded quotient the
+// occupancy test floors (the ends' quotients here come from rcp, whose error
+// pad[c] also covers).  Rectangles of more than 2 rows or 2 words are not
+// examined (the camera then stays in the bisection).
+__device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
+                                                    const uint32_t* __restrict__ sil,
+                                                    const float* X0, const float* X1) {
+    const float* P = &cams.P[c][0];
+    const float pad = cams.pad[c];
+    float x[2], y[2];
+    bool front = true;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const float* X = e ? X1 : X0;
-            const float a = __builtin_fmaf(P[2], X[2], __builtin_fmaf(P[1], X[1], __builtin_fmaf(P[0], X[0], P[3])));
-            const float b = __builtin_fmaf(P[6], X[2], __builtin_fmaf(P[5], X[1], __builtin_fmaf(P[4], X[0], P[7])));
-            const float w = __builtin_fmaf(P[10], X[2], __builtin_fmaf(P[9], X[1], __builtin_fmaf(P[8], X[0], P[11])));
-            const float r = __builtin_amdgcn_rcpf(w);
-            front = front && w > 0.0f;
-            x[e] = a * r;
-            y[e] = b * r;
-        }
-        const float fx0 = __builtin_floorf(fminf(x[0], x[1]) - pad);
-        const float fx1 = __builtin_floorf(fmaxf(x[0], x[1]) + pad);
-        const float fy0 = __builtin_floorf(fminf(y[0], y[1]) - pad);
-        const float fy1 = __builtin_floorf(fmaxf(y[0], y[1]) + pad);
-        bool safe = front && fx0 >= 0.0f && fy0 >= 0.0f && fx1 < (float)cams.W &&
-                    fy1 < (float)cams.H && fx1 - fx0 <= 31.0f && fy1 - fy0 <= 3.0f;
-        if (safe) {
-            const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-            const int w0 = x0 >> 5, w1 = x1 >> 5;
-            const uint32_t m0 = w0 == w1 ? (2u << (x1 & 31)) - (1u << (x0 & 31))
-                                         : 0u - (1u << (x0 & 31));
-            const uint32_t m1 = (2u << (x1 & 31)) - 1u;
-            const uint32_t* sil = sils + c * cam_words;
-            for (int yy = y0; yy <= y1; ++yy) {
-                const uint32_t* row = sil + yy * cams.wpr;
-                safe = safe && (row[w0] & m0) == m0;
-                if (w1 != w0)
-                    safe = safe && (row[w1] & m1) == m1;
-            }
-        }
-        mask |= (safe ? 0u : 1u) << c;
+    for (int e = 0; e < 2; ++e) {
+        const float* X = e ? X1 : X0;
+        const float a = __builtin_fmaf(P[2], X[2], __builtin_fmaf(P[1], X[1], __builtin_fmaf(P[0], X[0], P[3])));
+        const float b = __builtin_fmaf(P[6], X[2], __builtin_fmaf(P[5], X[1], __builtin_fmaf(P[4], X[0], P[7])));
+        const float w = __builtin_fmaf(P[10], X[2], __builtin_fmaf(P[9], X[1], __builtin_fmaf(P[8], X[0], P[11])));
+        const float r = __builtin_amdgcn_rcpf(w);
+        front = front && w > 0.0f;
+        x[e] = a * r;
+        y[e] = b * r;
     }
-    return mask;
+    const float fx0 = __builtin_floorf(fminf(x[0], x[1]) - pad);
+    const float fx1 = __builtin_floorf(fmaxf(x[0], x[1]) + pad);
+    const float fy0 = __builtin_floorf(fminf(y[0], y[1]) - pad);
+    const float fy1 = __builtin_floorf(fmaxf(y[0], y[1]) + pad);
+    const bool small = front && fx0 >= 0.0f && fy0 >= 0.0f && fx1 < (float)cams.W &&
+                       fy1 < (float)cams.H && fx1 - fx0 <= 31.0f && fy1 - fy0 <= 1.0f;
+    const int x0 = small ? (int)fx0 : 0, x1 = small ? (int)fx1 : 0;
+    const int y0 = small ? (int)fy0 : 0, y1 = small ? (int)fy1 : 0;
+    const int w0 = x0 >> 5, w1 = x1 >> 5;
+    const uint32_t m0 = w0 == w1 ? (2u << (x1 & 31)) - (1u << (x0 & 31)) : 0u - (1u << (x0 & 31));
+    const uint32_t m1 = w0 == w1 ? 0u : (2u << (x1 & 31)) - 1u;
+    // the four words are loaded together (unused ones repeat a used one)
+    const uint32_t* r0 = sil + y0 * cams.wpr;
+    const uint32_t* r1 = sil + y1 * cams.wpr;
+    const uint32_t a00 = r0[w0], a01 = r0[w1], a10 = r1[w0], a11 = r1[w1];
+    return small && (a00 & m0) == m0 && (a01 & m1) == m1 && (a10 & m0) == m0 &&
+           (a11 & m1) == m1;
 }
 
+// One crossing edge per group of kLanesPerEdge lanes; lane `sub` of the group
+// owns cameras sub, sub + kLanesPerEdge, ...  Each lane first keeps the ones of
+// its cameras that can reject some point of the edge, then every bisection
+// step tests the midpoint against those, and a wave ballot ANDs the group.
 __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ n_jobs_p,
                                                         const uint32_t* __restrict__ point_off,
@@ -237,15 +235,23 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                                                         const uint32_t* __restrict__ keys,
                                                         float* __restrict__ xyz,
                                                         uint32_t max_points) {
+    constexpr int kPerLane = (FVV_MAX_CAMS + kLanesPerEdge - 1) / kLanesPerEdge;
+    constexpr uint32_t kGroupMask = (1u << kLanesPerEdge) - 1u;
+    constexpr uint32_t kEdgesPerBlock = kBlock / kLanesPerEdge;
     const int nj = (int)*n_jobs_p;
     const uint32_t total = point_off[nj];
     const uint32_t E = total < max_points ? total : max_points;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < E; e += gridDim.x * kBlock) {
-        const int jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, e);
+    const int sub = lane_id() % kLanesPerEdge;
+    const int shift = lane_id() - sub;
+    for (uint32_t base = blockIdx.x * kEdgesPerBlock; base < E; base += gridDim.x * kEdgesPerBlock) {
+        const uint32_t e = base + threadIdx.x / kLanesPerEdge;
+        const bool act = e < E;
+        const uint32_t ee = act ? e : E - 1;
+        const int jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, ee);
         const fvv_grid g = jobs[jb].grid;
         const int64_t out_offset = jobs[jb].out_offset;
-        const uint32_t key = keys[e];
+        const uint32_t key = keys[ee];
         const uint32_t lin = key / 3u;
         const int axis = (int)(key - 3u * lin);
         const uint32_t i = lin % (uint32_t)g.dims[0];
@@ -260,9 +266,14 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                       lattice_coord(gidx[1], g.h, g.origin[1]),
                       lattice_coord(gidx[2], g.h, g.origin[2])};
         float X0[3] = {c[0], c[1], c[2]}, X1[3] = {c[0], c[1], c[2]};
-        X0[axis] = lattice_coord(gidx[axis], g.h, g.origin[axis]);
         X1[axis] = lattice_coord(gidx[axis] + 1, g.h, g.origin[axis]);
-        const uint32_t active = cameras_that_matter(cams, sils, cam_words, X0, X1);
+        uint32_t mine = 0;   // bit q: camera sub + q*kLanesPerEdge can reject
+#pragma unroll
+        for (int q = 0; q < kPerLane; ++q) {
+            const int cam = sub + q * kLanesPerEdge;
+            if (cam < cams.n && !camera_accepts_edge(cams, cam, sils + cam * cam_words, X0, X1))
+                mine |= 1u << q;
+        }
         float lo = 0.0f, hi = 1.0f;
         for (int s = 0; s < n_steps; ++s) {
             const float m = 0.5f * (lo + hi);
@@ -272,22 +283,25 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
             const float Y = axis == 1 ? ax : c[1];
             const float Z = axis == 2 ? ax : c[2];
             bool in = true;
-            for (uint32_t rest = active; rest && in; rest &= rest - 1) {
-                const int cam = __ffs(rest) - 1;
-                in = seen_inside(&cams.P[cam][0], X, Y, Z, sils + cam * cam_words, cams.W, cams.H,
-                                 cams.wpr);
+            for (uint32_t rest = mine; rest; rest &= rest - 1) {
+                const int cam = sub + (__ffs(rest) - 1) * kLanesPerEdge;
+                in = in && seen_inside(&cams.P[cam][0], X, Y, Z, sils + cam * cam_words, cams.W,
+                                       cams.H, cams.wpr);
             }
-            if (in)
+            const uint64_t fail = __ballot(!in);
+            if ((((uint32_t)(fail >> shift)) & kGroupMask) == 0)
                 lo = m;
             else
                 hi = m;
         }
-        const float t = 0.5f * (lo + hi);
-        const float q = (float)g_on + d * t;
-        c[axis] = __builtin_fmaf(q, g.h, g.origin[axis]);
-        xyz[3 * (int64_t)e + 0] = c[0];
-        xyz[3 * (int64_t)e + 1] = c[1];
-        xyz[3 * (int64_t)e + 2] = c[2];
+        if (act && sub == 0) {
+            const float t = 0.5f * (lo + hi);
+            const float q = (float)g_on + d * t;
+            c[axis] = __builtin_fmaf(q, g.h, g.origin[axis]);
+            xyz[3 * (int64_t)e + 0] = c[0];
+            xyz[3 * (int64_t)e + 1] = c[1];
+            xyz[3 * (int64_t)e + 2] = c[2];
+        }
     }
 }
 
@@ -307,7 +321,7 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                        n_jobs_dev, occ_fine, ctx->d_item_base, keys, max_points);
     if (edges_done)
         (void)hipEventRecord(edges_done, s);
-    hipLaunchKernelGGL(bisect_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, n_jobs_dev,
+    hipLaunchKernelGGL(bisect_kernel, dim3(ctx->n_cus * 16), dim3(kBlock), 0, s, jobs, n_jobs_dev,
                        point_off, occ_fine, cams, sils, n_steps, keys, xyz, max_points);
     return hipGetLastError();
 }
