@@ -239,7 +239,9 @@ typedef struct {
  * already holds the packed silhouettes.  events: NULL, or FVV_FRAME_EVENTS
  * HIP events recorded on `stream` at the start and after each stage (pack,
  * coarse carve, labelling, fine jobs + fine carve, crossing edges, exit
- * points) -- a per-stage timing of the frame.  EINVAL as the individual calls. */
+ * points) -- a per-stage timing of the frame.  EINVAL as the individual calls,
+ * and for spacings hc_um or hf_um above 2^28.  Calls on one context must not
+ * overlap (they share its scratch). */
 #define FVV_FRAME_EVENTS 7
 fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint8_t *d_masks,
                      uint32_t *d_sils, const fvv_frame_out *out, hipEvent_t *events,

@@ -15,6 +15,8 @@ namespace {
 
 constexpr int64_t kMaxSamples = 0x7fffffffLL;
 constexpr int32_t kMaxIndex = 1 << 24;  // (float)g is exact below this
+// Spacing bound of a frame: index * spacing stays below 2^53 (exact in double)
+constexpr int64_t kMaxSpacingUm = (int64_t)1 << 28;
 
 bool finite3(const float* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 
@@ -177,9 +179,9 @@ void fvv_destroy(fvv_ctx* ctx) {
     if (!ctx)
         return;
     hipDeviceSynchronize();
-    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_parent, ctx->d_stats, ctx->d_list,
-                    ctx->d_slot, ctx->d_list_count, ctx->d_bits0, ctx->d_bits1, ctx->d_words,
-                    ctx->d_prefix,
+    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_rowbits, ctx->d_rowmask, ctx->d_rows,
+                    ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_runP, ctx->d_stats,
+                    ctx->d_sample_label, ctx->d_prefix,
                     ctx->d_job_single, ctx->d_cams, ctx->d_item_cnt, ctx->d_item_base,
                     ctx->d_point_off_single, ctx->d_counts_single};
     for (void* p : ptrs)
@@ -215,8 +217,10 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         delete c;
         return FVV_EDEVICE;
     }
+    // a grid of at most V samples has at most V rows, V runs and V components,
+    // and at most V + V/64 row-bitmap words (rows padded to whole words)
     const int64_t V = lim->max_coarse;
-    const int64_t w0 = (V + 63) / 64 + 1, w1 = (V + 4095) / 4096 + 1;
+    const int64_t n_rowbits = V + V / 64 + 1, n_rowmask = V / 64 + 1;
     c->job_cap = (int64_t)(lim->max_jobs > lim->max_rois ? lim->max_jobs : lim->max_rois) + 2;
     c->item_cap = lim->max_fine / kEdgeChunk + (int64_t)lim->max_rois + 2;
     hipError_t e = hipSuccess;
@@ -225,14 +229,15 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         e = alloc(&c->ptr, (n));
     A(d_status, 1)
     A(d_counter, 4)
-    A(d_parent, V)
-    A(d_stats, (int64_t)kStatsRow * V)
-    A(d_list, V)
-    A(d_slot, V)
-    A(d_list_count, 1)
-    A(d_bits0, w0)
-    A(d_bits1, w1)
-    A(d_words, w0)
+    A(d_rowbits, n_rowbits)
+    A(d_rowmask, n_rowmask)
+    A(d_rows, V)
+    A(d_rs, V + 1)
+    A(d_x0, V)
+    A(d_x1, V)
+    A(d_runP, V)
+    A(d_stats, (int64_t)(kStatsRow + 1) * V)
+    A(d_sample_label, V)
     A(d_prefix, c->job_cap)
     A(d_job_single, 1)
     A(d_cams, FVV_MAX_CAMS)
@@ -251,11 +256,9 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     if (e == hipSuccess)
         e = hipMemset(c->d_status, 0, sizeof(uint32_t));
     if (e == hipSuccess)
-        e = hipMemset(c->d_list_count, 0, sizeof(uint32_t));
+        e = hipMemset(c->d_rowbits, 0, (size_t)n_rowbits * sizeof(uint64_t));
     if (e == hipSuccess)
-        e = hipMemset(c->d_bits0, 0, (size_t)w0 * sizeof(uint64_t));
-    if (e == hipSuccess)
-        e = hipMemset(c->d_bits1, 0, (size_t)w1 * sizeof(uint64_t));
+        e = hipMemset(c->d_rowmask, 0, (size_t)n_rowmask * sizeof(uint64_t));
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -390,7 +393,8 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
                      uint32_t* d_sils, const fvv_frame_out* o, hipEvent_t* events,
                      hipStream_t stream) {
     if (!ctx || !p || !o || !d_sils || !cams_ok(ctx, p->n_cams, p->cams) ||
-        !grid_ok(&p->coarse, kMaxIndex) || p->hc_um < 1 || p->hf_um < 1 || p->t_np > p->t_nb ||
+        !grid_ok(&p->coarse, kMaxIndex) || p->hc_um < 1 || p->hf_um < 1 ||
+        p->hc_um > kMaxSpacingUm || p->hf_um > kMaxSpacingUm || p->t_np > p->t_nb ||
         p->n_steps < 1 || p->n_steps > FVV_MAX_STEPS || !tile_ok(&p->coarse_tile) ||
         !tile_ok(&p->fine_tile))
         return FVV_EINVAL;
@@ -433,10 +437,10 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (d_masks)
         e = launch_pack(p->n_cams, cs.W, cs.H, d_masks, d_sils, stream);
     mark(1);
-    // the coarse carve seeds the labelling with its occupied samples
-    const LabelSeed seed = label_seed(ctx);
+    // the coarse carve also fills the labelling's row bitmap
+    const RowBits rb = row_bits(ctx, p->coarse);
     if (e == hipSuccess)
-        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, &seed, stream);
+        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, &rb, stream);
     mark(2);
     // labelling; its selection kernel also lays out the fine jobs of the ROIs
     FrameJobs fj;

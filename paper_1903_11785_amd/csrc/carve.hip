@@ -85,12 +85,14 @@ __device__ __forceinline__ void lds_append(bool pred, uint16_t val, uint16_t* li
 }
 
 // Carve tile `tile` of lattice g.  getP(c) returns camera c's 12 floats (a
-// wave-uniform address); sil_of(c) its silhouette rows.  With kSeed, every
-// occupied sample is also handed to the labelling stage (LabelSeed).
-template <int TX, int TZ, bool kSeed, typename GetP, typename GetSil>
+// wave-uniform address); sil_of(c) its silhouette rows.  With kRows, the
+// occupancy is also ORed into the labelling's row bitmap: the TX lanes of one
+// tile row cover TX consecutive x inside one bitmap word (TX divides 64), so
+// each tile row costs one atomic, and none where it is empty.
+template <int TX, int TZ, bool kRows, typename GetP, typename GetSil>
 __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, int W, int H,
                                            int wpr, const fvv_grid& g, uint64_t tile,
-                                           uint8_t* __restrict__ out, const LabelSeed& seed) {
+                                           uint8_t* __restrict__ out, const RowBits& rb) {
     constexpr int TY = kBlock / TX;
     constexpr int TV = TX * TY * TZ;
     constexpr int LX = log2_of(TX), LY = log2_of(TY);
@@ -168,20 +170,6 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
         const int s = act ? surv[idx] : 0;
         if (act)
             atomicOr(&s_alive[s >> 5], 1u << (s & 31));
-        if (kSeed) {
-            const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
-            const int32_t lin = (i0 + lx) + g.dims[0] * ((j0 + ly) + g.dims[1] * (k0 + lz));
-            const uint64_t m = __ballot(act);
-            if (m) {
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                uint32_t sbase = 0;
-                if (lane_id() == leader)
-                    sbase = atomicAdd(seed.count, (uint32_t)__popcll(m));
-                sbase = (uint32_t)__builtin_amdgcn_readlane((int)sbase, leader);
-                if (act)
-                    seed_sample(seed, lin, sbase + lane_rank(m));
-            }
-        }
     }
     __syncthreads();
     const uint64_t plane = (uint64_t)g.dims[0] * (uint64_t)g.dims[1];
@@ -190,22 +178,35 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
         const int s = rr * kBlock + (int)threadIdx.x;
         const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
         const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
-        if (i < g.dims[0] && j < g.dims[1] && k < g.dims[2])
-            out[(uint64_t)k * plane + (uint64_t)j * g.dims[0] + i] =
-                (uint8_t)((s_alive[s >> 5] >> (s & 31)) & 1u);
+        const bool valid = i < g.dims[0] && j < g.dims[1] && k < g.dims[2];
+        const uint32_t bit = (s_alive[s >> 5] >> (s & 31)) & 1u;
+        if (valid)
+            out[(uint64_t)k * plane + (uint64_t)j * g.dims[0] + i] = (uint8_t)bit;
+        if (kRows) {
+            // lanes [TX*q, TX*q + TX) of the wave hold one tile row (lx = 0..TX-1)
+            const uint64_t m = __ballot(valid && bit != 0u);
+            const int q = lane_id() / TX;
+            const uint64_t bits = TX == 64 ? m : (m >> (q * TX)) & ((1ull << (TX & 63)) - 1);
+            if (lx == 0 && bits != 0) {
+                const int64_t row = (int64_t)j + (int64_t)g.dims[1] * k;
+                atomicOr((unsigned long long*)&rb.words[row * rb.wr + (i0 >> 6)],
+                         (unsigned long long)(bits << (i0 & 63)));
+                atomicOr((unsigned long long*)&rb.rowmask[row >> 6], 1ull << (row & 63));
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------------ one lattice
-template <int TX, int TZ, bool kSeed>
+template <int TX, int TZ, bool kRows>
 __global__ __launch_bounds__(kBlock) void carve_kernel(const CamSet cams,
                                                        const uint32_t* __restrict__ sils,
                                                        const fvv_grid g, uint8_t* __restrict__ occ,
-                                                       const LabelSeed seed) {
+                                                       const RowBits rb) {
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-    carve_tile<TX, TZ, kSeed>([&](int c) { return &cams.P[c][0]; },
+    carve_tile<TX, TZ, kRows>([&](int c) { return &cams.P[c][0]; },
                               [&](int c) { return sils + c * cam_words; }, cams.n, cams.W, cams.H,
-                              cams.wpr, g, blockIdx.x, occ, seed);
+                              cams.wpr, g, blockIdx.x, occ, rb);
 }
 
 // ------------------------------------------------------------------ batched, persistent
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
     const uint32_t nj = counter[2];
     const uint64_t per = counter[1];
     const uint64_t total = pre[nj].tile_off;
-    const LabelSeed no_seed{};
+    const RowBits no_rows{};
     for (;;) {
         if (threadIdx.x == 0)
             s_item = atomicAdd(&counter[0], 1u);
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
             carve_tile<TX, TZ, false>([&](int c) { return &jc[c].P[0]; },
                                       [&](int c) { return js + c * cam_words; }, job.n_cams,
                                       job.width, job.height, wpr, job.grid, t - pre[jb].tile_off,
-                                      out + job.out_offset, no_seed);
+                                      out + job.out_offset, no_rows);
         }
     }
 }
@@ -284,21 +285,21 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
     X(16, 2) X(16, 4) X(16, 8)
 
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g, TileShape t,
-                        uint8_t* occ, const LabelSeed* seed, hipStream_t s) {
+                        uint8_t* occ, const RowBits* rows, hipStream_t s) {
     const uint64_t tiles = tiles_of_grid(g, t.tx, t.tz);
     if (tiles == 0)
         return hipSuccess;
     if (tiles > 0x7fffffffull)
         return hipErrorInvalidValue;
-    const LabelSeed sd = seed ? *seed : LabelSeed{};
+    const RowBits rb = rows ? *rows : RowBits{};
 #define X(TXV, TZV)                                                                           \
     if (t.tx == TXV && t.tz == TZV) {                                                         \
-        if (seed)                                                                             \
+        if (rows)                                                                             \
             hipLaunchKernelGGL((carve_kernel<TXV, TZV, true>), dim3((unsigned)tiles),         \
-                               dim3(kBlock), 0, s, cams, sils, g, occ, sd);                   \
+                               dim3(kBlock), 0, s, cams, sils, g, occ, rb);                   \
         else                                                                                  \
             hipLaunchKernelGGL((carve_kernel<TXV, TZV, false>), dim3((unsigned)tiles),        \
-                               dim3(kBlock), 0, s, cams, sils, g, occ, sd);                   \
+                               dim3(kBlock), 0, s, cams, sils, g, occ, rb);                   \
         return hipGetLastError();                                                             \
     }
     FVV_TILE_CASES(X)

@@ -2,43 +2,43 @@
 // (Sec. II-B-2) and, in a frame, the fine lattice of every ROI (Sec. II-B-3)
 // for gfx950.
 //
-// The coarse hull of a sports scene occupies well under 1 % of the volume, so
-// the work is organised around the list of occupied samples rather than the
-// grid.  Occupied samples are appended to a list, each with a union-find
-// parent (itself), its list position and a stats row; the coarse carve of a
-// frame does this as it writes the occupancy, fvv_label with a seed pass.
-//
-// Small lists (up to kLdsCap samples, the usual case) are labelled by ONE
-// workgroup with the whole forest in LDS: union-find over list positions,
-// linking the root with the larger linear index under the smaller with a CAS,
-// then flattening, per-root count and bounding box, and the selection below
-// -- one launch, no global round trips between the union steps.  Larger lists
-// take a global path of three kernels (unite, flatten, select) with the same
-// rules on the linear indices in global memory (atomicMin links).  Each path's
-// kernels return at once when the list belongs to the other.
-//
-// Selection: roots flag themselves in a two-level bitmap; the non-zero words
-// are walked in ascending order, so components are numbered 1..K by smallest
-// linear index without a sort, after the Eq. (1) filter T_np <= N(S) <= T_nb.
-// The selection clears the bitmap words it reads and the list count, so the
-// scratch is ready for the next call without a memset.  A final grid pass
-// writes the labels and the filtered occupancy.  Every root is the smallest
-// linear index of its component whatever the interleaving of the atomics, so
-// labels and boxes are identical from run to run.
+// The coarse hull of a sports scene occupies well under 1 % of the volume and
+// its occupied samples come in short runs along x, so the labelling works on
+// runs, not samples.  The occupancy reaches it as a row bitmap (RowBits): the
+// coarse carve of a frame ORs in the bits of its survivors, fvv_label builds
+// it with a grid pass.  One workgroup then
+//   1. lists the rows with an occupied sample (bit mask over the rows),
+//   2. cuts each such row into maximal runs of set bits, numbered in raster
+//      order, so run ids ascend with the linear index of the first sample,
+//   3. unites, for every row, each run with the runs of the four earlier
+//      neighbouring rows (y-1 of the same z; y-1, y, y+1 of z-1) whose
+//      extent, widened by one sample, overlaps it -- exactly the 26-adjacency
+//      between runs (a two-pointer merge of the two sorted run lists) --
+//      linking the larger run id under the smaller with a CAS,
+//   4. flattens the forest and numbers the roots in ascending run id,
+//   5. adds every run to its root's count and bounding box (LDS atomics),
+//   6. applies the Eq. (1) filter T_np <= N(S) <= T_nb and numbers the kept
+//      components 1..K in that order -- ascending smallest linear index,
+//      whatever the interleaving of the atomics -- writes the ROI table and
+//      every occupied sample's label, and clears the bitmap for the next call,
+//   7. in a frame, lays out the fine jobs of the carried ROIs.
+// Rows, runs, forest and stats live in LDS while they fit, otherwise the same
+// steps run on global scratch.  A grid pass finally writes the labels of all
+// samples and the filtered occupancy.
 #include "fvv_internal.h"
 
 namespace fvv {
 
-constexpr int kListBlocksPerCU = 4;
-constexpr int kSelectThreads = 256;
-constexpr int kSmallThreads = 512;
-constexpr int kLdsCap = 8192;
+constexpr int kLabelThreads = 512;
+constexpr int kRowCap = 4096;    // listed rows held in LDS
+constexpr int kRunCap = 6144;    // runs held in LDS
+constexpr int kRootCap = 1024;   // components whose stats are held in LDS
 
-// ------------------------------------------------------------------ helpers
+// ------------------------------------------------------------------ union-find
 // Root of x with path halving: each visited node is re-pointed at its
-// grandparent.  Links only ever change roots (by CAS or atomicMin on a node
-// that was a root), and a re-pointed node still reaches the same root through
-// an ancestor, so halving races with neither links nor other finds.
+// grandparent.  Links only ever change roots (CAS on a node that is still a
+// root), and a re-pointed node still reaches the same root through an
+// ancestor, so halving races with neither links nor other finds.
 __device__ __forceinline__ int32_t find_root(volatile int32_t* P, int32_t x) {
     for (;;) {
         const int32_t p = P[x];
@@ -52,38 +52,15 @@ __device__ __forceinline__ int32_t find_root(volatile int32_t* P, int32_t x) {
     }
 }
 
-// Global forest over linear indices: the larger root is linked under the
-// smaller with atomicMin; if that root was linked meanwhile, retry.
-__device__ __forceinline__ void unite_global(int32_t* P, int32_t a, int32_t b) {
+// Link the roots of runs a and b: the larger run id under the smaller, with a
+// CAS that only succeeds while the node is still a root; retry otherwise.
+__device__ __forceinline__ void unite(int32_t* P, int32_t a, int32_t b) {
     for (;;) {
         a = find_root(P, a);
         b = find_root(P, b);
         if (a == b)
             return;
         if (a < b) {
-            const int32_t old = atomicMin(&P[b], a);
-            if (old == b)
-                return;
-            b = old;
-        } else {
-            const int32_t old = atomicMin(&P[a], b);
-            if (old == a)
-                return;
-            a = old;
-        }
-    }
-}
-
-// LDS forest over list positions ordered by their linear indices L[]: the
-// root with the larger linear index is linked under the other with a CAS that
-// only succeeds while it is still a root.
-__device__ __forceinline__ void unite_lds(int32_t* P, const int32_t* L, int32_t a, int32_t b) {
-    for (;;) {
-        a = find_root(P, a);
-        b = find_root(P, b);
-        if (a == b)
-            return;
-        if (L[a] < L[b]) {
             const int32_t t = a;
             a = b;
             b = t;
@@ -93,83 +70,18 @@ __device__ __forceinline__ void unite_lds(int32_t* P, const int32_t* L, int32_t 
     }
 }
 
-// The 13 neighbours that precede a sample in raster order (dz = -1: 9, dz = 0,
-// dy = -1: 3, dz = 0, dy = 0, dx = -1: 1).
-__device__ __forceinline__ void earlier_neighbour(int n, int& dx, int& dy, int& dz) {
-    if (n < 9) {
-        dz = -1;
-        dy = n / 3 - 1;
-        dx = n % 3 - 1;
-    } else if (n < 12) {
-        dz = 0;
-        dy = -1;
-        dx = n - 10;
-    } else {
-        dz = 0;
-        dy = 0;
-        dx = -1;
-    }
-}
-
-__device__ __forceinline__ void coords_of(int32_t v, int nx, int ny, int& i, int& j, int& k) {
-    const uint32_t uv = (uint32_t)v;
-    i = (int)(uv % (uint32_t)nx);
-    j = (int)((uv / (uint32_t)nx) % (uint32_t)ny);
-    k = (int)(uv / ((uint32_t)nx * (uint32_t)ny));
-}
-
-// Add each active lane's sample (i, j, k) to the stats row of its root r: one
-// set of atomics per (wave, root).
-__device__ __forceinline__ void accumulate_stats(int32_t* __restrict__ stats, bool act, int32_t r,
-                                                 int i, int j, int k) {
-    uint64_t pending = __ballot(act);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t lr = __shfl(r, leader, kWave);
-        const bool mine = act && r == lr;
-        const uint64_t mm = __ballot(mine);
-        const int lo_i = wave_min(mine ? i : 0x7fffffff);
-        const int lo_j = wave_min(mine ? j : 0x7fffffff);
-        const int lo_k = wave_min(mine ? k : 0x7fffffff);
-        const int hi_i = wave_max(mine ? i : -1);
-        const int hi_j = wave_max(mine ? j : -1);
-        const int hi_k = wave_max(mine ? k : -1);
-        if (lane_id() == leader) {
-            int32_t* s = stats + (int64_t)kStatsRow * lr;
-            atomicAdd(&s[0], (int32_t)__popcll(mm));
-            atomicMin(&s[1], lo_i);
-            atomicMin(&s[2], lo_j);
-            atomicMin(&s[3], lo_k);
-            atomicMax(&s[4], hi_i);
-            atomicMax(&s[5], hi_j);
-            atomicMax(&s[6], hi_k);
-        }
-        pending &= ~mm;
-    }
-}
-
-// Load of a value other waves produced with device atomics, from L2 (not a
-// possibly stale L1 line).
-template <typename T>
-__device__ __forceinline__ T coherent_load(T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void flag_root(uint64_t* __restrict__ bits0, uint64_t* __restrict__ bits1,
-                                          uint32_t v) {
-    atomicOr((unsigned long long*)&bits0[v >> 6], 1ull << (v & 63));
-    atomicOr((unsigned long long*)&bits1[v >> 12], 1ull << ((v >> 6) & 63));
-}
-
 // ------------------------------------------------------------------ fine jobs of a frame
-__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
-    int64_t q = a / b;
-    if ((a % b != 0) && ((a < 0) != (b < 0)))
-        q -= 1;
+// floor(a / b) for b > 0 and |a| < 2^53: the correctly rounded double
+// quotient is within one of the exact one; the integer residual corrects it.
+__device__ __forceinline__ int64_t floor_div_pos(int64_t a, int64_t b) {
+    int64_t q = (int64_t)__builtin_floor((double)a / (double)b);
+    const int64_t r = a - q * b;
+    q -= (r < 0) ? 1 : 0;
+    q += (r >= b) ? 1 : 0;
     return q;
 }
 
-__device__ __forceinline__ int64_t ceil_div64(int64_t a, int64_t b) { return -floor_div64(-a, b); }
+__device__ __forceinline__ int64_t ceil_div_pos(int64_t a, int64_t b) { return -floor_div_pos(-a, b); }
 
 constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
 
@@ -213,10 +125,10 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
             for (int a = 0; a < 3; ++a) {
                 const int64_t A = (int64_t)fj.coarse.lo[a] + r.lo[a] - 1;
                 const int64_t B = (int64_t)fj.coarse.lo[a] + r.hi[a] + 1;
-                int64_t f0 = floor_div64(A * fj.hc_um, fj.hf_um);
-                int64_t f1 = ceil_div64(B * fj.hc_um, fj.hf_um);
-                const int64_t fmin = ceil_div64((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um);
-                const int64_t fmax = floor_div64(
+                int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um);
+                int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um);
+                const int64_t fmin = ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um);
+                const int64_t fmax = floor_div_pos(
                     ((int64_t)fj.coarse.lo[a] + fj.coarse.dims[a] - 1) * fj.hc_um, fj.hf_um);
                 f0 = f0 < fmin ? fmin : f0;
                 f1 = f1 > fmax ? fmax : f1;
@@ -284,93 +196,291 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
     }
 }
 
-// ------------------------------------------------------------------ selection
-struct SelectArgs {
-    int32_t V;
-    uint64_t* bits0;
-    uint64_t* bits1;
-    uint32_t* words;
-    int32_t* stats;
+// ------------------------------------------------------------------ run labelling
+// Rows, runs and forest: LDS arrays or their global-scratch twins.
+struct RunArrays {
+    int32_t* rows;   // listed rows, ascending
+    int32_t* rs;     // first run of each listed row; rs[n_rows] = number of runs
+    int32_t* x0;     // first x of each run
+    int32_t* x1;     // last x of each run
+    int32_t* P;      // union-find parent; after ranking, -1 - rank at roots
+};
+
+struct LabelArgs {
+    RowBits rb;
+    int32_t nx, ny, nz;
+    RunArrays g;                 // global scratch (used when LDS is too small)
+    int32_t* gstats;             // global stats rows, kStatsRow per component
+    int32_t* sample_label;       // label of every occupied sample (for the grid pass)
     uint32_t t_np, t_nb;
     fvv_roi* rois;
     uint32_t max_rois;
     uint32_t* n_rois;
-    uint32_t* list_count;
     uint32_t* status;
     JobPrefix* pre;
     uint32_t* counter;
     fvv_camera* dcams;
 };
 
-// Roots in ascending linear order -> Eq. (1) filter, labels 1..K, ROI table;
-// then, in a frame, the fine jobs.  Run by one workgroup of NT threads.
-template <int NT, bool kJobs>
-__device__ __forceinline__ void select_roots(const SelectArgs& a, const FrameJobs& fj) {
-    __shared__ uint32_t scratch[NT / kWave];
-    const uint32_t n1 = (uint32_t)((a.V + 4095) / 4096);
-    uint32_t nw = 0;
-    for (uint32_t base = 0; base < n1; base += NT) {
-        const uint32_t i = base + threadIdx.x;
-        uint64_t w1 = 0;
-        if (i < n1) {
-            w1 = coherent_load(&a.bits1[i]);
-            if (w1)
-                a.bits1[i] = 0;
-        }
-        uint32_t total;
-        uint32_t pos = nw + block_exclusive_sum<NT>((uint32_t)__popcll(w1), scratch, &total);
-        while (w1) {
-            const int b = __ffsll((unsigned long long)w1) - 1;
-            w1 &= w1 - 1;
-            a.words[pos++] = i * 64 + (uint32_t)b;
-        }
-        nw += total;
+// Rank of the component of run k (P flattened and ranked).
+__device__ __forceinline__ int32_t rank_of(const volatile int32_t* P, int32_t k) {
+    const int32_t p = P[k];
+    return p < 0 ? -1 - p : -1 - P[p];
+}
+
+// Row-mask word w with the bits of rows >= R cleared, and word q of a row
+// with the bits of x >= nx cleared: producers never set them, and masking
+// keeps stale scratch from reaching outside the grid.
+__device__ __forceinline__ uint64_t rowmask_word(const RowBits& rb, int32_t w, int32_t R) {
+    const uint64_t v = rb.rowmask[w];
+    return (w == (R - 1) / 64 && (R & 63)) ? v & ((1ull << (R & 63)) - 1) : v;
+}
+
+__device__ __forceinline__ uint64_t row_word(const uint64_t* rw, int32_t q, int32_t wr, int32_t nx) {
+    const uint64_t v = rw[q];
+    return (q == wr - 1 && (nx & 63)) ? v & ((1ull << (nx & 63)) - 1) : v;
+}
+
+// Unite the runs of listed rows i and j (j an earlier neighbouring row):
+// two-pointer sweep over both ascending run lists; a pair is adjacent iff
+// each run starts at most one sample past the other's end.  The run that
+// ends first cannot touch any later run of the other row, so it advances.
+__device__ __forceinline__ void unite_rows(const RunArrays& m, int i, int j) {
+    int a = m.rs[i], ae = m.rs[i + 1];
+    int b = m.rs[j], be = m.rs[j + 1];
+    while (a < ae && b < be) {
+        const int32_t a0 = m.x0[a], a1 = m.x1[a], b0 = m.x0[b], b1 = m.x1[b];
+        if (a0 <= b1 + 1 && b0 <= a1 + 1)
+            unite(m.P, a, b);
+        if (a1 < b1)
+            ++a;
+        else
+            ++b;
+    }
+}
+
+// Count per component and bounding box; stats rows: count, lo[3], hi[3],
+// then (min linear index) and label in the second half.
+constexpr int kStatCount = 0, kStatLo = 1, kStatHi = 4, kStatMin = 7;
+
+template <bool kLdsStats>
+__device__ __forceinline__ int32_t stat_load(const int32_t* s) {
+    if (kLdsStats)
+        return *(const volatile int32_t*)s;
+    return __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Steps 5-6 with the stats rows in `stats` (LDS or global).
+template <bool kLdsStats>
+__device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunArrays& m,
+                                                 int32_t n_rows, int32_t K_all, int32_t* stats,
+                                                 int32_t* labels_of_rank, uint32_t* scan,
+                                                 uint32_t* Kout) {
+    constexpr int NT = kLabelThreads;
+    for (int32_t j = threadIdx.x; j < K_all; j += NT) {
+        int32_t* s = stats + (int64_t)kStatsRow * j;
+        s[kStatCount] = 0;
+        s[kStatLo + 0] = s[kStatLo + 1] = s[kStatLo + 2] = 0x7fffffff;
+        s[kStatHi + 0] = s[kStatHi + 1] = s[kStatHi + 2] = -1;
+        s[kStatMin] = 0x7fffffff;
     }
     __syncthreads();
-    uint32_t K = 0;
-    for (uint32_t base = 0; base < nw; base += NT) {
-        const uint32_t j = base + threadIdx.x;
-        uint64_t w0 = 0;
-        uint32_t wi = 0;
-        if (j < nw) {
-            wi = a.words[j];
-            w0 = coherent_load(&a.bits0[wi]);
-            a.bits0[wi] = 0;
+    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
+        const int32_t r = m.rows[i];
+        const int32_t y = r % a.ny, z = r / a.ny;
+        const int64_t row_lin = (int64_t)a.nx * r;
+        for (int32_t k = m.rs[i]; k < m.rs[i + 1]; ++k) {
+            const int32_t x0 = m.x0[k], x1 = m.x1[k];
+            int32_t* s = stats + (int64_t)kStatsRow * rank_of(m.P, k);
+            atomicAdd(&s[kStatCount], x1 - x0 + 1);
+            atomicMin(&s[kStatLo + 0], x0);
+            atomicMax(&s[kStatHi + 0], x1);
+            atomicMin(&s[kStatLo + 1], y);
+            atomicMax(&s[kStatHi + 1], y);
+            atomicMin(&s[kStatLo + 2], z);
+            atomicMax(&s[kStatHi + 2], z);
+            atomicMin(&s[kStatMin], (int32_t)(row_lin + x0));
         }
-        uint32_t kc = 0;
-        for (uint64_t m = w0; m; m &= m - 1) {
-            const uint32_t v = wi * 64 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
-            const uint32_t cnt = (uint32_t)coherent_load(&a.stats[(int64_t)kStatsRow * v]);
-            kc += (a.t_np <= cnt && cnt <= a.t_nb) ? 1u : 0u;
+    }
+    __syncthreads();
+    // Eq. (1) filter and numbering in root order (= ascending smallest index)
+    uint32_t K = 0;
+    for (int32_t base = 0; base < K_all; base += NT) {
+        const int32_t j = base + threadIdx.x;
+        const int32_t* s = stats + (int64_t)kStatsRow * j;
+        uint32_t cnt = 0;
+        bool keep = false;
+        if (j < K_all) {
+            cnt = (uint32_t)stat_load<kLdsStats>(&s[kStatCount]);
+            keep = a.t_np <= cnt && cnt <= a.t_nb;
         }
         uint32_t total;
-        uint32_t lab = K + block_exclusive_sum<NT>(kc, scratch, &total);
-        for (uint64_t m = w0; m; m &= m - 1) {
-            const uint32_t v = wi * 64 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
-            int32_t* s = a.stats + (int64_t)kStatsRow * v;
-            const uint32_t cnt = (uint32_t)coherent_load(&s[0]);
-            if (a.t_np <= cnt && cnt <= a.t_nb) {
-                ++lab;
-                s[7] = (int32_t)lab;
-                if (lab <= a.max_rois) {
-                    fvv_roi r;
-                    r.lo[0] = coherent_load(&s[1]);
-                    r.lo[1] = coherent_load(&s[2]);
-                    r.lo[2] = coherent_load(&s[3]);
-                    r.hi[0] = coherent_load(&s[4]);
-                    r.hi[1] = coherent_load(&s[5]);
-                    r.hi[2] = coherent_load(&s[6]);
-                    r.count = cnt;
-                    r.min_index = v;
-                    a.rois[lab - 1] = r;
-                }
+        const uint32_t lab = K + block_exclusive_sum<NT>(keep ? 1u : 0u, scan, &total) + 1;
+        if (j < K_all)
+            labels_of_rank[j] = keep ? (int32_t)lab : 0;
+        if (keep && lab <= a.max_rois) {
+            fvv_roi roi;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                roi.lo[e] = stat_load<kLdsStats>(&s[kStatLo + e]);
+                roi.hi[e] = stat_load<kLdsStats>(&s[kStatHi + e]);
             }
+            roi.count = cnt;
+            roi.min_index = (uint32_t)stat_load<kLdsStats>(&s[kStatMin]);
+            a.rois[lab - 1] = roi;
         }
         K += total;
     }
+    *Kout = K;
+}
+
+// Steps 1-7 with rows, runs and forest in `m`.  With kLds, gives up (returns
+// false, before any global state changed) when the runs do not fit the LDS
+// arrays.
+template <bool kLds, bool kJobs>
+__device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& fj,
+                                           const RunArrays& m, int32_t n_rows,
+                                           int32_t* lds_stats, uint32_t* scan) {
+    constexpr int NT = kLabelThreads;
+    const int32_t R = a.ny * a.nz;
+    const int32_t n_rm = (R + 63) / 64;
+    const int32_t wr = a.rb.wr;
+    // 1. listed rows, ascending
+    int32_t pos0 = 0;
+    for (int32_t base = 0; base < n_rm; base += NT) {
+        const int32_t w = base + threadIdx.x;
+        const uint64_t bits = w < n_rm ? rowmask_word(a.rb, w, R) : 0ull;
+        uint32_t total;
+        int32_t pos = pos0 + (int32_t)block_exclusive_sum<NT>((uint32_t)__popcll(bits), scan, &total);
+        for (uint64_t b = bits; b; b &= b - 1)
+            m.rows[pos++] = w * 64 + (__ffsll((unsigned long long)b) - 1);
+        pos0 += (int32_t)total;
+    }
+    __syncthreads();
+    // 2. runs per row: a run starts at a set bit whose left neighbour is clear
+    int32_t n_runs = 0;
+    for (int32_t base = 0; base < n_rows; base += NT) {
+        const int32_t i = base + threadIdx.x;
+        uint32_t cnt = 0;
+        if (i < n_rows) {
+            const uint64_t* rw = a.rb.words + (int64_t)m.rows[i] * wr;
+            uint64_t carry = 0;
+            for (int32_t q = 0; q < wr; ++q) {
+                const uint64_t v = row_word(rw, q, wr, a.nx);
+                cnt += (uint32_t)__popcll(v & ~((v << 1) | carry));
+                carry = v >> 63;
+            }
+        }
+        uint32_t total;
+        const uint32_t ex = block_exclusive_sum<NT>(cnt, scan, &total);
+        if (i < n_rows)
+            m.rs[i] = n_runs + (int32_t)ex;
+        n_runs += (int32_t)total;
+    }
+    if (kLds && n_runs > kRunCap)
+        return false;
+    if (threadIdx.x == 0)
+        m.rs[n_rows] = n_runs;
+    __syncthreads();
+    // 3. run extents (the k-th start and the k-th end of a row belong to its
+    //    k-th run); the row's bitmap words are cleared once read
+    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
+        uint64_t* rw = a.rb.words + (int64_t)m.rows[i] * wr;
+        int32_t ks = m.rs[i], ke = ks;
+        uint64_t carry = 0, v = row_word(rw, 0, wr, a.nx);
+        for (int32_t q = 0; q < wr; ++q) {
+            const uint64_t nxt = q + 1 < wr ? row_word(rw, q + 1, wr, a.nx) : 0ull;
+            const uint64_t st = v & ~((v << 1) | carry);
+            const uint64_t en = v & ~((v >> 1) | (nxt << 63));
+            for (uint64_t b = st; b; b &= b - 1) {
+                m.x0[ks] = q * 64 + (__ffsll((unsigned long long)b) - 1);
+                m.P[ks] = ks;
+                ++ks;
+            }
+            for (uint64_t b = en; b; b &= b - 1)
+                m.x1[ke++] = q * 64 + (__ffsll((unsigned long long)b) - 1);
+            rw[q] = 0;
+            carry = v >> 63;
+            v = nxt;
+        }
+    }
+    __syncthreads();
+    // 4. unite with the earlier neighbouring rows
+    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
+        const int32_t r = m.rows[i];
+        const int32_t y = r % a.ny, z = r / a.ny;
+        if (y > 0 && i > 0 && m.rows[i - 1] == r - 1)
+            unite_rows(m, i, i - 1);
+        if (z > 0) {
+            // rows (y-1..y+1, z-1) lie among the ny+1 listed rows before i
+            const int32_t target = r - a.ny - 1;
+            int32_t lo = i - a.ny - 1 > 0 ? i - a.ny - 1 : 0, hi = i;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (m.rows[mid] < target)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            for (int32_t j = lo; j < i; ++j) {
+                const int32_t rj = m.rows[j];
+                if (rj > r - a.ny + 1)
+                    break;
+                const int32_t yj = rj % a.ny;
+                if (rj / a.ny == z - 1 && yj >= y - 1 && yj <= y + 1)
+                    unite_rows(m, i, j);
+            }
+        }
+    }
+    __syncthreads();
+    // 5. flatten, then number the roots in ascending run id.  The walk only
+    //    reads: the sole writes now set a node to its root, which keeps every
+    //    concurrent walk on course (path halving here could store a
+    //    grandparent over a root written meanwhile).
+    for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
+        volatile int32_t* P = m.P;
+        int32_t x = k;
+        for (int32_t p = P[x]; p != x; p = P[x])
+            x = p;
+        P[k] = x;
+    }
+    __syncthreads();
+    int32_t K_all = 0;
+    for (int32_t base = 0; base < n_runs; base += NT) {
+        const int32_t k = base + threadIdx.x;
+        const bool root = k < n_runs && ((volatile int32_t*)m.P)[k] == k;
+        uint32_t total;
+        const uint32_t rk = block_exclusive_sum<NT>(root ? 1u : 0u, scan, &total);
+        if (root)
+            m.P[k] = -1 - (K_all + (int32_t)rk);
+        K_all += (int32_t)total;
+    }
+    __syncthreads();
+    // 6. stats, filter, ROI table (stats rows in LDS while the components fit;
+    //    the label of each rank follows the rows)
+    uint32_t K = 0;
+    int32_t* lab;
+    if (K_all <= kRootCap) {
+        lab = lds_stats + (int64_t)kStatsRow * kRootCap;
+        stats_and_select<true>(a, m, n_rows, K_all, lds_stats, lab, scan, &K);
+    } else {
+        lab = a.gstats + (int64_t)kStatsRow * K_all;
+        stats_and_select<false>(a, m, n_rows, K_all, a.gstats, lab, scan, &K);
+    }
+    __syncthreads();
+    // labels of the occupied samples, and the row mask cleared
+    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
+        const int64_t row_lin = (int64_t)a.nx * m.rows[i];
+        for (int32_t k = m.rs[i]; k < m.rs[i + 1]; ++k) {
+            const int32_t l = ((volatile int32_t*)lab)[rank_of(m.P, k)];
+            for (int32_t x = m.x0[k]; x <= m.x1[k]; ++x)
+                a.sample_label[row_lin + x] = l;
+        }
+    }
+    for (int32_t w = threadIdx.x; w < n_rm; w += NT)
+        a.rb.rowmask[w] = 0;
     if (threadIdx.x == 0) {
         *a.n_rois = K;
-        *a.list_count = 0;
         if (K > a.max_rois)
             atomicOr(a.status, kFlagCapacity);
     }
@@ -378,192 +488,67 @@ __device__ __forceinline__ void select_roots(const SelectArgs& a, const FrameJob
         __syncthreads();
         build_fine_jobs<NT>(fj, a.rois, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);
     }
-}
-
-// ------------------------------------------------------------------ kernels
-__global__ __launch_bounds__(kBlock) void ccl_seed_kernel(const uint8_t* __restrict__ occ,
-                                                          int32_t V, const LabelSeed seed) {
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool on = v < V && occ[v] != 0;
-    const uint64_t m = __ballot(on);
-    if (m == 0)
-        return;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader)
-        base = atomicAdd(seed.count, (uint32_t)__popcll(m));
-    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-    if (on)
-        seed_sample(seed, (int32_t)v, base + lane_rank(m));
-}
-
-// Global forest, one thread per (listed sample, earlier neighbour) from
-// `first` in steps of `stride`.
-__device__ __forceinline__ void unite_listed(const uint8_t* __restrict__ occ, int32_t* parent,
-                                             const int32_t* __restrict__ list, uint32_t n, int nx,
-                                             int ny, uint64_t first, uint64_t stride) {
-    const uint64_t pairs = (uint64_t)n * 13;
-    for (uint64_t idx = first; idx < pairs; idx += stride) {
-        const int32_t v = list[idx / 13];
-        const int q = (int)(idx % 13);
-        int x, y, z, dx, dy, dz;
-        coords_of(v, nx, ny, x, y, z);
-        earlier_neighbour(q, dx, dy, dz);
-        const int ax = x + dx, ay = y + dy, az = z + dz;
-        if (ax < 0 || ax >= nx || ay < 0 || ay >= ny || az < 0)
-            continue;
-        const int32_t u = ax + nx * (ay + ny * az);
-        if (occ[u] != 0)
-            unite_global(parent, v, u);
-    }
-}
-
-// Global forest: every listed sample points at its root, adds itself to the
-// root's stats, and roots flag themselves.  Entry base + tid for base = first,
-// first + stride, ...; whole waves iterate together.
-__device__ __forceinline__ void flatten_listed(int32_t* parent, int32_t* __restrict__ stats,
-                                               const int32_t* __restrict__ list, uint32_t n,
-                                               uint64_t* bits0, uint64_t* bits1, int nx, int ny,
-                                               uint32_t first, uint32_t stride, uint32_t tid) {
-    for (uint32_t base = first; base < n; base += stride) {
-        const uint32_t idx = base + tid;
-        const bool act = idx < n;
-        const int32_t v = act ? list[idx] : 0;
-        const int32_t r = act ? find_root(parent, v) : -1;
-        if (act && r != v)
-            parent[v] = r;
-        int i, j, k;
-        coords_of(v, nx, ny, i, j, k);
-        accumulate_stats(stats, act, r, i, j, k);
-        if (act && r == v)
-            flag_root(bits0, bits1, (uint32_t)v);
-    }
-}
-
-// The whole labelling in one workgroup.  Lists of up to kLdsCap samples keep
-// the forest in LDS; longer ones (kFallback) use the global forest with the
-// same rules, still in this workgroup, or are left to the multi-workgroup
-// kernels below (!kFallback).
-template <bool kJobs, bool kFallback>
-__global__ __launch_bounds__(kSmallThreads) void ccl_small_kernel(
-    const uint8_t* __restrict__ occ, int32_t* __restrict__ parent,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ slot,
-    const uint32_t* __restrict__ count, int nx, int ny, int nz, const SelectArgs sa,
-    const FrameJobs fj) {
-    __shared__ int32_t L[kLdsCap];
-    __shared__ int32_t P[kLdsCap];
-    const uint32_t n = *count;
-    if (n > (uint32_t)kLdsCap) {
-        if (!kFallback)
-            return;
-        unite_listed(occ, parent, list, n, nx, ny, threadIdx.x, kSmallThreads);
-        __threadfence();
-        __syncthreads();
-        flatten_listed(parent, sa.stats, list, n, sa.bits0, sa.bits1, nx, ny, 0, kSmallThreads,
-                       threadIdx.x);
-        __threadfence();
-        __syncthreads();
-        select_roots<kSmallThreads, kJobs>(sa, fj);
-        return;
-    }
-    for (uint32_t c = threadIdx.x; c < n; c += kSmallThreads) {
-        L[c] = list[c];
-        P[c] = (int32_t)c;
-    }
-    __syncthreads();
-    for (uint32_t c = threadIdx.x; c < n; c += kSmallThreads) {
-        const int32_t v = L[c];
-        int x, y, z;
-        coords_of(v, nx, ny, x, y, z);
-        int32_t nb[13];
-        bool on[13];
-#pragma unroll
-        for (int q = 0; q < 13; ++q) {
-            int dx, dy, dz;
-            earlier_neighbour(q, dx, dy, dz);
-            const int ax = x + dx, ay = y + dy, az = z + dz;
-            const bool in = ax >= 0 && ax < nx && ay >= 0 && ay < ny && az >= 0;
-            nb[q] = in ? ax + nx * (ay + ny * az) : v;
-            on[q] = in && occ[nb[q]] != 0;
-        }
-        int32_t other[13];
-#pragma unroll
-        for (int q = 0; q < 13; ++q)
-            other[q] = on[q] ? slot[nb[q]] : (int32_t)c;
-#pragma unroll
-        for (int q = 0; q < 13; ++q)
-            if (other[q] != (int32_t)c)
-                unite_lds(P, L, (int32_t)c, other[q]);
-    }
-    __syncthreads();
-    for (uint32_t base = 0; base < n; base += kSmallThreads) {
-        const uint32_t c = base + threadIdx.x;
-        const bool act = c < n;
-        int32_t v = 0, r = 0;
-        if (act) {
-            v = L[c];
-            r = L[find_root(P, (int32_t)c)];
-            parent[v] = r;
-            if (r == v)
-                flag_root(sa.bits0, sa.bits1, (uint32_t)v);
-        }
-        int i, j, k;
-        coords_of(v, nx, ny, i, j, k);
-        accumulate_stats(sa.stats, act, r, i, j, k);
-    }
-    // one workgroup: the barrier orders the atomics above before the
-    // selection's (L2-coherent) loads of their results
-    __syncthreads();
-    select_roots<kSmallThreads, kJobs>(sa, fj);
-}
-
-// Global path: one thread per (listed sample, earlier neighbour).
-__global__ __launch_bounds__(kBlock) void ccl_unite_kernel(const uint8_t* __restrict__ occ,
-                                                           int32_t* __restrict__ parent,
-                                                           const int32_t* __restrict__ list,
-                                                           const uint32_t* __restrict__ count,
-                                                           int nx, int ny, int nz) {
-    (void)nz;
-    const uint32_t n = *count;
-    if (n <= (uint32_t)kLdsCap)
-        return;
-    unite_listed(occ, parent, list, n, nx, ny, (uint64_t)blockIdx.x * kBlock + threadIdx.x,
-                 (uint64_t)gridDim.x * kBlock);
-}
-
-__global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(int32_t* __restrict__ parent,
-                                                             int32_t* __restrict__ stats,
-                                                             const int32_t* __restrict__ list,
-                                                             const uint32_t* __restrict__ count,
-                                                             uint64_t* __restrict__ bits0,
-                                                             uint64_t* __restrict__ bits1, int nx,
-                                                             int ny) {
-    const uint32_t n = *count;
-    if (n <= (uint32_t)kLdsCap)
-        return;
-    flatten_listed(parent, stats, list, n, bits0, bits1, nx, ny, blockIdx.x * kBlock,
-                   gridDim.x * kBlock, threadIdx.x);
+    return true;
 }
 
 template <bool kJobs>
-__global__ __launch_bounds__(kSelectThreads) void ccl_select_kernel(const uint32_t* __restrict__ count,
-                                                                    const SelectArgs sa,
-                                                                    const FrameJobs fj) {
-    if (*count <= (uint32_t)kLdsCap)
-        return;
-    select_roots<kSelectThreads, kJobs>(sa, fj);
+__global__ __launch_bounds__(kLabelThreads) void label_runs_kernel(const LabelArgs a,
+                                                                   const FrameJobs fj) {
+    __shared__ int32_t s_rows[kRowCap];
+    __shared__ int32_t s_rs[kRowCap + 1];
+    __shared__ int32_t s_x0[kRunCap];
+    __shared__ int32_t s_x1[kRunCap];
+    __shared__ int32_t s_P[kRunCap];
+    __shared__ int32_t s_stats[kStatsRow * kRootCap + kRootCap];   // rows, then labels
+    __shared__ uint32_t s_scan[kLabelThreads / kWave];
+    const int32_t R = a.ny * a.nz;
+    const int32_t n_rm = (R + 63) / 64;
+    int32_t n_rows = 0;
+    for (int32_t base = 0; base < n_rm; base += kLabelThreads) {
+        const int32_t w = base + threadIdx.x;
+        const uint64_t bits = w < n_rm ? rowmask_word(a.rb, w, R) : 0ull;
+        uint32_t total;
+        (void)block_exclusive_sum<kLabelThreads>((uint32_t)__popcll(bits), s_scan, &total);
+        n_rows += (int32_t)total;
+    }
+    if (n_rows <= kRowCap) {
+        const RunArrays m{s_rows, s_rs, s_x0, s_x1, s_P};
+        if (label_body<true, kJobs>(a, fj, m, n_rows, s_stats, s_scan))
+            return;
+        __syncthreads();
+    }
+    label_body<false, kJobs>(a, fj, a.g, n_rows, s_stats, s_scan);
 }
 
-__global__ __launch_bounds__(kBlock) void ccl_write_kernel(const int32_t* __restrict__ parent,
-                                                           const int32_t* __restrict__ stats,
-                                                           uint8_t* __restrict__ occ,
-                                                           int32_t* __restrict__ labels,
-                                                           int32_t V) {
+// Row bitmap of an occupancy grid: one wave per (row, word), lane = bit.
+// Every word of the grid is stored (zeros included); rows with a set bit are
+// ORed into the (all-zero) row mask.
+__global__ __launch_bounds__(kBlock) void label_bitmap_kernel(const uint8_t* __restrict__ occ,
+                                                              int32_t nx, int64_t n_words,
+                                                              const RowBits rb) {
+    const int64_t word = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    if (word >= n_words)
+        return;
+    const int64_t row = word / rb.wr;
+    const int32_t x = (int32_t)(word - row * rb.wr) * kWave + lane_id();
+    const bool on = x < nx && occ[row * nx + x] != 0;
+    const uint64_t bits = __ballot(on);
+    if (lane_id() == 0) {
+        rb.words[word] = bits;
+        if (bits)
+            atomicOr((unsigned long long*)&rb.rowmask[row >> 6], 1ull << (row & 63));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void label_write_kernel(const int32_t* __restrict__ sample_label,
+                                                             uint8_t* __restrict__ occ,
+                                                             int32_t* __restrict__ labels,
+                                                             int32_t V) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= V)
         return;
     if (occ[v]) {
-        const int32_t lab = stats[(int64_t)kStatsRow * parent[v] + 7];
+        const int32_t lab = sample_label[v];
         labels[v] = lab;
         if (lab == 0)
             occ[v] = 0;
@@ -572,54 +557,41 @@ __global__ __launch_bounds__(kBlock) void ccl_write_kernel(const int32_t* __rest
     }
 }
 
-LabelSeed label_seed(fvv_ctx* ctx) {
-    return LabelSeed{ctx->d_parent, ctx->d_stats, ctx->d_list, ctx->d_slot, ctx->d_list_count};
+RowBits row_bits(fvv_ctx* ctx, const fvv_grid& g) {
+    return RowBits{ctx->d_rowbits, ctx->d_rowmask, (g.dims[0] + 63) / 64};
 }
 
 hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                         uint32_t t_np, uint32_t t_nb, fvv_roi* rois, uint32_t max_rois,
                         uint32_t* n_rois, bool seeded, const FrameJobs* frame, hipStream_t s) {
-    const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
-    const int32_t V = nx * ny * nz;
-    const unsigned vblocks = (unsigned)((V + kBlock - 1) / kBlock);
-    const unsigned lblocks = (unsigned)(ctx->n_cus * kListBlocksPerCU);
-    const LabelSeed seed = label_seed(ctx);
-    SelectArgs sa;
-    sa.V = V;
-    sa.bits0 = ctx->d_bits0;
-    sa.bits1 = ctx->d_bits1;
-    sa.words = ctx->d_words;
-    sa.stats = ctx->d_stats;
-    sa.t_np = t_np;
-    sa.t_nb = t_nb;
-    sa.rois = rois;
-    sa.max_rois = max_rois;
-    sa.n_rois = n_rois;
-    sa.list_count = ctx->d_list_count;
-    sa.status = ctx->d_status;
-    sa.pre = ctx->d_prefix;
-    sa.counter = ctx->d_counter;
-    sa.dcams = ctx->d_cams;
-    const FrameJobs fj = frame ? *frame : FrameJobs{};
-    if (!seeded)
-        hipLaunchKernelGGL(ccl_seed_kernel, dim3(vblocks), dim3(kBlock), 0, s, occ, V, seed);
-    if (frame) {
-        // a frame's list is labelled by one workgroup whatever its length
-        hipLaunchKernelGGL((ccl_small_kernel<true, true>), dim3(1), dim3(kSmallThreads), 0, s,
-                           occ, ctx->d_parent, ctx->d_list, ctx->d_slot, ctx->d_list_count, nx, ny,
-                           nz, sa, fj);
-    } else {
-        hipLaunchKernelGGL((ccl_small_kernel<false, false>), dim3(1), dim3(kSmallThreads), 0, s,
-                           occ, ctx->d_parent, ctx->d_list, ctx->d_slot, ctx->d_list_count, nx, ny,
-                           nz, sa, fj);
-        hipLaunchKernelGGL(ccl_unite_kernel, dim3(lblocks), dim3(kBlock), 0, s, occ,
-                           ctx->d_parent, ctx->d_list, ctx->d_list_count, nx, ny, nz);
-        hipLaunchKernelGGL(ccl_flatten_kernel, dim3(lblocks), dim3(kBlock), 0, s, ctx->d_parent,
-                           ctx->d_stats, ctx->d_list, ctx->d_list_count, ctx->d_bits0,
-                           ctx->d_bits1, nx, ny);
-        hipLaunchKernelGGL((ccl_select_kernel<false>), dim3(1), dim3(kSelectThreads), 0, s,
-                           ctx->d_list_count, sa, fj);
+    LabelArgs a;
+    a.rb = row_bits(ctx, g);
+    a.nx = g.dims[0];
+    a.ny = g.dims[1];
+    a.nz = g.dims[2];
+    a.g = RunArrays{ctx->d_rows, ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_runP};
+    a.gstats = ctx->d_stats;
+    a.sample_label = ctx->d_sample_label;
+    a.t_np = t_np;
+    a.t_nb = t_nb;
+    a.rois = rois;
+    a.max_rois = max_rois;
+    a.n_rois = n_rois;
+    a.status = ctx->d_status;
+    a.pre = ctx->d_prefix;
+    a.counter = ctx->d_counter;
+    a.dcams = ctx->d_cams;
+    if (!seeded) {
+        const int64_t n_words = (int64_t)a.ny * a.nz * a.rb.wr;
+        const int64_t blocks = (n_words * kWave + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(label_bitmap_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, occ,
+                           a.nx, n_words, a.rb);
     }
+    if (frame)
+        hipLaunchKernelGGL(label_runs_kernel<true>, dim3(1), dim3(kLabelThreads), 0, s, a, *frame);
+    else
+        hipLaunchKernelGGL(label_runs_kernel<false>, dim3(1), dim3(kLabelThreads), 0, s, a,
+                           FrameJobs{});
     if (!labels)
         return hipGetLastError();
     return launch_label_write(ctx, g, occ, labels, s);
@@ -630,8 +602,8 @@ hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int
                               hipStream_t s) {
     const int32_t V = g.dims[0] * g.dims[1] * g.dims[2];
     const unsigned vblocks = (unsigned)((V + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(ccl_write_kernel, dim3(vblocks), dim3(kBlock), 0, s, ctx->d_parent,
-                       ctx->d_stats, occ, labels, V);
+    hipLaunchKernelGGL(label_write_kernel, dim3(vblocks), dim3(kBlock), 0, s,
+                       ctx->d_sample_label, occ, labels, V);
     return hipGetLastError();
 }
 

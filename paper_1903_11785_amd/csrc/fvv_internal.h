@@ -13,7 +13,6 @@ namespace fvv {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;              // threads per workgroup everywhere
 constexpr int kEdgeChunk = 2048;         // fine samples per crossing-edge work item
-constexpr int kRootChunk = 16384;        // coarse samples per root-numbering block
 constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits
 
 // Projections of a camera rig passed by value in the kernel arguments.
@@ -244,29 +243,19 @@ __host__ __device__ inline uint32_t grab_size(uint64_t total_tiles, uint32_t blo
     return (uint32_t)(per < 1 ? 1 : (per > 0xffffffffull ? 0xffffffffull : per));
 }
 
-// ------------------------------------------------------------------ labelling seeds
-// Where the labelling stage starts: the list of occupied samples, and per
-// sample a union-find parent and a stats row (count, lo[3], hi[3], label).
-// The coarse carve of a frame fills these as it writes the occupancy.
-struct LabelSeed {
-    int32_t* parent;
-    int32_t* stats;
-    int32_t* list;
-    int32_t* slot;       // position of each occupied sample in the list
-    uint32_t* count;
+// ------------------------------------------------------------------ labelling input
+// Row bitmap of a coarse occupancy, the labelling's input: bit x of row
+// r = j + ny*k lies in word r*wr + x/64 (each row padded to whole words, the
+// bits past nx clear) and bit r of `rowmask` flags a row with a set bit.  Both
+// are all-zero between calls: producers OR bits in, the labelling clears what
+// it read.
+struct RowBits {
+    uint64_t* words;
+    uint64_t* rowmask;
+    int32_t wr;          // words per row, ceil(nx / 64)
 };
 
-constexpr int kStatsRow = 8;
-
-// Append occupied sample lin at list position pos.
-__device__ __forceinline__ void seed_sample(const LabelSeed& s, int32_t lin, uint32_t pos) {
-    s.list[pos] = lin;
-    s.slot[lin] = (int32_t)pos;
-    s.parent[lin] = lin;
-    int4* row = reinterpret_cast<int4*>(s.stats + (int64_t)kStatsRow * lin);
-    row[0] = make_int4(0, 0x7fffffff, 0x7fffffff, 0x7fffffff);
-    row[1] = make_int4(-1, -1, -1, 0);
-}
+constexpr int kStatsRow = 8;   // per component: count, lo[3], hi[3], smallest linear index
 
 // ------------------------------------------------------------------ device-side job prefix data
 // Per job of a batched carve / surface: first carving tile and first
@@ -301,14 +290,15 @@ struct fvv_ctx {
     uint32_t* d_status;          // sticky flags
     uint32_t* d_counter;         // persistent carve: [0] next item, [1] grab size, [2] jobs
     // labelling
-    int32_t* d_parent;           // union-find forest over the occupied coarse samples
-    int32_t* d_stats;            // per sample (used at roots): count, lo[3], hi[3], label
-    int32_t* d_list;             // occupied coarse samples
-    int32_t* d_slot;             // list position of each occupied coarse sample
-    uint32_t* d_list_count;      // their number (reset by the selection kernel)
-    uint64_t* d_bits0;           // root flags, one bit per coarse sample
-    uint64_t* d_bits1;           // one bit per non-zero word of d_bits0
-    uint32_t* d_words;           // non-zero d_bits0 words in ascending order
+    uint64_t* d_rowbits;         // row bitmap of the coarse occupancy (RowBits)
+    uint64_t* d_rowmask;         // rows with a set bit
+    int32_t* d_rows;             // listed rows, run starts per row, run extents and
+    int32_t* d_rs;               // union-find forest over runs: the global twins of the
+    int32_t* d_x0;               // labelling workgroup's LDS arrays, used when those
+    int32_t* d_x1;               // are too small
+    int32_t* d_runP;
+    int32_t* d_stats;            // per component: kStatsRow ints, then one label each
+    int32_t* d_sample_label;     // label of every occupied coarse sample
     // batched carve / frame
     fvv::JobPrefix* d_prefix;    // per job (max(max_jobs, max_rois) + 1)
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
@@ -345,11 +335,12 @@ struct FrameJobs {
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils, hipStream_t s);
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g,
-                        TileShape t, uint8_t* occ, const LabelSeed* seed, hipStream_t s);
+                        TileShape t, uint8_t* occ, const RowBits* rows, hipStream_t s);
 hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jobs,
                                 const fvv_camera* cams, const uint32_t* sils, uint8_t* out,
                                 TileShape t, int blocks, bool jobs_prepared, hipStream_t s);
-LabelSeed label_seed(fvv_ctx* ctx);
+RowBits row_bits(fvv_ctx* ctx, const fvv_grid& g);
+// seeded: the row bitmap is already filled (by the coarse carve of a frame).
 // labels == nullptr: stop before the grid pass (launch_label_write does it).
 hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                         uint32_t t_np, uint32_t t_nb, fvv_roi* rois, uint32_t max_rois,
