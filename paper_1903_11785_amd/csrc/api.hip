@@ -179,10 +179,11 @@ void fvv_destroy(fvv_ctx* ctx) {
     if (!ctx)
         return;
     hipDeviceSynchronize();
-    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_rowbits, ctx->d_rowmask, ctx->d_rows,
-                    ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_runP, ctx->d_stats,
+    void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_rowbits, ctx->d_rowmask, ctx->d_rmpre,
+                    ctx->d_rows, ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_rrow, ctx->d_runP,
+                    ctx->d_stats,
                     ctx->d_sample_label, ctx->d_prefix,
-                    ctx->d_job_single, ctx->d_cams, ctx->d_item_cnt, ctx->d_item_base,
+                    ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
                     ctx->d_point_off_single, ctx->d_counts_single};
     for (void* p : ptrs)
         if (p)
@@ -222,7 +223,11 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     const int64_t V = lim->max_coarse;
     const int64_t n_rowbits = V + V / 64 + 1, n_rowmask = V / 64 + 1;
     c->job_cap = (int64_t)(lim->max_jobs > lim->max_rois ? lim->max_jobs : lim->max_rois) + 2;
-    c->item_cap = lim->max_fine / kEdgeChunk + (int64_t)lim->max_rois + 2;
+    // fine bitmaps: rows padded to whole words cost at most 1/4 + 1/64 word per
+    // sample for lattices at least 4 samples wide (every frame ROI spans three
+    // coarse cells); a single lattice of fvv_surface must fit as well
+    c->bit_cap = lim->max_fine / 4 + lim->max_fine / 64 + (int64_t)lim->max_rois + 1;
+    c->item_cap = c->bit_cap / kEdgeWords + (int64_t)lim->max_rois + 2;
     hipError_t e = hipSuccess;
 #define A(ptr, n)                  \
     if (e == hipSuccess)           \
@@ -231,18 +236,20 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_counter, 4)
     A(d_rowbits, n_rowbits)
     A(d_rowmask, n_rowmask)
+    A(d_rmpre, n_rowmask)
     A(d_rows, V)
     A(d_rs, V + 1)
     A(d_x0, V)
     A(d_x1, V)
+    A(d_rrow, V)
     A(d_runP, V)
     A(d_stats, (int64_t)(kStatsRow + 1) * V)
     A(d_sample_label, V)
     A(d_prefix, c->job_cap)
     A(d_job_single, 1)
     A(d_cams, FVV_MAX_CAMS)
+    A(d_finebits, c->bit_cap)
     A(d_item_cnt, c->item_cap)
-    A(d_item_base, c->item_cap)
     A(d_point_off_single, 2)
     A(d_counts_single, 4)
 #undef A
@@ -362,7 +369,8 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
         n_steps < 1 || n_steps > FVV_MAX_STEPS || !cams_ok(ctx, n_cams, cams) ||
         !grid_ok(roi, 1 << (23 - n_steps)))
         return FVV_EINVAL;
-    if (grid_samples(*roi) > ctx->lim.max_fine || grid_samples(*roi) > 1431655765LL)
+    if (grid_samples(*roi) > ctx->lim.max_fine || grid_samples(*roi) > 1431655765LL ||
+        fine_bitmap_words(*roi) > ctx->bit_cap)
         return FVV_EINVAL;
     const CamSet cs = make_camset(n_cams, cams, roi);
     fvv_job job;
@@ -371,7 +379,7 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
     job.n_cams = n_cams;
     job.width = cs.W;
     job.height = cs.H;
-    hipError_t e = launch_surface_prepare_single(ctx, job, stream);
+    hipError_t e = launch_surface_prepare_single(ctx, job, d_occ_fine, stream);
     if (e == hipSuccess)
         e = launch_surface(ctx, ctx->d_job_single, ctx->d_counts_single + 3, 1, d_occ_fine, cs,
                            d_sils, n_steps, d_keys, d_xyz, max_points, ctx->d_point_off_single,
@@ -385,7 +393,7 @@ fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_job
     if (!ctx || !d_jobs || !d_cams || !d_sils || !d_occ_out || n_jobs < 1 ||
         n_jobs > ctx->lim.max_jobs || !tile_ok(tile))
         return FVV_EINVAL;
-    return dev(launch_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out,
+    return dev(launch_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out, nullptr,
                                     tile_of(tile), persistent_blocks(ctx, tile), false, stream));
 }
 
@@ -455,6 +463,7 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     fj.tile_x = ft.tx;
     fj.tile_z = ft.tz;
     fj.blocks = (uint32_t)blocks;
+    fj.bit_cap = ctx->bit_cap;
     if (e == hipSuccess)
         e = launch_label(ctx, p->coarse, o->d_occ_coarse, nullptr, p->t_np, p->t_nb, o->d_rois,
                          o->max_rois, o->d_counts + 0, true, &fj, stream);
@@ -470,8 +479,8 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev_join, ctx->side);
     if (e == hipSuccess)
-        e = launch_carve_batched(ctx, o->d_jobs, 0, ctx->d_cams, d_sils, o->d_occ_fine, ft, blocks,
-                                 true, stream);
+        e = launch_carve_frame(ctx, o->d_jobs, cs, d_sils, o->d_occ_fine, ctx->d_finebits, ft,
+                               blocks, stream);
     mark(4);
     if (e == hipSuccess)
         e = launch_surface(ctx, o->d_jobs, o->d_counts + 3, o->max_rois, o->d_occ_fine, cs, d_sils,

@@ -84,12 +84,17 @@ __device__ __forceinline__ void lds_append(bool pred, uint16_t val, uint16_t* li
         list[base + lane_rank(m)] = val;
 }
 
+// Where the carve also writes its occupancy as bits: nowhere, ORed into the
+// labelling's row bitmap (RowBits, all-zero before), or stored into a fine
+// bitmap (rows padded to words, every word of the lattice written).
+constexpr int kBitsNone = 0, kBitsLabel = 1, kBitsFine = 2;
+
 // Carve tile `tile` of lattice g.  getP(c) returns camera c's 12 floats (a
-// wave-uniform address); sil_of(c) its silhouette rows.  With kRows, the
-// occupancy is also ORed into the labelling's row bitmap: the TX lanes of one
-// tile row cover TX consecutive x inside one bitmap word (TX divides 64), so
-// each tile row costs one atomic, and none where it is empty.
-template <int TX, int TZ, bool kRows, typename GetP, typename GetSil>
+// wave-uniform address); sil_of(c) its silhouette rows.  The TX lanes of one
+// tile row cover TX consecutive x inside one bitmap word (TX divides 64), so a
+// tile row's bits cost one atomic (kBitsLabel, none where the row is empty)
+// or one store (kBitsFine).
+template <int TX, int TZ, int kBits, typename GetP, typename GetSil>
 __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, int W, int H,
                                            int wpr, const fvv_grid& g, uint64_t tile,
                                            uint8_t* __restrict__ out, const RowBits& rb) {
@@ -182,16 +187,24 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
         const uint32_t bit = (s_alive[s >> 5] >> (s & 31)) & 1u;
         if (valid)
             out[(uint64_t)k * plane + (uint64_t)j * g.dims[0] + i] = (uint8_t)bit;
-        if (kRows) {
+        if (kBits != kBitsNone) {
             // lanes [TX*q, TX*q + TX) of the wave hold one tile row (lx = 0..TX-1)
             const uint64_t m = __ballot(valid && bit != 0u);
             const int q = lane_id() / TX;
             const uint64_t bits = TX == 64 ? m : (m >> (q * TX)) & ((1ull << (TX & 63)) - 1);
-            if (lx == 0 && bits != 0) {
-                const int64_t row = (int64_t)j + (int64_t)g.dims[1] * k;
-                atomicOr((unsigned long long*)&rb.words[row * rb.wr + (i0 >> 6)],
-                         (unsigned long long)(bits << (i0 & 63)));
+            const int64_t row = (int64_t)j + (int64_t)g.dims[1] * k;
+            uint64_t* word = rb.words + row * rb.wr + (i0 >> 6);
+            if (kBits == kBitsLabel && lx == 0 && bits != 0) {
+                atomicOr((unsigned long long*)word, (unsigned long long)(bits << (i0 & 63)));
                 atomicOr((unsigned long long*)&rb.rowmask[row >> 6], 1ull << (row & 63));
+            }
+            if (kBits == kBitsFine && lx == 0 && j < g.dims[1] && k < g.dims[2]) {
+                if (TX == 64)
+                    *word = bits;
+                else if (TX == 32)
+                    reinterpret_cast<uint32_t*>(word)[(i0 >> 5) & 1] = (uint32_t)bits;
+                else
+                    reinterpret_cast<uint16_t*>(word)[(i0 >> 4) & 3] = (uint16_t)bits;
             }
         }
     }
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void carve_kernel(const CamSet cams,
                                                        const fvv_grid g, uint8_t* __restrict__ occ,
                                                        const RowBits rb) {
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-    carve_tile<TX, TZ, kRows>([&](int c) { return &cams.P[c][0]; },
+    carve_tile<TX, TZ, kRows ? kBitsLabel : kBitsNone>([&](int c) { return &cams.P[c][0]; },
                               [&](int c) { return sils + c * cam_words; }, cams.n, cams.W, cams.H,
                               cams.wpr, g, blockIdx.x, occ, rb);
 }
@@ -245,16 +258,15 @@ __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* 
     }
 }
 
-template <int TX, int TZ>
+template <int TX, int TZ, bool kFineBits>
 __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
     const fvv_job* __restrict__ jobs, const JobPrefix* __restrict__ pre,
     uint32_t* __restrict__ counter, const fvv_camera* __restrict__ cams,
-    const uint32_t* __restrict__ sils, uint8_t* __restrict__ out) {
+    const uint32_t* __restrict__ sils, uint8_t* __restrict__ out, uint64_t* __restrict__ finebits) {
     __shared__ uint32_t s_item;
     const uint32_t nj = counter[2];
     const uint64_t per = counter[1];
     const uint64_t total = pre[nj].tile_off;
-    const RowBits no_rows{};
     for (;;) {
         if (threadIdx.x == 0)
             s_item = atomicAdd(&counter[0], 1u);
@@ -271,12 +283,285 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
             const int64_t cam_words = (int64_t)job.height * wpr;
             const fvv_camera* jc = cams + job.cam_base;
             const uint32_t* js = sils + job.sil_base;
-            carve_tile<TX, TZ, false>([&](int c) { return &jc[c].P[0]; },
-                                      [&](int c) { return js + c * cam_words; }, job.n_cams,
-                                      job.width, job.height, wpr, job.grid, t - pre[jb].tile_off,
-                                      out + job.out_offset, no_rows);
+            RowBits fb{};
+            if (kFineBits) {
+                fb.words = finebits + pre[jb].bit_off;
+                fb.wr = (job.grid.dims[0] + 63) / 64;
+            }
+            carve_tile<TX, TZ, kFineBits ? kBitsFine : kBitsNone>(
+                [&](int c) { return &jc[c].P[0]; }, [&](int c) { return js + c * cam_words; },
+                job.n_cams, job.width, job.height, wpr, job.grid, t - pre[jb].tile_off,
+                out + job.out_offset, fb);
         }
     }
+}
+
+// ------------------------------------------------------------------ frame fine carve, culled
+// The fine carve of a frame classifies cameras per box of lattice samples
+// before testing samples.  The projections of a box's samples lie in the
+// convex hull of its eight corner projections (w > 0 over the whole lattice
+// box wherever the rounding pad is finite), and the pad bounds how far a
+// sample's floored quotient and the corners' rcp quotients can be from the
+// real projections; so every sample's pixel lies in the corners' pixel
+// rectangle widened by the pad.  If that rectangle holds no foreground pixel
+// of the image, the camera rejects every sample of the box; if it lies inside
+// the image and is all foreground, it accepts every sample.  Otherwise the
+// camera is mixed for the box and its samples are tested one by one.  A tile
+// (TX x TY x 4) is classified as 16 sub-blocks of 4 x 4 x 4 samples, one
+// (sub-block, camera) pair per thread; one wave then carves one sub-block,
+// lane = sample, testing only the sub-block's mixed cameras.  Results are
+// identical to testing every camera: the skipped tests are decided by the
+// rectangles.
+constexpr int kCullMixed = 0, kCullAccept = 1, kCullReject = 2;
+
+// Classification of camera c for the box of samples with world corners lo,
+// hi: rectangles of more than kRows rows or kWords silhouette words count as
+// mixed.
+template <int kRows, int kWords>
+__device__ __forceinline__ int classify_box(const CamSet& cams, int c,
+                                            const uint32_t* __restrict__ sil, const float* lo,
+                                            const float* hi) {
+    const float pad = cams.pad[c];
+    if (!(pad < 1.0f))
+        return kCullMixed;
+    const float* P = &cams.P[c][0];
+    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float X = (k & 1) ? hi[0] : lo[0];
+        const float Y = (k & 2) ? hi[1] : lo[1];
+        const float Z = (k & 4) ? hi[2] : lo[2];
+        const float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
+        const float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
+        const float w = __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
+        const float r = __builtin_amdgcn_rcpf(w);
+        const float qa = a * r, qb = b * r;
+        x0 = fminf(x0, qa);
+        x1 = fmaxf(x1, qa);
+        y0 = fminf(y0, qb);
+        y1 = fmaxf(y1, qb);
+    }
+    const float W = (float)cams.W, H = (float)cams.H;
+    // pixel bounds, clamped a little outside the image (keeps the conversions exact)
+    const int px0 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(x0 - pad, -2.0f, W + 1.0f));
+    const int px1 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(x1 + pad, -2.0f, W + 1.0f));
+    const int py0 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(y0 - pad, -2.0f, H + 1.0f));
+    const int py1 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(y1 + pad, -2.0f, H + 1.0f));
+    const bool inside = px0 >= 0 && py0 >= 0 && px1 < cams.W && py1 < cams.H;
+    const int cx0 = max(px0, 0), cx1 = min(px1, cams.W - 1);
+    const int cy0 = max(py0, 0), cy1 = min(py1, cams.H - 1);
+    if (cx0 > cx1 || cy0 > cy1)
+        return kCullReject;                    // every sample projects off the image
+    const int w0 = cx0 >> 5, w1 = cx1 >> 5;
+    if (cy1 - cy0 >= kRows || w1 - w0 >= kWords)
+        return kCullMixed;
+    bool any = false, all = true;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const bool row_on = r <= cy1 - cy0;
+        const uint32_t* row = sil + (row_on ? cy0 + r : cy0) * cams.wpr;
+#pragma unroll
+        for (int q = 0; q < kWords; ++q) {
+            const int wq = w0 + q;
+            const bool on = row_on && wq <= w1;
+            const uint32_t lo_m = wq == w0 ? ~0u << (cx0 & 31) : ~0u;
+            const uint32_t hi_m = wq == w1 ? (~0u >> (31 - (cx1 & 31))) : ~0u;
+            const uint32_t m = on ? (lo_m & hi_m) : 0u;
+            const uint32_t v = row[on ? wq : w0];
+            any |= (v & m) != 0u;
+            all &= (v & m) == m;
+        }
+    }
+    if (!any)
+        return kCullReject;
+    return (inside && all) ? kCullAccept : kCullMixed;
+}
+
+// World corners of the samples [i0, i1] x [j0, j1] x [k0, k1] of lattice g.
+__device__ __forceinline__ void box_corners(const fvv_grid& g, int i0, int i1, int j0, int j1,
+                                            int k0, int k1, float* lo, float* hi) {
+    lo[0] = lattice_coord(g.lo[0] + i0, g.h, g.origin[0]);
+    hi[0] = lattice_coord(g.lo[0] + i1, g.h, g.origin[0]);
+    lo[1] = lattice_coord(g.lo[1] + j0, g.h, g.origin[1]);
+    hi[1] = lattice_coord(g.lo[1] + j1, g.h, g.origin[1]);
+    lo[2] = lattice_coord(g.lo[2] + k0, g.h, g.origin[2]);
+    hi[2] = lattice_coord(g.lo[2] + k1, g.h, g.origin[2]);
+}
+
+template <int TX>
+__device__ __forceinline__ void carve_tile_culled(const CamSet& cams,
+                                                  const uint32_t* __restrict__ sils,
+                                                  const fvv_grid& g, uint64_t tile,
+                                                  uint8_t* __restrict__ out, const RowBits& rb) {
+    constexpr int TY = kBlock / TX, TZ = 4;
+    constexpr int TV = TX * TY * TZ;
+    constexpr int SBX = TX / 4;                 // sub-blocks along x (16 in all)
+    constexpr int LX = log2_of(TX), LY = log2_of(TY);
+    __shared__ uint8_t s_occ[TV];
+    __shared__ uint32_t s_mixed[16];
+    __shared__ uint32_t s_reject;
+    const int64_t cam_words = (int64_t)cams.H * cams.wpr;
+
+    const int ntx = (g.dims[0] + TX - 1) / TX;
+    const int nty = (g.dims[1] + TY - 1) / TY;
+    const int bx = (int)(tile % (uint64_t)ntx);
+    const uint64_t rq = tile / (uint64_t)ntx;
+    const int by = (int)(rq % (uint64_t)nty);
+    const int bz = (int)(rq / (uint64_t)nty);
+    const int i0 = bx * TX, j0 = by * TY, k0 = bz * TZ;
+
+    __syncthreads();   // the previous tile of this workgroup is done with the LDS
+    if (threadIdx.x < 16)
+        s_mixed[threadIdx.x] = 0;
+    if (threadIdx.x == 0)
+        s_reject = 0;
+    __syncthreads();
+    const int tk1 = min(k0 + TZ, g.dims[2]) - 1;
+    for (int p = threadIdx.x; p < 16 * cams.n; p += kBlock) {
+        const int b = p & 15, c = p >> 4;
+        const int si0 = i0 + (b % SBX) * 4, sj0 = j0 + (b / SBX) * 4;
+        if (si0 >= g.dims[0] || sj0 >= g.dims[1])
+            continue;
+        float lo[3], hi[3];
+        box_corners(g, si0, min(si0 + 4, g.dims[0]) - 1, sj0, min(sj0 + 4, g.dims[1]) - 1, k0, tk1,
+                    lo, hi);
+        const int cl = classify_box<6, 2>(cams, c, sils + c * cam_words, lo, hi);
+        if (cl == kCullReject)
+            atomicOr(&s_reject, 1u << b);
+        else if (cl == kCullMixed)
+            atomicOr(&s_mixed[b], 1u << c);
+    }
+    __syncthreads();
+    // one wave per sub-block, lane = sample (x fastest, then y, then z)
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    for (int b = wave; b < 16; b += kBlock / kWave) {
+        const int lx = (b % SBX) * 4 + (lane & 3);
+        const int ly = (b / SBX) * 4 + ((lane >> 2) & 3);
+        const int lz = lane >> 4;
+        const bool valid = i0 + lx < g.dims[0] && j0 + ly < g.dims[1] && k0 + lz < g.dims[2];
+        bool alive = valid && !((s_reject >> b) & 1u);
+        if (__ballot(alive) != 0) {
+            const float X = lattice_coord(g.lo[0] + i0 + lx, g.h, g.origin[0]);
+            const float Y = lattice_coord(g.lo[1] + j0 + ly, g.h, g.origin[1]);
+            const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
+            // wave-uniform: the sub-block's mixed cameras, two per pass (the
+            // second repeats the first when one is left)
+            uint32_t rest = s_mixed[b];
+            while (rest && __ballot(alive) != 0) {
+                const int ca = __ffs(rest) - 1;
+                rest &= rest - 1;
+                int cb = ca;
+                if (rest) {
+                    cb = __ffs(rest) - 1;
+                    rest &= rest - 1;
+                }
+                const float* P2[2] = {&cams.P[ca][0], &cams.P[cb][0]};
+                const uint32_t* S2[2] = {sils + ca * cam_words, sils + cb * cam_words};
+                alive = alive && group_inside<2>(P2, X, Y, Z, S2, cams.W, cams.H, cams.wpr);
+            }
+        }
+        s_occ[lx + TX * (ly + TY * lz)] = alive ? 1 : 0;
+    }
+    __syncthreads();
+    const uint64_t plane = (uint64_t)g.dims[0] * (uint64_t)g.dims[1];
+#pragma unroll
+    for (int rr = 0; rr < TZ; ++rr) {
+        const int s = rr * kBlock + (int)threadIdx.x;
+        const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
+        const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
+        const bool valid = i < g.dims[0] && j < g.dims[1] && k < g.dims[2];
+        const uint8_t bit = s_occ[s];
+        if (valid)
+            out[(uint64_t)k * plane + (uint64_t)j * g.dims[0] + i] = bit;
+        // fine bitmap: lanes [TX*q, TX*q + TX) of the wave hold one tile row
+        const uint64_t m = __ballot(valid && bit != 0);
+        const int q = lane_id() / TX;
+        const uint64_t bits = TX == 64 ? m : (m >> (q * TX)) & ((1ull << (TX & 63)) - 1);
+        if (rb.words && lx == 0 && j < g.dims[1] && k < g.dims[2]) {
+            uint64_t* word = rb.words + ((int64_t)j + (int64_t)g.dims[1] * k) * rb.wr + (i0 >> 6);
+            if (TX == 64)
+                *word = bits;
+            else if (TX == 32)
+                reinterpret_cast<uint32_t*>(word)[(i0 >> 5) & 1] = (uint32_t)bits;
+            else
+                reinterpret_cast<uint16_t*>(word)[(i0 >> 4) & 3] = (uint16_t)bits;
+        }
+    }
+}
+
+// The fine carve of a frame: a static, XCD-aware partition of the tiles of
+// all carried ROIs (contiguous tile ranges per XCD keep each L2's share of the
+// silhouettes small); cameras and rounding pads of the frame by value.  Job
+// tables of up to kJobLds ROIs are kept in LDS for the tile -> job search.
+constexpr int kJobLds = 64;
+
+template <int TX>
+__global__ __launch_bounds__(kBlock, 6) void carve_frame_kernel(const fvv_job* __restrict__ jobs,
+                                                             const JobPrefix* __restrict__ pre,
+                                                             const uint32_t* __restrict__ counter,
+                                                             const CamSet cams,
+                                                             const uint32_t* __restrict__ sils,
+                                                             uint8_t* __restrict__ out,
+                                                             uint64_t* __restrict__ finebits) {
+    __shared__ uint64_t s_tile_off[kJobLds + 1];
+    __shared__ uint64_t s_bit_off[kJobLds];
+    __shared__ int64_t s_out[kJobLds];
+    __shared__ fvv_grid s_grid[kJobLds];
+    const int nj = (int)counter[2];
+    const bool lds = nj <= kJobLds;
+    if (lds)
+        for (int j = threadIdx.x; j <= nj; j += kBlock) {
+            s_tile_off[j] = pre[j].tile_off;
+            if (j < nj) {
+                s_bit_off[j] = pre[j].bit_off;
+                s_out[j] = jobs[j].out_offset;
+                s_grid[j] = jobs[j].grid;
+            }
+        }
+    __syncthreads();
+    const uint64_t total = lds ? s_tile_off[nj] : pre[nj].tile_off;
+    const XcdSlice xs = xcd_slice(total);
+    for (uint64_t t = xs.begin + xs.slot; t < xs.end; t += xs.stride) {
+        int jb;
+        fvv_grid g;
+        int64_t out_off;
+        uint64_t tile0, bit_off;
+        if (lds) {
+            jb = upper_job([&](int m) { return s_tile_off[m]; }, nj, t);
+            g = s_grid[jb];
+            out_off = s_out[jb];
+            tile0 = s_tile_off[jb];
+            bit_off = s_bit_off[jb];
+        } else {
+            jb = upper_job([&](int m) { return pre[m].tile_off; }, nj, t);
+            g = jobs[jb].grid;
+            out_off = jobs[jb].out_offset;
+            tile0 = pre[jb].tile_off;
+            bit_off = pre[jb].bit_off;
+        }
+        RowBits fb{};
+        fb.words = finebits + bit_off;
+        fb.wr = (g.dims[0] + 63) / 64;
+        carve_tile_culled<TX>(cams, sils, g, t - tile0, out + out_off, fb);
+    }
+}
+
+hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& cams,
+                              const uint32_t* sils, uint8_t* out, uint64_t* finebits, TileShape t,
+                              int blocks, hipStream_t s) {
+    if (t.tz != 4)
+        return launch_carve_batched(ctx, jobs, 0, ctx->d_cams, sils, out, finebits, t, blocks,
+                                    true, s);
+    blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+#define X(TXV)                                                                                 \
+    if (t.tx == TXV) {                                                                         \
+        hipLaunchKernelGGL((carve_frame_kernel<TXV>), dim3(blocks), dim3(kBlock), 0, s, jobs,  \
+                           ctx->d_prefix, ctx->d_counter, cams, sils, out, finebits);          \
+        return hipGetLastError();                                                              \
+    }
+    X(64) X(32) X(16)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -309,15 +594,22 @@ hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid
 
 hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jobs,
                                 const fvv_camera* cams, const uint32_t* sils, uint8_t* out,
-                                TileShape t, int blocks, bool jobs_prepared, hipStream_t s) {
-#define X(TXV, TZV)                                                                            \
-    if (t.tx == TXV && t.tz == TZV) {                                                          \
-        if (!jobs_prepared)                                                                    \
-            hipLaunchKernelGGL((batched_prepare_kernel<TXV, TZV>), dim3(1), dim3(kBlock), 0, s, \
-                               jobs, n_jobs, ctx->d_prefix, ctx->d_counter, (uint32_t)blocks);  \
-        hipLaunchKernelGGL((carve_persistent_kernel<TXV, TZV>), dim3(blocks), dim3(kBlock), 0, \
-                           s, jobs, ctx->d_prefix, ctx->d_counter, cams, sils, out);           \
-        return hipGetLastError();                                                              \
+                                uint64_t* finebits, TileShape t, int blocks, bool jobs_prepared,
+                                hipStream_t s) {
+#define X(TXV, TZV)                                                                             \
+    if (t.tx == TXV && t.tz == TZV) {                                                           \
+        if (!jobs_prepared)                                                                     \
+            hipLaunchKernelGGL((batched_prepare_kernel<TXV, TZV>), dim3(1), dim3(kBlock), 0, s,  \
+                               jobs, n_jobs, ctx->d_prefix, ctx->d_counter, (uint32_t)blocks);   \
+        if (finebits)                                                                           \
+            hipLaunchKernelGGL((carve_persistent_kernel<TXV, TZV, true>), dim3(blocks),          \
+                               dim3(kBlock), 0, s, jobs, ctx->d_prefix, ctx->d_counter, cams,    \
+                               sils, out, finebits);                                            \
+        else                                                                                    \
+            hipLaunchKernelGGL((carve_persistent_kernel<TXV, TZV, false>), dim3(blocks),         \
+                               dim3(kBlock), 0, s, jobs, ctx->d_prefix, ctx->d_counter, cams,    \
+                               sils, out, finebits);                                            \
+        return hipGetLastError();                                                               \
     }
     FVV_TILE_CASES(X)
 #undef X

@@ -87,18 +87,19 @@ constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
 
 // Map each ROI to its fine lattice (integer micrometres, one-coarse-cell
 // dilation, clamped to the coarse lattice's extent), lay the carried ROIs out
-// back to back in the fine occupancy buffer (the longest prefix that fits
-// max_fine), and build the tile and work-item prefixes of the batched carve
-// and the surface passes.  counts: [0] K, [1] fine samples, [3] ROIs carried.
-template <int NT>
-__device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
-                                                const fvv_roi* __restrict__ rois, uint32_t K_all,
+// back to back in the fine occupancy buffer and the fine bitmap scratch (the
+// longest prefix that fits both), and build the tile and work-item prefixes of
+// the batched carve and the surface passes.  box(t, lo, hi) gives ROI t's
+// coarse box.  counts: [0] K, [1] fine samples, [3] ROIs carried.
+template <int NT, typename Box>
+__device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, uint32_t K_all,
                                                 uint32_t max_rois, JobPrefix* __restrict__ pre,
                                                 uint32_t* __restrict__ counter,
                                                 fvv_camera* __restrict__ dcams,
                                                 uint32_t* __restrict__ status) {
     __shared__ uint64_t scratch[NT / kWave];
-    __shared__ uint64_t c_vox, c_tiles, c_items;
+    __shared__ uint64_t c_vox, c_bits, c_tiles, c_items;   // running totals over whole chunks
+    __shared__ uint64_t e_vox, e_tiles, e_items;           // totals over the carried ROIs
     __shared__ uint32_t carried;
     for (int c = threadIdx.x; c < fj.cams.n; c += NT) {
         fvv_camera cam;
@@ -110,7 +111,8 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
     }
     const uint32_t K = K_all < max_rois ? K_all : max_rois;
     if (threadIdx.x == 0) {
-        c_vox = c_tiles = c_items = 0;
+        c_vox = c_bits = c_tiles = c_items = 0;
+        e_vox = e_tiles = e_items = 0;
         carried = K;
     }
     __syncthreads();
@@ -119,12 +121,13 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
         fvv_grid fg;
         int64_t V = 0;
         if (t < K) {
-            const fvv_roi r = rois[t];
+            int32_t lo[3], hi[3];
+            box(t, lo, hi);
             V = 1;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int64_t A = (int64_t)fj.coarse.lo[a] + r.lo[a] - 1;
-                const int64_t B = (int64_t)fj.coarse.lo[a] + r.hi[a] + 1;
+                const int64_t A = (int64_t)fj.coarse.lo[a] + lo[a] - 1;
+                const int64_t B = (int64_t)fj.coarse.lo[a] + hi[a] + 1;
                 int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um);
                 int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um);
                 const int64_t fmin = ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um);
@@ -139,13 +142,21 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
             }
             fg.h = fj.h_fine;
         }
-        uint64_t tot_v;
+        const uint64_t words = t < K ? (uint64_t)fine_bitmap_words(fg) : 0;
+        uint64_t tot_v, tot_b;
         const uint64_t ex_v = block_exclusive_sum64<NT>((uint64_t)V, scratch, &tot_v);
+        const uint64_t ex_b = block_exclusive_sum64<NT>(words, scratch, &tot_b);
         const uint64_t off = c_vox + ex_v;
-        const bool fits = t < K && off + (uint64_t)V <= (uint64_t)fj.max_fine &&
-                          V <= kMaxKeyedSamples && t < carried;
+        const uint64_t boff = c_bits + ex_b;
+        // the carried ROIs are the prefix before the first one that does not fit
+        if (t < K && (off + (uint64_t)V > (uint64_t)fj.max_fine || V > kMaxKeyedSamples ||
+                      boff + words > (uint64_t)fj.bit_cap))
+            atomicMin(&carried, t);
+        __syncthreads();
+        const uint32_t n = carried;
+        const bool fits = t < n;
         const uint64_t tiles = fits ? tiles_of_grid(fg, fj.tile_x, fj.tile_z) : 0;
-        const uint64_t items = fits ? ((uint64_t)V + kEdgeChunk - 1) / kEdgeChunk : 0;
+        const uint64_t items = fits ? (words + kEdgeWords - 1) / kEdgeWords : 0;
         uint64_t tot_t, tot_i;
         const uint64_t ex_t = block_exclusive_sum64<NT>(tiles, scratch, &tot_t);
         const uint64_t ex_i = block_exclusive_sum64<NT>(items, scratch, &tot_i);
@@ -160,36 +171,34 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
             j.out_offset = (int64_t)off;
             fj.jobs[t] = j;
             pre[t].tile_off = c_tiles + ex_t;
+            pre[t].bit_off = boff;
             pre[t].item_off = (uint32_t)(c_items + ex_i);
+            if (t + 1 == n) {
+                e_vox = off + (uint64_t)V;
+                e_tiles = c_tiles + ex_t + tiles;
+                e_items = c_items + ex_i + items;
+            }
         }
-        if (t < K && !fits)
-            atomicMin(&carried, t);     // the carried ROIs are the prefix that fits
         __syncthreads();
         if (threadIdx.x == 0) {
             c_vox += tot_v;
+            c_bits += tot_b;
             c_tiles += tot_t;
             c_items += tot_i;
         }
         __syncthreads();
+        if (n < base + NT)
+            break;
     }
     if (threadIdx.x == 0) {
         const uint32_t n = carried;
-        uint64_t vox = 0, tiles = 0, items = 0;   // totals over the carried prefix
-        if (n > 0) {
-            const fvv_job& last = fj.jobs[n - 1];
-            const uint64_t Vl =
-                (uint64_t)last.grid.dims[0] * last.grid.dims[1] * last.grid.dims[2];
-            vox = (uint64_t)last.out_offset + Vl;
-            tiles = pre[n - 1].tile_off + tiles_of_grid(last.grid, fj.tile_x, fj.tile_z);
-            items = pre[n - 1].item_off + (Vl + kEdgeChunk - 1) / kEdgeChunk;
-        }
-        pre[n].tile_off = tiles;
-        pre[n].item_off = (uint32_t)items;
+        pre[n].tile_off = e_tiles;
+        pre[n].item_off = (uint32_t)e_items;
         fj.counts[0] = K_all;
-        fj.counts[1] = (uint32_t)(vox > 0xffffffffull ? 0xffffffffull : vox);
+        fj.counts[1] = (uint32_t)(e_vox > 0xffffffffull ? 0xffffffffull : e_vox);
         fj.counts[3] = n;
         counter[0] = 0;
-        counter[1] = grab_size(tiles, fj.blocks);
+        counter[1] = grab_size(e_tiles, fj.blocks);
         counter[2] = n;
         if (n < K_all)
             atomicOr(status, kFlagCapacity);
@@ -197,20 +206,28 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj,
 }
 
 // ------------------------------------------------------------------ run labelling
+constexpr int kMaskCap = 1024;   // row-mask words held in LDS (grids of up to 65536 rows)
+constexpr int kRowWords = 4;     // row-bitmap words a thread keeps in registers
+
 // Rows, runs and forest: LDS arrays or their global-scratch twins.
 struct RunArrays {
-    int32_t* rows;   // listed rows, ascending
-    int32_t* rs;     // first run of each listed row; rs[n_rows] = number of runs
-    int32_t* x0;     // first x of each run
-    int32_t* x1;     // last x of each run
-    int32_t* P;      // union-find parent; after ranking, -1 - rank at roots
+    uint64_t* rm;      // row-mask words
+    int32_t* rmpre;    // listed rows before each row-mask word
+    int32_t* rows;     // listed rows, ascending
+    int32_t* rs;       // first run of each listed row, rs[n_rows] = runs; once the
+                       // runs are united, the component rank of each label
+    int32_t* x0;       // run extents (global twin) ...
+    int32_t* x1;
+    uint32_t* xx;      // ... or packed x0 | x1 << 16 (LDS)
+    int32_t* rrow;     // listed row of each run
+    int32_t* P;        // union-find parent; after ranking, -1 - rank at roots
 };
 
 struct LabelArgs {
     RowBits rb;
     int32_t nx, ny, nz;
     RunArrays g;                 // global scratch (used when LDS is too small)
-    int32_t* gstats;             // global stats rows, kStatsRow per component
+    int32_t* gstats;             // global stats rows, kStatsRow per component, then labels
     int32_t* sample_label;       // label of every occupied sample (for the grid pass)
     uint32_t t_np, t_nb;
     fvv_roi* rois;
@@ -221,6 +238,33 @@ struct LabelArgs {
     uint32_t* counter;
     fvv_camera* dcams;
 };
+
+template <bool kLds>
+__device__ __forceinline__ void put_run(const RunArrays& m, int32_t k, int32_t x0, int32_t x1) {
+    if (kLds) {
+        m.xx[k] = (uint32_t)x0 | ((uint32_t)x1 << 16);
+    } else {
+        m.x0[k] = x0;
+        m.x1[k] = x1;
+    }
+}
+
+template <bool kLds>
+__device__ __forceinline__ int2 get_run(const RunArrays& m, int32_t k) {
+    if (kLds) {
+        const uint32_t v = m.xx[k];
+        return make_int2((int32_t)(v & 0xffffu), (int32_t)(v >> 16));
+    }
+    return make_int2(m.x0[k], m.x1[k]);
+}
+
+// List index of row r, or -1 when the row has no occupied sample: the rank of
+// its bit in the row mask.
+__device__ __forceinline__ int32_t row_index(const RunArrays& m, int32_t r) {
+    const uint64_t wv = m.rm[r >> 6];
+    const uint64_t bit = 1ull << (r & 63);
+    return (wv & bit) ? m.rmpre[r >> 6] + __popcll(wv & (bit - 1)) : -1;
+}
 
 // Rank of the component of run k (P flattened and ranked).
 __device__ __forceinline__ int32_t rank_of(const volatile int32_t* P, int32_t k) {
@@ -241,26 +285,7 @@ __device__ __forceinline__ uint64_t row_word(const uint64_t* rw, int32_t q, int3
     return (q == wr - 1 && (nx & 63)) ? v & ((1ull << (nx & 63)) - 1) : v;
 }
 
-// Unite the runs of listed rows i and j (j an earlier neighbouring row):
-// two-pointer sweep over both ascending run lists; a pair is adjacent iff
-// each run starts at most one sample past the other's end.  The run that
-// ends first cannot touch any later run of the other row, so it advances.
-__device__ __forceinline__ void unite_rows(const RunArrays& m, int i, int j) {
-    int a = m.rs[i], ae = m.rs[i + 1];
-    int b = m.rs[j], be = m.rs[j + 1];
-    while (a < ae && b < be) {
-        const int32_t a0 = m.x0[a], a1 = m.x1[a], b0 = m.x0[b], b1 = m.x1[b];
-        if (a0 <= b1 + 1 && b0 <= a1 + 1)
-            unite(m.P, a, b);
-        if (a1 < b1)
-            ++a;
-        else
-            ++b;
-    }
-}
-
-// Count per component and bounding box; stats rows: count, lo[3], hi[3],
-// then (min linear index) and label in the second half.
+// Stats rows: count, lo[3], hi[3], smallest linear index.
 constexpr int kStatCount = 0, kStatLo = 1, kStatHi = 4, kStatMin = 7;
 
 template <bool kLdsStats>
@@ -270,12 +295,14 @@ __device__ __forceinline__ int32_t stat_load(const int32_t* s) {
     return __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Steps 5-6 with the stats rows in `stats` (LDS or global).
-template <bool kLdsStats>
+// Stats of every component (one set of atomics per run), the Eq. (1) filter
+// and the numbering in root order (= ascending smallest linear index), the
+// ROI table, and per label its component rank (in m.rs, free by now).
+template <bool kLds, bool kLdsStats>
 __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunArrays& m,
-                                                 int32_t n_rows, int32_t K_all, int32_t* stats,
-                                                 int32_t* labels_of_rank, uint32_t* scan,
-                                                 uint32_t* Kout) {
+                                                 int32_t n_runs, int32_t K_all, int32_t* stats,
+                                                 int32_t* labels_of_rank, int32_t* rank_of_label,
+                                                 uint32_t* scan, uint32_t* Kout) {
     constexpr int NT = kLabelThreads;
     for (int32_t j = threadIdx.x; j < K_all; j += NT) {
         int32_t* s = stats + (int64_t)kStatsRow * j;
@@ -285,25 +312,21 @@ __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunAr
         s[kStatMin] = 0x7fffffff;
     }
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
-        const int32_t r = m.rows[i];
+    for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
+        const int32_t r = m.rows[m.rrow[k]];
         const int32_t y = r % a.ny, z = r / a.ny;
-        const int64_t row_lin = (int64_t)a.nx * r;
-        for (int32_t k = m.rs[i]; k < m.rs[i + 1]; ++k) {
-            const int32_t x0 = m.x0[k], x1 = m.x1[k];
-            int32_t* s = stats + (int64_t)kStatsRow * rank_of(m.P, k);
-            atomicAdd(&s[kStatCount], x1 - x0 + 1);
-            atomicMin(&s[kStatLo + 0], x0);
-            atomicMax(&s[kStatHi + 0], x1);
-            atomicMin(&s[kStatLo + 1], y);
-            atomicMax(&s[kStatHi + 1], y);
-            atomicMin(&s[kStatLo + 2], z);
-            atomicMax(&s[kStatHi + 2], z);
-            atomicMin(&s[kStatMin], (int32_t)(row_lin + x0));
-        }
+        const int2 x = get_run<kLds>(m, k);
+        int32_t* s = stats + (int64_t)kStatsRow * rank_of(m.P, k);
+        atomicAdd(&s[kStatCount], x.y - x.x + 1);
+        atomicMin(&s[kStatLo + 0], x.x);
+        atomicMax(&s[kStatHi + 0], x.y);
+        atomicMin(&s[kStatLo + 1], y);
+        atomicMax(&s[kStatHi + 1], y);
+        atomicMin(&s[kStatLo + 2], z);
+        atomicMax(&s[kStatHi + 2], z);
+        atomicMin(&s[kStatMin], (int32_t)((int64_t)a.nx * r + x.x));
     }
     __syncthreads();
-    // Eq. (1) filter and numbering in root order (= ascending smallest index)
     uint32_t K = 0;
     for (int32_t base = 0; base < K_all; base += NT) {
         const int32_t j = base + threadIdx.x;
@@ -328,15 +351,16 @@ __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunAr
             roi.count = cnt;
             roi.min_index = (uint32_t)stat_load<kLdsStats>(&s[kStatMin]);
             a.rois[lab - 1] = roi;
+            rank_of_label[lab - 1] = j;
         }
         K += total;
     }
     *Kout = K;
 }
 
-// Steps 1-7 with rows, runs and forest in `m`.  With kLds, gives up (returns
-// false, before any global state changed) when the runs do not fit the LDS
-// arrays.
+// The labelling with rows, runs and forest in `m`.  With kLds, gives up
+// (returns false, before any global state changed) when the runs do not fit
+// the LDS arrays.
 template <bool kLds, bool kJobs>
 __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& fj,
                                            const RunArrays& m, int32_t n_rows,
@@ -345,95 +369,123 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     const int32_t R = a.ny * a.nz;
     const int32_t n_rm = (R + 63) / 64;
     const int32_t wr = a.rb.wr;
-    // 1. listed rows, ascending
+    // 1. listed rows, ascending (the LDS row mask and its prefix are ready;
+    //    the global twin builds the prefix here)
     int32_t pos0 = 0;
     for (int32_t base = 0; base < n_rm; base += NT) {
         const int32_t w = base + threadIdx.x;
-        const uint64_t bits = w < n_rm ? rowmask_word(a.rb, w, R) : 0ull;
-        uint32_t total;
-        int32_t pos = pos0 + (int32_t)block_exclusive_sum<NT>((uint32_t)__popcll(bits), scan, &total);
+        uint64_t bits;
+        int32_t pos;
+        if (kLds) {
+            bits = w < n_rm ? m.rm[w] : 0ull;
+            pos = w < n_rm ? m.rmpre[w] : 0;
+        } else {
+            bits = w < n_rm ? rowmask_word(a.rb, w, R) : 0ull;
+            uint32_t total;
+            pos = pos0 + (int32_t)block_exclusive_sum<NT>((uint32_t)__popcll(bits), scan, &total);
+            if (w < n_rm)
+                m.rmpre[w] = pos;
+            pos0 += (int32_t)total;
+        }
         for (uint64_t b = bits; b; b &= b - 1)
             m.rows[pos++] = w * 64 + (__ffsll((unsigned long long)b) - 1);
-        pos0 += (int32_t)total;
     }
     __syncthreads();
-    // 2. runs per row: a run starts at a set bit whose left neighbour is clear
+    // 2. runs of each row, numbered in raster order: a run starts at a set
+    //    bit whose left neighbour is clear and ends at one whose right
+    //    neighbour is clear
     int32_t n_runs = 0;
     for (int32_t base = 0; base < n_rows; base += NT) {
         const int32_t i = base + threadIdx.x;
+        const bool act = i < n_rows;
+        const uint64_t* rw = a.rb.words + (act ? (int64_t)m.rows[i] * wr : 0);
+        uint64_t cw[kRowWords + 1];
+#pragma unroll
+        for (int q = 0; q <= kRowWords; ++q)
+            cw[q] = act && q < wr ? row_word(rw, q, wr, a.nx) : 0ull;
         uint32_t cnt = 0;
-        if (i < n_rows) {
-            const uint64_t* rw = a.rb.words + (int64_t)m.rows[i] * wr;
-            uint64_t carry = 0;
-            for (int32_t q = 0; q < wr; ++q) {
+        uint64_t carry = 0;
+#pragma unroll
+        for (int q = 0; q < kRowWords; ++q) {
+            cnt += (uint32_t)__popcll(cw[q] & ~((cw[q] << 1) | carry));
+            carry = cw[q] >> 63;
+        }
+        if (act)
+            for (int32_t q = kRowWords; q < wr; ++q) {
                 const uint64_t v = row_word(rw, q, wr, a.nx);
                 cnt += (uint32_t)__popcll(v & ~((v << 1) | carry));
                 carry = v >> 63;
             }
-        }
         uint32_t total;
-        const uint32_t ex = block_exclusive_sum<NT>(cnt, scan, &total);
-        if (i < n_rows)
-            m.rs[i] = n_runs + (int32_t)ex;
+        const int32_t first = n_runs + (int32_t)block_exclusive_sum<NT>(cnt, scan, &total);
+        if (kLds && n_runs + (int32_t)total > kRunCap)
+            return false;
+        if (act) {
+            m.rs[i] = first;
+            int32_t k = first, x_start = 0;
+            auto emit = [&](int32_t q, uint64_t v, uint64_t nxt, uint64_t cin) {
+                const uint64_t st = v & ~((v << 1) | cin);
+                const uint64_t en = v & ~((v >> 1) | (nxt << 63));
+                for (uint64_t b = st | en; b; b &= b - 1) {
+                    const int bit = __ffsll((unsigned long long)b) - 1;
+                    const int32_t x = q * 64 + bit;
+                    if ((st >> bit) & 1u)
+                        x_start = x;
+                    if ((en >> bit) & 1u) {
+                        put_run<kLds>(m, k, x_start, x);
+                        m.rrow[k] = i;
+                        m.P[k] = k;
+                        ++k;
+                    }
+                }
+            };
+            uint64_t cin = 0;
+#pragma unroll
+            for (int q = 0; q < kRowWords; ++q) {
+                emit(q, cw[q], cw[q + 1], cin);
+                cin = cw[q] >> 63;
+            }
+            for (int32_t q = kRowWords; q < wr; ++q) {
+                const uint64_t v = row_word(rw, q, wr, a.nx);
+                emit(q, v, q + 1 < wr ? row_word(rw, q + 1, wr, a.nx) : 0ull, cin);
+                cin = v >> 63;
+            }
+        }
         n_runs += (int32_t)total;
     }
-    if (kLds && n_runs > kRunCap)
-        return false;
     if (threadIdx.x == 0)
         m.rs[n_rows] = n_runs;
     __syncthreads();
-    // 3. run extents (the k-th start and the k-th end of a row belong to its
-    //    k-th run); the row's bitmap words are cleared once read
-    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
-        uint64_t* rw = a.rb.words + (int64_t)m.rows[i] * wr;
-        int32_t ks = m.rs[i], ke = ks;
-        uint64_t carry = 0, v = row_word(rw, 0, wr, a.nx);
-        for (int32_t q = 0; q < wr; ++q) {
-            const uint64_t nxt = q + 1 < wr ? row_word(rw, q + 1, wr, a.nx) : 0ull;
-            const uint64_t st = v & ~((v << 1) | carry);
-            const uint64_t en = v & ~((v >> 1) | (nxt << 63));
-            for (uint64_t b = st; b; b &= b - 1) {
-                m.x0[ks] = q * 64 + (__ffsll((unsigned long long)b) - 1);
-                m.P[ks] = ks;
-                ++ks;
-            }
-            for (uint64_t b = en; b; b &= b - 1)
-                m.x1[ke++] = q * 64 + (__ffsll((unsigned long long)b) - 1);
-            rw[q] = 0;
-            carry = v >> 63;
-            v = nxt;
-        }
-    }
-    __syncthreads();
-    // 4. unite with the earlier neighbouring rows
-    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
-        const int32_t r = m.rows[i];
+    // 3. unite every run with the adjacent runs of its earlier neighbouring
+    //    rows: (y-1, z) and (y-1..y+1, z-1); a row's runs ascend in x, so the
+    //    scan stops at the first run starting past this one's reach
+    for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
+        const int32_t r = m.rows[m.rrow[k]];
         const int32_t y = r % a.ny, z = r / a.ny;
-        if (y > 0 && i > 0 && m.rows[i - 1] == r - 1)
-            unite_rows(m, i, i - 1);
-        if (z > 0) {
-            // rows (y-1..y+1, z-1) lie among the ny+1 listed rows before i
-            const int32_t target = r - a.ny - 1;
-            int32_t lo = i - a.ny - 1 > 0 ? i - a.ny - 1 : 0, hi = i;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (m.rows[mid] < target)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            for (int32_t j = lo; j < i; ++j) {
-                const int32_t rj = m.rows[j];
-                if (rj > r - a.ny + 1)
+        const int2 xk = get_run<kLds>(m, k);
+        int32_t jn[4];
+        jn[0] = y > 0 ? row_index(m, r - 1) : -1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int32_t yy = y - 1 + d;
+            jn[1 + d] = (z > 0 && yy >= 0 && yy < a.ny) ? row_index(m, r - a.ny - 1 + d) : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (jn[q] < 0)
+                continue;
+            const int32_t be = m.rs[jn[q] + 1];
+            for (int32_t b = m.rs[jn[q]]; b < be; ++b) {
+                const int2 xb = get_run<kLds>(m, b);
+                if (xb.x > xk.y + 1)
                     break;
-                const int32_t yj = rj % a.ny;
-                if (rj / a.ny == z - 1 && yj >= y - 1 && yj <= y + 1)
-                    unite_rows(m, i, j);
+                if (xb.y + 1 >= xk.x)
+                    unite(m.P, k, b);
             }
         }
     }
     __syncthreads();
-    // 5. flatten, then number the roots in ascending run id.  The walk only
+    // 4. flatten, then number the roots in ascending run id.  The walk only
     //    reads: the sole writes now set a node to its root, which keeps every
     //    concurrent walk on course (path halving here could store a
     //    grandparent over a root written meanwhile).
@@ -456,26 +508,35 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         K_all += (int32_t)total;
     }
     __syncthreads();
-    // 6. stats, filter, ROI table (stats rows in LDS while the components fit;
+    // 5. stats, filter, ROI table (stats rows in LDS while the components fit;
     //    the label of each rank follows the rows)
     uint32_t K = 0;
+    int32_t* stats;
     int32_t* lab;
-    if (K_all <= kRootCap) {
+    const bool lds_stats_ok = K_all <= kRootCap;
+    int32_t* rank_of_label = lds_stats_ok ? m.rs : a.g.rs;
+    if (lds_stats_ok) {
+        stats = lds_stats;
         lab = lds_stats + (int64_t)kStatsRow * kRootCap;
-        stats_and_select<true>(a, m, n_rows, K_all, lds_stats, lab, scan, &K);
+        stats_and_select<kLds, true>(a, m, n_runs, K_all, stats, lab, rank_of_label, scan, &K);
     } else {
+        stats = a.gstats;
         lab = a.gstats + (int64_t)kStatsRow * K_all;
-        stats_and_select<false>(a, m, n_rows, K_all, a.gstats, lab, scan, &K);
+        stats_and_select<kLds, false>(a, m, n_runs, K_all, stats, lab, rank_of_label, scan, &K);
     }
     __syncthreads();
-    // labels of the occupied samples, and the row mask cleared
+    // 6. labels of the occupied samples; the bitmap cleared for the next call
+    for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
+        const int64_t row_lin = (int64_t)a.nx * m.rows[m.rrow[k]];
+        const int32_t l = ((volatile int32_t*)lab)[rank_of(m.P, k)];
+        const int2 x = get_run<kLds>(m, k);
+        for (int32_t xi = x.x; xi <= x.y; ++xi)
+            a.sample_label[row_lin + xi] = l;
+    }
     for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
-        const int64_t row_lin = (int64_t)a.nx * m.rows[i];
-        for (int32_t k = m.rs[i]; k < m.rs[i + 1]; ++k) {
-            const int32_t l = ((volatile int32_t*)lab)[rank_of(m.P, k)];
-            for (int32_t x = m.x0[k]; x <= m.x1[k]; ++x)
-                a.sample_label[row_lin + x] = l;
-        }
+        uint64_t* rw = a.rb.words + (int64_t)m.rows[i] * wr;
+        for (int32_t q = 0; q < wr; ++q)
+            rw[q] = 0;
     }
     for (int32_t w = threadIdx.x; w < n_rm; w += NT)
         a.rb.rowmask[w] = 0;
@@ -486,7 +547,15 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     }
     if (kJobs) {
         __syncthreads();
-        build_fine_jobs<NT>(fj, a.rois, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);
+        auto box = [&](uint32_t t, int32_t* lo, int32_t* hi) {
+            const int32_t* s = stats + (int64_t)kStatsRow * rank_of_label[t];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                lo[e] = lds_stats_ok ? stat_load<true>(&s[kStatLo + e]) : stat_load<false>(&s[kStatLo + e]);
+                hi[e] = lds_stats_ok ? stat_load<true>(&s[kStatHi + e]) : stat_load<false>(&s[kStatHi + e]);
+            }
+        };
+        build_fine_jobs<NT>(fj, box, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);
     }
     return true;
 }
@@ -494,25 +563,35 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
 template <bool kJobs>
 __global__ __launch_bounds__(kLabelThreads) void label_runs_kernel(const LabelArgs a,
                                                                    const FrameJobs fj) {
+    __shared__ uint64_t s_rm[kMaskCap];
+    __shared__ int32_t s_rmpre[kMaskCap];
     __shared__ int32_t s_rows[kRowCap];
     __shared__ int32_t s_rs[kRowCap + 1];
-    __shared__ int32_t s_x0[kRunCap];
-    __shared__ int32_t s_x1[kRunCap];
+    __shared__ uint32_t s_xx[kRunCap];
+    __shared__ int32_t s_rrow[kRunCap];
     __shared__ int32_t s_P[kRunCap];
     __shared__ int32_t s_stats[kStatsRow * kRootCap + kRootCap];   // rows, then labels
     __shared__ uint32_t s_scan[kLabelThreads / kWave];
     const int32_t R = a.ny * a.nz;
     const int32_t n_rm = (R + 63) / 64;
+    const bool lds_ok = n_rm <= kMaskCap && a.nx <= 65535;
+    // listed rows: count them, and keep the row mask and its prefix in LDS
     int32_t n_rows = 0;
     for (int32_t base = 0; base < n_rm; base += kLabelThreads) {
         const int32_t w = base + threadIdx.x;
         const uint64_t bits = w < n_rm ? rowmask_word(a.rb, w, R) : 0ull;
         uint32_t total;
-        (void)block_exclusive_sum<kLabelThreads>((uint32_t)__popcll(bits), s_scan, &total);
+        const uint32_t ex =
+            block_exclusive_sum<kLabelThreads>((uint32_t)__popcll(bits), s_scan, &total);
+        if (lds_ok && w < n_rm) {
+            s_rm[w] = bits;
+            s_rmpre[w] = n_rows + (int32_t)ex;
+        }
         n_rows += (int32_t)total;
     }
-    if (n_rows <= kRowCap) {
-        const RunArrays m{s_rows, s_rs, s_x0, s_x1, s_P};
+    __syncthreads();
+    if (lds_ok && n_rows <= kRowCap) {
+        const RunArrays m{s_rm, s_rmpre, s_rows, s_rs, nullptr, nullptr, s_xx, s_rrow, s_P};
         if (label_body<true, kJobs>(a, fj, m, n_rows, s_stats, s_scan))
             return;
         __syncthreads();
@@ -569,7 +648,8 @@ hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* 
     a.nx = g.dims[0];
     a.ny = g.dims[1];
     a.nz = g.dims[2];
-    a.g = RunArrays{ctx->d_rows, ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_runP};
+    a.g = RunArrays{ctx->d_rowmask, ctx->d_rmpre, ctx->d_rows, ctx->d_rs, ctx->d_x0,
+                    ctx->d_x1,      nullptr,      ctx->d_rrow, ctx->d_runP};
     a.gstats = ctx->d_stats;
     a.sample_label = ctx->d_sample_label;
     a.t_np = t_np;

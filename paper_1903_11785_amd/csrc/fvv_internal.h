@@ -12,7 +12,7 @@ namespace fvv {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;              // threads per workgroup everywhere
-constexpr int kEdgeChunk = 2048;         // fine samples per crossing-edge work item
+constexpr int kEdgeWords = 256;          // fine-bitmap words per crossing-edge work item
 constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits
 
 // Projections of a camera rig passed by value in the kernel arguments.
@@ -73,22 +73,24 @@ __device__ __forceinline__ bool sil_test(float a, float b, float w,
     return ok & (((word >> (px & 31)) & 1u) != 0u);
 }
 
-// Occupancy test of one world point against G cameras at once (AND of the
-// single-camera tests), phased so that the G silhouette loads are issued
-// together: all projections first, one wave-uniform check for the rare tiny
-// w, then all floors and loads, then the bits.
+// G occupancy tests at once, test q of point (X[q], Y[q], Z[q]) in camera
+// P[q] with silhouette sil[q]; bit q of the result is its outcome.  Phased so
+// that the G silhouette loads are issued together: all projections first, one
+// wave-uniform check for the rare tiny w, then all floors and loads, then the
+// bits.  Each test is the single-camera test above, operation for operation.
 template <int G>
-__device__ __forceinline__ bool group_inside(const float* const* __restrict__ P, float X, float Y,
-                                             float Z, const uint32_t* const* __restrict__ sil,
-                                             int W, int H, int wpr) {
+__device__ __forceinline__ uint32_t multi_inside(const float* const* __restrict__ P,
+                                                 const float* X, const float* Y, const float* Z,
+                                                 const uint32_t* const* __restrict__ sil, int W,
+                                                 int H, int wpr) {
     float a[G], b[G], w[G], qa[G], qb[G];
     bool tiny_any = false;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const float* p = P[q];
-        a[q] = __builtin_fmaf(p[2], Z, __builtin_fmaf(p[1], Y, __builtin_fmaf(p[0], X, p[3])));
-        b[q] = __builtin_fmaf(p[6], Z, __builtin_fmaf(p[5], Y, __builtin_fmaf(p[4], X, p[7])));
-        w[q] = __builtin_fmaf(p[10], Z, __builtin_fmaf(p[9], Y, __builtin_fmaf(p[8], X, p[11])));
+        a[q] = __builtin_fmaf(p[2], Z[q], __builtin_fmaf(p[1], Y[q], __builtin_fmaf(p[0], X[q], p[3])));
+        b[q] = __builtin_fmaf(p[6], Z[q], __builtin_fmaf(p[5], Y[q], __builtin_fmaf(p[4], X[q], p[7])));
+        w[q] = __builtin_fmaf(p[10], Z[q], __builtin_fmaf(p[9], Y[q], __builtin_fmaf(p[8], X[q], p[11])));
         const float r = __builtin_amdgcn_rcpf(w[q]);
         qa[q] = a[q] * r;
         qb[q] = b[q] * r;
@@ -113,11 +115,26 @@ __device__ __forceinline__ bool group_inside(const float* const* __restrict__ P,
         ok[q] = (w[q] > 0.0f) & ((unsigned)px[q] < (unsigned)W) & ((unsigned)py < (unsigned)H);
         word[q] = sil[q][ok[q] ? py * wpr + (px[q] >> 5) : 0];
     }
-    bool in = true;
+    uint32_t in = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q)
-        in &= ok[q] & (((word[q] >> (px[q] & 31)) & 1u) != 0u);
+        in |= (uint32_t)(ok[q] & (((word[q] >> (px[q] & 31)) & 1u) != 0u)) << q;
     return in;
+}
+
+// One world point against G cameras (AND of the single-camera tests).
+template <int G>
+__device__ __forceinline__ bool group_inside(const float* const* __restrict__ P, float X, float Y,
+                                             float Z, const uint32_t* const* __restrict__ sil,
+                                             int W, int H, int wpr) {
+    float Xs[G], Ys[G], Zs[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        Xs[q] = X;
+        Ys[q] = Y;
+        Zs[q] = Z;
+    }
+    return multi_inside<G>(P, Xs, Ys, Zs, sil, W, H, wpr) == (1u << G) - 1u;
 }
 
 // World coordinate of global lattice index g on one axis.
@@ -144,14 +161,21 @@ __device__ __forceinline__ uint64_t lanes_below_mask() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Inclusive prefix sum over a wave.
+// Inclusive prefix sum over a wave with DPP lane moves: shifts by 1, 2, 4, 8
+// within each row of 16 lanes, then row 15 -> rows 1 and 3 and row 31 -> rows
+// 2 and 3 (lanes outside the source range add 0).
+template <int kCtrl, int kRowMask, bool kBound>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, kBound);
+}
+
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, kWave);
-        if (lane_id() >= d)
-            v += u;
-    }
+    v += dpp_u32<0x111, 0xf, true>(v);    // row_shr:1
+    v += dpp_u32<0x112, 0xf, true>(v);    // row_shr:2
+    v += dpp_u32<0x114, 0xf, true>(v);    // row_shr:4
+    v += dpp_u32<0x118, 0xf, true>(v);    // row_shr:8
+    v += dpp_u32<0x142, 0xa, false>(v);   // row_bcast:15
+    v += dpp_u32<0x143, 0xc, false>(v);   // row_bcast:31
     return v;
 }
 
@@ -178,13 +202,20 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* sc
     return base + inc - v;
 }
 
+template <int kCtrl, int kRowMask, bool kBound>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = dpp_u32<kCtrl, kRowMask, kBound>((uint32_t)v);
+    const uint32_t hi = dpp_u32<kCtrl, kRowMask, kBound>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint64_t u = __shfl_up((unsigned long long)v, d, kWave);
-        if (lane_id() >= d)
-            v += u;
-    }
+    v += dpp_u64<0x111, 0xf, true>(v);
+    v += dpp_u64<0x112, 0xf, true>(v);
+    v += dpp_u64<0x114, 0xf, true>(v);
+    v += dpp_u64<0x118, 0xf, true>(v);
+    v += dpp_u64<0x142, 0xa, false>(v);
+    v += dpp_u64<0x143, 0xc, false>(v);
     return v;
 }
 
@@ -207,20 +238,6 @@ __device__ __forceinline__ uint64_t block_exclusive_sum64(uint64_t v, uint64_t* 
     __syncthreads();
     *total = sum;
     return base + inc - v;
-}
-
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-        v = min(v, __shfl_xor(v, d, kWave));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-        v = max(v, __shfl_xor(v, d, kWave));
-    return v;
 }
 
 // Carving tiles of lattice g for a TX x (256/TX) x TZ tile.
@@ -262,9 +279,35 @@ constexpr int kStatsRow = 8;   // per component: count, lo[3], hi[3], smallest l
 // crossing-edge work item (exclusive prefix sums over the job table).
 struct JobPrefix {
     uint64_t tile_off;   // first tile of the job
+    uint64_t bit_off;    // first word of the job's fine bitmap
     uint32_t item_off;   // first crossing-edge work item of the job
     uint32_t pad;
 };
+
+// Fine bitmap of one lattice (a job): its occupancy with each x-row padded to
+// whole 64-bit words, rows in raster order (bit x of row j + ny*k in word
+// (j + ny*k)*ceil(nx/64) + x/64).  The bits past nx are unspecified.
+__host__ __device__ inline int64_t fine_bitmap_words(const fvv_grid& g) {
+    return (int64_t)g.dims[1] * g.dims[2] * ((g.dims[0] + 63) / 64);
+}
+
+// XCD-aware static partition: the workgroups of a launch go to the 8 XCDs
+// round-robin in launch order, so the workgroups b with b % 8 == x share XCD
+// x's L2.  Item range [begin, end) belongs to XCD x; its workgroups take
+// items begin + slot, begin + slot + stride, ...  The grid must be a multiple
+// of 8 workgroups.  Every item is covered exactly once whatever the actual
+// placement; only cache locality depends on it.
+constexpr int kXcds = 8;
+
+struct XcdSlice {
+    uint64_t begin, end;
+    uint32_t slot, stride;
+};
+
+__device__ __forceinline__ XcdSlice xcd_slice(uint64_t n) {
+    const uint32_t x = blockIdx.x % kXcds;
+    return XcdSlice{n * x / kXcds, n * (x + 1) / kXcds, blockIdx.x / kXcds, gridDim.x / kXcds};
+}
 
 // Largest j in [0, n) with off(j) <= x, for ascending offsets (binary search).
 template <typename F>
@@ -292,10 +335,12 @@ struct fvv_ctx {
     // labelling
     uint64_t* d_rowbits;         // row bitmap of the coarse occupancy (RowBits)
     uint64_t* d_rowmask;         // rows with a set bit
-    int32_t* d_rows;             // listed rows, run starts per row, run extents and
-    int32_t* d_rs;               // union-find forest over runs: the global twins of the
-    int32_t* d_x0;               // labelling workgroup's LDS arrays, used when those
-    int32_t* d_x1;               // are too small
+    int32_t* d_rmpre;            // row-mask prefix, listed rows, run starts per row, run
+    int32_t* d_rows;             // extents, run rows and the union-find forest over runs:
+    int32_t* d_rs;               // the global twins of the labelling workgroup's LDS
+    int32_t* d_x0;               // arrays, used when those are too small
+    int32_t* d_x1;
+    int32_t* d_rrow;
     int32_t* d_runP;
     int32_t* d_stats;            // per component: kStatsRow ints, then one label each
     int32_t* d_sample_label;     // label of every occupied coarse sample
@@ -303,12 +348,13 @@ struct fvv_ctx {
     fvv::JobPrefix* d_prefix;    // per job (max(max_jobs, max_rois) + 1)
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
     fvv_camera* d_cams;          // camera table of fvv_frame
+    uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)
     uint32_t* d_item_cnt;        // crossing edges per work item
-    uint32_t* d_item_base;       // first edge of each work item
     uint32_t* d_point_off_single;
     uint32_t* d_counts_single;
     int64_t item_cap;
     int64_t job_cap;
+    int64_t bit_cap;
     int n_cus;
     // side branch of a frame (work off the critical path), default priority
     hipStream_t side;
@@ -330,15 +376,18 @@ struct FrameJobs {
     uint32_t* counts;
     int tile_x, tile_z;
     uint32_t blocks;
+    int64_t bit_cap;     // words of the fine bitmap scratch
 };
 
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils, hipStream_t s);
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g,
                         TileShape t, uint8_t* occ, const RowBits* rows, hipStream_t s);
+// finebits: NULL, or where each job's fine bitmap goes (at its bit_off).
 hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jobs,
                                 const fvv_camera* cams, const uint32_t* sils, uint8_t* out,
-                                TileShape t, int blocks, bool jobs_prepared, hipStream_t s);
+                                uint64_t* finebits, TileShape t, int blocks, bool jobs_prepared,
+                                hipStream_t s);
 RowBits row_bits(fvv_ctx* ctx, const fvv_grid& g);
 // seeded: the row bitmap is already filled (by the coarse carve of a frame).
 // labels == nullptr: stop before the grid pass (launch_label_write does it).
@@ -352,6 +401,14 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                           const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,
                           uint32_t max_points, uint32_t* point_off, uint32_t* n_points,
                           hipEvent_t edges_done, hipStream_t s);
-hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, hipStream_t s);
+// The fine carve of a frame (jobs prepared by the labelling): tiles with
+// tz == 4 classify cameras per box first (rounding pads of `cams`), others
+// take the batched carve.
+hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& cams,
+                              const uint32_t* sils, uint8_t* out, uint64_t* finebits, TileShape t,
+                              int blocks, hipStream_t s);
+// The job table and fine bitmap of a single lattice with occupancy occ.
+hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, const uint8_t* occ,
+                                         hipStream_t s);
 
 }  // namespace fvv

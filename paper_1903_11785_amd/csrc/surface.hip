@@ -1,13 +1,16 @@
 // Crossing-edge compaction and exit-point bisection (Sec. II-C) for gfx950.
 //
-// Crossing edges: work items are chunks of kEdgeChunk consecutive samples of
-// one ROI, eight consecutive samples per thread.  A first pass counts each
-// item's edges, one workgroup scans the counts, and a second pass writes keys
-// 3*lin+axis in ascending order (a thread's keys are in order, and a block
-// scan orders the threads).  Exit points: a group of four lanes per edge, each
-// owning a quarter of the cameras; a first pass keeps the cameras that can
-// reject some point of the edge at all, and the n_steps bisection steps test
-// only those at each bracket midpoint.
+// Crossing edges come from the fine bitmap of each lattice (each x-row padded
+// to whole 64-bit words; in a frame the fine carve writes it): one thread per
+// word tests 64 samples at once, x-edges by XOR with the word shifted by one
+// sample, y- and z-edges by XOR with the words one row and one slab further.
+// Work items are kEdgeWords consecutive words of one lattice.  A first pass
+// counts each item's edges; a second sums the counts of the items before it
+// and writes the keys 3*lin+axis in ascending order (a thread's keys are in
+// order, and a block scan orders the threads).  Exit points: a group of four
+// lanes per edge, each owning a quarter of the cameras; a first pass keeps the
+// cameras that can reject some point of the edge at all, and the bisection
+// tests only those, two steps per round.
 #include "fvv_internal.h"
 
 namespace fvv {
@@ -17,158 +20,208 @@ __global__ void surface_single_kernel(const fvv_job job, fvv_job* __restrict__ d
                                       JobPrefix* __restrict__ pre, uint32_t* __restrict__ counts) {
     if (threadIdx.x == 0) {
         dst[0] = job;
-        const uint64_t V = (uint64_t)job.grid.dims[0] * job.grid.dims[1] * job.grid.dims[2];
+        const int64_t words = fine_bitmap_words(job.grid);
+        pre[0].tile_off = 0;
+        pre[0].bit_off = 0;
         pre[0].item_off = 0;
-        pre[1].item_off = (uint32_t)((V + kEdgeChunk - 1) / kEdgeChunk);
+        pre[1].item_off = (uint32_t)((words + kEdgeWords - 1) / kEdgeWords);
         counts[3] = 1;
     }
 }
 
-hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, hipStream_t s) {
+// Fine bitmap of one lattice from its uint8 occupancy: one wave per word,
+// lane = bit.
+__global__ __launch_bounds__(kBlock) void fine_bitmap_kernel(const uint8_t* __restrict__ occ,
+                                                             int32_t nx, int32_t wr,
+                                                             int64_t n_words,
+                                                             uint64_t* __restrict__ bits) {
+    const int64_t word = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    if (word >= n_words)
+        return;
+    const int64_t row = word / wr;
+    const int32_t x = (int32_t)(word - row * wr) * kWave + lane_id();
+    const uint64_t b = __ballot(x < nx && occ[row * nx + x] != 0);
+    if (lane_id() == 0)
+        bits[word] = b;
+}
+
+hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, const uint8_t* occ,
+                                         hipStream_t s) {
     hipLaunchKernelGGL(surface_single_kernel, dim3(1), dim3(64), 0, s, job, ctx->d_job_single,
                        ctx->d_prefix, ctx->d_counts_single);
+    const int64_t n_words = fine_bitmap_words(job.grid);
+    const int64_t blocks = (n_words * kWave + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(fine_bitmap_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, occ,
+                       job.grid.dims[0], (job.grid.dims[0] + 63) / 64, n_words, ctx->d_finebits);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ crossing edges
-constexpr int kEdgeRun = kEdgeChunk / kBlock;   // consecutive samples per thread
+constexpr int kJobTable = 1024;   // jobs whose item offsets a workgroup keeps in LDS
 
-struct ItemRef {
-    int job;
-    uint32_t lin0;
+// Item offsets of the jobs in LDS (when they fit) for the item -> job search.
+struct ItemJobs {
+    const JobPrefix* pre;
+    const uint32_t* lds;   // item_off of jobs 0..nj, or nullptr
+    int nj;
+    __device__ int job_of(uint32_t item) const {
+        if (lds)
+            return upper_job([&](int m) { return (uint64_t)lds[m]; }, nj, item);
+        return upper_job([&](int m) { return (uint64_t)pre[m].item_off; }, nj, item);
+    }
+    __device__ uint32_t first_item(int j) const { return lds ? lds[j] : pre[j].item_off; }
 };
 
-__device__ __forceinline__ ItemRef locate_item(const JobPrefix* __restrict__ pre, int nj,
-                                               uint32_t item) {
-    const int jb = upper_job([&](int m) { return (uint64_t)pre[m].item_off; }, nj, item);
-    return {jb, (item - pre[jb].item_off) * (uint32_t)kEdgeChunk};
+__device__ __forceinline__ ItemJobs load_item_jobs(const JobPrefix* __restrict__ pre, int nj,
+                                                   uint32_t* table) {
+    const bool fit = nj < kJobTable;
+    if (fit)
+        for (int j = threadIdx.x; j <= nj; j += kBlock)
+            table[j] = pre[j].item_off;
+    __syncthreads();
+    return ItemJobs{pre, fit ? table : nullptr, nj};
 }
 
-// Crossing bits (x, y, z in bits 3s, 3s+1, 3s+2) of this thread's kEdgeRun
-// consecutive samples starting at lin; samples at or past V give 0.
-__device__ __forceinline__ uint32_t run_bits(const uint8_t* __restrict__ occ, uint32_t lin,
-                                             uint32_t V, int dx, int dy, int dz) {
-    if (lin >= V)
-        return 0;
-    const uint32_t sx = (uint32_t)dx, sxy = (uint32_t)dx * (uint32_t)dy;
-    uint32_t i = lin % sx;
-    const uint32_t r = lin / sx;
-    uint32_t j = r % (uint32_t)dy;
-    uint32_t k = r / (uint32_t)dy;
-    uint8_t o[kEdgeRun + 1], oy[kEdgeRun], oz[kEdgeRun];
-#pragma unroll
-    for (int s = 0; s <= kEdgeRun; ++s)
-        o[s] = lin + s < V ? occ[lin + s] : 0;
-#pragma unroll
-    for (int s = 0; s < kEdgeRun; ++s) {
-        oy[s] = lin + s + sx < V ? occ[lin + s + sx] : 0;
-        oz[s] = lin + s + sxy < V ? occ[lin + s + sxy] : 0;
-    }
-    uint32_t bits = 0;
-#pragma unroll
-    for (int s = 0; s < kEdgeRun; ++s) {
-        if (lin + s < V) {
-            const bool c = o[s] != 0;
-            if (i + 1 < sx && (o[s + 1] != 0) != c)
-                bits |= 1u << (3 * s);
-            if (j + 1 < (uint32_t)dy && (oy[s] != 0) != c)
-                bits |= 2u << (3 * s);
-            if (k + 1 < (uint32_t)dz && (oz[s] != 0) != c)
-                bits |= 4u << (3 * s);
-        }
-        if (++i == sx) {
-            i = 0;
-            if (++j == (uint32_t)dy) {
-                j = 0;
-                ++k;
-            }
-        }
-    }
-    return bits;
+// Crossing-edge masks of word w of a fine bitmap of lattice dims d, wr words
+// per row: bit b of ex / ey / ez flags the edge from sample x = 64*q + b of
+// the word's row along x / y / z (both ends in the lattice, occupancies
+// differ).
+struct EdgeMasks {
+    uint64_t ex, ey, ez;
+    uint64_t v;          // the word's samples
+};
+
+__device__ __forceinline__ EdgeMasks edge_masks(const uint64_t* __restrict__ bits, int64_t w,
+                                                const int32_t* d, int32_t wr) {
+    const int64_t row = w / wr;
+    const int32_t q = (int32_t)(w - row * wr);
+    const int32_t y = (int32_t)(row % d[1]);
+    const int32_t z = (int32_t)(row / d[1]);
+    const uint64_t tail = (d[0] & 63) ? (1ull << (d[0] & 63)) - 1 : ~0ull;
+    const bool last = q == wr - 1;
+    const uint64_t in = last ? tail : ~0ull;           // samples of the lattice
+    const bool hy = y + 1 < d[1], hz = z + 1 < d[2];
+    // the four loads are issued together (absent ones repeat this word)
+    const uint64_t v = bits[w] & in;
+    const uint64_t nx = last ? 0ull : bits[w + 1] & (q + 1 == wr - 1 ? tail : ~0ull);
+    const uint64_t vy = bits[hy ? w + wr : w];
+    const uint64_t vz = bits[hz ? w + (int64_t)wr * d[1] : w];
+    EdgeMasks m;
+    m.v = v;
+    m.ex = (v ^ ((v >> 1) | (nx << 63))) & (last ? tail >> 1 : ~0ull);
+    m.ey = hy ? (v ^ vy) & in : 0ull;
+    m.ez = hz ? (v ^ vz) & in : 0ull;
+    return m;
 }
 
+__device__ __forceinline__ uint32_t edge_count(const EdgeMasks& m) {
+    return (uint32_t)(__popcll(m.ex) + __popcll(m.ey) + __popcll(m.ez));
+}
+
+// Per work item: its number of crossing edges.
 __global__ __launch_bounds__(kBlock) void edge_count_kernel(const fvv_job* __restrict__ jobs,
                                                             const JobPrefix* __restrict__ pre,
                                                             const uint32_t* __restrict__ n_jobs_p,
-                                                            const uint8_t* __restrict__ occ_base,
+                                                            const uint64_t* __restrict__ bits,
                                                             uint32_t* __restrict__ item_cnt) {
+    __shared__ uint32_t table[kJobTable];
     __shared__ uint32_t scratch[kBlock / kWave];
     const int nj = (int)*n_jobs_p;
-    const uint32_t n_items = pre[nj].item_off;
+    const ItemJobs ij = load_item_jobs(pre, nj, table);
+    const uint32_t n_items = ij.first_item(nj);
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const ItemRef ref = locate_item(pre, nj, item);
-        const fvv_job job = jobs[ref.job];
-        const uint32_t V = (uint32_t)job.grid.dims[0] * job.grid.dims[1] * job.grid.dims[2];
-        const uint32_t bits = run_bits(occ_base + job.out_offset, ref.lin0 + threadIdx.x * kEdgeRun,
-                                       V, job.grid.dims[0], job.grid.dims[1], job.grid.dims[2]);
+        const int jb = ij.job_of(item);
+        const fvv_grid g = jobs[jb].grid;
+        const int64_t n_words = fine_bitmap_words(g);
+        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
+        const int32_t wr = (g.dims[0] + 63) / 64;
+        uint32_t c = 0;
+        if (w < n_words)
+            c = edge_count(edge_masks(bits + pre[jb].bit_off, w, g.dims, wr));
         uint32_t total;
-        block_exclusive_sum<kBlock>((uint32_t)__popc(bits), scratch, &total);
+        block_exclusive_sum<kBlock>(c, scratch, &total);
         if (threadIdx.x == 0)
             item_cnt[item] = total;
     }
 }
 
-// One workgroup: exclusive scan of the item counts, first edge of every job,
-// and the total.
-__global__ __launch_bounds__(1024) void edge_scan_kernel(const JobPrefix* __restrict__ pre,
-                                                         const uint32_t* __restrict__ n_jobs_p,
-                                                         const uint32_t* __restrict__ item_cnt,
-                                                         uint32_t* __restrict__ item_base,
-                                                         uint32_t* __restrict__ point_off,
-                                                         uint32_t* __restrict__ n_points,
-                                                         uint32_t max_points,
-                                                         uint32_t* __restrict__ status) {
-    __shared__ uint64_t scratch[1024 / kWave];
-    const int nj = (int)*n_jobs_p;
-    const uint32_t n_items = pre[nj].item_off;
-    uint64_t carry = 0;
-    for (uint32_t base = 0; base < n_items; base += 1024) {
-        const uint32_t it = base + threadIdx.x;
-        const uint64_t c = it < n_items ? item_cnt[it] : 0;
-        uint64_t total;
-        const uint64_t ex = block_exclusive_sum64<1024>(c, scratch, &total);
-        if (it < n_items)
-            item_base[it] = (uint32_t)min(carry + ex, (uint64_t)0xffffffffull);
-        carry += total;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < nj; j += 1024)
-        point_off[j] = item_base[pre[j].item_off];
-    if (threadIdx.x == 0) {
-        const uint32_t tot = (uint32_t)min(carry, (uint64_t)0xffffffffull);
-        point_off[nj] = tot;
-        *n_points = tot;
-        if (carry > max_points)
-            atomicOr(status, kFlagCapacity);
-    }
-}
-
+// Per work item: first edge = sum of the counts of the items before it; then
+// every thread writes its word's keys.  The first item of a job gives the
+// job's point offset, the last item the total (ECAPACITY past max_points).
+// xyz[3e] carries, until the bisection overwrites it, +1 if the edge's first
+// sample (lin of its key) is occupied and -1 otherwise.
 __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __restrict__ jobs,
                                                             const JobPrefix* __restrict__ pre,
                                                             const uint32_t* __restrict__ n_jobs_p,
-                                                            const uint8_t* __restrict__ occ_base,
-                                                            const uint32_t* __restrict__ item_base,
+                                                            const uint64_t* __restrict__ bits,
+                                                            const uint32_t* __restrict__ item_cnt,
                                                             uint32_t* __restrict__ keys,
-                                                            uint32_t max_points) {
+                                                            float* __restrict__ xyz,
+                                                            uint32_t max_points,
+                                                            uint32_t* __restrict__ point_off,
+                                                            uint32_t* __restrict__ n_points,
+                                                            uint32_t* __restrict__ status) {
+    __shared__ uint32_t table[kJobTable];
     __shared__ uint32_t scratch[kBlock / kWave];
+    __shared__ uint64_t scratch64[kBlock / kWave];
     const int nj = (int)*n_jobs_p;
-    const uint32_t n_items = pre[nj].item_off;
+    const ItemJobs ij = load_item_jobs(pre, nj, table);
+    const uint32_t n_items = ij.first_item(nj);
+    if (n_items == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int j = 0; j <= nj; ++j)
+            point_off[j] = 0;
+        *n_points = 0;
+    }
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const ItemRef ref = locate_item(pre, nj, item);
-        const fvv_job job = jobs[ref.job];
-        const uint32_t V = (uint32_t)job.grid.dims[0] * job.grid.dims[1] * job.grid.dims[2];
-        const uint32_t lin = ref.lin0 + threadIdx.x * kEdgeRun;
-        uint32_t bits = run_bits(occ_base + job.out_offset, lin, V, job.grid.dims[0],
-                                 job.grid.dims[1], job.grid.dims[2]);
+        // edges of all earlier items
+        uint64_t before = 0;
+        for (uint32_t i = threadIdx.x; i < item; i += kBlock)
+            before += item_cnt[i];
+        uint64_t first;
+        block_exclusive_sum64<kBlock>(before, scratch64, &first);
+        const int jb = ij.job_of(item);
+        const fvv_grid g = jobs[jb].grid;
+        const int64_t n_words = fine_bitmap_words(g);
+        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
+        const int32_t wr = (g.dims[0] + 63) / 64;
+        EdgeMasks m{0ull, 0ull, 0ull, 0ull};
+        if (w < n_words)
+            m = edge_masks(bits + pre[jb].bit_off, w, g.dims, wr);
         uint32_t total;
-        uint32_t pos = item_base[item] + block_exclusive_sum<kBlock>((uint32_t)__popc(bits),
-                                                                     scratch, &total);
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1;
-            if (pos < max_points)
-                keys[pos] = 3u * (lin + (uint32_t)(b / 3)) + (uint32_t)(b % 3);
-            ++pos;
+        const uint32_t ex = block_exclusive_sum<kBlock>(edge_count(m), scratch, &total);
+        uint64_t pos = first + ex;
+        if (w < n_words) {
+            const int64_t row = w / wr;
+            const uint32_t lin0 =
+                (uint32_t)(row * g.dims[0] + (w - row * wr) * kWave);   // sample of bit 0
+            for (uint64_t b = m.ex | m.ey | m.ez; b; b &= b - 1) {
+                const int bit = __ffsll((unsigned long long)b) - 1;
+                const uint32_t key = 3u * (lin0 + (uint32_t)bit);
+                const float d = ((m.v >> bit) & 1u) ? 1.0f : -1.0f;
+#pragma unroll
+                for (int axis = 0; axis < 3; ++axis) {
+                    const uint64_t mk = axis == 0 ? m.ex : axis == 1 ? m.ey : m.ez;
+                    if ((mk >> bit) & 1u) {
+                        if (pos < max_points) {
+                            keys[pos] = key + (uint32_t)axis;
+                            xyz[3 * pos] = d;
+                        }
+                        ++pos;
+                    }
+                }
+            }
+        }
+        if (threadIdx.x == 0) {
+            const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
+            if (item == ij.first_item(jb))
+                point_off[jb] = clamp(first);
+            if (item + 1 == n_items) {
+                const uint64_t all = first + total;
+                point_off[nj] = clamp(all);
+                *n_points = clamp(all);
+                if (all > max_points)
+                    atomicOr(status, kFlagCapacity);
+            }
         }
     }
 }
@@ -223,34 +276,61 @@ __device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
 
 // One crossing edge per group of kLanesPerEdge lanes; lane `sub` of the group
 // owns cameras sub, sub + kLanesPerEdge, ...  Each lane first keeps the ones of
-// its cameras that can reject some point of the edge, then every bisection
-// step tests the midpoint against those, and a wave ballot ANDs the group.
-__global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restrict__ jobs,
+// its cameras that can reject some point of the edge (all their loads in
+// flight together).  The n_steps bisection steps then run two at a time: a
+// round tests the three points lo + (1, 2, 3) w/4 of the bracket [lo, lo + w]
+// and replays the two binary steps from them -- the first step tests the
+// midpoint (2), the second the midpoint of the half it kept (3 if 2 was
+// inside, else 1) -- so the final bracket is exactly that of n_steps binary
+// steps (all points are dyadic, exact in float).  A wave ballot ANDs the
+// group's cameras for each point.
+constexpr int kCullChunk = 4;      // cameras per lane whose culling loads are in flight together
+constexpr int kBisectJobs = 64;    // jobs whose lattices a workgroup keeps in LDS
+
+__global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ n_jobs_p,
                                                         const uint32_t* __restrict__ point_off,
-                                                        const uint8_t* __restrict__ occ_base,
                                                         const CamSet cams,
                                                         const uint32_t* __restrict__ sils,
                                                         int n_steps,
                                                         const uint32_t* __restrict__ keys,
                                                         float* __restrict__ xyz,
                                                         uint32_t max_points) {
-    constexpr int kPerLane = (FVV_MAX_CAMS + kLanesPerEdge - 1) / kLanesPerEdge;
     constexpr uint32_t kGroupMask = (1u << kLanesPerEdge) - 1u;
     constexpr uint32_t kEdgesPerBlock = kBlock / kLanesPerEdge;
+    __shared__ uint32_t s_off[kBisectJobs + 1];
+    __shared__ fvv_grid s_grid[kBisectJobs];
     const int nj = (int)*n_jobs_p;
-    const uint32_t total = point_off[nj];
+    const bool lds = nj <= kBisectJobs;
+    if (lds)
+        for (int j = threadIdx.x; j <= nj; j += kBlock) {
+            s_off[j] = point_off[j];
+            if (j < nj)
+                s_grid[j] = jobs[j].grid;
+        }
+    __syncthreads();
+    const uint32_t total = lds ? s_off[nj] : point_off[nj];
     const uint32_t E = total < max_points ? total : max_points;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
     const int sub = lane_id() % kLanesPerEdge;
     const int shift = lane_id() - sub;
-    for (uint32_t base = blockIdx.x * kEdgesPerBlock; base < E; base += gridDim.x * kEdgesPerBlock) {
-        const uint32_t e = base + threadIdx.x / kLanesPerEdge;
+    // camera slots per lane, rounded up to whole culling chunks (wave-uniform)
+    const int slots = (cams.n + kLanesPerEdge - 1) / kLanesPerEdge;
+    // contiguous edge ranges per XCD, in chunks of one block's edges
+    const XcdSlice xs = xcd_slice((E + kEdgesPerBlock - 1) / kEdgesPerBlock);
+    for (uint64_t chunk = xs.begin + xs.slot; chunk < xs.end; chunk += xs.stride) {
+        const uint32_t e = (uint32_t)chunk * kEdgesPerBlock + threadIdx.x / kLanesPerEdge;
         const bool act = e < E;
         const uint32_t ee = act ? e : E - 1;
-        const int jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, ee);
-        const fvv_grid g = jobs[jb].grid;
-        const int64_t out_offset = jobs[jb].out_offset;
+        int jb;
+        fvv_grid g;
+        if (lds) {
+            jb = upper_job([&](int m) { return (uint64_t)s_off[m]; }, nj, ee);
+            g = s_grid[jb];
+        } else {
+            jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, ee);
+            g = jobs[jb].grid;
+        }
         const uint32_t key = keys[ee];
         const uint32_t lin = key / 3u;
         const int axis = (int)(key - 3u * lin);
@@ -259,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
         const uint32_t j = r % (uint32_t)g.dims[1];
         const uint32_t k = r / (uint32_t)g.dims[1];
         const int gidx[3] = {g.lo[0] + (int)i, g.lo[1] + (int)j, g.lo[2] + (int)k};
-        const bool p_on = occ_base[out_offset + lin] != 0;
+        const bool p_on = xyz[3 * (int64_t)ee] > 0.0f;   // left there by the edge pass
         const int g_on = gidx[axis] + (p_on ? 0 : 1);
         const float d = p_on ? 1.0f : -1.0f;
         float c[3] = {lattice_coord(gidx[0], g.h, g.origin[0]),
@@ -267,34 +347,69 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                       lattice_coord(gidx[2], g.h, g.origin[2])};
         float X0[3] = {c[0], c[1], c[2]}, X1[3] = {c[0], c[1], c[2]};
         X1[axis] = lattice_coord(gidx[axis] + 1, g.h, g.origin[axis]);
-        uint32_t mine = 0;   // bit q: camera sub + q*kLanesPerEdge can reject
+        uint64_t mine = 0;   // bit q: camera sub + q*kLanesPerEdge can reject
+        for (int q0 = 0; q0 < slots; q0 += kCullChunk) {
+            bool acc[kCullChunk];
 #pragma unroll
-        for (int q = 0; q < kPerLane; ++q) {
-            const int cam = sub + q * kLanesPerEdge;
-            if (cam < cams.n && !camera_accepts_edge(cams, cam, sils + cam * cam_words, X0, X1))
-                mine |= 1u << q;
-        }
-        float lo = 0.0f, hi = 1.0f;
-        for (int s = 0; s < n_steps; ++s) {
-            const float m = 0.5f * (lo + hi);
-            const float q = (float)g_on + d * m;
-            const float ax = __builtin_fmaf(q, g.h, g.origin[axis]);
-            const float X = axis == 0 ? ax : c[0];
-            const float Y = axis == 1 ? ax : c[1];
-            const float Z = axis == 2 ? ax : c[2];
-            bool in = true;
-            for (uint32_t rest = mine; rest; rest &= rest - 1) {
-                const int cam = sub + (__ffs(rest) - 1) * kLanesPerEdge;
-                in = in && seen_inside(&cams.P[cam][0], X, Y, Z, sils + cam * cam_words, cams.W,
-                                       cams.H, cams.wpr);
+            for (int u = 0; u < kCullChunk; ++u) {
+                const int cam = sub + (q0 + u) * kLanesPerEdge;
+                const int cc = cam < cams.n ? cam : 0;
+                acc[u] = camera_accepts_edge(cams, cc, sils + cc * cam_words, X0, X1);
             }
-            const uint64_t fail = __ballot(!in);
-            if ((((uint32_t)(fail >> shift)) & kGroupMask) == 0)
-                lo = m;
-            else
-                hi = m;
+#pragma unroll
+            for (int u = 0; u < kCullChunk; ++u) {
+                const int cam = sub + (q0 + u) * kLanesPerEdge;
+                if (cam < cams.n && !acc[u])
+                    mine |= 1ull << (q0 + u);
+            }
+        }
+        float lo = 0.0f, w = 1.0f;
+        for (int s = 0; s < n_steps; s += 2) {
+            const bool two = s + 1 < n_steps;   // wave-uniform
+            const float w4 = 0.25f * w;
+            float pt[3] = {lo + w4, lo + 2.0f * w4, lo + 3.0f * w4};
+            float Xp[3], Yp[3], Zp[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const float qq = (float)g_on + d * pt[p];
+                const float ax = __builtin_fmaf(qq, g.h, g.origin[axis]);
+                Xp[p] = axis == 0 ? ax : c[0];
+                Yp[p] = axis == 1 ? ax : c[1];
+                Zp[p] = axis == 2 ? ax : c[2];
+            }
+            uint32_t in = 7u;   // bit p: point p inside every camera of this lane
+            for (uint64_t rest = mine; rest; rest &= rest - 1) {
+                // one camera per pass, the loads of its points in flight together
+                const int ca = sub + (__ffsll((unsigned long long)rest) - 1) * kLanesPerEdge;
+                const float* P3[3] = {&cams.P[ca][0], &cams.P[ca][0], &cams.P[ca][0]};
+                const uint32_t* S3[3] = {sils + ca * cam_words, sils + ca * cam_words,
+                                         sils + ca * cam_words};
+                if (two) {
+                    in &= multi_inside<3>(P3, Xp, Yp, Zp, S3, cams.W, cams.H, cams.wpr);
+                } else if (!(multi_inside<1>(P3, Xp + 1, Yp + 1, Zp + 1, S3, cams.W, cams.H,
+                                            cams.wpr) & 1u)) {
+                    in &= ~2u;
+                }
+            }
+            // the group's verdict per point: inside iff no lane saw it outside
+            bool ok[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const uint64_t fail = __ballot(((in >> p) & 1u) == 0u);
+                ok[p] = (((uint32_t)(fail >> shift)) & kGroupMask) == 0;
+            }
+            if (two) {
+                int idx = ok[1] ? (ok[2] ? 3 : 2) : (ok[0] ? 1 : 0);
+                lo = lo + (float)idx * w4;
+                w = w4;
+            } else {
+                if (ok[1])
+                    lo = pt[1];
+                w = 0.5f * w;
+            }
         }
         if (act && sub == 0) {
+            const float hi = lo + w;
             const float t = 0.5f * (lo + hi);
             const float q = (float)g_on + d * t;
             c[axis] = __builtin_fmaf(q, g.h, g.origin[axis]);
@@ -313,16 +428,14 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
     (void)max_jobs;
     const unsigned blocks = (unsigned)(ctx->n_cus * 8);
     hipLaunchKernelGGL(edge_count_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
-                       n_jobs_dev, occ_fine, ctx->d_item_cnt);
-    hipLaunchKernelGGL(edge_scan_kernel, dim3(1), dim3(1024), 0, s, ctx->d_prefix, n_jobs_dev,
-                       ctx->d_item_cnt, ctx->d_item_base, point_off, n_points, max_points,
-                       ctx->d_status);
+                       n_jobs_dev, ctx->d_finebits, ctx->d_item_cnt);
     hipLaunchKernelGGL(edge_write_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
-                       n_jobs_dev, occ_fine, ctx->d_item_base, keys, max_points);
+                       n_jobs_dev, ctx->d_finebits, ctx->d_item_cnt, keys, xyz, max_points,
+                       point_off, n_points, ctx->d_status);
     if (edges_done)
         (void)hipEventRecord(edges_done, s);
-    hipLaunchKernelGGL(bisect_kernel, dim3(ctx->n_cus * 16), dim3(kBlock), 0, s, jobs, n_jobs_dev,
-                       point_off, occ_fine, cams, sils, n_steps, keys, xyz, max_points);
+    hipLaunchKernelGGL(bisect_kernel, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs, n_jobs_dev,
+                       point_off, cams, sils, n_steps, keys, xyz, max_points);
     return hipGetLastError();
 }
 
