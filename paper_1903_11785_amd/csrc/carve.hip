@@ -367,7 +367,9 @@ __device__ __forceinline__ int classify_box(const CamSet& cams, int c,
             const uint32_t lo_m = wq == w0 ? ~0u << (cx0 & 31) : ~0u;
             const uint32_t hi_m = wq == w1 ? (~0u >> (31 - (cx1 & 31))) : ~0u;
             const uint32_t m = on ? (lo_m & hi_m) : 0u;
-            const uint32_t v = row[on ? wq : w0];
+            uint32_t v = 0;
+            if (on)
+                v = row[wq];
             any |= (v & m) != 0u;
             all &= (v & m) == m;
         }
@@ -444,20 +446,22 @@ __device__ __forceinline__ void carve_tile_culled(const CamSet& cams,
             const float X = lattice_coord(g.lo[0] + i0 + lx, g.h, g.origin[0]);
             const float Y = lattice_coord(g.lo[1] + j0 + ly, g.h, g.origin[1]);
             const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
-            // wave-uniform: the sub-block's mixed cameras, two per pass (the
-            // second repeats the first when one is left)
+            // wave-uniform: the sub-block's mixed cameras, two per pass
             uint32_t rest = s_mixed[b];
             while (rest && __ballot(alive) != 0) {
                 const int ca = __ffs(rest) - 1;
                 rest &= rest - 1;
-                int cb = ca;
                 if (rest) {
-                    cb = __ffs(rest) - 1;
+                    const int cb = __ffs(rest) - 1;
                     rest &= rest - 1;
+                    const float* P2[2] = {&cams.P[ca][0], &cams.P[cb][0]};
+                    const uint32_t* S2[2] = {sils + ca * cam_words, sils + cb * cam_words};
+                    alive = alive && group_inside<2>(P2, X, Y, Z, S2, cams.W, cams.H, cams.wpr);
+                } else {
+                    const float* P1[1] = {&cams.P[ca][0]};
+                    const uint32_t* S1[1] = {sils + ca * cam_words};
+                    alive = alive && group_inside<1>(P1, X, Y, Z, S1, cams.W, cams.H, cams.wpr);
                 }
-                const float* P2[2] = {&cams.P[ca][0], &cams.P[cb][0]};
-                const uint32_t* S2[2] = {sils + ca * cam_words, sils + cb * cam_words};
-                alive = alive && group_inside<2>(P2, X, Y, Z, S2, cams.W, cams.H, cams.wpr);
             }
         }
         s_occ[lx + TX * (ly + TY * lz)] = alive ? 1 : 0;

@@ -266,12 +266,21 @@ __device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
     const int w0 = x0 >> 5, w1 = x1 >> 5;
     const uint32_t m0 = w0 == w1 ? (2u << (x1 & 31)) - (1u << (x0 & 31)) : 0u - (1u << (x0 & 31));
     const uint32_t m1 = w0 == w1 ? 0u : (2u << (x1 & 31)) - 1u;
-    // the four words are loaded together (unused ones repeat a used one)
+    // only the words the rectangle covers are loaded, all of them together
     const uint32_t* r0 = sil + y0 * cams.wpr;
     const uint32_t* r1 = sil + y1 * cams.wpr;
-    const uint32_t a00 = r0[w0], a01 = r0[w1], a10 = r1[w0], a11 = r1[w1];
-    return small && (a00 & m0) == m0 && (a01 & m1) == m1 && (a10 & m0) == m0 &&
-           (a11 & m1) == m1;
+    const bool two_w = w1 != w0, two_r = y1 != y0;
+    uint32_t a00 = 0, a01 = 0, a10 = 0, a11 = 0;
+    if (small)
+        a00 = r0[w0];
+    if (small && two_w)
+        a01 = r0[w1];
+    if (small && two_r)
+        a10 = r1[w0];
+    if (small && two_w && two_r)
+        a11 = r1[w1];
+    return small && (a00 & m0) == m0 && (a01 & m1) == m1 && (!two_r || (a10 & m0) == m0) &&
+           (!two_r || (a11 & m1) == m1);
 }
 
 // One crossing edge per group of kLanesPerEdge lanes; lane `sub` of the group
@@ -314,8 +323,7 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
     const int sub = lane_id() % kLanesPerEdge;
     const int shift = lane_id() - sub;
-    // camera slots per lane, rounded up to whole culling chunks (wave-uniform)
-    const int slots = (cams.n + kLanesPerEdge - 1) / kLanesPerEdge;
+    const uint32_t all_cams = cams.n >= 32 ? ~0u : (1u << cams.n) - 1u;
     // contiguous edge ranges per XCD, in chunks of one block's edges
     const XcdSlice xs = xcd_slice((E + kEdgesPerBlock - 1) / kEdgesPerBlock);
     for (uint64_t chunk = xs.begin + xs.slot; chunk < xs.end; chunk += xs.stride) {
@@ -347,21 +355,45 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
                       lattice_coord(gidx[2], g.h, g.origin[2])};
         float X0[3] = {c[0], c[1], c[2]}, X1[3] = {c[0], c[1], c[2]};
         X1[axis] = lattice_coord(gidx[axis] + 1, g.h, g.origin[axis]);
-        uint64_t mine = 0;   // bit q: camera sub + q*kLanesPerEdge can reject
-        for (int q0 = 0; q0 < slots; q0 += kCullChunk) {
-            bool acc[kCullChunk];
+        const uint32_t cand = all_cams;
+        // per edge, the candidates go round-robin to the group's lanes; each
+        // keeps the ones whose padded rectangle around the edge is not all
+        // foreground, kCullChunk cameras' loads in flight at a time
+        uint32_t keep = 0;
+        {
+            uint32_t my = 0;
+            int n = 0;
+            for (uint32_t m = cand; m; m &= m - 1, ++n)
+                if ((n & (kLanesPerEdge - 1)) == sub)
+                    my |= m & (0u - m);
+            while (my) {
+                int cs[kCullChunk];
+                uint32_t took = 0;
 #pragma unroll
-            for (int u = 0; u < kCullChunk; ++u) {
-                const int cam = sub + (q0 + u) * kLanesPerEdge;
-                const int cc = cam < cams.n ? cam : 0;
-                acc[u] = camera_accepts_edge(cams, cc, sils + cc * cam_words, X0, X1);
-            }
+                for (int u = 0; u < kCullChunk; ++u) {
+                    cs[u] = my ? __ffs(my) - 1 : cs[0];
+                    took |= my & (0u - my);
+                    my &= my - 1;
+                }
+                bool acc[kCullChunk];
 #pragma unroll
-            for (int u = 0; u < kCullChunk; ++u) {
-                const int cam = sub + (q0 + u) * kLanesPerEdge;
-                if (cam < cams.n && !acc[u])
-                    mine |= 1ull << (q0 + u);
+                for (int u = 0; u < kCullChunk; ++u)
+                    acc[u] = camera_accepts_edge(cams, cs[u], sils + cs[u] * cam_words, X0, X1);
+#pragma unroll
+                for (int u = 0; u < kCullChunk; ++u)
+                    if (!acc[u])
+                        keep |= (1u << cs[u]) & took;
             }
+        }
+        // the group's kept cameras, then again round-robin over its lanes
+        keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0xB1, 0xf, 0xf, false);  // quad [1,0,3,2]
+        keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0x4E, 0xf, 0xf, false);  // quad [2,3,0,1]
+        uint32_t mine = 0;
+        {
+            int n = 0;
+            for (uint32_t m = keep; m; m &= m - 1, ++n)
+                if ((n & (kLanesPerEdge - 1)) == sub)
+                    mine |= m & (0u - m);
         }
         float lo = 0.0f, w = 1.0f;
         for (int s = 0; s < n_steps; s += 2) {
@@ -378,9 +410,9 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
                 Zp[p] = axis == 2 ? ax : c[2];
             }
             uint32_t in = 7u;   // bit p: point p inside every camera of this lane
-            for (uint64_t rest = mine; rest; rest &= rest - 1) {
+            for (uint32_t rest = mine; rest; rest &= rest - 1) {
                 // one camera per pass, the loads of its points in flight together
-                const int ca = sub + (__ffsll((unsigned long long)rest) - 1) * kLanesPerEdge;
+                const int ca = __ffs(rest) - 1;
                 const float* P3[3] = {&cams.P[ca][0], &cams.P[ca][0], &cams.P[ca][0]};
                 const uint32_t* S3[3] = {sils + ca * cam_words, sils + ca * cam_words,
                                          sils + ca * cam_words};
@@ -426,6 +458,7 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                           uint32_t max_points, uint32_t* point_off, uint32_t* n_points,
                           hipEvent_t edges_done, hipStream_t s) {
     (void)max_jobs;
+    (void)occ_fine;
     const unsigned blocks = (unsigned)(ctx->n_cus * 8);
     hipLaunchKernelGGL(edge_count_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
                        n_jobs_dev, ctx->d_finebits, ctx->d_item_cnt);
