@@ -46,7 +46,48 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-baseline time budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fine-tile", default="64x4", help="TXxTZ of the fine carve")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing (a known-size "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
+
+
+# Kernels whose roofline the bench reports: the stage that brackets each, its
+# source files (a stored counter measurement is used only while they are
+# unchanged) and the stored measurement.
+KERNELS = {
+    "fine_carve": {"kernel": "carve_frame_kernel", "stage": "fine_carve",
+                   "sources": ["paper_1903_11785_amd/csrc/carve.hip",
+                               "paper_1903_11785_amd/csrc/fvv_internal.h"],
+                   "traffic": "profiles/carve_frame_kernel_volleyball_traffic.json"},
+    "exit_points": {"kernel": "bisect_kernel", "stage": "exit_points",
+                    "sources": ["paper_1903_11785_amd/csrc/surface.hip",
+                                "paper_1903_11785_amd/csrc/fvv_internal.h"],
+                    "traffic": "profiles/bisect_kernel_volleyball_traffic.json"},
+}
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(k):
+    """HBM bytes per launch from the stored counter runs, if the kernel's sources
+    are those the counters were taken on; else None."""
+    spec = KERNELS[k]
+    path = os.path.join(ROOT, spec["traffic"])
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != sources_sha256(spec["sources"]):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def pct(xs, q):
@@ -64,7 +105,9 @@ def cpu_baseline(frames, budget_s):
                          sc.t_nb, sc.n_steps)
         spent += time.perf_counter() - t0
         done_vox += r.fine_voxels
-        tests[n % len(frames)] = (r.fine_voxels, r.tests_fine)
+        tests[n % len(frames)] = {"vox": r.fine_voxels, "tests_fine": r.tests_fine,
+                                  "edges": int(sum(k.size for k in r.keys)),
+                                  "tests_surface": r.tests_surface}
         n += 1
     return {"value": done_vox / spent, "unit": "fine voxels/s", "cores": oracle.threads(),
             "kind": "oracle",
@@ -102,6 +145,7 @@ def main():
     # per-frame work (from one eager run each) and the per-stage split
     fine_vox, rois, points = [], [], []
     stage_ms = {s: [] for s in fvv.STAGES}
+    stage_ms_frame = {s: [[] for _ in masks] for s in fvv.STAGES}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(fvv.FRAME_EVENTS)]
     for f, m in enumerate(masks):
         for rep in range(max(1, args.stage_reps)):
@@ -109,13 +153,24 @@ def main():
             torch.cuda.synchronize()
             if rep > 0:
                 for i, s in enumerate(fvv.STAGES):
-                    stage_ms[s].append(ev[i].elapsed_time(ev[i + 1]))
+                    dt = ev[i].elapsed_time(ev[i + 1])
+                    stage_ms[s].append(dt)
+                    stage_ms_frame[s][f].append(dt)
         if ctx.check() != fvv.FVV_OK:
             raise RuntimeError("frame exceeded a capacity")
         c = bufs.counts.cpu().numpy()
         rois.append(int(c[0]))
         fine_vox.append(int(c[1]))
         points.append(int(c[2]))
+
+    if args.calib_copy_mib > 0:              # known-size reference for byte counters
+        a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     graphs = [ctx.frame_graph(params, sils, bufs, masks=m) for m in masks]
     for k in range(args.warmup):
@@ -138,9 +193,6 @@ def main():
     wall = t1 - t0
     value = total_fine / wall
 
-    # dominant kernel: the persistent fine carve (with its one-workgroup job
-    # builder), timed by the stage events of the eager runs
-    fine_ms = float(np.mean(stage_ms["fine_carve"]))
     result = {
         "metric": METRIC,
         "value": value,
@@ -162,29 +214,37 @@ def main():
                    "fine_tile": [tx, 256 // tx, tz]},
         "latency_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99), "mean": float(np.mean(lat_ms))},
         "stages_ms": {s: float(np.mean(v)) for s, v in stage_ms.items()},
-        "fine_carve_voxels_per_s": float(np.mean(fine_vox)) / (fine_ms * 1e-3),
     }
 
     tests = {}
     if not args.no_cpu_baseline:
         result["cpu_baseline"], tests = cpu_baseline(frames, args.cpu_seconds)
 
-    # roofline of the dominant kernel: per fine voxel 1 B of occupancy written
-    # plus one 4-byte silhouette word per (voxel, camera) test of the
-    # index-order early exit (T, counted by the CPU baseline's run on the
-    # same frames)
+    # Rooflines (HBM, algorithmic bytes per launch / stage time of the eager
+    # runs, whose events bracket the kernel on its stream):
+    #   fine carve:  per fine voxel 1 B of occupancy written, plus one 4-byte
+    #                silhouette word per (voxel, camera) test of the index-order
+    #                early exit (counted by the oracle on the same frames);
+    #   exit points: per crossing edge 16 B written (key, xyz), plus one 4-byte
+    #                word per (point, camera) test of the index-order early exit.
+    # The kernel with the longer stage is the dominant one, reported as
+    # "roofline"; both are listed under "rooflines".
     if tests:
-        vox = sum(tests[f][0] for f in tests)
-        T = sum(tests[f][1] for f in tests)
-        fine_ms_f = float(np.mean([stage_ms["fine_carve"][i] for i in range(len(stage_ms["fine_carve"]))
-                                   if (i // max(1, args.stage_reps - 1)) in tests]))
-        bytes_per_launch = (vox + 4 * T) / len(tests)
-        achieved = bytes_per_launch / (fine_ms_f * 1e-3) / 1e9
-        result["roofline"] = {"kernel": "fine carve (carve_persistent + frame_jobs)",
-                              "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                              "bytes_per_launch": bytes_per_launch,
-                              "tests_per_voxel": T / vox}
+        rl = {}
+        for k, spec in KERNELS.items():
+            ms = float(np.mean([np.mean(stage_ms_frame[spec["stage"]][f]) for f in tests]))
+            if k == "fine_carve":
+                per = np.mean([tests[f]["vox"] + 4 * tests[f]["tests_fine"] for f in tests])
+            else:
+                per = np.mean([16 * tests[f]["edges"] + 4 * tests[f]["tests_surface"] for f in tests])
+            achieved = per / (ms * 1e-3) / 1e9
+            rl[k] = {"kernel": spec["kernel"], "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(k), "bytes_per_launch": float(per),
+                     "stage_ms": ms}
+        dominant = max(rl, key=lambda k: rl[k]["stage_ms"])
+        result["roofline"] = rl[dominant]
+        result["rooflines"] = rl
     print(json.dumps(result))
 
 

@@ -60,6 +60,7 @@ def lib():
         L.orc_edges.restype = i64
         L.orc_bisect.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, f32, p, p, p, p, i64,
                                  C.c_int, p, p]
+        L.orc_bisect.restype = i64
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
         L.orc_threads.restype = i32
@@ -161,8 +162,10 @@ def edges(occ: np.ndarray) -> np.ndarray:
     return keys[:E].copy()
 
 
-def bisect(P, sils, W, H, lat: Lattice, occ: np.ndarray, keys: np.ndarray, steps: int = 8
-           ) -> Tuple[np.ndarray, np.ndarray]:
+def bisect(P, sils, W, H, lat: Lattice, occ: np.ndarray, keys: np.ndarray, steps: int = 8,
+           count_tests: bool = False):
+    """Exit points (xyz, t*) of the crossing edges; with count_tests also the
+    number of (point, camera) tests of the index-order early exit."""
     P = np.ascontiguousarray(P, dtype=np.float32).reshape(-1, 12)
     sils = np.ascontiguousarray(sils, dtype=np.uint32)
     occ = np.ascontiguousarray(occ, dtype=np.uint8)
@@ -170,8 +173,11 @@ def bisect(P, sils, W, H, lat: Lattice, occ: np.ndarray, keys: np.ndarray, steps
     E = keys.size
     xyz = np.empty((max(E, 1), 3), np.float32)
     t = np.empty(max(E, 1), np.float32)
-    lib().orc_bisect(P.shape[0], _p(P), W, H, _p(sils), _p(_f3(lat.origin)), np.float32(lat.h),
-                     _p(_i3(lat.lo)), _p(_i3(lat.dims)), _p(occ), _p(keys), E, steps, _p(xyz), _p(t))
+    T = lib().orc_bisect(P.shape[0], _p(P), W, H, _p(sils), _p(_f3(lat.origin)),
+                         np.float32(lat.h), _p(_i3(lat.lo)), _p(_i3(lat.dims)), _p(occ), _p(keys),
+                         E, steps, _p(xyz), _p(t))
+    if count_tests:
+        return xyz[:E].copy(), t[:E].copy(), int(T)
     return xyz[:E].copy(), t[:E].copy()
 
 
@@ -197,6 +203,7 @@ class FrameResult:
     tstar: List[np.ndarray] = field(default_factory=list)
     tests_coarse: int = 0
     tests_fine: int = 0
+    tests_surface: int = 0          # (point, camera) tests of the bisection
 
     @property
     def fine_voxels(self) -> int:
@@ -225,7 +232,8 @@ def frame(masks: np.ndarray, P: np.ndarray, origin, hc_um: int, hf_um: int,
         res.tests_fine += Tf
         if surface:
             keys = edges(of)
-            xyz, t = bisect(P, sils, W, H, lat, of, keys, steps)
+            xyz, t, Ts = bisect(P, sils, W, H, lat, of, keys, steps, count_tests=True)
+            res.tests_surface += Ts
             res.keys.append(keys)
             res.xyz.append(xyz)
             res.tstar.append(t)

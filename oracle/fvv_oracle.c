@@ -349,12 +349,13 @@ int64_t orc_edges(const int32_t *n, const uint8_t *occ, uint32_t *keys, int64_t 
  * with the axis coordinate computed as fmaf(g_on + d*t*, h, o) (d = +1 or -1
  * toward the OFF endpoint) and the other two coordinates as lattice values.
  */
-void orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
-                const float *o, float h, const int32_t *lo, const int32_t *n,
-                const uint8_t *occ, const uint32_t *keys, int64_t E, int steps,
-                float *xyz, float *tstar)
+int64_t orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
+                   const float *o, float h, const int32_t *lo, const int32_t *n,
+                   const uint8_t *occ, const uint32_t *keys, int64_t E, int steps,
+                   float *xyz, float *tstar)
 {
-#pragma omp parallel for schedule(static)
+    int64_t tests = 0;
+#pragma omp parallel for schedule(static) reduction(+ : tests)
     for (int64_t e = 0; e < E; ++e) {
         int64_t lin = keys[e] / 3;
         int axis = (int)(keys[e] % 3);
@@ -381,6 +382,7 @@ void orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
                 tlo = m;
             else
                 thi = m;
+            tests += nt;
         }
         float t = 0.5f * (tlo + thi);
         float q = (float)g_on + d * t;
@@ -390,6 +392,7 @@ void orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
         xyz[3 * e + 2] = c[2];
         tstar[e] = t;
     }
+    return tests;
 }
 
 /* Single world point against all cameras (for checks of the occupancy test). */

@@ -35,29 +35,46 @@ constexpr int kRunCap = 6144;    // runs held in LDS
 constexpr int kRootCap = 1024;   // components whose stats are held in LDS
 
 // ------------------------------------------------------------------ union-find
+// Loads and stores of values other threads change concurrently: relaxed
+// atomics, at workgroup scope in LDS (plain ds instructions) and at agent
+// scope in the global-scratch twin (past the per-CU cache).
+template <bool kLds>
+__device__ __forceinline__ int32_t ld(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED,
+                             kLds ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool kLds>
+__device__ __forceinline__ void st(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED,
+                       kLds ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Root of x with path halving: each visited node is re-pointed at its
 // grandparent.  Links only ever change roots (CAS on a node that is still a
 // root), and a re-pointed node still reaches the same root through an
 // ancestor, so halving races with neither links nor other finds.
-__device__ __forceinline__ int32_t find_root(volatile int32_t* P, int32_t x) {
+template <bool kLds>
+__device__ __forceinline__ int32_t find_root(int32_t* P, int32_t x) {
     for (;;) {
-        const int32_t p = P[x];
+        const int32_t p = ld<kLds>(P + x);
         if (p == x)
             return x;
-        const int32_t gp = P[p];
+        const int32_t gp = ld<kLds>(P + p);
         if (gp == p)
             return p;
-        P[x] = gp;
+        st<kLds>(P + x, gp);
         x = gp;
     }
 }
 
 // Link the roots of runs a and b: the larger run id under the smaller, with a
 // CAS that only succeeds while the node is still a root; retry otherwise.
+template <bool kLds>
 __device__ __forceinline__ void unite(int32_t* P, int32_t a, int32_t b) {
     for (;;) {
-        a = find_root(P, a);
-        b = find_root(P, b);
+        a = find_root<kLds>(P, a);
+        b = find_root<kLds>(P, b);
         if (a == b)
             return;
         if (a < b) {
@@ -65,7 +82,10 @@ __device__ __forceinline__ void unite(int32_t* P, int32_t a, int32_t b) {
             a = b;
             b = t;
         }
-        if (atomicCAS(&P[a], a, b) == a)
+        int32_t expect = a;
+        if (__hip_atomic_compare_exchange_strong(
+                P + a, &expect, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                kLds ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT))
             return;
     }
 }
@@ -267,9 +287,10 @@ __device__ __forceinline__ int32_t row_index(const RunArrays& m, int32_t r) {
 }
 
 // Rank of the component of run k (P flattened and ranked).
-__device__ __forceinline__ int32_t rank_of(const volatile int32_t* P, int32_t k) {
-    const int32_t p = P[k];
-    return p < 0 ? -1 - p : -1 - P[p];
+template <bool kLds>
+__device__ __forceinline__ int32_t rank_of(const int32_t* P, int32_t k) {
+    const int32_t p = ld<kLds>(P + k);
+    return p < 0 ? -1 - p : -1 - ld<kLds>(P + p);
 }
 
 // Row-mask word w with the bits of rows >= R cleared, and word q of a row
@@ -290,9 +311,7 @@ constexpr int kStatCount = 0, kStatLo = 1, kStatHi = 4, kStatMin = 7;
 
 template <bool kLdsStats>
 __device__ __forceinline__ int32_t stat_load(const int32_t* s) {
-    if (kLdsStats)
-        return *(const volatile int32_t*)s;
-    return __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ld<kLdsStats>(s);
 }
 
 // Stats of every component (one set of atomics per run), the Eq. (1) filter
@@ -316,7 +335,7 @@ __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunAr
         const int32_t r = m.rows[m.rrow[k]];
         const int32_t y = r % a.ny, z = r / a.ny;
         const int2 x = get_run<kLds>(m, k);
-        int32_t* s = stats + (int64_t)kStatsRow * rank_of(m.P, k);
+        int32_t* s = stats + (int64_t)kStatsRow * rank_of<kLds>(m.P, k);
         atomicAdd(&s[kStatCount], x.y - x.x + 1);
         atomicMin(&s[kStatLo + 0], x.x);
         atomicMax(&s[kStatHi + 0], x.y);
@@ -356,6 +375,37 @@ __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunAr
         K += total;
     }
     *Kout = K;
+}
+
+// Every run b adjacent to run k in an earlier neighbouring row: (y-1, z) and
+// (y-1..y+1, z-1).  A row's runs ascend in x, so the scan of a row stops at
+// the first run starting past k's reach.
+template <bool kLds, typename F>
+__device__ __forceinline__ void for_each_earlier_adjacent(const LabelArgs& a, const RunArrays& m,
+                                                          int32_t k, F f) {
+    const int32_t r = m.rows[m.rrow[k]];
+    const int32_t y = r % a.ny, z = r / a.ny;
+    const int2 xk = get_run<kLds>(m, k);
+    int32_t jn[4];
+    jn[0] = y > 0 ? row_index(m, r - 1) : -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int32_t yy = y - 1 + d;
+        jn[1 + d] = (z > 0 && yy >= 0 && yy < a.ny) ? row_index(m, r - a.ny - 1 + d) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (jn[q] < 0)
+            continue;
+        const int32_t be = m.rs[jn[q] + 1];
+        for (int32_t b = m.rs[jn[q]]; b < be; ++b) {
+            const int2 xb = get_run<kLds>(m, b);
+            if (xb.x > xk.y + 1)
+                break;
+            if (xb.y + 1 >= xk.x)
+                f(b);
+        }
+    }
 }
 
 // The labelling with rows, runs and forest in `m`.  With kLds, gives up
@@ -456,79 +506,49 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     if (threadIdx.x == 0)
         m.rs[n_rows] = n_runs;
     __syncthreads();
-    // 3. unite every run with the adjacent runs of its earlier neighbouring
-    //    rows: (y-1, z) and (y-1..y+1, z-1); a row's runs ascend in x, so the
-    //    scan stops at the first run starting past this one's reach
-    for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
-        const int32_t r = m.rows[m.rrow[k]];
-        const int32_t y = r % a.ny, z = r / a.ny;
-        const int2 xk = get_run<kLds>(m, k);
-        int32_t jn[4];
-        jn[0] = y > 0 ? row_index(m, r - 1) : -1;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int32_t yy = y - 1 + d;
-            jn[1 + d] = (z > 0 && yy >= 0 && yy < a.ny) ? row_index(m, r - a.ny - 1 + d) : -1;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (jn[q] < 0)
-                continue;
-            const int32_t be = m.rs[jn[q] + 1];
-            for (int32_t b = m.rs[jn[q]]; b < be; ++b) {
-                const int2 xb = get_run<kLds>(m, b);
-                if (xb.x > xk.y + 1)
-                    break;
-                if (xb.y + 1 >= xk.x)
-                    unite(m.P, k, b);
-            }
-        }
-    }
+    // 3. unite every run with the adjacent runs of its earlier neighbouring rows
+    for (int32_t k = threadIdx.x; k < n_runs; k += NT)
+        for_each_earlier_adjacent<kLds>(a, m, k, [&](int32_t b) { unite<kLds>(m.P, k, b); });
     __syncthreads();
     // 4. flatten, then number the roots in ascending run id.  The walk only
     //    reads: the sole writes now set a node to its root, which keeps every
     //    concurrent walk on course (path halving here could store a
     //    grandparent over a root written meanwhile).
     for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
-        volatile int32_t* P = m.P;
         int32_t x = k;
-        for (int32_t p = P[x]; p != x; p = P[x])
+        for (int32_t p = ld<kLds>(m.P + x); p != x; p = ld<kLds>(m.P + x))
             x = p;
-        P[k] = x;
+        st<kLds>(m.P + k, x);
     }
     __syncthreads();
     int32_t K_all = 0;
     for (int32_t base = 0; base < n_runs; base += NT) {
         const int32_t k = base + threadIdx.x;
-        const bool root = k < n_runs && ((volatile int32_t*)m.P)[k] == k;
+        const bool root = k < n_runs && ld<kLds>(m.P + k) == k;
         uint32_t total;
         const uint32_t rk = block_exclusive_sum<NT>(root ? 1u : 0u, scan, &total);
         if (root)
-            m.P[k] = -1 - (K_all + (int32_t)rk);
+            st<kLds>(m.P + k, -1 - (K_all + (int32_t)rk));
         K_all += (int32_t)total;
     }
     __syncthreads();
     // 5. stats, filter, ROI table (stats rows in LDS while the components fit;
     //    the label of each rank follows the rows)
     uint32_t K = 0;
-    int32_t* stats;
-    int32_t* lab;
     const bool lds_stats_ok = K_all <= kRootCap;
-    int32_t* rank_of_label = lds_stats_ok ? m.rs : a.g.rs;
-    if (lds_stats_ok) {
-        stats = lds_stats;
-        lab = lds_stats + (int64_t)kStatsRow * kRootCap;
-        stats_and_select<kLds, true>(a, m, n_runs, K_all, stats, lab, rank_of_label, scan, &K);
-    } else {
-        stats = a.gstats;
-        lab = a.gstats + (int64_t)kStatsRow * K_all;
-        stats_and_select<kLds, false>(a, m, n_runs, K_all, stats, lab, rank_of_label, scan, &K);
-    }
+    if (lds_stats_ok)
+        stats_and_select<kLds, true>(a, m, n_runs, K_all, lds_stats,
+                                     lds_stats + (int64_t)kStatsRow * kRootCap, m.rs, scan, &K);
+    else
+        stats_and_select<kLds, false>(a, m, n_runs, K_all, a.gstats,
+                                      a.gstats + (int64_t)kStatsRow * K_all, a.g.rs, scan, &K);
     __syncthreads();
     // 6. labels of the occupied samples; the bitmap cleared for the next call
     for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
         const int64_t row_lin = (int64_t)a.nx * m.rows[m.rrow[k]];
-        const int32_t l = ((volatile int32_t*)lab)[rank_of(m.P, k)];
+        const int32_t rk = rank_of<kLds>(m.P, k);
+        const int32_t l = lds_stats_ok ? ld<true>(lds_stats + (int64_t)kStatsRow * kRootCap + rk)
+                                       : ld<false>(a.gstats + (int64_t)kStatsRow * K_all + rk);
         const int2 x = get_run<kLds>(m, k);
         for (int32_t xi = x.x; xi <= x.y; ++xi)
             a.sample_label[row_lin + xi] = l;
@@ -548,11 +568,20 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     if (kJobs) {
         __syncthreads();
         auto box = [&](uint32_t t, int32_t* lo, int32_t* hi) {
-            const int32_t* s = stats + (int64_t)kStatsRow * rank_of_label[t];
+            if (lds_stats_ok) {
+                const int32_t* s = lds_stats + (int64_t)kStatsRow * m.rs[t];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                lo[e] = lds_stats_ok ? stat_load<true>(&s[kStatLo + e]) : stat_load<false>(&s[kStatLo + e]);
-                hi[e] = lds_stats_ok ? stat_load<true>(&s[kStatHi + e]) : stat_load<false>(&s[kStatHi + e]);
+                for (int e = 0; e < 3; ++e) {
+                    lo[e] = ld<true>(&s[kStatLo + e]);
+                    hi[e] = ld<true>(&s[kStatHi + e]);
+                }
+            } else {
+                const int32_t* s = a.gstats + (int64_t)kStatsRow * ld<false>(a.g.rs + t);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    lo[e] = ld<false>(&s[kStatLo + e]);
+                    hi[e] = ld<false>(&s[kStatHi + e]);
+                }
             }
         };
         build_fine_jobs<NT>(fj, box, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);

@@ -8,9 +8,9 @@
 // counts each item's edges; a second sums the counts of the items before it
 // and writes the keys 3*lin+axis in ascending order (a thread's keys are in
 // order, and a block scan orders the threads).  Exit points: a group of four
-// lanes per edge, each owning a quarter of the cameras; a first pass keeps the
-// cameras that can reject some point of the edge at all, and the bisection
-// tests only those, two steps per round.
+// lanes per edge sharing its cameras; a first pass keeps the cameras that can
+// reject some point of the edge at all, and the bisection tests only those,
+// two steps per round.
 #include "fvv_internal.h"
 
 namespace fvv {
@@ -283,10 +283,11 @@ __device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
            (!two_r || (a11 & m1) == m1);
 }
 
-// One crossing edge per group of kLanesPerEdge lanes; lane `sub` of the group
-// owns cameras sub, sub + kLanesPerEdge, ...  Each lane first keeps the ones of
-// its cameras that can reject some point of the edge (all their loads in
-// flight together).  The n_steps bisection steps then run two at a time: a
+// One crossing edge per group of kLanesPerEdge lanes, which share its cameras
+// round-robin: each lane first keeps the ones of its cameras that can reject
+// some point of the edge (kCullChunk cameras' loads in flight together), the
+// group pools the kept ones and shares them out again.  The n_steps bisection
+// steps then run two at a time: a
 // round tests the three points lo + (1, 2, 3) w/4 of the bracket [lo, lo + w]
 // and replays the two binary steps from them -- the first step tests the
 // midpoint (2), the second the midpoint of the half it kept (3 if 2 was
@@ -386,8 +387,10 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
             }
         }
         // the group's kept cameras, then again round-robin over its lanes
+        static_assert(kLanesPerEdge == 2 || kLanesPerEdge == 4, "lane groups are DPP quads or pairs");
         keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0xB1, 0xf, 0xf, false);  // quad [1,0,3,2]
-        keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0x4E, 0xf, 0xf, false);  // quad [2,3,0,1]
+        if (kLanesPerEdge == 4)
+            keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0x4E, 0xf, 0xf, false);  // [2,3,0,1]
         uint32_t mine = 0;
         {
             int n = 0;

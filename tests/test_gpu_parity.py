@@ -309,10 +309,10 @@ def test_batched_equals_per_roi_and_oracle(fvv, ctx):
 
 # ------------------------------------------------------------------ whole frame
 def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, graph=False,
-              pack_first=False):
+              pack_first=False, coarse_tile=None, fine_tile=None):
     coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
     params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
-                              sc.n_steps)
+                              sc.n_steps, coarse_tile=coarse_tile, fine_tile=fine_tile)
     bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
     import torch
     masks = dev(sc.masks)
@@ -364,6 +364,31 @@ def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
     res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
                        sc.t_nb, sc.n_steps)
     _, bufs, _ = run_frame(fvv, ctx, sc, pack_first=(frame % 2 == 1))
+    assert ctx.check() == fvv.FVV_OK
+    compare_frame(fvv, sc, bufs, res)
+
+
+_frame_oracle = {}
+
+
+def oracle_frame(sc, cfg, frame):
+    key = (cfg, frame)
+    if key not in _frame_oracle:
+        _frame_oracle[key] = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um,
+                                          sc.coarse_dims, sc.t_np, sc.t_nb, sc.n_steps)
+    return _frame_oracle[key]
+
+
+# coarse tiles of 32 and 16 samples in x OR their bits into shared bitmap
+# words; fine tiles of depth 4 take the culled carve at every width, other
+# depths the batched carve
+@pytest.mark.parametrize("cfg,frame,ct,ft", [
+    (1, 0, (32, 2), (32, 4)), (1, 1, (16, 1), (16, 4)), (1, 2, (64, 2), (64, 2)),
+    (1, 0, (16, 4), (32, 8)), (2, 0, (32, 1), (16, 4)), (2, 1, (64, 1), (32, 4))])
+def test_frame_tile_shapes(fvv, ctx, scene_cache, cfg, frame, ct, ft):
+    sc = scene_cache(cfg, frame)
+    res = oracle_frame(sc, cfg, frame)
+    _, bufs, _ = run_frame(fvv, ctx, sc, coarse_tile=fvv.tile(*ct), fine_tile=fvv.tile(*ft))
     assert ctx.check() == fvv.FVV_OK
     compare_frame(fvv, sc, bufs, res)
 

@@ -263,3 +263,18 @@ def test_bisection_brackets_are_consistent(scene_cache):
             q = np.float32(np.float32(g_on) + d * np.float32(tt))
             c[axis] = np.float32(np.float64(q) * np.float64(lat.h) + np.float64(lat.origin[axis]))
             assert oracle.point_inside(sc.P32, sils, sc.W, sc.H, *c) in (want, not want)
+
+
+def test_bisection_test_count_bounds(scene_cache):
+    """The bisection's (point, camera) test count of the index-order early exit:
+    every step tests at least the first camera and at most all of them, and
+    with a single camera exactly one per step."""
+    sc = scene_cache(1, 0)
+    res = _surface(sc)
+    lat, occ, keys = res.fine[0], res.occ_fine[0], res.keys[0]
+    E, S, N = keys.size, sc.n_steps, sc.P32.shape[0]
+    _, _, T = oracle.bisect(sc.P32, res.sils, sc.W, sc.H, lat, occ, keys, S, count_tests=True)
+    assert E > 0 and S * E <= T <= S * E * N
+    _, _, T1 = oracle.bisect(sc.P32[:1], res.sils[:1], sc.W, sc.H, lat, occ, keys, S,
+                             count_tests=True)
+    assert T1 == S * E
