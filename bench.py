@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-baseline time budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fine-tile", default="64x4", help="TXxTZ of the fine carve")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-carve leg")
+    ap.add_argument("--batched-reps", type=int, default=10, help="timed batched-carve launches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a known-size "
                          "reference for hardware byte counters)")
@@ -113,6 +115,99 @@ def cpu_baseline(frames, budget_s):
             "kind": "oracle",
             "sample": f"{n} whole volleyball-like frames (same inputs as the GPU steps), "
                       f"{spent:.1f} s of oracle time on host CPU"}, tests
+
+
+BATCHED_WORKLOAD = ("batched fine carve: 64 frames of the tiny rig (4 cams 320x240) x 12 ROI boxes "
+                    "with edges U[0.6, 2.5] m at 10 mm")
+
+
+def batched_leg(args, fvv, torch):
+    """The batched workload: one persistent launch (captured as a HIP graph)
+    carving 64 frames x 12 uneven ROIs with the autotuned tile, against the
+    same ROIs as 768 fvv_carve launches (captured as one graph too, so launch
+    gaps count but host overhead does not); the outputs must be identical."""
+    import scenes
+    from paper_1903_11785_amd import autotune
+    scs, boxes = scenes.batched_rois()
+    N = scs[0].P32.shape[0]
+    W, H = scs[0].W, scs[0].H
+    ctx = fvv.Context(max_cams=N, max_w=W, max_h=H, max_coarse=1, max_fine=1, max_rois=1,
+                      max_points=1, max_jobs=len(boxes))
+    P_all = np.concatenate([s.P32 for s in scs], 0)
+    sils = ctx.pack_silhouettes(torch.from_numpy(np.concatenate([s.masks for s in scs], 0)).cuda())
+    cams_dev = fvv.cameras_to_device(P_all, W, H)
+    jobs, total = fvv.frame_major_jobs([(b.frame, b.lo, b.dims) for b in boxes],
+                                       [s.origin for s in scs], [s.hf for s in scs], N, W, H)
+    jobs_d = fvv.jobs_to_device(jobs)
+    out = torch.empty(total, dtype=torch.uint8, device="cuda")
+    tuned = autotune.tune_batched(ctx, jobs, jobs_d, cams_dev, P_all, sils, out, reps=2)
+    t = tuned["tile"]
+    g = ctx.carve_batched_graph(jobs_d, len(boxes), cams_dev, sils, out, t)
+    for _ in range(2):
+        g.launch()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(max(1, args.batched_reps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.launch()
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    if ctx.check() != fvv.FVV_OK:
+        raise RuntimeError("batched carve reported an invalid job")
+
+    # the same ROIs, one fvv_carve launch each
+    per = torch.empty(total, dtype=torch.uint8, device="cuda")
+    grids = [fvv.Grid(origin=tuple(np.float32(scs[b.frame].origin)), h=np.float32(scs[b.frame].hf),
+                      lo=tuple(b.lo), dims=tuple(b.dims)) for b in boxes]
+    offs = [int(j["out_offset"]) for j in jobs]
+
+    def per_roi(stream=None):
+        for b, gr, o in zip(boxes, grids, offs):
+            ctx.carve(scs[b.frame].P32, W, H, sils[b.frame * N:(b.frame + 1) * N], gr,
+                      out=per[o:o + gr.size], stream=stream)
+
+    per_roi()                                     # eager, once (also the warm-up)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_roi()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3
+    pg = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(pg, stream=side):
+            per_roi(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    per_ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pg.replay()
+        e1.record()
+        e1.synchronize()
+        per_ms.append(e0.elapsed_time(e1))
+    identical = bool(torch.equal(out, per))
+    del pg, per
+    ctx.close()
+    b_ms, p_ms = pct(ms, 50), pct(per_ms, 50)
+    achieved = total / (b_ms * 1e-3) / 1e9
+    return {
+        "workload": BATCHED_WORKLOAD, "rois": len(boxes), "samples": int(total),
+        "tile": [t.tx, t.ty, t.tz, t.persistent_blocks], "tuner_key": tuned["key"],
+        "tuner_ms": {f"{tx}x{256 // tx}x{tz}/{blk}": round(m, 4)
+                     for (tx, tz, blk, m) in tuned["table"]},
+        "batch_ms_p50": b_ms, "batch_ms_min": float(min(ms)), "per_frame_ms": b_ms / 64,
+        "samples_per_s": total / (b_ms * 1e-3),
+        "per_roi_graph_ms_p50": p_ms, "per_roi_eager_wall_ms": eager_ms,
+        "speedup_vs_per_roi": p_ms / b_ms, "identical_to_per_roi": identical,
+        # compulsory bytes only: one occupancy byte per sample written
+        "roofline": {"kernel": "carve_batched_culled_kernel", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": int(total)},
+    }
 
 
 def main():
@@ -215,6 +310,9 @@ def main():
         "latency_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99), "mean": float(np.mean(lat_ms))},
         "stages_ms": {s: float(np.mean(v)) for s, v in stage_ms.items()},
     }
+
+    if not args.no_batched:
+        result["batched"] = batched_leg(args, fvv, torch)
 
     tests = {}
     if not args.no_cpu_baseline:

@@ -126,11 +126,14 @@ void fvv_destroy(fvv_ctx *ctx);
 const char *fvv_status_str(fvv_status s);
 
 /* Wait for `stream`, then report and clear the context's sticky device flags:
- * FVV_ECAPACITY if a capacity was exceeded since the last check, else FVV_OK. */
+ * FVV_EINVAL if a batched carve met a job out of range since the last check,
+ * else FVV_ECAPACITY if a capacity was exceeded, else FVV_OK. */
 fvv_status fvv_check(fvv_ctx *ctx, hipStream_t stream);
 
 /* Pack n silhouettes, uint8 [n][height][width] (non-zero = foreground, the
- * binary silhouette of Sec. II-A), into d_sils [n][height][wpr]. */
+ * binary silhouette of Sec. II-A), into d_sils [n][height][wpr].  n >= 1 is
+ * not bounded by max_cams (the images of many frames can be packed at once);
+ * EINVAL for NULL pointers or a size outside 1..max_w x 1..max_h. */
 fvv_status fvv_pack_silhouettes(fvv_ctx *ctx, int32_t n, int32_t width, int32_t height,
                                 const uint8_t *d_masks, uint32_t *d_sils, hipStream_t stream);
 
@@ -185,14 +188,34 @@ fvv_status fvv_surface(fvv_ctx *ctx, const fvv_grid *roi, const uint8_t *d_occ_f
                        uint32_t *d_n_points, hipStream_t stream);
 
 /* Batched fine carving (Sec. II-B-3 over many ROIs, of one or many frames) in
- * ONE persistent launch: workgroups take (job, tile) work items from a device
- * counter until none are left.  d_jobs: n_jobs jobs (device, <= max_jobs);
- * d_cams: device camera table; output bytes as each job states.  The output
- * is byte-identical to carving each job with fvv_carve.  tile may be NULL
- * (default tile). */
+ * ONE persistent launch.  d_jobs: n_jobs jobs (device, <= max_jobs); d_cams:
+ * device camera table; output bytes as each job states.  The output is
+ * byte-identical to carving each job with fvv_carve, whatever the tile.
+ * With tile->tz == 4 (and for tile == NULL, the default 64x4x4 tile) the
+ * cameras are culled per 4x4x4 box of samples (a camera whose padded pixel
+ * rectangle over the box holds no foreground rejects the box; one whose
+ * rectangle is all foreground accepts it) and the tiles are split statically
+ * over the XCDs; other depths test every sample against every camera, the
+ * workgroups taking tiles from a device counter.  A job with n_cams outside
+ * 1..FVV_MAX_CAMS, an image side outside 1..65536, an empty lattice or a
+ * negative base or offset is skipped, and the next fvv_check reports
+ * FVV_EINVAL.  Calls on one context must not overlap (they share its
+ * scratch). */
 fvv_status fvv_carve_batched(fvv_ctx *ctx, const fvv_job *d_jobs, uint32_t n_jobs,
                              const fvv_camera *d_cams, const uint32_t *d_sils,
                              uint8_t *d_occ_out, const fvv_tile *tile, hipStream_t stream);
+
+/* Tile selection for fvv_carve_batched (the autotuner's measurement): for
+ * each of the n_cands candidate tiles, one untimed call and then `reps`
+ * (1..1000) calls between two HIP events on `stream`; ms[i] receives the
+ * mean milliseconds per call of candidate i, *best the index of the fastest.
+ * Every call writes the same bytes to d_occ_out.  Synchronous.  EINVAL for
+ * an invalid candidate or argument (nothing is run then), else the status of
+ * the first failing call. */
+fvv_status fvv_tune_carve_batched(fvv_ctx *ctx, const fvv_job *d_jobs, uint32_t n_jobs,
+                                  const fvv_camera *d_cams, const uint32_t *d_sils,
+                                  uint8_t *d_occ_out, const fvv_tile *cands, uint32_t n_cands,
+                                  int32_t reps, float *ms, uint32_t *best, hipStream_t stream);
 
 /* ---------------------------------------------------------------- one frame
  * The whole path for one frame with every intermediate on the device, so it
@@ -254,6 +277,12 @@ typedef struct fvv_graph fvv_graph;
 fvv_status fvv_frame_graph_create(fvv_ctx *ctx, const fvv_frame_params *params,
                                   const uint8_t *d_masks, uint32_t *d_sils,
                                   const fvv_frame_out *out, fvv_graph **graph);
+/* fvv_carve_batched captured as a HIP graph with the same arguments (the job
+ * table, cameras and silhouettes are read when the graph runs). */
+fvv_status fvv_carve_batched_graph_create(fvv_ctx *ctx, const fvv_job *d_jobs, uint32_t n_jobs,
+                                          const fvv_camera *d_cams, const uint32_t *d_sils,
+                                          uint8_t *d_occ_out, const fvv_tile *tile,
+                                          fvv_graph **graph);
 fvv_status fvv_graph_launch(fvv_graph *graph, hipStream_t stream);
 void fvv_graph_destroy(fvv_graph *graph);
 

@@ -6,8 +6,10 @@ binding has no CPU path: importing it without the built library, or calling it
 without a GPU, raises.
 
 Names follow the C ABI: ``pack_silhouettes``, ``carve``, ``label``,
-``roi_grids``, ``surface``, ``carve_batched``, ``frame`` and ``frame_graph``,
-as methods of :class:`Context` (which owns the library's device scratch).
+``roi_grids``, ``surface``, ``carve_batched`` (+ ``carve_batched_graph``,
+``tune_carve_batched``), ``frame`` and ``frame_graph``, as methods of
+:class:`Context` (which owns the library's device scratch).  The tile
+autotuner of the batched carve is :mod:`paper_1903_11785_amd.autotune`.
 """
 from __future__ import annotations
 
@@ -120,6 +122,10 @@ def _load():
         "fvv_frame": ([P, C.POINTER(FrameParams), P, P, C.POINTER(FrameOut), P, P], i32),
         "fvv_frame_graph_create": ([P, C.POINTER(FrameParams), P, P, C.POINTER(FrameOut),
                                     C.POINTER(P)], i32),
+        "fvv_carve_batched_graph_create": ([P, P, u32, P, P, P, C.POINTER(Tile), C.POINTER(P)],
+                                           i32),
+        "fvv_tune_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), u32, i32,
+                                    C.POINTER(C.c_float), C.POINTER(u32), P], i32),
         "fvv_graph_launch": ([P, P], i32),
         "fvv_graph_destroy": ([P], None),
     }
@@ -318,6 +324,29 @@ class Context:
                                      C.c_void_p(_stream(stream))), "fvv_carve_batched")
         return out
 
+    def carve_batched_graph(self, jobs_dev, n_jobs: int, cams_dev, sils, out,
+                            tile_: Optional[Tile] = None) -> "FrameGraph":
+        """fvv_carve_batched captured as a HIP graph (launch with .launch(stream))."""
+        g = C.c_void_p()
+        _ok(self.L.fvv_carve_batched_graph_create(self.h, _ptr(jobs_dev), int(n_jobs),
+                                                  _ptr(cams_dev), _ptr(sils), _ptr(out),
+                                                  C.byref(tile_) if tile_ is not None else None,
+                                                  C.byref(g)), "fvv_carve_batched_graph_create")
+        return FrameGraph(self.L, g)
+
+    def tune_carve_batched(self, jobs_dev, n_jobs: int, cams_dev, sils, out,
+                           cands: Sequence[Tile], reps: int = 3, stream=None):
+        """Time each candidate tile of fvv_carve_batched on this job table;
+        returns (index of the fastest, list of ms per call)."""
+        arr = (Tile * len(cands))(*cands)
+        ms = (C.c_float * len(cands))()
+        best = C.c_uint32()
+        _ok(self.L.fvv_tune_carve_batched(self.h, _ptr(jobs_dev), int(n_jobs), _ptr(cams_dev),
+                                          _ptr(sils), _ptr(out), arr, len(cands), int(reps), ms,
+                                          C.byref(best), C.c_void_p(_stream(stream))),
+            "fvv_tune_carve_batched")
+        return int(best.value), [float(v) for v in ms]
+
     def frame(self, params: FrameParams, sils, out: "FrameBuffers", masks=None, events=None,
               stream=None):
         """The whole path for one frame.  masks (uint8 [N][H][W], optional) are
@@ -411,3 +440,29 @@ def cameras_to_device(P: np.ndarray, W: int, H: int, device="cuda"):
     arr["width"] = W
     arr["height"] = H
     return torch.from_numpy(arr.view(np.uint8).reshape(-1, CAMERA_DTYPE.itemsize).copy()).to(device)
+
+
+def frame_major_jobs(boxes: Sequence[Tuple[int, Sequence[int], Sequence[int]]],
+                     origins: Sequence[Sequence[float]], hs: Sequence[float], n_cams: int, W: int,
+                     H: int) -> Tuple[np.ndarray, int]:
+    """Job table of ROIs of several frames whose cameras and silhouettes are
+    stored frame-major (frame f's cameras from row f*n_cams of the camera
+    table, its silhouettes from word f*n_cams*H*ceil(W/32)), outputs back to
+    back in table order.  boxes: (frame, lo, dims) per ROI, lo in global
+    lattice indices of the frame's lattice (origins[f], hs[f]).  Returns the
+    JOB_DTYPE table and the total output bytes."""
+    wpr = (W + 31) // 32
+    jobs = np.zeros(len(boxes), JOB_DTYPE)
+    off = 0
+    for t, (f, lo, dims) in enumerate(boxes):
+        jobs[t]["origin"] = origins[f]
+        jobs[t]["h"] = hs[f]
+        jobs[t]["lo"] = lo
+        jobs[t]["dims"] = dims
+        jobs[t]["cam_base"] = f * n_cams
+        jobs[t]["n_cams"] = n_cams
+        jobs[t]["width"], jobs[t]["height"] = W, H
+        jobs[t]["sil_base"] = f * n_cams * H * wpr
+        jobs[t]["out_offset"] = off
+        off += int(np.prod(np.asarray(dims, np.int64)))
+    return jobs, off

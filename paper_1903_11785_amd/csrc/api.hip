@@ -11,6 +11,12 @@
 
 using namespace fvv;
 
+// An instantiated HIP graph (opaque to callers).
+struct fvv_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 namespace {
 
 constexpr int64_t kMaxSamples = 0x7fffffffLL;
@@ -53,49 +59,6 @@ bool cams_ok(const fvv_ctx* ctx, int32_t n, const fvv_camera* cams) {
                 return false;
     }
     return true;
-}
-
-// World box of the samples of g (corner samples, as the kernels compute them).
-void grid_box(const fvv_grid& g, double lo[3], double hi[3]) {
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = (double)fmaf((float)g.lo[a], g.h, g.origin[a]);
-        hi[a] = (double)fmaf((float)(g.lo[a] + g.dims[a] - 1), g.h, g.origin[a]);
-    }
-}
-
-// Rounding pad of camera P over the world box [lo, hi] (see CamSet::pad).
-// Each projection row is a chain of three fmas, so its rounded value is within
-// 3u(1+u)^2 < 4u of S = sum |P_k||X_k| + |P_3| (u = 2^-24); the quotient of the
-// rounded rows is then within d = (4u S_ab + M 4u S_w) / (w_min - 4u S_w) of the
-// real projection wherever |a/w| <= M, and a quotient formed with rcp adds at
-// most M 2^-22.  The pad covers a point's rounded quotient against the rcp
-// quotients of two other points: 2d + M 2^-21, plus slack.
-float rounding_pad(const float* P, int W, int H, const double lo[3], const double hi[3]) {
-    const double u = std::ldexp(1.0, -24);
-    double s[3] = {0, 0, 0}, wmin = INFINITY;
-    for (int corner = 0; corner < 8; ++corner) {
-        const double X[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1],
-                             (corner & 4) ? hi[2] : lo[2]};
-        for (int r = 0; r < 3; ++r) {
-            double acc = std::fabs((double)P[4 * r + 3]);
-            for (int k = 0; k < 3; ++k)
-                acc += std::fabs((double)P[4 * r + k]) * std::fabs(X[k]);
-            s[r] = std::fmax(s[r], acc);
-        }
-        double w = (double)P[11];
-        for (int k = 0; k < 3; ++k)
-            w += (double)P[8 + k] * X[k];
-        wmin = std::fmin(wmin, w);
-    }
-    const double M = 4.0 * (double)(W > H ? W : H);
-    const double ew = 4.0 * u * s[2];
-    if (!(wmin - ew > 0.0))
-        return INFINITY;
-    const double d = (4.0 * u * std::fmax(s[0], s[1]) + M * ew) / (wmin - ew);
-    const double pad = 2.0 * d + M * std::ldexp(1.0, -21) + std::ldexp(1.0, -10);
-    if (!(pad < 0.25))
-        return INFINITY;       // too coarse to be useful
-    return (float)pad * (1.0f + 0x1p-20f);
 }
 
 CamSet make_camset(int32_t n, const fvv_camera* cams, const fvv_grid* box = nullptr) {
@@ -160,6 +123,47 @@ hipError_t alloc(T** p, int64_t count) {
     return hipMalloc((void**)p, (size_t)count * sizeof(T));
 }
 
+// Capture what `record` enqueues on a fresh stream into an instantiated graph.
+template <typename F>
+fvv_status capture_graph(fvv_graph** out, F record) {
+    if (!out)
+        return FVV_EINVAL;
+    *out = nullptr;
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return FVV_EDEVICE;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamDestroy(s);
+        return FVV_EDEVICE;
+    }
+    const fvv_status st = record(s);
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    hipStreamDestroy(s);
+    if (st != FVV_OK) {
+        if (g)
+            hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess || !g)
+        return FVV_EDEVICE;
+    hipGraphExec_t ex;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return FVV_EDEVICE;
+    }
+    fvv_graph* r = new (std::nothrow) fvv_graph;
+    if (!r) {
+        hipGraphExecDestroy(ex);
+        hipGraphDestroy(g);
+        return FVV_ENOMEM;
+    }
+    r->graph = g;
+    r->exec = ex;
+    *out = r;
+    return FVV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -182,7 +186,7 @@ void fvv_destroy(fvv_ctx* ctx) {
     void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_rowbits, ctx->d_rowmask, ctx->d_rmpre,
                     ctx->d_rows, ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_rrow, ctx->d_runP,
                     ctx->d_stats,
-                    ctx->d_sample_label, ctx->d_prefix,
+                    ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
                     ctx->d_point_off_single, ctx->d_counts_single};
     for (void* p : ptrs)
@@ -246,6 +250,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_stats, (int64_t)(kStatsRow + 1) * V)
     A(d_sample_label, V)
     A(d_prefix, c->job_cap)
+    A(d_job_pad, c->job_cap * FVV_MAX_CAMS)
     A(d_job_single, 1)
     A(d_cams, FVV_MAX_CAMS)
     A(d_finebits, c->bit_cap)
@@ -290,13 +295,15 @@ fvv_status fvv_check(fvv_ctx* ctx, hipStream_t stream) {
         if (hipDeviceSynchronize() != hipSuccess)
             return FVV_EDEVICE;
     }
+    if (flags & kFlagJob)
+        return FVV_EINVAL;
     return (flags & kFlagCapacity) ? FVV_ECAPACITY : FVV_OK;
 }
 
 fvv_status fvv_pack_silhouettes(fvv_ctx* ctx, int32_t n, int32_t width, int32_t height,
                                 const uint8_t* d_masks, uint32_t* d_sils, hipStream_t stream) {
     if (!ctx || !d_masks || !d_sils || n < 1 || width < 1 || height < 1 ||
-        width > ctx->lim.max_w || height > ctx->lim.max_h || n > ctx->lim.max_cams)
+        width > ctx->lim.max_w || height > ctx->lim.max_h)
         return FVV_EINVAL;
     return dev(launch_pack(n, width, height, d_masks, d_sils, stream));
 }
@@ -492,51 +499,67 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     return dev(e);
 }
 
-struct fvv_graph {
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-};
-
 fvv_status fvv_frame_graph_create(fvv_ctx* ctx, const fvv_frame_params* p,
                                   const uint8_t* d_masks, uint32_t* d_sils,
                                   const fvv_frame_out* o, fvv_graph** out) {
-    if (!out)
+    return capture_graph(out, [&](hipStream_t s) {
+        return fvv_frame(ctx, p, d_masks, d_sils, o, nullptr, s);
+    });
+}
+
+fvv_status fvv_carve_batched_graph_create(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_jobs,
+                                          const fvv_camera* d_cams, const uint32_t* d_sils,
+                                          uint8_t* d_occ_out, const fvv_tile* tile,
+                                          fvv_graph** out) {
+    return capture_graph(out, [&](hipStream_t s) {
+        return fvv_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out, tile, s);
+    });
+}
+
+fvv_status fvv_tune_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_jobs,
+                                  const fvv_camera* d_cams, const uint32_t* d_sils,
+                                  uint8_t* d_occ_out, const fvv_tile* cands, uint32_t n_cands,
+                                  int32_t reps, float* ms, uint32_t* best, hipStream_t stream) {
+    if (!ctx || !cands || n_cands < 1 || reps < 1 || reps > 1000 || !ms || !best)
         return FVV_EINVAL;
-    *out = nullptr;
-    hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    for (uint32_t i = 0; i < n_cands; ++i)
+        if (!tile_ok(&cands[i]))
+            return FVV_EINVAL;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
         return FVV_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return FVV_EDEVICE;
+    }
     fvv_status st = FVV_OK;
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        hipStreamDestroy(s);
-        return FVV_EDEVICE;
+    uint32_t arg = 0;
+    for (uint32_t i = 0; i < n_cands && st == FVV_OK; ++i) {
+        // one untimed call, then reps calls between the events
+        st = fvv_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out, &cands[i], stream);
+        if (st == FVV_OK)
+            st = dev(hipEventRecord(e0, stream));
+        for (int32_t r = 0; r < reps && st == FVV_OK; ++r)
+            st = fvv_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out, &cands[i],
+                                   stream);
+        if (st == FVV_OK)
+            st = dev(hipEventRecord(e1, stream));
+        if (st == FVV_OK)
+            st = dev(hipEventSynchronize(e1));
+        float t = 0.0f;
+        if (st == FVV_OK)
+            st = dev(hipEventElapsedTime(&t, e0, e1));
+        if (st == FVV_OK) {
+            ms[i] = t / (float)reps;
+            if (ms[i] < ms[arg])
+                arg = i;
+        }
     }
-    st = fvv_frame(ctx, p, d_masks, d_sils, o, nullptr, s);
-    hipError_t e = hipStreamEndCapture(s, &g);
-    hipStreamDestroy(s);
-    if (st != FVV_OK) {
-        if (g)
-            hipGraphDestroy(g);
-        return st;
-    }
-    if (e != hipSuccess || !g)
-        return FVV_EDEVICE;
-    hipGraphExec_t ex;
-    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
-        return FVV_EDEVICE;
-    }
-    fvv_graph* r = new (std::nothrow) fvv_graph;
-    if (!r) {
-        hipGraphExecDestroy(ex);
-        hipGraphDestroy(g);
-        return FVV_ENOMEM;
-    }
-    r->graph = g;
-    r->exec = ex;
-    *out = r;
-    return FVV_OK;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st == FVV_OK)
+        *best = arg;
+    return st;
 }
 
 fvv_status fvv_graph_launch(fvv_graph* g, hipStream_t stream) {

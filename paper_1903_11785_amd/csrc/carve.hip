@@ -223,13 +223,24 @@ __global__ __launch_bounds__(kBlock) void carve_kernel(const CamSet cams,
 }
 
 // ------------------------------------------------------------------ batched, persistent
+// A job of a batched carve that the kernels can carve: 1..FVV_MAX_CAMS cameras
+// of a valid image size, a non-empty lattice and non-negative offsets.
+__device__ __forceinline__ bool job_ok(const fvv_job& j) {
+    return j.n_cams >= 1 && j.n_cams <= FVV_MAX_CAMS && j.width >= 1 && j.height >= 1 &&
+           j.width <= (1 << 16) && j.height <= (1 << 16) && j.grid.dims[0] >= 1 &&
+           j.grid.dims[1] >= 1 && j.grid.dims[2] >= 1 && j.cam_base >= 0 && j.sil_base >= 0 &&
+           j.out_offset >= 0;
+}
+
 // Prefix sums of tile counts over a host-given job table; resets the work
 // counter.  counter[0] = next work item, [1] = tiles per item, [2] = jobs.
+// A job out of range gets no tiles and raises the job flag.
 template <int TX, int TZ>
 __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* __restrict__ jobs,
                                                                  uint32_t n_jobs,
                                                                  JobPrefix* __restrict__ pre,
                                                                  uint32_t* __restrict__ counter,
+                                                                 uint32_t* __restrict__ status,
                                                                  uint32_t blocks) {
     __shared__ uint64_t scratch[kBlock / kWave];
     __shared__ uint64_t carry;
@@ -238,7 +249,13 @@ __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* 
     __syncthreads();
     for (uint32_t base = 0; base < n_jobs; base += kBlock) {
         uint32_t j = base + threadIdx.x;
-        uint64_t t = j < n_jobs ? tiles_of_grid(jobs[j].grid, TX, TZ) : 0;
+        uint64_t t = 0;
+        if (j < n_jobs) {
+            if (job_ok(jobs[j]))
+                t = tiles_of_grid(jobs[j].grid, TX, TZ);
+            else
+                atomicOr(status, kFlagJob);
+        }
         uint64_t tot;
         uint64_t ex = block_exclusive_sum64<kBlock>(t, scratch, &tot);
         uint64_t c0 = carry;
@@ -256,6 +273,24 @@ __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* 
         counter[1] = grab_size(total, blocks);
         counter[2] = n_jobs;
     }
+}
+
+// Rounding pad of every (job, camera) pair over the job's lattice box, for the
+// camera culling of the batched carve: job_pad[j * FVV_MAX_CAMS + c].
+__global__ __launch_bounds__(kBlock) void job_pad_kernel(const fvv_job* __restrict__ jobs,
+                                                         uint32_t n_jobs,
+                                                         const fvv_camera* __restrict__ cams,
+                                                         float* __restrict__ job_pad) {
+    const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= (uint64_t)n_jobs * FVV_MAX_CAMS)
+        return;
+    const fvv_job& j = jobs[p / FVV_MAX_CAMS];
+    const int c = (int)(p % FVV_MAX_CAMS);
+    if (!job_ok(j) || c >= j.n_cams)
+        return;
+    double lo[3], hi[3];
+    grid_box(j.grid, lo, hi);
+    job_pad[p] = rounding_pad(cams[j.cam_base + c].P, j.width, j.height, lo, hi);
 }
 
 template <int TX, int TZ, bool kFineBits>
@@ -314,69 +349,181 @@ __global__ __launch_bounds__(kBlock) void carve_persistent_kernel(
 // rectangles.
 constexpr int kCullMixed = 0, kCullAccept = 1, kCullReject = 2;
 
-// Classification of camera c for the box of samples with world corners lo,
-// hi: rectangles of more than kRows rows or kWords silhouette words count as
-// mixed.
-template <int kRows, int kWords>
-__device__ __forceinline__ int classify_box(const CamSet& cams, int c,
-                                            const uint32_t* __restrict__ sil, const float* lo,
-                                            const float* hi) {
-    const float pad = cams.pad[c];
+// Pixel rectangle from the corner quotient bounds [x0, x1] x [y0, y1] of a
+// box: widened by the rounding pad, clamped a little outside the image (which
+// keeps the conversions exact) and then to the image.  Returns kCullMixed when
+// no pad bound holds, kCullReject when the rectangle misses the image, else -1
+// with the clamped rectangle [cx0, cx1] x [cy0, cy1] and whether the unclamped
+// one lies inside the image.
+__device__ __forceinline__ int rect_of_bounds(float x0, float x1, float y0, float y1, float pad,
+                                              int Wi, int Hi, int& cx0, int& cx1, int& cy0,
+                                              int& cy1, bool& inside) {
     if (!(pad < 1.0f))
         return kCullMixed;
-    const float* P = &cams.P[c][0];
+    const float W = (float)Wi, H = (float)Hi;
+    const int px0 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(x0 - pad, -2.0f, W + 1.0f));
+    const int px1 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(x1 + pad, -2.0f, W + 1.0f));
+    const int py0 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(y0 - pad, -2.0f, H + 1.0f));
+    const int py1 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(y1 + pad, -2.0f, H + 1.0f));
+    inside = px0 >= 0 && py0 >= 0 && px1 < Wi && py1 < Hi;
+    cx0 = max(px0, 0);
+    cx1 = min(px1, Wi - 1);
+    cy0 = max(py0, 0);
+    cy1 = min(py1, Hi - 1);
+    if (cx0 > cx1 || cy0 > cy1)
+        return kCullReject;                    // every sample projects off the image
+    return -1;
+}
+
+// Quotients of camera P at one corner of the box lo, hi (bit a of `corner`
+// picks hi on axis a), with an rcp-based division.
+__device__ __forceinline__ void corner_quotients(const float* P, const float* lo, const float* hi,
+                                                 int corner, float& qa, float& qb) {
+    const float X = (corner & 1) ? hi[0] : lo[0];
+    const float Y = (corner & 2) ? hi[1] : lo[1];
+    const float Z = (corner & 4) ? hi[2] : lo[2];
+    const float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
+    const float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
+    const float w =
+        __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
+    const float r = __builtin_amdgcn_rcpf(w);
+    qa = a * r;
+    qb = b * r;
+}
+
+// Pixel rectangle of camera c over the box of samples with world corners lo,
+// hi (see rect_of_bounds).
+template <class Cams>
+__device__ __forceinline__ int box_rect(const Cams& cams, int c, const float* lo, const float* hi,
+                                        int& cx0, int& cx1, int& cy0, int& cy1, bool& inside) {
+    const float pad = cams.padc(c);
+    if (!(pad < 1.0f))
+        return kCullMixed;
+    const float* P = cams.Pc(c);
     float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const float X = (k & 1) ? hi[0] : lo[0];
-        const float Y = (k & 2) ? hi[1] : lo[1];
-        const float Z = (k & 4) ? hi[2] : lo[2];
-        const float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
-        const float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
-        const float w = __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
-        const float r = __builtin_amdgcn_rcpf(w);
-        const float qa = a * r, qb = b * r;
+        float qa, qb;
+        corner_quotients(P, lo, hi, k, qa, qb);
         x0 = fminf(x0, qa);
         x1 = fmaxf(x1, qa);
         y0 = fminf(y0, qb);
         y1 = fmaxf(y1, qb);
     }
-    const float W = (float)cams.W, H = (float)cams.H;
-    // pixel bounds, clamped a little outside the image (keeps the conversions exact)
-    const int px0 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(x0 - pad, -2.0f, W + 1.0f));
-    const int px1 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(x1 + pad, -2.0f, W + 1.0f));
-    const int py0 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(y0 - pad, -2.0f, H + 1.0f));
-    const int py1 = (int)__builtin_floorf(__builtin_amdgcn_fmed3f(y1 + pad, -2.0f, H + 1.0f));
-    const bool inside = px0 >= 0 && py0 >= 0 && px1 < cams.W && py1 < cams.H;
-    const int cx0 = max(px0, 0), cx1 = min(px1, cams.W - 1);
-    const int cy0 = max(py0, 0), cy1 = min(py1, cams.H - 1);
-    if (cx0 > cx1 || cy0 > cy1)
-        return kCullReject;                    // every sample projects off the image
+    return rect_of_bounds(x0, x1, y0, y1, pad, cams.W, cams.H, cx0, cx1, cy0, cy1, inside);
+}
+
+// Lane permutations within aligned groups of 8 lanes (DPP): swap neighbours,
+// swap pairs, swap quads.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float min8(float v) {
+    v = fminf(v, dpp_f32<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fminf(v, dpp_f32<0x4E>(v));    // quad_perm [2,3,0,1]
+    return fminf(v, dpp_f32<0x141>(v));  // row_half_mirror
+}
+
+__device__ __forceinline__ float max8(float v) {
+    v = fmaxf(v, dpp_f32<0xB1>(v));
+    v = fmaxf(v, dpp_f32<0x4E>(v));
+    return fmaxf(v, dpp_f32<0x141>(v));
+}
+
+// Foreground test of row y of silhouette `sil` over columns [cx0, cx1], at
+// most kWords words from word w0: any / all of the pixels set.
+template <int kWords>
+__device__ __forceinline__ void row_any_all(const uint32_t* __restrict__ row, int cx0, int cx1,
+                                            bool on, bool& any, bool& all) {
     const int w0 = cx0 >> 5, w1 = cx1 >> 5;
-    if (cy1 - cy0 >= kRows || w1 - w0 >= kWords)
+#pragma unroll
+    for (int q = 0; q < kWords; ++q) {
+        const int wq = w0 + q;
+        const bool won = on && wq <= w1;
+        const uint32_t lo_m = wq == w0 ? ~0u << (cx0 & 31) : ~0u;
+        const uint32_t hi_m = wq == w1 ? (~0u >> (31 - (cx1 & 31))) : ~0u;
+        const uint32_t m = won ? (lo_m & hi_m) : 0u;
+        uint32_t v = 0;
+        if (won)
+            v = row[wq];
+        any |= (v & m) != 0u;
+        all &= (v & m) == m;
+    }
+}
+
+// Classification of camera c for the box of samples with world corners lo,
+// hi: rectangles of more than kRows rows or kWords silhouette words count as
+// mixed.
+template <int kRows, int kWords, class Cams>
+__device__ __forceinline__ int classify_box(const Cams& cams, int c,
+                                            const uint32_t* __restrict__ sil, const float* lo,
+                                            const float* hi) {
+    int cx0, cx1, cy0, cy1;
+    bool inside;
+    const int r0 = box_rect(cams, c, lo, hi, cx0, cx1, cy0, cy1, inside);
+    if (r0 >= 0)
+        return r0;
+    if (cy1 - cy0 >= kRows || (cx1 >> 5) - (cx0 >> 5) >= kWords)
         return kCullMixed;
     bool any = false, all = true;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const bool row_on = r <= cy1 - cy0;
-        const uint32_t* row = sil + (row_on ? cy0 + r : cy0) * cams.wpr;
-#pragma unroll
-        for (int q = 0; q < kWords; ++q) {
-            const int wq = w0 + q;
-            const bool on = row_on && wq <= w1;
-            const uint32_t lo_m = wq == w0 ? ~0u << (cx0 & 31) : ~0u;
-            const uint32_t hi_m = wq == w1 ? (~0u >> (31 - (cx1 & 31))) : ~0u;
-            const uint32_t m = on ? (lo_m & hi_m) : 0u;
-            uint32_t v = 0;
-            if (on)
-                v = row[wq];
-            any |= (v & m) != 0u;
-            all &= (v & m) == m;
-        }
+        row_any_all<kWords>(sil + (row_on ? cy0 + r : cy0) * cams.wpr, cx0, cx1, row_on, any,
+                            all);
     }
     if (!any)
         return kCullReject;
     return (inside && all) ? kCullAccept : kCullMixed;
+}
+
+// Classification of every camera for the box lo, hi by one wave, four cameras
+// per pass: the 16 lanes of camera cb + l/16 project one corner each (lanes
+// l%8) and reduce the corner bounds over 8 lanes, then test row l%16 of the
+// rectangle (rectangles of more than 16 rows or kWords words count as mixed).
+// Returns, uniform over the wave, the cameras that reject every sample of the
+// box and those that are mixed; the others accept every sample.
+template <int kWords, class Cams>
+__device__ __forceinline__ void classify_box_wave(const Cams& cams,
+                                                  const uint32_t* __restrict__ sils,
+                                                  int64_t cam_words, const float* lo,
+                                                  const float* hi, uint32_t& reject,
+                                                  uint32_t& mixed) {
+    const int lane = lane_id(), r = lane & 15, grp = lane >> 4;
+    reject = 0;
+    mixed = 0;
+    for (int cb = 0; cb < cams.n; cb += 4) {
+        const int c = cb + grp;
+        const bool cam_on = c < cams.n;
+        const int cc = cam_on ? c : cb;
+        float qa, qb;
+        corner_quotients(cams.Pc(cc), lo, hi, lane & 7, qa, qb);
+        const float x0 = min8(qa), x1 = max8(qa), y0 = min8(qb), y1 = max8(qb);
+        int cx0, cx1, cy0, cy1;
+        bool inside = false;
+        int st = rect_of_bounds(x0, x1, y0, y1, cams.padc(cc), cams.W, cams.H, cx0, cx1, cy0, cy1,
+                                inside);
+        if (st < 0 && (cy1 - cy0 >= 16 || (cx1 >> 5) - (cx0 >> 5) >= kWords))
+            st = kCullMixed;
+        bool any = false, all = true;
+        if (cam_on && st < 0) {
+            const bool row_on = r <= cy1 - cy0;
+            row_any_all<kWords>(sils + cc * cam_words + (row_on ? cy0 + r : cy0) * cams.wpr, cx0,
+                                cx1, row_on, any, all);
+        }
+        const uint32_t gany = (uint32_t)(__ballot(any) >> (16 * grp)) & 0xffffu;
+        const uint32_t gall = (uint32_t)(__ballot(all) >> (16 * grp)) & 0xffffu;
+        const bool rej = cam_on && (st == kCullReject || (st < 0 && gany == 0));
+        const bool acc = cam_on && st < 0 && gany != 0 && inside && gall == 0xffffu;
+        const uint64_t rb = __ballot(r == 0 && rej), mb = __ballot(r == 0 && cam_on && !rej && !acc);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            reject |= (uint32_t)((rb >> (16 * g)) & 1u) << (cb + g);
+            mixed |= (uint32_t)((mb >> (16 * g)) & 1u) << (cb + g);
+        }
+    }
 }
 
 // World corners of the samples [i0, i1] x [j0, j1] x [k0, k1] of lattice g.
@@ -390,11 +537,57 @@ __device__ __forceinline__ void box_corners(const fvv_grid& g, int i0, int i1, i
     hi[2] = lattice_coord(g.lo[2] + k1, g.h, g.origin[2]);
 }
 
+// Tile t of lattice g (x fastest, then y, then z): its first sample.
 template <int TX>
-__device__ __forceinline__ void carve_tile_culled(const CamSet& cams,
+__device__ __forceinline__ void tile_origin(const fvv_grid& g, uint64_t tile, int& i0, int& j0,
+                                            int& k0) {
+    constexpr int TY = kBlock / TX;
+    const int ntx = (g.dims[0] + TX - 1) / TX;
+    const int nty = (g.dims[1] + TY - 1) / TY;
+    int bx, by, bz;
+    if ((tile >> 32) == 0) {                    // 32-bit index arithmetic where it fits
+        const uint32_t t32 = (uint32_t)tile, rq = t32 / (uint32_t)ntx;
+        bx = (int)(t32 - rq * (uint32_t)ntx);
+        by = (int)(rq % (uint32_t)nty);
+        bz = (int)(rq / (uint32_t)nty);
+    } else {
+        const uint64_t rq = tile / (uint64_t)ntx;
+        bx = (int)(tile - rq * (uint64_t)ntx);
+        by = (int)(rq % (uint64_t)nty);
+        bz = (int)(rq / (uint64_t)nty);
+    }
+    i0 = bx * TX;
+    j0 = by * TY;
+    k0 = bz * 4;
+}
+
+// Camera classification of a whole culled tile (TX x TY x 4 samples from
+// i0, j0, k0) by one wave: rejecting and mixed cameras, uniform over the wave.
+template <int TX, class Cams>
+__device__ __forceinline__ void classify_tile(const Cams& cams, const uint32_t* __restrict__ sils,
+                                              const fvv_grid& g, int i0, int j0, int k0,
+                                              uint32_t& reject, uint32_t& mixed) {
+    constexpr int TY = kBlock / TX;
+    float lo[3], hi[3];
+    box_corners(g, i0, min(i0 + TX, g.dims[0]) - 1, j0, min(j0 + TY, g.dims[1]) - 1, k0,
+                min(k0 + 4, g.dims[2]) - 1, lo, hi);
+    classify_box_wave<2>(cams, sils, (int64_t)cams.H * cams.wpr, lo, hi, reject, mixed);
+}
+
+// One culled tile (first sample i0, j0, k0).  tile_off (uniform): a camera
+// rejects the whole tile, which
+// is written as zeros with no other work; tile_mixed: the cameras left to
+// classify per sub-block (cameras outside it accept the whole tile).  Every
+// LDS read of a tile happens before its last barrier except the s_occ reads
+// of the output pass, and the next tile writes s_occ only after two barriers,
+// so consecutive tiles need no barrier between them.
+template <int TX, class Cams>
+__device__ __forceinline__ void carve_tile_culled(const Cams& cams,
                                                   const uint32_t* __restrict__ sils,
-                                                  const fvv_grid& g, uint64_t tile,
-                                                  uint8_t* __restrict__ out, const RowBits& rb) {
+                                                  const fvv_grid& g, int i0, int j0, int k0,
+                                                  uint8_t* __restrict__ out, const RowBits& rb,
+                                                  bool tile_off = false,
+                                                  uint32_t tile_mixed = ~0u) {
     constexpr int TY = kBlock / TX, TZ = 4;
     constexpr int TV = TX * TY * TZ;
     constexpr int SBX = TX / 4;                 // sub-blocks along x (16 in all)
@@ -403,80 +596,79 @@ __device__ __forceinline__ void carve_tile_culled(const CamSet& cams,
     __shared__ uint32_t s_mixed[16];
     __shared__ uint32_t s_reject;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-
-    const int ntx = (g.dims[0] + TX - 1) / TX;
-    const int nty = (g.dims[1] + TY - 1) / TY;
-    const int bx = (int)(tile % (uint64_t)ntx);
-    const uint64_t rq = tile / (uint64_t)ntx;
-    const int by = (int)(rq % (uint64_t)nty);
-    const int bz = (int)(rq / (uint64_t)nty);
-    const int i0 = bx * TX, j0 = by * TY, k0 = bz * TZ;
-
-    __syncthreads();   // the previous tile of this workgroup is done with the LDS
-    if (threadIdx.x < 16)
-        s_mixed[threadIdx.x] = 0;
-    if (threadIdx.x == 0)
-        s_reject = 0;
-    __syncthreads();
     const int tk1 = min(k0 + TZ, g.dims[2]) - 1;
-    for (int p = threadIdx.x; p < 16 * cams.n; p += kBlock) {
-        const int b = p & 15, c = p >> 4;
-        const int si0 = i0 + (b % SBX) * 4, sj0 = j0 + (b / SBX) * 4;
-        if (si0 >= g.dims[0] || sj0 >= g.dims[1])
-            continue;
-        float lo[3], hi[3];
-        box_corners(g, si0, min(si0 + 4, g.dims[0]) - 1, sj0, min(sj0 + 4, g.dims[1]) - 1, k0, tk1,
-                    lo, hi);
-        const int cl = classify_box<6, 2>(cams, c, sils + c * cam_words, lo, hi);
-        if (cl == kCullReject)
-            atomicOr(&s_reject, 1u << b);
-        else if (cl == kCullMixed)
-            atomicOr(&s_mixed[b], 1u << c);
-    }
-    __syncthreads();
-    // one wave per sub-block, lane = sample (x fastest, then y, then z)
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    for (int b = wave; b < 16; b += kBlock / kWave) {
-        const int lx = (b % SBX) * 4 + (lane & 3);
-        const int ly = (b / SBX) * 4 + ((lane >> 2) & 3);
-        const int lz = lane >> 4;
-        const bool valid = i0 + lx < g.dims[0] && j0 + ly < g.dims[1] && k0 + lz < g.dims[2];
-        bool alive = valid && !((s_reject >> b) & 1u);
-        if (__ballot(alive) != 0) {
-            const float X = lattice_coord(g.lo[0] + i0 + lx, g.h, g.origin[0]);
-            const float Y = lattice_coord(g.lo[1] + j0 + ly, g.h, g.origin[1]);
-            const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
-            // wave-uniform: the sub-block's mixed cameras, two per pass
-            uint32_t rest = s_mixed[b];
-            while (rest && __ballot(alive) != 0) {
-                const int ca = __ffs(rest) - 1;
-                rest &= rest - 1;
-                if (rest) {
-                    const int cb = __ffs(rest) - 1;
+
+    if (!tile_off) {
+        if (threadIdx.x < 16)
+            s_mixed[threadIdx.x] = 0;
+        if (threadIdx.x == 0)
+            s_reject = 0;
+        __syncthreads();
+        for (int p = threadIdx.x; p < 16 * cams.n; p += kBlock) {
+            const int b = p & 15, c = p >> 4;
+            const int si0 = i0 + (b % SBX) * 4, sj0 = j0 + (b / SBX) * 4;
+            if (si0 >= g.dims[0] || sj0 >= g.dims[1] || !((tile_mixed >> c) & 1u))
+                continue;
+            float lo[3], hi[3];
+            box_corners(g, si0, min(si0 + 4, g.dims[0]) - 1, sj0, min(sj0 + 4, g.dims[1]) - 1,
+                        k0, tk1, lo, hi);
+            const int cl = classify_box<6, 2>(cams, c, sils + c * cam_words, lo, hi);
+            if (cl == kCullReject)
+                atomicOr(&s_reject, 1u << b);
+            else if (cl == kCullMixed)
+                atomicOr(&s_mixed[b], 1u << c);
+        }
+        __syncthreads();
+        // one wave per sub-block, lane = sample (x fastest, then y, then z)
+        for (int b = wave; b < 16; b += kBlock / kWave) {
+            const int lx = (b % SBX) * 4 + (lane & 3);
+            const int ly = (b / SBX) * 4 + ((lane >> 2) & 3);
+            const int lz = lane >> 4;
+            const bool valid = i0 + lx < g.dims[0] && j0 + ly < g.dims[1] && k0 + lz < g.dims[2];
+            bool alive = valid && !((s_reject >> b) & 1u);
+            if (__ballot(alive) != 0) {
+                const float X = lattice_coord(g.lo[0] + i0 + lx, g.h, g.origin[0]);
+                const float Y = lattice_coord(g.lo[1] + j0 + ly, g.h, g.origin[1]);
+                const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
+                // wave-uniform: the sub-block's mixed cameras, two per pass
+                uint32_t rest = s_mixed[b];
+                while (rest && __ballot(alive) != 0) {
+                    const int ca = __ffs(rest) - 1;
                     rest &= rest - 1;
-                    const float* P2[2] = {&cams.P[ca][0], &cams.P[cb][0]};
-                    const uint32_t* S2[2] = {sils + ca * cam_words, sils + cb * cam_words};
-                    alive = alive && group_inside<2>(P2, X, Y, Z, S2, cams.W, cams.H, cams.wpr);
-                } else {
-                    const float* P1[1] = {&cams.P[ca][0]};
-                    const uint32_t* S1[1] = {sils + ca * cam_words};
-                    alive = alive && group_inside<1>(P1, X, Y, Z, S1, cams.W, cams.H, cams.wpr);
+                    if (rest) {
+                        const int cb = __ffs(rest) - 1;
+                        rest &= rest - 1;
+                        const float* P2[2] = {cams.Pc(ca), cams.Pc(cb)};
+                        const uint32_t* S2[2] = {sils + ca * cam_words,
+                                                 sils + cb * cam_words};
+                        alive = alive &&
+                                group_inside<2>(P2, X, Y, Z, S2, cams.W, cams.H, cams.wpr);
+                    } else {
+                        const float* P1[1] = {cams.Pc(ca)};
+                        const uint32_t* S1[1] = {sils + ca * cam_words};
+                        alive = alive &&
+                                group_inside<1>(P1, X, Y, Z, S1, cams.W, cams.H, cams.wpr);
+                    }
                 }
             }
+            s_occ[lx + TX * (ly + TY * lz)] = alive ? 1 : 0;
         }
-        s_occ[lx + TX * (ly + TY * lz)] = alive ? 1 : 0;
+        __syncthreads();
     }
-    __syncthreads();
+    // output: thread (lx, ly) writes sample row ly, column lx of every z layer
     const uint64_t plane = (uint64_t)g.dims[0] * (uint64_t)g.dims[1];
+    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> LX;
+    const int i = i0 + lx, j = j0 + ly;
+    const bool vxy = i < g.dims[0] && j < g.dims[1];
+    uint8_t* const o = out + ((uint64_t)k0 * plane + (uint64_t)j * (uint64_t)g.dims[0] + i);
 #pragma unroll
     for (int rr = 0; rr < TZ; ++rr) {
-        const int s = rr * kBlock + (int)threadIdx.x;
-        const int lx = s & (TX - 1), ly = (s >> LX) & (TY - 1), lz = s >> (LX + LY);
-        const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
-        const bool valid = i < g.dims[0] && j < g.dims[1] && k < g.dims[2];
-        const uint8_t bit = s_occ[s];
+        const int k = k0 + rr;
+        const bool valid = vxy && k < g.dims[2];
+        const uint8_t bit = tile_off ? 0 : s_occ[rr * kBlock + threadIdx.x];
         if (valid)
-            out[(uint64_t)k * plane + (uint64_t)j * g.dims[0] + i] = bit;
+            o[rr * plane] = bit;
         // fine bitmap: lanes [TX*q, TX*q + TX) of the wave hold one tile row
         const uint64_t m = __ballot(valid && bit != 0);
         const int q = lane_id() / TX;
@@ -546,7 +738,89 @@ __global__ __launch_bounds__(kBlock, 6) void carve_frame_kernel(const fvv_job* _
         RowBits fb{};
         fb.words = finebits + bit_off;
         fb.wr = (g.dims[0] + 63) / 64;
-        carve_tile_culled<TX>(cams, sils, g, t - tile0, out + out_off, fb);
+        int i0, j0, k0;
+        tile_origin<TX>(g, t - tile0, i0, j0, k0);
+        carve_tile_culled<TX>(cams, sils, g, i0, j0, k0, out + out_off, fb);
+    }
+}
+
+// The batched carve with camera culling: the tiles of all jobs in a static
+// XCD-aware partition; each job's cameras from the device table and its
+// rounding pads from job_pad_kernel.  A workgroup takes its tiles in groups
+// of four: each wave classifies one tile of the group for its whole box (four
+// latency chains of job, camera and silhouette loads in flight at once), then
+// the workgroup carves the group's tiles one after the other, writing
+// rejected tiles as zeros directly.  Each wave's tiles ascend, so its job
+// index only moves forward (the tile prefix is read from LDS when the job
+// table fits).
+constexpr int kBatchedJobLds = 1024;
+constexpr int kGroup = kBlock / kWave;
+
+template <int TX>
+__global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
+    const fvv_job* __restrict__ jobs, const JobPrefix* __restrict__ pre,
+    const uint32_t* __restrict__ counter, const fvv_camera* __restrict__ cams,
+    const float* __restrict__ job_pad, const uint32_t* __restrict__ sils,
+    uint8_t* __restrict__ out) {
+    __shared__ uint64_t s_tile_off[kBatchedJobLds + 1];
+    __shared__ int32_t s_tile[kGroup][6];      // job, i0, j0, k0, rejecting, mixed cameras
+    const int nj = (int)counter[2];
+    const bool lds = nj <= kBatchedJobLds;
+    if (lds)
+        for (int j = threadIdx.x; j <= nj; j += kBlock)
+            s_tile_off[j] = pre[j].tile_off;
+    __syncthreads();
+    auto off = [&](int m) { return lds ? s_tile_off[m] : pre[m].tile_off; };
+    const XcdSlice xs = xcd_slice(off(nj));
+    const int wave = threadIdx.x / kWave;
+    const uint64_t step = (uint64_t)xs.stride;
+    int jb = 0;
+    {
+        const uint64_t t = xs.begin + xs.slot + wave * step;
+        if (t < xs.end)
+            jb = upper_job(off, nj, t);
+    }
+    for (uint64_t tg = xs.begin + xs.slot; tg < xs.end; tg += kGroup * step) {
+        const uint64_t t = tg + wave * step;
+        __syncthreads();                       // the previous group is done with s_job/s_rej/s_mix
+        if (t < xs.end) {
+            while (jb + 1 < nj && off(jb + 1) <= t)
+                ++jb;
+            const int j = __builtin_amdgcn_readfirstlane(jb);
+            const fvv_job& job = jobs[j];
+            const JobCams jc{cams + job.cam_base, job_pad + (int64_t)j * FVV_MAX_CAMS, job.n_cams,
+                             job.width, job.height, (job.width + 31) / 32};
+            int i0, j0, k0;
+            tile_origin<TX>(job.grid, t - off(j), i0, j0, k0);
+            uint32_t rej, mix;
+            classify_tile<TX>(jc, sils + job.sil_base, job.grid, i0, j0, k0, rej, mix);
+            if (lane_id() == 0) {
+                s_tile[wave][0] = j;
+                s_tile[wave][1] = i0;
+                s_tile[wave][2] = j0;
+                s_tile[wave][3] = k0;
+                s_tile[wave][4] = (int32_t)rej;
+                s_tile[wave][5] = (int32_t)mix;
+            }
+        }
+        __syncthreads();
+        for (int w = 0; w < kGroup; ++w) {
+            const uint64_t tw = tg + w * step;
+            if (tw >= xs.end)
+                break;
+            // uniform values read back from LDS: scalar registers
+            const int j = __builtin_amdgcn_readfirstlane(s_tile[w][0]);
+            const int i0 = __builtin_amdgcn_readfirstlane(s_tile[w][1]);
+            const int j0 = __builtin_amdgcn_readfirstlane(s_tile[w][2]);
+            const int k0 = __builtin_amdgcn_readfirstlane(s_tile[w][3]);
+            const uint32_t rej = (uint32_t)__builtin_amdgcn_readfirstlane(s_tile[w][4]);
+            const uint32_t mix = (uint32_t)__builtin_amdgcn_readfirstlane(s_tile[w][5]);
+            const fvv_job& job = jobs[j];
+            const JobCams jc{cams + job.cam_base, job_pad + (int64_t)j * FVV_MAX_CAMS, job.n_cams,
+                             job.width, job.height, (job.width + 31) / 32};
+            carve_tile_culled<TX>(jc, sils + job.sil_base, job.grid, i0, j0, k0,
+                                  out + job.out_offset, RowBits{}, rej != 0, mix);
+        }
     }
 }
 
@@ -600,11 +874,32 @@ hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jo
                                 const fvv_camera* cams, const uint32_t* sils, uint8_t* out,
                                 uint64_t* finebits, TileShape t, int blocks, bool jobs_prepared,
                                 hipStream_t s) {
+    // a fresh job table carved without fine bitmaps, 4 samples deep: culled
+    if (!jobs_prepared && !finebits && t.tz == 4) {
+        blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+        const uint64_t pairs = (uint64_t)n_jobs * FVV_MAX_CAMS;
+        hipLaunchKernelGGL(job_pad_kernel, dim3((unsigned)((pairs + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, s, jobs, n_jobs, cams, ctx->d_job_pad);
+#define X(TXV)                                                                                 \
+        if (t.tx == TXV) {                                                                     \
+            hipLaunchKernelGGL((batched_prepare_kernel<TXV, 4>), dim3(1), dim3(kBlock), 0, s,  \
+                               jobs, n_jobs, ctx->d_prefix, ctx->d_counter, ctx->d_status,     \
+                               (uint32_t)blocks);                                              \
+            hipLaunchKernelGGL((carve_batched_culled_kernel<TXV>), dim3(blocks), dim3(kBlock), \
+                               0, s, jobs, ctx->d_prefix, ctx->d_counter, cams,                \
+                               ctx->d_job_pad, sils, out);                                     \
+            return hipGetLastError();                                                          \
+        }
+        X(64) X(32) X(16)
+#undef X
+        return hipErrorInvalidValue;
+    }
 #define X(TXV, TZV)                                                                             \
     if (t.tx == TXV && t.tz == TZV) {                                                           \
         if (!jobs_prepared)                                                                     \
             hipLaunchKernelGGL((batched_prepare_kernel<TXV, TZV>), dim3(1), dim3(kBlock), 0, s,  \
-                               jobs, n_jobs, ctx->d_prefix, ctx->d_counter, (uint32_t)blocks);   \
+                               jobs, n_jobs, ctx->d_prefix, ctx->d_counter, ctx->d_status,       \
+                               (uint32_t)blocks);                                               \
         if (finebits)                                                                           \
             hipLaunchKernelGGL((carve_persistent_kernel<TXV, TZV, true>), dim3(blocks),          \
                                dim3(kBlock), 0, s, jobs, ctx->d_prefix, ctx->d_counter, cams,    \

@@ -13,7 +13,8 @@ namespace fvv {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;              // threads per workgroup everywhere
 constexpr int kEdgeWords = 256;          // fine-bitmap words per crossing-edge work item
-constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits
+constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits: an output capacity
+constexpr uint32_t kFlagJob = 2u;        // was exceeded; a batched job was out of range
 
 // Projections of a camera rig passed by value in the kernel arguments.
 // pad[c] bounds, for every point of the lattice box the call works in, how far
@@ -23,7 +24,66 @@ struct CamSet {
     float P[FVV_MAX_CAMS][12];
     float pad[FVV_MAX_CAMS];
     int32_t n, W, H, wpr;
+    __device__ const float* Pc(int c) const { return P[c]; }
+    __device__ float padc(int c) const { return pad[c]; }
 };
+
+// The cameras of one job of a batched carve: a slice of a device camera table
+// and the job's rounding pads (as CamSet::pad, over the job's lattice box).
+struct JobCams {
+    const fvv_camera* cam;
+    const float* pads;
+    int32_t n, W, H, wpr;
+    __device__ const float* Pc(int c) const { return cam[c].P; }
+    __device__ float padc(int c) const { return pads[c]; }
+};
+
+// World box of the samples of g (its corner samples, rounded as the kernels
+// round lattice coordinates).
+__host__ __device__ inline void grid_box(const fvv_grid& g, double lo[3], double hi[3]) {
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (double)__builtin_fmaf((float)g.lo[a], g.h, g.origin[a]);
+        hi[a] = (double)__builtin_fmaf((float)(g.lo[a] + g.dims[a] - 1), g.h, g.origin[a]);
+    }
+}
+
+// Rounding pad of camera P over the world box [lo, hi] (see CamSet::pad).
+// Each projection row is a chain of three fmas, so its rounded value is within
+// 3u(1+u)^2 < 4u of S = sum |P_k||X_k| + |P_3| (u = 2^-24); the quotient of the
+// rounded rows is then within d = (4u S_ab + M 4u S_w) / (w_min - 4u S_w) of the
+// real projection wherever |a/w| <= M, and a quotient formed with rcp adds at
+// most M 2^-22.  The pad covers a point's rounded quotient against the rcp
+// quotients of two other points: 2d + M 2^-21, plus slack.  Double precision,
+// no contraction, so host and device compute the same value.
+__host__ __device__ inline float rounding_pad(const float* P, int W, int H, const double lo[3],
+                                              const double hi[3]) {
+#pragma clang fp contract(off)
+    const double u = 0x1p-24;
+    double s[3] = {0, 0, 0}, wmin = INFINITY;
+    for (int corner = 0; corner < 8; ++corner) {
+        const double X[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1],
+                             (corner & 4) ? hi[2] : lo[2]};
+        for (int r = 0; r < 3; ++r) {
+            double acc = fabs((double)P[4 * r + 3]);
+            for (int k = 0; k < 3; ++k)
+                acc += fabs((double)P[4 * r + k]) * fabs(X[k]);
+            s[r] = fmax(s[r], acc);
+        }
+        double w = (double)P[11];
+        for (int k = 0; k < 3; ++k)
+            w += (double)P[8 + k] * X[k];
+        wmin = fmin(wmin, w);
+    }
+    const double M = 4.0 * (double)(W > H ? W : H);
+    const double ew = 4.0 * u * s[2];
+    if (!(wmin - ew > 0.0))
+        return INFINITY;
+    const double d = (4.0 * u * fmax(s[0], s[1]) + M * ew) / (wmin - ew);
+    const double pad = 2.0 * d + M * 0x1p-21 + 0x1p-10;
+    if (!(pad < 0.25))
+        return INFINITY;       // too coarse to be useful
+    return (float)pad * (1.0f + 0x1p-20f);
+}
 
 // Tile of the carving kernels: TX*TY == 256 threads, TZ samples per thread.
 struct TileShape {
@@ -346,6 +406,7 @@ struct fvv_ctx {
     int32_t* d_sample_label;     // label of every occupied coarse sample
     // batched carve / frame
     fvv::JobPrefix* d_prefix;    // per job (max(max_jobs, max_rois) + 1)
+    float* d_job_pad;            // rounding pad per (job, camera) of a batched carve
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
     fvv_camera* d_cams;          // camera table of fvv_frame
     uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)

@@ -266,35 +266,33 @@ def batched_case(n_frames=3, rois_per_frame=4, scale=0.35):
     return sc_list, boxes
 
 
-def test_batched_equals_per_roi_and_oracle(fvv, ctx):
-    import torch
-    scs, boxes = batched_case()
+def batched_inputs(fvv, ctx, scs, boxes):
     W, H = scs[0].W, scs[0].H
     N = scs[0].P32.shape[0]
     P_all = np.concatenate([s.P32 for s in scs], 0)
-    masks_all = np.concatenate([s.masks for s in scs], 0)
-    sils = sils_dev(ctx, masks_all)
+    sils = sils_dev(ctx, np.concatenate([s.masks for s in scs], 0))
     cams_dev = fvv.cameras_to_device(P_all, W, H)
-    wpr = (W + 31) // 32
-    jobs = np.zeros(len(boxes), fvv.JOB_DTYPE)
-    off = 0
-    for t, b in enumerate(boxes):
-        jobs[t]["origin"] = scs[b.frame].origin
-        jobs[t]["h"] = scs[b.frame].hf
-        jobs[t]["lo"] = b.lo
-        jobs[t]["dims"] = b.dims
-        jobs[t]["cam_base"] = b.frame * N
-        jobs[t]["n_cams"] = N
-        jobs[t]["width"], jobs[t]["height"] = W, H
-        jobs[t]["sil_base"] = b.frame * N * H * wpr
-        jobs[t]["out_offset"] = off
-        off += int(np.prod(b.dims))
-    jobs_d = fvv.jobs_to_device(jobs)
+    jobs, total = fvv.frame_major_jobs([(b.frame, b.lo, b.dims) for b in boxes],
+                                       [s.origin for s in scs], [s.hf for s in scs], N, W, H)
+    return P_all, sils, cams_dev, jobs, fvv.jobs_to_device(jobs), total
+
+
+# culled (depth 4, static XCD split; grids rounded up to whole XCD rounds) and
+# plain (dynamic grabbing) tiles, with grids from one workgroup up
+BATCHED_TILES = [(64, 4, 0), (32, 4, 5), (16, 4, 1), (32, 2, 7), (16, 8, 1), (64, 1, 3000)]
+
+
+def test_batched_equals_per_roi_and_oracle(fvv, ctx):
+    import torch
+    scs, boxes = batched_case()
+    P_all, sils, cams_dev, jobs, jobs_d, total = batched_inputs(fvv, ctx, scs, boxes)
+    W, H = scs[0].W, scs[0].H
     outs = []
-    for (tx, tz, blocks) in [(64, 4, 0), (32, 2, 7), (16, 8, 1), (64, 1, 3000)]:
-        out = torch.full((off,), 7, dtype=torch.uint8, device="cuda")
+    for (tx, tz, blocks) in BATCHED_TILES:
+        out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
         ctx.carve_batched(jobs_d, len(boxes), cams_dev, sils, out, fvv.tile(tx, tz, blocks))
         outs.append(host(out))
+    assert ctx.check() == fvv.FVV_OK
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
     for t, b in enumerate(boxes):
@@ -305,6 +303,123 @@ def test_batched_equals_per_roi_and_oracle(fvv, ctx):
         assert int((seg.reshape(ref.shape) != ref).sum()) == 0
         per = host(ctx.carve(s.P32, W, H, sils_dev(ctx, s.masks), grid_of(fvv, lat)))
         np.testing.assert_array_equal(per, ref)
+
+
+def test_batched_graph_replays(fvv, ctx):
+    """The captured batched carve equals the eager call on every replay, with
+    the output reset and other eager work in between."""
+    import torch
+    scs, boxes = batched_case(n_frames=2, rois_per_frame=3)
+    P_all, sils, cams_dev, jobs, jobs_d, total = batched_inputs(fvv, ctx, scs, boxes)
+    ref = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    ctx.carve_batched(jobs_d, len(boxes), cams_dev, sils, ref)
+    for (tx, tz, blocks) in [(64, 4, 0), (32, 2, 0)]:
+        out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+        g = ctx.carve_batched_graph(jobs_d, len(boxes), cams_dev, sils, out,
+                                    fvv.tile(tx, tz, blocks))
+        for rep in range(3):
+            out.fill_(9)
+            other = torch.full((total,), 5, dtype=torch.uint8, device="cuda")
+            ctx.carve_batched(jobs_d, len(boxes), cams_dev, sils, other, fvv.tile(16, 1, 3))
+            g.launch(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (tx, tz, rep)
+            assert torch.equal(other, ref)
+        g.close()
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_batched_autotuner(fvv, ctx, tmp_path):
+    """The tuner times every candidate, returns the fastest, caches it under
+    its key, and leaves the (tile-independent) output in place."""
+    import torch
+    from paper_1903_11785_amd import autotune
+    scs, boxes = batched_case(n_frames=2, rois_per_frame=3)
+    P_all, sils, cams_dev, jobs, jobs_d, total = batched_inputs(fvv, ctx, scs, boxes)
+    ref = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    ctx.carve_batched(jobs_d, len(boxes), cams_dev, sils, ref)
+    out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    cands = [fvv.tile(64, 4, 256), fvv.tile(32, 2, 512), fvv.tile(16, 4, 64)]
+    r = autotune.tune_batched(ctx, jobs, jobs_d, cams_dev, P_all, sils, out, cache_path=cache,
+                              cands=cands, reps=2)
+    assert not r["cached"] and len(r["table"]) == 3
+    ms = [row[3] for row in r["table"]]
+    assert all(m > 0 for m in ms)
+    best = int(np.argmin(ms))
+    assert (r["tile"].tx, r["tile"].tz) == (cands[best].tx, cands[best].tz)
+    assert torch.equal(out, ref)
+    r2 = autotune.tune_batched(ctx, jobs, jobs_d, cams_dev, P_all, sils, out, cache_path=cache)
+    assert r2["cached"] and r2["key"] == r["key"]
+    assert (r2["tile"].tx, r2["tile"].tz) == (r["tile"].tx, r["tile"].tz)
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_batched_skips_invalid_jobs(fvv, ctx):
+    """A job out of range is not carved (its bytes stay untouched), the others
+    are, and the next check reports EINVAL."""
+    import torch
+    scs, boxes = batched_case(n_frames=1, rois_per_frame=3)
+    P_all, sils, cams_dev, jobs, jobs_d, total = batched_inputs(fvv, ctx, scs, boxes)
+    ref = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    ctx.carve_batched(jobs_d, len(boxes), cams_dev, sils, ref)
+    assert ctx.check() == fvv.FVV_OK
+    bad = jobs.copy()
+    bad[1]["n_cams"] = fvv.MAX_CAMS + 1
+    bad_d = fvv.jobs_to_device(bad)
+    a, b = int(jobs[1]["out_offset"]), int(jobs[2]["out_offset"])
+    for (tx, tz) in [(64, 4), (32, 2)]:
+        out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+        ctx.carve_batched(bad_d, len(boxes), cams_dev, sils, out, fvv.tile(tx, tz, 0))
+        assert ctx.check() == fvv.FVV_EINVAL
+        o, r = host(out), host(ref)
+        assert (o[a:b] == 7).all()
+        np.testing.assert_array_equal(o[:a], r[:a])
+        np.testing.assert_array_equal(o[b:], r[b:])
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_batched_full_workload(fvv, ctx):
+    """The batched workload at full size (64 frames x 12 uneven ROIs at 1 cm,
+    2.9e9 samples) in the launch the benchmark times: the graph of the culled
+    batched carve equals 768 per-ROI fvv_carve launches byte for byte, and
+    sampled sub-boxes of every 16th ROI equal the oracle."""
+    import torch
+    scs, boxes = scenes.batched_rois()
+    P_all, sils, cams_dev, jobs, jobs_d, total = batched_inputs(fvv, ctx, scs, boxes)
+    W, H = scs[0].W, scs[0].H
+    print(f"batched full: {len(boxes)} ROIs, {total} samples", flush=True)
+    out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    g = ctx.carve_batched_graph(jobs_d, len(boxes), cams_dev, sils, out)
+    g.launch(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g.close()
+    assert ctx.check() == fvv.FVV_OK
+    per = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    for t, b in enumerate(boxes):
+        s = scs[b.frame]
+        o = int(jobs[t]["out_offset"])
+        n = int(np.prod(b.dims))
+        grid = fvv.Grid(origin=tuple(np.float32(s.origin)), h=np.float32(s.hf), lo=tuple(b.lo),
+                        dims=tuple(b.dims))
+        ctx.carve(s.P32, W, H, sils[b.frame * 4:(b.frame + 1) * 4], grid, out=per[o:o + n])
+    torch.cuda.synchronize()
+    assert torch.equal(out, per)
+    del per
+    rng = np.random.default_rng(11)
+    for t in range(0, len(boxes), 16):
+        b = boxes[t]
+        s = scs[b.frame]
+        nx, ny, nz = b.dims
+        sub = (min(16, nx), min(16, ny), min(8, nz))
+        i0, j0, k0 = (int(rng.integers(0, d - e + 1)) for d, e in zip(b.dims, sub))
+        lat = oracle.Lattice(origin=s.origin, h=s.hf, lo=(b.lo[0] + i0, b.lo[1] + j0, b.lo[2] + k0),
+                             dims=sub)
+        ref, _ = oracle.carve(s.P32, oracle.pack(s.masks), W, H, lat)
+        o = int(jobs[t]["out_offset"])
+        seg = out[o:o + nx * ny * nz].view(nz, ny, nx)[k0:k0 + sub[2], j0:j0 + sub[1],
+                                                        i0:i0 + sub[0]]
+        np.testing.assert_array_equal(host(seg), ref)
 
 
 # ------------------------------------------------------------------ whole frame
