@@ -29,7 +29,7 @@ from . import JOB_DTYPE, Tile, tile
 # camera with dynamic tile grabbing.
 CULLED_SHAPES = ((64, 4), (32, 4), (16, 4))
 PLAIN_SHAPES = ((64, 1), (64, 2), (32, 2), (64, 8))
-GRID_MULTIPLES = (4, 8, 16, 32)
+GRID_MULTIPLES = (8, 32, 64, 128)
 
 
 def candidates(n_cus: int) -> List[Tile]:

@@ -662,6 +662,13 @@ __device__ __forceinline__ void carve_tile_culled(const Cams& cams,
     const int i = i0 + lx, j = j0 + ly;
     const bool vxy = i < g.dims[0] && j < g.dims[1];
     uint8_t* const o = out + ((uint64_t)k0 * plane + (uint64_t)j * (uint64_t)g.dims[0] + i);
+    if (tile_off && !rb.words) {
+        const int nzr = min(TZ, g.dims[2] - k0);
+        if (vxy)
+            for (int rr = 0; rr < nzr; ++rr)
+                o[rr * plane] = 0;
+        return;
+    }
 #pragma unroll
     for (int rr = 0; rr < TZ; ++rr) {
         const int k = k0 + rr;
@@ -746,45 +753,51 @@ __global__ __launch_bounds__(kBlock, 6) void carve_frame_kernel(const fvv_job* _
 
 // The batched carve with camera culling: the tiles of all jobs in a static
 // XCD-aware partition; each job's cameras from the device table and its
-// rounding pads from job_pad_kernel.  A workgroup takes its tiles in groups
-// of four: each wave classifies one tile of the group for its whole box (four
-// latency chains of job, camera and silhouette loads in flight at once), then
-// the workgroup carves the group's tiles one after the other, writing
-// rejected tiles as zeros directly.  Each wave's tiles ascend, so its job
-// index only moves forward (the tile prefix is read from LDS when the job
-// table fits).
+// rounding pads from job_pad_kernel.  A workgroup takes runs of four
+// consecutive tiles (x-neighbours, so one workgroup writes 4*TX bytes of each
+// output row and partly written cache lines are few): each wave classifies one
+// tile of the run for its whole box (four latency chains of job, camera and
+// silhouette loads in flight at once), then the workgroup carves the run's
+// tiles one after the other, writing rejected tiles as zeros directly.  Each
+// wave's tiles ascend, so its job index only moves forward (the tile prefix
+// is read from LDS when the job table fits).
 constexpr int kBatchedJobLds = 1024;
 constexpr int kGroup = kBlock / kWave;
 
-template <int TX>
+template <int TX, bool kLds>
 __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
     const fvv_job* __restrict__ jobs, const JobPrefix* __restrict__ pre,
     const uint32_t* __restrict__ counter, const fvv_camera* __restrict__ cams,
     const float* __restrict__ job_pad, const uint32_t* __restrict__ sils,
     uint8_t* __restrict__ out) {
-    __shared__ uint64_t s_tile_off[kBatchedJobLds + 1];
+    __shared__ uint64_t s_tile_off[kLds ? kBatchedJobLds + 1 : 1];
     __shared__ int32_t s_tile[kGroup][6];      // job, i0, j0, k0, rejecting, mixed cameras
     const int nj = (int)counter[2];
-    const bool lds = nj <= kBatchedJobLds;
-    if (lds)
+    if (kLds)
         for (int j = threadIdx.x; j <= nj; j += kBlock)
             s_tile_off[j] = pre[j].tile_off;
     __syncthreads();
-    auto off = [&](int m) { return lds ? s_tile_off[m] : pre[m].tile_off; };
+    auto off = [&](int m) -> uint64_t {
+        if (kLds)
+            return s_tile_off[m];
+        return pre[m].tile_off;
+    };
     const XcdSlice xs = xcd_slice(off(nj));
-    const int wave = threadIdx.x / kWave;
-    const uint64_t step = (uint64_t)xs.stride;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // runs of kGroup consecutive tiles (x-neighbours, whose rows share cache lines)
+    const uint64_t runs = (xs.end - xs.begin + kGroup - 1) / kGroup;
     int jb = 0;
     {
-        const uint64_t t = xs.begin + xs.slot + wave * step;
+        const uint64_t t = xs.begin + (uint64_t)xs.slot * kGroup + wave;
         if (t < xs.end)
             jb = upper_job(off, nj, t);
     }
-    for (uint64_t tg = xs.begin + xs.slot; tg < xs.end; tg += kGroup * step) {
-        const uint64_t t = tg + wave * step;
-        __syncthreads();                       // the previous group is done with s_job/s_rej/s_mix
+    for (uint64_t run = xs.slot; run < runs; run += xs.stride) {
+        const uint64_t tg = xs.begin + run * kGroup;
+        const uint64_t t = tg + wave;
+        __syncthreads();                       // the previous run is done with s_tile
         if (t < xs.end) {
-            while (jb + 1 < nj && off(jb + 1) <= t)
+            while (jb + 1 < nj && __builtin_amdgcn_readfirstlane((uint32_t)(off(jb + 1) <= t)))
                 ++jb;
             const int j = __builtin_amdgcn_readfirstlane(jb);
             const fvv_job& job = jobs[j];
@@ -805,8 +818,7 @@ __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
         }
         __syncthreads();
         for (int w = 0; w < kGroup; ++w) {
-            const uint64_t tw = tg + w * step;
-            if (tw >= xs.end)
+            if (tg + w >= xs.end)
                 break;
             // uniform values read back from LDS: scalar registers
             const int j = __builtin_amdgcn_readfirstlane(s_tile[w][0]);
@@ -885,9 +897,14 @@ hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jo
             hipLaunchKernelGGL((batched_prepare_kernel<TXV, 4>), dim3(1), dim3(kBlock), 0, s,  \
                                jobs, n_jobs, ctx->d_prefix, ctx->d_counter, ctx->d_status,     \
                                (uint32_t)blocks);                                              \
-            hipLaunchKernelGGL((carve_batched_culled_kernel<TXV>), dim3(blocks), dim3(kBlock), \
-                               0, s, jobs, ctx->d_prefix, ctx->d_counter, cams,                \
-                               ctx->d_job_pad, sils, out);                                     \
+            if (n_jobs <= (uint32_t)kBatchedJobLds)                                           \
+                hipLaunchKernelGGL((carve_batched_culled_kernel<TXV, true>), dim3(blocks),     \
+                                   dim3(kBlock), 0, s, jobs, ctx->d_prefix, ctx->d_counter,    \
+                                   cams, ctx->d_job_pad, sils, out);                           \
+            else                                                                               \
+                hipLaunchKernelGGL((carve_batched_culled_kernel<TXV, false>), dim3(blocks),    \
+                                   dim3(kBlock), 0, s, jobs, ctx->d_prefix, ctx->d_counter,    \
+                                   cams, ctx->d_job_pad, sils, out);                           \
             return hipGetLastError();                                                          \
         }
         X(64) X(32) X(16)
