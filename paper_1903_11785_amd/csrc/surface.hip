@@ -227,7 +227,6 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
 }
 
 // ------------------------------------------------------------------ exit points
-constexpr int kLanesPerEdge = 4;
 
 // Whether camera c accepts every point of the edge X0-X1: the pixel rectangle
 // of the edge's projection, widened by cams.pad[c], lies inside the image and
@@ -283,21 +282,41 @@ __device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
            (!two_r || (a11 & m1) == m1);
 }
 
-// One crossing edge per group of kLanesPerEdge lanes, which share its cameras
-// round-robin: each lane first keeps the ones of its cameras that can reject
-// some point of the edge (kCullChunk cameras' loads in flight together), the
-// group pools the kept ones and shares them out again.  The n_steps bisection
-// steps then run two at a time: a
-// round tests the three points lo + (1, 2, 3) w/4 of the bracket [lo, lo + w]
-// and replays the two binary steps from them -- the first step tests the
-// midpoint (2), the second the midpoint of the half it kept (3 if 2 was
-// inside, else 1) -- so the final bracket is exactly that of n_steps binary
-// steps (all points are dyadic, exact in float).  A wave ballot ANDs the
-// group's cameras for each point.
-constexpr int kCullChunk = 4;      // cameras per lane whose culling loads are in flight together
+// One crossing edge per lane.  Each lane decodes its edge and keeps the
+// cameras that can reject some point of it (the others accept the whole edge;
+// kCullChunk cameras' loads in flight together).  The wave then lists its
+// (edge, kept camera) pairs in LDS and runs the bisection over that list in
+// passes of 64 pairs, so every lane tests one pair per pass however unevenly
+// the kept cameras fall on the edges; a pair's failing points are ORed into
+// its edge's LDS word and each lane then advances its own edge.  The n_steps
+// bisection steps run two at a time: a round tests the three points
+// lo + (1, 2, 3) w/4 of the bracket [lo, lo + w] and replays the two binary
+// steps from them -- the first step tests the midpoint (2), the second the
+// midpoint of the half it kept (3 if 2 was inside, else 1) -- so the final
+// bracket is exactly that of n_steps binary steps (all points are dyadic,
+// exact in float).  The bracket width w is the same for every edge.
+constexpr int kCullChunk = 4;      // cameras whose culling loads are in flight together
 constexpr int kBisectJobs = 64;    // jobs whose lattices a workgroup keeps in LDS
 
-__global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __restrict__ jobs,
+// An edge as the pair passes need it: the ON-end sample's coordinates, the
+// axis, the ON end's index along it (as float), the direction toward the OFF
+// end, the lattice spacing and origin on that axis, and the bracket start.
+struct EdgeRec {
+    float c[3];
+    float gq, d, h, o, lo;
+    int axis;
+    int pad_[3];
+};
+
+// LDS-only ordering between the lanes of one wave (the LDS serves a wave's
+// requests in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int kCamsCap>
+__global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ n_jobs_p,
                                                         const uint32_t* __restrict__ point_off,
                                                         const CamSet cams,
@@ -306,10 +325,13 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
                                                         const uint32_t* __restrict__ keys,
                                                         float* __restrict__ xyz,
                                                         uint32_t max_points) {
-    constexpr uint32_t kGroupMask = (1u << kLanesPerEdge) - 1u;
-    constexpr uint32_t kEdgesPerBlock = kBlock / kLanesPerEdge;
+    constexpr int kWaves = kBlock / kWave;
     __shared__ uint32_t s_off[kBisectJobs + 1];
     __shared__ fvv_grid s_grid[kBisectJobs];
+    __shared__ float s_P[kCamsCap][12];
+    __shared__ EdgeRec s_rec[kWaves][kWave];
+    __shared__ uint16_t s_pair[kWaves][kWave * kCamsCap];
+    __shared__ uint32_t s_fail[kWaves][kWave];
     const int nj = (int)*n_jobs_p;
     const bool lds = nj <= kBisectJobs;
     if (lds)
@@ -318,17 +340,21 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
             if (j < nj)
                 s_grid[j] = jobs[j].grid;
         }
+    for (int q = threadIdx.x; q < cams.n * 12; q += kBlock)
+        s_P[q / 12][q % 12] = cams.P[q / 12][q % 12];
     __syncthreads();
     const uint32_t total = lds ? s_off[nj] : point_off[nj];
     const uint32_t E = total < max_points ? total : max_points;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-    const int sub = lane_id() % kLanesPerEdge;
-    const int shift = lane_id() - sub;
-    const uint32_t all_cams = cams.n >= 32 ? ~0u : (1u << cams.n) - 1u;
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    EdgeRec* const rec = s_rec[wave];
+    uint16_t* const pairs = s_pair[wave];
+    uint32_t* const fails = s_fail[wave];
     // contiguous edge ranges per XCD, in chunks of one block's edges
-    const XcdSlice xs = xcd_slice((E + kEdgesPerBlock - 1) / kEdgesPerBlock);
+    const XcdSlice xs = xcd_slice((E + kBlock - 1) / kBlock);
     for (uint64_t chunk = xs.begin + xs.slot; chunk < xs.end; chunk += xs.stride) {
-        const uint32_t e = (uint32_t)chunk * kEdgesPerBlock + threadIdx.x / kLanesPerEdge;
+        const uint32_t e = (uint32_t)chunk * kBlock + threadIdx.x;
         const bool act = e < E;
         const uint32_t ee = act ? e : E - 1;
         int jb;
@@ -356,102 +382,100 @@ __global__ __launch_bounds__(kBlock, 8) void bisect_kernel(const fvv_job* __rest
                       lattice_coord(gidx[2], g.h, g.origin[2])};
         float X0[3] = {c[0], c[1], c[2]}, X1[3] = {c[0], c[1], c[2]};
         X1[axis] = lattice_coord(gidx[axis] + 1, g.h, g.origin[axis]);
-        const uint32_t cand = all_cams;
-        // per edge, the candidates go round-robin to the group's lanes; each
-        // keeps the ones whose padded rectangle around the edge is not all
-        // foreground, kCullChunk cameras' loads in flight at a time
+        const float o_axis = axis == 0 ? g.origin[0] : (axis == 1 ? g.origin[1] : g.origin[2]);
+        // cull: the cameras whose padded rectangle around the edge is not all
+        // foreground stay (the same camera on every lane: scalar loads)
         uint32_t keep = 0;
-        {
-            uint32_t my = 0;
-            int n = 0;
-            for (uint32_t m = cand; m; m &= m - 1, ++n)
-                if ((n & (kLanesPerEdge - 1)) == sub)
-                    my |= m & (0u - m);
-            while (my) {
-                int cs[kCullChunk];
-                uint32_t took = 0;
+        for (int cb = 0; cb < cams.n; cb += kCullChunk) {
+            bool acc[kCullChunk];
 #pragma unroll
-                for (int u = 0; u < kCullChunk; ++u) {
-                    cs[u] = my ? __ffs(my) - 1 : cs[0];
-                    took |= my & (0u - my);
-                    my &= my - 1;
-                }
-                bool acc[kCullChunk];
-#pragma unroll
-                for (int u = 0; u < kCullChunk; ++u)
-                    acc[u] = camera_accepts_edge(cams, cs[u], sils + cs[u] * cam_words, X0, X1);
-#pragma unroll
-                for (int u = 0; u < kCullChunk; ++u)
-                    if (!acc[u])
-                        keep |= (1u << cs[u]) & took;
+            for (int u = 0; u < kCullChunk; ++u) {
+                const int cc = min(cb + u, cams.n - 1);
+                acc[u] = camera_accepts_edge(cams, cc, sils + cc * cam_words, X0, X1);
             }
+#pragma unroll
+            for (int u = 0; u < kCullChunk; ++u)
+                if (cb + u < cams.n && !acc[u])
+                    keep |= 1u << (cb + u);
         }
-        // the group's kept cameras, then again round-robin over its lanes
-        static_assert(kLanesPerEdge == 2 || kLanesPerEdge == 4, "lane groups are DPP quads or pairs");
-        keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0xB1, 0xf, 0xf, false);  // quad [1,0,3,2]
-        if (kLanesPerEdge == 4)
-            keep |= (uint32_t)__builtin_amdgcn_mov_dpp((int)keep, 0x4E, 0xf, 0xf, false);  // [2,3,0,1]
-        uint32_t mine = 0;
+        if (!act)
+            keep = 0;
+        // this lane's edge record and its pairs, listed wave-wide
+        EdgeRec& mine = rec[lane];
+        mine.c[0] = c[0];
+        mine.c[1] = c[1];
+        mine.c[2] = c[2];
+        mine.gq = (float)g_on;
+        mine.d = d;
+        mine.h = g.h;
+        mine.o = o_axis;
+        mine.lo = 0.0f;
+        mine.axis = axis;
+        const uint32_t cnt = (uint32_t)__builtin_popcount(keep);
+        const uint32_t incl = wave_inclusive_sum(cnt);
+        const uint32_t n_pairs = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
         {
-            int n = 0;
-            for (uint32_t m = keep; m; m &= m - 1, ++n)
-                if ((n & (kLanesPerEdge - 1)) == sub)
-                    mine |= m & (0u - m);
+            uint32_t pos = incl - cnt;
+            for (uint32_t m = keep; m; m &= m - 1)
+                pairs[pos++] = (uint16_t)((lane << 5) | (__ffs(m) - 1));
         }
         float lo = 0.0f, w = 1.0f;
-        for (int s = 0; s < n_steps; s += 2) {
-            const bool two = s + 1 < n_steps;   // wave-uniform
+        for (int st = 0; st < n_steps; st += 2) {
+            const bool two = st + 1 < n_steps;   // uniform
             const float w4 = 0.25f * w;
-            float pt[3] = {lo + w4, lo + 2.0f * w4, lo + 3.0f * w4};
-            float Xp[3], Yp[3], Zp[3];
+            fails[lane] = 0u;
+            wave_lds_sync();
+            for (uint32_t base = 0; base < n_pairs; base += kWave) {
+                const uint32_t pi = base + (uint32_t)lane;
+                const bool live = pi < n_pairs;
+                const uint32_t pr = pairs[live ? pi : 0];
+                const int el = (int)(pr >> 5), ca = (int)(pr & 31u);
+                const EdgeRec& er = rec[el];
+                float Xp[3], Yp[3], Zp[3];
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                const float qq = (float)g_on + d * pt[p];
-                const float ax = __builtin_fmaf(qq, g.h, g.origin[axis]);
-                Xp[p] = axis == 0 ? ax : c[0];
-                Yp[p] = axis == 1 ? ax : c[1];
-                Zp[p] = axis == 2 ? ax : c[2];
-            }
-            uint32_t in = 7u;   // bit p: point p inside every camera of this lane
-            for (uint32_t rest = mine; rest; rest &= rest - 1) {
-                // one camera per pass, the loads of its points in flight together
-                const int ca = __ffs(rest) - 1;
-                const float* P3[3] = {&cams.P[ca][0], &cams.P[ca][0], &cams.P[ca][0]};
-                const uint32_t* S3[3] = {sils + ca * cam_words, sils + ca * cam_words,
-                                         sils + ca * cam_words};
-                if (two) {
-                    in &= multi_inside<3>(P3, Xp, Yp, Zp, S3, cams.W, cams.H, cams.wpr);
-                } else if (!(multi_inside<1>(P3, Xp + 1, Yp + 1, Zp + 1, S3, cams.W, cams.H,
-                                            cams.wpr) & 1u)) {
-                    in &= ~2u;
+                for (int q = 0; q < 3; ++q) {
+                    const float t = er.lo + (float)(q + 1) * w4;
+                    const float ax = __builtin_fmaf(er.gq + er.d * t, er.h, er.o);
+                    Xp[q] = er.axis == 0 ? ax : er.c[0];
+                    Yp[q] = er.axis == 1 ? ax : er.c[1];
+                    Zp[q] = er.axis == 2 ? ax : er.c[2];
                 }
+                const float* P3[3] = {s_P[ca], s_P[ca], s_P[ca]};
+                const uint32_t* sc = sils + ca * cam_words;
+                const uint32_t* S3[3] = {sc, sc, sc};
+                uint32_t fail;
+                if (two)
+                    fail = ~multi_inside<3>(P3, Xp, Yp, Zp, S3, cams.W, cams.H, cams.wpr) & 7u;
+                else
+                    fail = (~multi_inside<1>(P3, Xp + 1, Yp + 1, Zp + 1, S3, cams.W, cams.H,
+                                             cams.wpr) & 1u) << 1;
+                if (live && fail)
+                    atomicOr(&fails[el], fail);
             }
-            // the group's verdict per point: inside iff no lane saw it outside
-            bool ok[3];
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                const uint64_t fail = __ballot(((in >> p) & 1u) == 0u);
-                ok[p] = (((uint32_t)(fail >> shift)) & kGroupMask) == 0;
-            }
+            wave_lds_sync();
+            const uint32_t f = fails[lane];
             if (two) {
-                int idx = ok[1] ? (ok[2] ? 3 : 2) : (ok[0] ? 1 : 0);
+                const int idx = !(f & 2u) ? (!(f & 4u) ? 3 : 2) : (!(f & 1u) ? 1 : 0);
                 lo = lo + (float)idx * w4;
                 w = w4;
             } else {
-                if (ok[1])
-                    lo = pt[1];
+                if (!(f & 2u))
+                    lo = lo + 2.0f * w4;
                 w = 0.5f * w;
             }
+            mine.lo = lo;
+            wave_lds_sync();
         }
-        if (act && sub == 0) {
+        if (act) {
             const float hi = lo + w;
             const float t = 0.5f * (lo + hi);
             const float q = (float)g_on + d * t;
-            c[axis] = __builtin_fmaf(q, g.h, g.origin[axis]);
+            c[axis] = __builtin_fmaf(q, g.h, o_axis);
             xyz[3 * (int64_t)e + 0] = c[0];
             xyz[3 * (int64_t)e + 1] = c[1];
             xyz[3 * (int64_t)e + 2] = c[2];
         }
+        wave_lds_sync();   // the next chunk rewrites this wave's records and pairs
     }
 }
 
@@ -470,8 +494,13 @@ hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_j
                        point_off, n_points, ctx->d_status);
     if (edges_done)
         (void)hipEventRecord(edges_done, s);
-    hipLaunchKernelGGL(bisect_kernel, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs, n_jobs_dev,
-                       point_off, cams, sils, n_steps, keys, xyz, max_points);
+    if (cams.n <= 16)
+        hipLaunchKernelGGL(bisect_kernel<16>, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs,
+                           n_jobs_dev, point_off, cams, sils, n_steps, keys, xyz, max_points);
+    else
+        hipLaunchKernelGGL(bisect_kernel<FVV_MAX_CAMS>, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s,
+                           jobs, n_jobs_dev, point_off, cams, sils, n_steps, keys, xyz,
+                           max_points);
     return hipGetLastError();
 }
 
