@@ -20,16 +20,55 @@ namespace fvv {
 constexpr int kCamGroup = 2;
 
 // ------------------------------------------------------------------ packing
+// Non-zero flags of the four bytes of x as bits 0..3.  Adding 0x7f to a
+// byte's low seven bits sets its high bit iff they are not all zero (no carry
+// leaves the byte); ORed with the byte's own high bit, that bit says the byte
+// is non-zero.  Shifted to bits 0, 8, 16, 24, the flags are gathered into bits
+// 21..24 by one multiply by 1 + 2^7 + 2^14 + 2^21 (no two partial products
+// share a bit there).
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t x) {
+    const uint32_t f = ((((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) >> 7) & 0x01010101u;
+    return ((f * 0x00204081u) >> 21) & 0xfu;
+}
+
+// Unsigned 32-bit division by a fixed divisor d >= 1 with a host-computed
+// multiplier (the round-up method of Granlund and Montgomery, exact for every
+// 32-bit dividend): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = (n m) >> 32.
+struct DivU32 {
+    uint32_t m;
+    int s1, s2;
+};
+
+DivU32 divu32_magic(uint32_t d) {
+    int l = 0;
+    while (l < 32 && (1ull << l) < d)
+        ++l;
+    const uint64_t m = (((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1;
+    return DivU32{(uint32_t)m, l < 1 ? l : 1, l > 1 ? l - 1 : 0};
+}
+
+__device__ __forceinline__ uint32_t divu32(uint32_t n, const DivU32& d) {
+    const uint32_t t = __umulhi(n, d.m);
+    return (t + ((n - t) >> d.s1)) >> d.s2;
+}
+
 // One lane per 32-pixel word.  Fast path: rows of a multiple of 32 pixels
-// whose 32 bytes per word are read with two 16-byte loads.
+// whose 32 bytes per word are read with two 16-byte loads.  k32: every word
+// index fits 32 bits (row = index / wpr by multiply and shifts).
+template <bool k32>
 __global__ __launch_bounds__(kBlock) void pack_kernel(const uint8_t* __restrict__ masks,
                                                       uint32_t* __restrict__ sils, int n, int W,
-                                                      int H, int wpr) {
+                                                      int H, int wpr, DivU32 by_wpr) {
     const int64_t total = (int64_t)n * H * wpr;
     for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * kBlock) {
-        int64_t row = idx / wpr;
-        int word = (int)(idx - row * wpr);
+        int64_t row;
+        if (k32)
+            row = divu32((uint32_t)idx, by_wpr);
+        else
+            row = idx / wpr;
+        const int word = (int)(idx - row * wpr);
         const uint8_t* src = masks + row * W + (int64_t)word * 32;
         uint32_t bits = 0;
         if ((W & 31) == 0) {
@@ -37,12 +76,8 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const uint8_t* __restrict_
             uint4 q[2] = {v[0], v[1]};
             const uint32_t* d = reinterpret_cast<const uint32_t*>(q);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                uint32_t x = d[k];
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    bits |= (uint32_t)(((x >> (8 * b)) & 0xffu) != 0u) << (4 * k + b);
-            }
+            for (int k = 0; k < 8; ++k)
+                bits |= nonzero_bytes(d[k]) << (4 * k);
         } else {
             int nb = min(32, W - word * 32);
             for (int b = 0; b < nb; ++b)
@@ -60,8 +95,14 @@ hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils
         blocks = 65536;
     if (blocks < 1)
         blocks = 1;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, masks, sils, n, W,
-                       H, wpr);
+    const DivU32 dw = divu32_magic((uint32_t)wpr);
+    // 32-bit indices while every index the grid-stride loop forms stays below 2^32
+    if (total + (int64_t)blocks * kBlock <= ((int64_t)1 << 32))
+        hipLaunchKernelGGL(pack_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, masks,
+                           sils, n, W, H, wpr, dw);
+    else
+        hipLaunchKernelGGL(pack_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, masks,
+                           sils, n, W, H, wpr, dw);
     return hipGetLastError();
 }
 
