@@ -447,3 +447,83 @@ def batched_rois(n_frames: int = 64, rois_per_frame: int = 12, hf_um: int = 1000
             lo = c_idx - n // 2
             boxes.append(RoiBox(frame=fr, lo=tuple(int(v) for v in lo), dims=tuple(int(v) for v in n)))
     return scenes, boxes
+
+
+# --------------------------------------------------------------------------- soft hull
+CFG_SOFT = 5
+
+
+@dataclass
+class SoftScene:
+    """Inputs of the differentiable soft hull: a 16-camera tiny ring with
+    perturbed poses, silhouette logits and a lattice around one object with
+    its true occupancy as the target."""
+    cams: List[Camera]                # base poses (the rig as calibrated)
+    omega: np.ndarray                 # float32 [N][3], rotation perturbations (radians)
+    tau: np.ndarray                   # float32 [N][3], translation perturbations (metres)
+    logits: np.ndarray                # float32 [N][H][W]
+    origin: np.ndarray                # float32 (3,)
+    h: np.float32
+    lo: Tuple[int, int, int]
+    dims: Tuple[int, int, int]
+    target: np.ndarray                # float32 [nz][ny][nx], 1 inside the object
+    ellipsoids: List[Ellipsoid]
+
+    @property
+    def W(self) -> int:
+        return self.cams[0].W
+
+    @property
+    def H(self) -> int:
+        return self.cams[0].H
+
+    def base_pose(self):
+        """fx, fy, cx, cy [N][4], R0 [N][3][3], t0 [N][3] (float64): X_cam = R0 X + t0."""
+        K = np.array([[c.K[0, 0], c.K[1, 1], c.K[0, 2], c.K[1, 2]] for c in self.cams])
+        R0 = np.stack([c.R for c in self.cams])
+        t0 = np.stack([-c.R @ c.C for c in self.cams])
+        return K, R0, t0
+
+
+def _blur3(img: np.ndarray, passes: int) -> np.ndarray:
+    """Separable [1, 2, 1]/4 smoothing, edge-replicated, `passes` times."""
+    out = img.astype(np.float64)
+    for _ in range(passes):
+        for ax in (0, 1):
+            p = np.pad(out, [(1, 1) if a == ax else (0, 0) for a in range(2)], mode="edge")
+            sl = [slice(None)] * 2
+            a = p[tuple(sl[:ax] + [slice(0, -2)] + sl[ax + 1:])]
+            b = p[tuple(sl[:ax] + [slice(1, -1)] + sl[ax + 1:])]
+            c = p[tuple(sl[:ax] + [slice(2, None)] + sl[ax + 1:])]
+            out = 0.25 * a + 0.5 * b + 0.25 * c
+    return out
+
+
+def scene_soft(seed: int, n_cams: int = 16, h_um: int = 20000, margin: float = 0.06,
+               rot_sigma_deg: float = 0.5, trans_sigma_m: float = 0.01) -> SoftScene:
+    """The tiny scene of `seed` seen by an n_cams ring; logits = 6 (2 s - 1) for
+    the rendered silhouettes smoothed to s in [0, 1] (two [1,2,1] passes) plus
+    N(0, 0.1) noise; poses perturbed by omega ~ N(0, rot_sigma) per axis and
+    tau ~ N(0, trans_sigma); the lattice covers object 0's box plus `margin`."""
+    sc = scene_tiny(seed)
+    cams = tiny_rig(n_cams)
+    masks = render_masks(cams, sc.ellipsoids)
+    rng = rng_for(CFG_SOFT, seed, 2)
+    logits = np.stack([6.0 * (2.0 * _blur3(m, 2) - 1.0) for m in masks])
+    logits = (logits + rng.normal(0.0, 0.1, size=logits.shape)).astype(np.float32)
+    rng = rng_for(CFG_SOFT, seed, 0)
+    omega = rng.normal(0.0, np.deg2rad(rot_sigma_deg), size=(n_cams, 3)).astype(np.float32)
+    tau = rng.normal(0.0, trans_sigma_m, size=(n_cams, 3)).astype(np.float32)
+    e = sc.ellipsoids[0]
+    blo, bhi = e.aabb()
+    h = um_to_h(h_um)
+    origin = sc.origin
+    hd = float(h_um) * 1e-6
+    lo = tuple(int(np.floor((blo[a] - margin - origin[a]) / hd)) for a in range(3))
+    hi = tuple(int(np.ceil((bhi[a] + margin - origin[a]) / hd)) for a in range(3))
+    dims = tuple(hi[a] - lo[a] + 1 for a in range(3))
+    g = [origin[a] + (lo[a] + np.arange(dims[a])) * hd for a in range(3)]
+    Z, Y, X = np.meshgrid(g[2], g[1], g[0], indexing="ij")
+    target = e.inside(np.stack([X, Y, Z], -1)).astype(np.float32)
+    return SoftScene(cams=cams, omega=omega, tau=tau, logits=logits, origin=origin, h=h, lo=lo,
+                     dims=dims, target=target, ellipsoids=sc.ellipsoids)
