@@ -270,6 +270,53 @@ fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint8_t
                      uint32_t *d_sils, const fvv_frame_out *out, hipEvent_t *events,
                      hipStream_t stream);
 
+/* ---------------------------------------------------------------- soft hull
+ * A differentiable relative of the binary hull of Sec. II-B-1 (not in the
+ * paper), for refining silhouette logits and camera poses by gradient descent.
+ * Camera c maps a world point X to X_c = R X + t with R = exp([omega]x) R0 and
+ * t = t0 + tau (a 6-DoF perturbation of the calibrated pose), and to the
+ * continuous pixel position u = fx X_c.x / X_c.z + cx, v = fy X_c.y / X_c.z + cy
+ * (pixel (x, y) covers [x, x+1) x [y, y+1), its centre is (x + 0.5, y + 0.5)).
+ * p_c(X) is the bilinear interpolation of sigmoid(logits_c) between pixel
+ * centres at (u, v), off-image pixels counting 0, and 0 behind the camera; the
+ * soft occupancy of a lattice sample is o = prod_c p_c, and the L2 loss
+ * against a target occupancy is sum_v (o_v - target_v)^2.  fp32 arithmetic. */
+typedef struct {
+    float K[4];      /* fx, fy, cx, cy (pixels) */
+    float R0[9];     /* calibrated world->camera rotation, row-major */
+    float t0[3];     /* calibrated translation: X_cam = R0 X + t0 */
+    float omega[3];  /* rotation perturbation (radians), R = exp([omega]x) R0 */
+    float tau[3];    /* translation perturbation (metres), t = t0 + tau */
+} fvv_soft_camera;
+
+/* Soft occupancy of `grid` (device output d_occ [samples], x fastest; may be
+ * NULL) and, with d_target (device [samples]) given, the loss into *d_loss
+ * (device double; overwritten).  cams: host array of n_cams (1..max_cams)
+ * cameras; d_logits: device float [n_cams][height][width].  EINVAL on NULL
+ * logits or cameras, no output, d_loss without d_target, bad counts or sizes,
+ * non-finite camera values, non-positive focal lengths, or a grid as for
+ * fvv_carve. */
+fvv_status fvv_soft_forward(fvv_ctx *ctx, const fvv_grid *grid, int32_t n_cams,
+                            const fvv_soft_camera *cams, int32_t width, int32_t height,
+                            const float *d_logits, const float *d_target, float *d_occ,
+                            double *d_loss, hipStream_t stream);
+
+/* Adjoint of fvv_soft_forward, recomputing every sample (nothing is stored
+ * between the calls).  The upstream gradient per sample is
+ * scale * 2 (o - target) with d_target (the L2 loss), else scale * d_grad_occ
+ * (device float [samples]); exactly one of the two is given.  scale:
+ * device double scalar, or NULL for 1.  Outputs (device, overwritten):
+ * d_grad_logits float [n_cams][height][width]; d_grad_pose double [n_cams][6],
+ * the derivatives with respect to omega (3) then tau (3).  Float atomics
+ * order the sums, so results vary in the last bits between runs.  EINVAL as
+ * the forward, plus missing outputs or both or neither upstream input.
+ * Calls on one context must not overlap (they share its pose accumulators). */
+fvv_status fvv_soft_backward(fvv_ctx *ctx, const fvv_grid *grid, int32_t n_cams,
+                             const fvv_soft_camera *cams, int32_t width, int32_t height,
+                             const float *d_logits, const float *d_target,
+                             const float *d_grad_occ, const double *d_scale,
+                             float *d_grad_logits, double *d_grad_pose, hipStream_t stream);
+
 /* Capture fvv_frame (with fixed arguments, no events) into an executable HIP
  * graph.  The capture runs on an internal stream; the graph replays the frame
  * with the same pointers.  Release with fvv_graph_destroy. */

@@ -7,9 +7,11 @@ without a GPU, raises.
 
 Names follow the C ABI: ``pack_silhouettes``, ``carve``, ``label``,
 ``roi_grids``, ``surface``, ``carve_batched`` (+ ``carve_batched_graph``,
-``tune_carve_batched``), ``frame`` and ``frame_graph``, as methods of
-:class:`Context` (which owns the library's device scratch).  The tile
-autotuner of the batched carve is :mod:`paper_1903_11785_amd.autotune`.
+``tune_carve_batched``), ``frame``, ``frame_graph``, ``soft_forward`` and
+``soft_backward``, as methods of :class:`Context` (which owns the library's
+device scratch).  The tile autotuner of the batched carve is
+:mod:`paper_1903_11785_amd.autotune`; the soft hull's autograd functions are in
+:mod:`paper_1903_11785_amd.soft`.
 """
 from __future__ import annotations
 
@@ -55,6 +57,11 @@ class Job(C.Structure):
     _fields_ = [("grid", GridC), ("cam_base", C.c_int32), ("n_cams", C.c_int32),
                 ("width", C.c_int32), ("height", C.c_int32), ("sil_base", C.c_int64),
                 ("out_offset", C.c_int64)]
+
+
+class SoftCamera(C.Structure):
+    _fields_ = [("K", C.c_float * 4), ("R0", C.c_float * 9), ("t0", C.c_float * 3),
+                ("omega", C.c_float * 3), ("tau", C.c_float * 3)]
 
 
 class Limits(C.Structure):
@@ -126,6 +133,10 @@ def _load():
                                            i32),
         "fvv_tune_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), u32, i32,
                                     C.POINTER(C.c_float), C.POINTER(u32), P], i32),
+        "fvv_soft_forward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P, P,
+                              P], i32),
+        "fvv_soft_backward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P,
+                               P, P, P, P], i32),
         "fvv_graph_launch": ([P, P], i32),
         "fvv_graph_destroy": ([P], None),
     }
@@ -347,6 +358,21 @@ class Context:
             "fvv_tune_carve_batched")
         return int(best.value), [float(v) for v in ms]
 
+    def soft_forward(self, grid: Grid, cams, W: int, H: int, logits, target=None, occ=None,
+                     loss=None, stream=None):
+        """Soft occupancy (and L2 loss with a target) of `grid`; cams: a
+        SoftCamera ctypes array (see soft_cameras)."""
+        _ok(self.L.fvv_soft_forward(self.h, C.byref(grid.c()), len(cams), cams, int(W), int(H),
+                                    _ptr(logits), _ptr(target), _ptr(occ), _ptr(loss),
+                                    C.c_void_p(_stream(stream))), "fvv_soft_forward")
+
+    def soft_backward(self, grid: Grid, cams, W: int, H: int, logits, grad_logits, grad_pose,
+                      target=None, grad_occ=None, scale=None, stream=None):
+        _ok(self.L.fvv_soft_backward(self.h, C.byref(grid.c()), len(cams), cams, int(W), int(H),
+                                     _ptr(logits), _ptr(target), _ptr(grad_occ), _ptr(scale),
+                                     _ptr(grad_logits), _ptr(grad_pose),
+                                     C.c_void_p(_stream(stream))), "fvv_soft_backward")
+
     def frame(self, params: FrameParams, sils, out: "FrameBuffers", masks=None, events=None,
               stream=None):
         """The whole path for one frame.  masks (uint8 [N][H][W], optional) are
@@ -466,3 +492,20 @@ def frame_major_jobs(boxes: Sequence[Tuple[int, Sequence[int], Sequence[int]]],
         jobs[t]["out_offset"] = off
         off += int(np.prod(np.asarray(dims, np.int64)))
     return jobs, off
+
+
+def soft_cameras(K: np.ndarray, R0: np.ndarray, t0: np.ndarray, omega: np.ndarray,
+                 tau: np.ndarray):
+    """SoftCamera ctypes array from K [N][4] (fx, fy, cx, cy), R0 [N][3][3],
+    t0 [N][3], omega [N][3], tau [N][3] (host arrays)."""
+    K, R0, t0 = (np.asarray(a, np.float64) for a in (K, R0, t0))
+    omega, tau = (np.asarray(a, np.float64) for a in (omega, tau))
+    n = K.shape[0]
+    arr = (SoftCamera * n)()
+    for c in range(n):
+        arr[c].K[:] = [float(v) for v in K[c]]
+        arr[c].R0[:] = [float(v) for v in R0[c].reshape(-1)]
+        arr[c].t0[:] = [float(v) for v in t0[c]]
+        arr[c].omega[:] = [float(v) for v in omega[c]]
+        arr[c].tau[:] = [float(v) for v in tau[c]]
+    return arr

@@ -123,6 +123,13 @@ hipError_t alloc(T** p, int64_t count) {
     return hipMalloc((void**)p, (size_t)count * sizeof(T));
 }
 
+bool soft_args_ok(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams, const fvv_soft_camera* cams,
+                  int32_t width, int32_t height, const float* d_logits) {
+    return ctx && cams && d_logits && n_cams >= 1 && n_cams <= ctx->lim.max_cams && width >= 1 &&
+           height >= 1 && width <= ctx->lim.max_w && height <= ctx->lim.max_h &&
+           grid_ok(grid, kMaxIndex);
+}
+
 // Capture what `record` enqueues on a fresh stream into an instantiated graph.
 template <typename F>
 fvv_status capture_graph(fvv_graph** out, F record) {
@@ -186,7 +193,7 @@ void fvv_destroy(fvv_ctx* ctx) {
     void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_rowbits, ctx->d_rowmask, ctx->d_rmpre,
                     ctx->d_rows, ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_rrow, ctx->d_runP,
                     ctx->d_stats,
-                    ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad,
+                    ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
                     ctx->d_point_off_single, ctx->d_counts_single};
     for (void* p : ptrs)
@@ -251,6 +258,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_sample_label, V)
     A(d_prefix, c->job_cap)
     A(d_job_pad, c->job_cap * FVV_MAX_CAMS)
+    A(d_soft_acc, FVV_MAX_CAMS * 6)
     A(d_job_single, 1)
     A(d_cams, FVV_MAX_CAMS)
     A(d_finebits, c->bit_cap)
@@ -402,6 +410,37 @@ fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_job
         return FVV_EINVAL;
     return dev(launch_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out, nullptr,
                                     tile_of(tile), persistent_blocks(ctx, tile), false, stream));
+}
+
+// ------------------------------------------------------------------ soft hull
+fvv_status fvv_soft_forward(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams,
+                            const fvv_soft_camera* cams, int32_t width, int32_t height,
+                            const float* d_logits, const float* d_target, float* d_occ,
+                            double* d_loss, hipStream_t stream) {
+    if (!soft_args_ok(ctx, grid, n_cams, cams, width, height, d_logits) || (!d_occ && !d_loss) ||
+        (d_loss && !d_target))
+        return FVV_EINVAL;
+    SoftCamSet cs;
+    SoftJacobians jac;
+    if (!make_soft_cams(n_cams, width, height, cams, &cs, &jac))
+        return FVV_EINVAL;
+    return dev(launch_soft_forward(ctx, cs, *grid, d_logits, d_target, d_occ, d_loss, stream));
+}
+
+fvv_status fvv_soft_backward(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams,
+                             const fvv_soft_camera* cams, int32_t width, int32_t height,
+                             const float* d_logits, const float* d_target,
+                             const float* d_grad_occ, const double* d_scale,
+                             float* d_grad_logits, double* d_grad_pose, hipStream_t stream) {
+    if (!soft_args_ok(ctx, grid, n_cams, cams, width, height, d_logits) || !d_grad_logits ||
+        !d_grad_pose || (!d_target) == (!d_grad_occ))
+        return FVV_EINVAL;
+    SoftCamSet cs;
+    SoftJacobians jac;
+    if (!make_soft_cams(n_cams, width, height, cams, &cs, &jac))
+        return FVV_EINVAL;
+    return dev(launch_soft_backward(ctx, cs, jac, *grid, d_logits, d_target, d_grad_occ, d_scale,
+                                    d_grad_logits, d_grad_pose, stream));
 }
 
 fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_masks,

@@ -407,6 +407,7 @@ struct fvv_ctx {
     // batched carve / frame
     fvv::JobPrefix* d_prefix;    // per job (max(max_jobs, max_rois) + 1)
     float* d_job_pad;            // rounding pad per (job, camera) of a batched carve
+    double* d_soft_acc;          // soft hull: per camera sum g and sum (R X) x g
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
     fvv_camera* d_cams;          // camera table of fvv_frame
     uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)
@@ -457,6 +458,33 @@ hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* 
                         uint32_t* n_rois, bool seeded, const FrameJobs* frame, hipStream_t s);
 hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                               hipStream_t s);
+// Soft hull: one camera as the kernels use it (intrinsics and the perturbed
+// pose, formed on the host in double and rounded once), and each camera's left
+// Jacobian of SO(3) at its rotation perturbation.
+struct SoftCam {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+};
+
+struct SoftCamSet {
+    SoftCam c[FVV_MAX_CAMS];
+    int32_t n, W, H;
+};
+
+struct SoftJacobians {
+    double Jl[FVV_MAX_CAMS][9];
+};
+
+bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
+                    SoftJacobians* jac);
+hipError_t launch_soft_forward(fvv_ctx* ctx, const SoftCamSet& cams, const fvv_grid& g,
+                               const float* logits, const float* target, float* occ,
+                               double* loss, hipStream_t s);
+hipError_t launch_soft_backward(fvv_ctx* ctx, const SoftCamSet& cams, const SoftJacobians& jac,
+                                const fvv_grid& g, const float* logits, const float* target,
+                                const float* grad_occ, const double* scale, float* grad_logits,
+                                double* grad_pose, hipStream_t s);
 hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                           uint32_t max_jobs, const uint8_t* occ_fine, const CamSet& cams,
                           const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,
