@@ -53,6 +53,7 @@ def parse():
                     help="frames in flight for the throughput figure (one context, buffer set "
                          "and stream each); latency is measured one frame at a time")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-carve leg")
+    ap.add_argument("--no-soft", action="store_true", help="skip the soft-hull leg")
     ap.add_argument("--batched-reps", type=int, default=10, help="timed batched-carve launches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a known-size "
@@ -216,6 +217,69 @@ def batched_leg(args, fvv, torch):
     }
 
 
+SOFT_WORKLOAD = ("soft hull: 16 cams 320x240 on the tiny ring, poses perturbed 0.5 deg / 1 cm, "
+                 "fp32 logits, the 2 cm lattice around one object, L2 loss to its occupancy")
+
+
+def soft_leg(args, fvv, torch):
+    """The differentiable soft hull: forward (fused L2 loss) and forward plus
+    adjoint (logit and pose gradients) through the autograd function."""
+    import scenes
+    from paper_1903_11785_amd.soft import SoftHull
+    s = scenes.scene_soft(0)
+    K, R0, t0 = s.base_pose()
+    N = K.shape[0]
+    ctx = fvv.Context(max_cams=N, max_w=s.W, max_h=s.H, max_coarse=1, max_fine=1, max_rois=1,
+                      max_points=1, max_jobs=1)
+    grid = fvv.Grid(origin=tuple(np.float32(s.origin)), h=np.float32(s.h), lo=s.lo, dims=s.dims)
+    hull = SoftHull(ctx, grid, K, R0, t0, s.W, s.H)
+    L = torch.from_numpy(s.logits).cuda().requires_grad_(True)
+    w = torch.from_numpy(s.omega).requires_grad_(True)
+    t = torch.from_numpy(s.tau).requires_grad_(True)
+    target = torch.from_numpy(s.target.reshape(-1)).cuda()
+
+    def step(backward):
+        if backward:
+            loss = hull.l2_loss(L, w, t, target)
+            return torch.autograd.grad(loss, (L, w, t))
+        with torch.no_grad():
+            return hull.l2_loss(L, w, t, target)
+
+    reps = 20
+    out = {}
+    for name, bw in (("forward_ms", False), ("forward_backward_ms", True)):
+        for _ in range(3):
+            step(bw)
+        torch.cuda.synchronize()
+        t0_ = time.perf_counter()
+        for _ in range(reps):
+            step(bw)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0_) * 1e3 / reps
+    V = int(np.prod(s.dims))
+    ctx.close()
+    return {"workload": SOFT_WORKLOAD, "samples": V, "cameras": N,
+            "forward_ms": out["forward_ms"], "forward_backward_ms": out["forward_backward_ms"],
+            "samples_per_s_forward_backward": V / (out["forward_backward_ms"] * 1e-3),
+            "note": "wall time per call through the autograd function, including the host-side "
+                    "pose set-up and the copy of the pose gradients to the host"}
+
+
+def soft_cpu_baseline():
+    """The soft-hull oracle (float64 PyTorch CPU: forward + autograd) on the
+    same scene, timed once."""
+    import scenes
+    from oracle import soft as osoft
+    s = scenes.scene_soft(0)
+    K, R0, t0 = s.base_pose()
+    t0_ = time.perf_counter()
+    osoft.soft_grad(s.logits, K, R0, t0, s.omega, s.tau, s.origin, s.h, s.lo, s.dims,
+                    target=s.target)
+    import torch
+    return {"forward_backward_ms": (time.perf_counter() - t0_) * 1e3, "kind": "oracle",
+            "cores": torch.get_num_threads(), "sample": "one forward + gradient of the same scene"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -353,6 +417,10 @@ def main():
 
     if not args.no_batched:
         result["batched"] = batched_leg(args, fvv, torch)
+    if not args.no_soft:
+        result["soft_hull"] = soft_leg(args, fvv, torch)
+        if not args.no_cpu_baseline:
+            result["soft_hull"]["cpu_baseline"] = soft_cpu_baseline()
 
     tests = {}
     if not args.no_cpu_baseline:

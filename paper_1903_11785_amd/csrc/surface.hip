@@ -373,16 +373,20 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
         const uint32_t r = lin / (uint32_t)g.dims[0];
         const uint32_t j = r % (uint32_t)g.dims[1];
         const uint32_t k = r / (uint32_t)g.dims[1];
-        const int gidx[3] = {g.lo[0] + (int)i, g.lo[1] + (int)j, g.lo[2] + (int)k};
+        // (selects rather than run-time indices into local arrays, which would
+        // put them in scratch memory)
+        const int gx = g.lo[0] + (int)i, gy = g.lo[1] + (int)j, gz = g.lo[2] + (int)k;
+        const int g_axis = axis == 0 ? gx : (axis == 1 ? gy : gz);
         const bool p_on = xyz[3 * (int64_t)ee] > 0.0f;   // left there by the edge pass
-        const int g_on = gidx[axis] + (p_on ? 0 : 1);
+        const int g_on = g_axis + (p_on ? 0 : 1);
         const float d = p_on ? 1.0f : -1.0f;
-        float c[3] = {lattice_coord(gidx[0], g.h, g.origin[0]),
-                      lattice_coord(gidx[1], g.h, g.origin[1]),
-                      lattice_coord(gidx[2], g.h, g.origin[2])};
-        float X0[3] = {c[0], c[1], c[2]}, X1[3] = {c[0], c[1], c[2]};
-        X1[axis] = lattice_coord(gidx[axis] + 1, g.h, g.origin[axis]);
         const float o_axis = axis == 0 ? g.origin[0] : (axis == 1 ? g.origin[1] : g.origin[2]);
+        const float c[3] = {lattice_coord(gx, g.h, g.origin[0]), lattice_coord(gy, g.h, g.origin[1]),
+                            lattice_coord(gz, g.h, g.origin[2])};
+        const float x1a = lattice_coord(g_axis + 1, g.h, o_axis);
+        const float X0[3] = {c[0], c[1], c[2]};
+        const float X1[3] = {axis == 0 ? x1a : c[0], axis == 1 ? x1a : c[1],
+                             axis == 2 ? x1a : c[2]};
         // cull: the cameras whose padded rectangle around the edge is not all
         // foreground stay (the same camera on every lane: scalar loads)
         uint32_t keep = 0;
@@ -470,10 +474,10 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
             const float hi = lo + w;
             const float t = 0.5f * (lo + hi);
             const float q = (float)g_on + d * t;
-            c[axis] = __builtin_fmaf(q, g.h, o_axis);
-            xyz[3 * (int64_t)e + 0] = c[0];
-            xyz[3 * (int64_t)e + 1] = c[1];
-            xyz[3 * (int64_t)e + 2] = c[2];
+            const float ax = __builtin_fmaf(q, g.h, o_axis);
+            xyz[3 * (int64_t)e + 0] = axis == 0 ? ax : c[0];
+            xyz[3 * (int64_t)e + 1] = axis == 1 ? ax : c[1];
+            xyz[3 * (int64_t)e + 2] = axis == 2 ? ax : c[2];
         }
         wave_lds_sync();   // the next chunk rewrites this wave's records and pairs
     }
