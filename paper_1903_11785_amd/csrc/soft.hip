@@ -17,6 +17,7 @@
 // d loss / d tau = sum g and d loss / d omega = J_l(omega)^T sum (R X) x g,
 // J_l being the left Jacobian of SO(3) (exp([omega + d]x) = exp([J_l d]x)
 // exp([omega]x) to first order).
+#include <limits.h>
 #include <math.h>
 #include <string.h>
 
@@ -206,8 +207,36 @@ __global__ __launch_bounds__(kBlock) void soft_fwd_kernel(const SoftCamSet cams,
     }
 }
 
-// kN: a compile-time bound on the camera count (registers for p and suffix).
-// acc [n][6]: per camera sum of g (d loss / d X_c) and of (R X) x g.
+__device__ __forceinline__ int wave_min_i32(int v) {
+    for (int off = kWave / 2; off >= 1; off >>= 1)
+        v = min(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+    for (int off = kWave / 2; off >= 1; off >>= 1)
+        v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+// The adjoint.  A block takes bricks of 8 x 8 x 4 lattice samples, one per
+// thread, and walks the cameras in order with the prefix product, the suffix
+// products of all cameras' p held in registers (kN: a compile-time bound on the
+// camera count).  Per camera, the brick's logit-gradient contributions fall in
+// a small pixel window (the brick spans a few pixels): they are summed there
+// with LDS atomics and the window is added to the gradient image with one
+// global atomic per touched pixel, instead of four contended global atomics
+// per sample (all samples along a camera ray hit the same pixels).  Windows
+// larger than kWin pixels fall back to global atomics.  A work item is a brick
+// and one of kCamGroups camera groups (cameras c = group mod kCamGroups): each
+// item forms all cameras' p but does the gradient work of its group only, so
+// kCamGroups times as many workgroups share the latency.  acc [n][6]: per camera
+// sum of g = d loss / d X_c and of (R X) x g (DPP wave sums, LDS, then double
+// atomics per block).
+constexpr int kBrickX = 8, kBrickY = 8, kBrickZ = kBlock / (kBrickX * kBrickY);
+constexpr int kWin = 4096;
+constexpr int kCamGroups = 4;
+
 template <int kN, bool kL2>
 __global__ __launch_bounds__(kBlock) void soft_bwd_kernel(const SoftCamSet cams, const fvv_grid g,
                                                           const float* __restrict__ logits,
@@ -217,18 +246,30 @@ __global__ __launch_bounds__(kBlock) void soft_bwd_kernel(const SoftCamSet cams,
                                                           float* __restrict__ grad_logits,
                                                           double* __restrict__ acc) {
     __shared__ float s_acc[kN][6];
+    __shared__ float s_win[kWin];
+    // window of the item's m-th camera in s_box[m & 1]: min x, min y, max x,
+    // max y of the taps (two buffers: a buffer's readers have all passed the
+    // next camera's barrier before thread 0 resets it)
+    __shared__ int s_box[2][4];
     for (int q = threadIdx.x; q < kN * 6; q += kBlock)
         s_acc[q / 6][q % 6] = 0.0f;
-    __syncthreads();
-    const uint32_t V = (uint32_t)((int64_t)g.dims[0] * g.dims[1] * g.dims[2]);
+    const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
+    const int nbx = (nx + kBrickX - 1) / kBrickX, nby = (ny + kBrickY - 1) / kBrickY;
+    const int nbz = (nz + kBrickZ - 1) / kBrickZ;
+    const int64_t bricks = (int64_t)nbx * nby * nbz;
     const int64_t cam_px = (int64_t)cams.W * cams.H;
     const float scale = scale_p ? (float)*scale_p : 1.0f;
-    // all lanes of the block run the same rounds (the wave sums need every lane)
-    for (uint32_t base = blockIdx.x * kBlock; base < V; base += gridDim.x * kBlock) {
-        const uint32_t idx = base + threadIdx.x;
-        const bool act = idx < V;
+    const int lx = threadIdx.x % kBrickX, ly = (threadIdx.x / kBrickX) % kBrickY;
+    const int lz = threadIdx.x / (kBrickX * kBrickY);
+    for (int64_t item = blockIdx.x; item < bricks * kCamGroups; item += gridDim.x) {
+        const int64_t br = item / kCamGroups;
+        const int group = (int)(item % kCamGroups);
+        const int bx = (int)(br % nbx), by = (int)((br / nbx) % nby), bz = (int)(br / nbx / nby);
+        const int i = bx * kBrickX + lx, j = by * kBrickY + ly, k = bz * kBrickZ + lz;
+        const bool act = i < nx && j < ny && k < nz;
+        const uint32_t idx = act ? (uint32_t)(((int64_t)k * ny + j) * nx + i) : 0u;
         float X, Y, Z;
-        sample_coords(g, act ? idx : 0u, X, Y, Z);
+        sample_coords(g, idx, X, Y, Z);
         float p[kN], suf[kN];
 #pragma unroll
         for (int c = 0; c < kN; ++c)
@@ -249,45 +290,88 @@ __global__ __launch_bounds__(kBlock) void soft_bwd_kernel(const SoftCamSet cams,
                 break;
             const float gp = go * pre * suf[c];
             pre *= p[c];
-            float gx = 0.0f, gy = 0.0f, gz = 0.0f, bx = 0.0f, by = 0.0f, bz = 0.0f;
-            if (__ballot(gp != 0.0f) != 0) {
-                const SoftCam& k = cams.c[c];
-                const SoftSample s = soft_sample(k, logits + c * cam_px, cams.W, cams.H, X, Y, Z);
-                if (gp != 0.0f && s.front) {
-                    // logits: d p / d L_tap = weight * sigmoid' (taps off-image have sg = 0)
-                    const float w4[4] = {(1.0f - s.ax) * (1.0f - s.ay), s.ax * (1.0f - s.ay),
-                                         (1.0f - s.ax) * s.ay, s.ax * s.ay};
-                    float* gl = grad_logits + c * cam_px;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int x = s.x0 + (q & 1), y = s.y0 + (q >> 1);
-                        if (x >= 0 && x < cams.W && y >= 0 && y < cams.H)
-                            unsafeAtomicAdd(&gl[(int64_t)y * cams.W + x],
-                                            gp * w4[q] * s.sg[q] * (1.0f - s.sg[q]));
-                    }
-                    // pose: d p / d u and d p / d v, then through the projection
-                    const float du = (1.0f - s.ay) * (s.sg[1] - s.sg[0]) + s.ay * (s.sg[3] - s.sg[2]);
-                    const float dv = (1.0f - s.ax) * (s.sg[2] - s.sg[0]) + s.ax * (s.sg[3] - s.sg[1]);
-                    const float rz = 1.0f / s.Xc[2];
-                    gx = gp * du * k.fx * rz;
-                    gy = gp * dv * k.fy * rz;
-                    gz = -(gx * s.Xc[0] + gy * s.Xc[1]) * rz;
-                    // R X = X_c - t
-                    const float rx = s.Xc[0] - k.t[0], ry = s.Xc[1] - k.t[1],
-                                rzv = s.Xc[2] - k.t[2];
-                    bx = ry * gz - rzv * gy;
-                    by = rzv * gx - rx * gz;
-                    bz = rx * gy - ry * gx;
+            if (c % kCamGroups != group)
+                continue;                      // another work item's camera
+            int* const box = s_box[(c / kCamGroups) & 1];
+            if (threadIdx.x == 0) {
+                box[0] = box[1] = INT_MAX;
+                box[2] = box[3] = INT_MIN;
+            }
+            if (!__syncthreads_or(gp != 0.0f))
+                continue;                      // the whole brick has no gradient here
+            const SoftCam& cm = cams.c[c];
+            const SoftSample sm = soft_sample(cm, logits + c * cam_px, cams.W, cams.H, X, Y, Z);
+            const bool live = gp != 0.0f && sm.front;
+            // the brick's tap window
+            {
+                const int a0 = wave_min_i32(live ? sm.x0 : INT_MAX);
+                const int a1 = wave_min_i32(live ? sm.y0 : INT_MAX);
+                const int a2 = wave_max_i32(live ? sm.x0 + 1 : INT_MIN);
+                const int a3 = wave_max_i32(live ? sm.y0 + 1 : INT_MIN);
+                if (lane_id() == 0) {
+                    atomicMin(&box[0], a0);
+                    atomicMin(&box[1], a1);
+                    atomicMax(&box[2], a2);
+                    atomicMax(&box[3], a3);
                 }
             }
-            const float v6[6] = {gx, gy, gz, bx, by, bz};
+            __syncthreads();
+            const int wx0 = box[0], wy0 = box[1];
+            const int64_t wxn = (int64_t)box[2] - wx0 + 1, wyn = (int64_t)box[3] - wy0 + 1;
+            const bool in_lds = box[2] >= wx0 && wxn * wyn <= kWin;   // uniform
+            float* gl = grad_logits + c * cam_px;
+            const float w4[4] = {(1.0f - sm.ax) * (1.0f - sm.ay), sm.ax * (1.0f - sm.ay),
+                                 (1.0f - sm.ax) * sm.ay, sm.ax * sm.ay};
+            if (in_lds) {
+                for (int q = threadIdx.x; q < (int)(wxn * wyn); q += kBlock)
+                    s_win[q] = 0.0f;
+                __syncthreads();
+            }
+            float gx = 0.0f, gy = 0.0f, gz = 0.0f, bxv = 0.0f, byv = 0.0f, bzv = 0.0f;
+            if (live) {
+                // logits: d p / d L_tap = weight * sigmoid' (taps off-image have sg = 0)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int x = sm.x0 + (q & 1), y = sm.y0 + (q >> 1);
+                    if (x >= 0 && x < cams.W && y >= 0 && y < cams.H) {
+                        const float v = gp * w4[q] * sm.sg[q] * (1.0f - sm.sg[q]);
+                        if (in_lds)
+                            atomicAdd(&s_win[(y - wy0) * wxn + (x - wx0)], v);
+                        else
+                            unsafeAtomicAdd(&gl[(int64_t)y * cams.W + x], v);
+                    }
+                }
+                // pose: d p / d u and d p / d v, then through the projection
+                const float du = (1.0f - sm.ay) * (sm.sg[1] - sm.sg[0]) + sm.ay * (sm.sg[3] - sm.sg[2]);
+                const float dv = (1.0f - sm.ax) * (sm.sg[2] - sm.sg[0]) + sm.ax * (sm.sg[3] - sm.sg[1]);
+                const float rz = 1.0f / sm.Xc[2];
+                gx = gp * du * cm.fx * rz;
+                gy = gp * dv * cm.fy * rz;
+                gz = -(gx * sm.Xc[0] + gy * sm.Xc[1]) * rz;
+                // R X = X_c - t
+                const float rx = sm.Xc[0] - cm.t[0], ry = sm.Xc[1] - cm.t[1],
+                            rzv = sm.Xc[2] - cm.t[2];
+                bxv = ry * gz - rzv * gy;
+                byv = rzv * gx - rx * gz;
+                bzv = rx * gy - ry * gx;
+            }
+            const float v6[6] = {gx, gy, gz, bxv, byv, bzv};
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const float t = wave_sum(v6[q]);
                 if (lane_id() == 0 && t != 0.0f)
                     atomicAdd(&s_acc[c][q], t);
             }
+            if (in_lds) {
+                __syncthreads();
+                for (int q = threadIdx.x; q < (int)(wxn * wyn); q += kBlock) {
+                    const float v = s_win[q];
+                    if (v != 0.0f)      // only in-image taps were added
+                        unsafeAtomicAdd(&gl[(int64_t)(wy0 + q / wxn) * cams.W + (wx0 + q % wxn)], v);
+                }
+            }
         }
+        __syncthreads();   // the next brick's first camera resets a window buffer
     }
     __syncthreads();
     for (int q = threadIdx.x; q < cams.n * 6; q += kBlock)
@@ -337,8 +421,12 @@ hipError_t launch_soft_backward(fvv_ctx* ctx, const SoftCamSet& cams, const Soft
     const unsigned zb = (unsigned)std::min<int64_t>((npx + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(soft_zero_kernel, dim3(zb), dim3(kBlock), 0, s, grad_logits, npx,
                        ctx->d_soft_acc, FVV_MAX_CAMS * 6);
+    const int64_t bricks = (int64_t)((g.dims[0] + kBrickX - 1) / kBrickX) *
+                           ((g.dims[1] + kBrickY - 1) / kBrickY) *
+                           ((g.dims[2] + kBrickZ - 1) / kBrickZ);
     const unsigned blocks =
-        (unsigned)std::min<int64_t>((V + kBlock - 1) / kBlock, (int64_t)ctx->n_cus * 16);
+        (unsigned)std::min<int64_t>(bricks * kCamGroups, (int64_t)ctx->n_cus * 16);
+    (void)V;
 #define X(KN)                                                                                   \
     if (target)                                                                                 \
         hipLaunchKernelGGL((soft_bwd_kernel<KN, true>), dim3(blocks), dim3(kBlock), 0, s, cams, \
