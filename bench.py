@@ -85,10 +85,17 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
+BATCHED_KERNEL = {"kernel": "carve_batched_culled_kernel",
+                  "sources": ["paper_1903_11785_amd/csrc/carve.hip",
+                              "paper_1903_11785_amd/csrc/fvv_internal.h"],
+                  "traffic": "profiles/carve_batched_culled_kernel_batched_traffic.json",
+                  "tile": [16, 16, 4]}
+
+
 def stored_traffic(k):
     """HBM bytes per launch from the stored counter runs, if the kernel's sources
     are those the counters were taken on; else None."""
-    spec = KERNELS[k]
+    spec = KERNELS[k] if isinstance(k, str) else k
     path = os.path.join(ROOT, spec["traffic"])
     if not os.path.exists(path):
         return None
@@ -210,10 +217,13 @@ def batched_leg(args, fvv, torch):
         "samples_per_s": total / (b_ms * 1e-3),
         "per_roi_graph_ms_p50": p_ms, "per_roi_eager_wall_ms": eager_ms,
         "speedup_vs_per_roi": p_ms / b_ms, "identical_to_per_roi": identical,
-        # compulsory bytes only: one occupancy byte per sample written
+        # compulsory bytes only: one occupancy byte per sample written; traffic from
+        # the stored counter runs (taken with the 16x16x4 tile)
         "roofline": {"kernel": "carve_batched_culled_kernel", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": int(total)},
+                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": int(total),
+                     "traffic": (stored_traffic(BATCHED_KERNEL)
+                                 if [t.tx, t.ty, t.tz] == BATCHED_KERNEL["tile"] else None)},
     }
 
 
