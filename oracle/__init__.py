@@ -6,7 +6,7 @@ C written from the paper's definitions) through ctypes with numpy arrays, and
 shares no code with the HIP library.
 
 Functions (paper sections in ``fvv_oracle.c``):
-  pack, carve, label, label_bfs, roi_fine, edges, bisect, point_inside,
+  pack, carve, label, label_bfs, roi_fine, edges, bisect, mesh, point_inside,
   floor_div, and ``frame`` which chains them in the paper's order
   (Sec. II-B-1 sparse hull, II-B-2 labelling + Eq. (1) filter + boxes,
   II-B-3 dense hull per ROI, II-C crossing edges + exit points).
@@ -58,6 +58,8 @@ def lib():
         L.orc_roi_fine.argtypes = [p, p, i64, i64, p, p, p, p]
         L.orc_edges.argtypes = [p, p, p, i64]
         L.orc_edges.restype = i64
+        L.orc_mesh.argtypes = [p, p, p, i64, p, i64]
+        L.orc_mesh.restype = i64
         L.orc_bisect.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, f32, p, p, p, p, i64,
                                  C.c_int, p, p]
         L.orc_bisect.restype = i64
@@ -160,6 +162,21 @@ def edges(occ: np.ndarray) -> np.ndarray:
     keys = np.empty(max(E, 1), np.uint32)
     lib().orc_edges(_p(dims), _p(occ), _p(keys), E)
     return keys[:E].copy()
+
+
+def mesh(occ: np.ndarray, keys: np.ndarray) -> np.ndarray:
+    """Triangles [T][3] (indices into keys) of the isosurface over the cells
+    of the lattice occ [nz][ny][nx]; keys: its crossing edges (edges())."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    nz, ny, nx = occ.shape
+    dims = _i3((nx, ny, nz))
+    T = lib().orc_mesh(_p(dims), _p(occ), _p(keys), keys.size, None, 0)
+    if T < 0:
+        raise ValueError("a crossing edge is missing from keys")
+    tris = np.empty((max(T, 1), 3), np.uint32)
+    lib().orc_mesh(_p(dims), _p(occ), _p(keys), keys.size, _p(tris), T)
+    return tris[:T].copy()
 
 
 def bisect(P, sils, W, H, lat: Lattice, occ: np.ndarray, keys: np.ndarray, steps: int = 8,

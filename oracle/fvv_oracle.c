@@ -415,3 +415,241 @@ int32_t orc_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ mesh */
+
+/*
+ * Triangles of the isosurface over the cells of one lattice (Sec. II-C: once
+ * every crossing edge has its vertex, the surface follows the marching-cubes
+ * configurations and is expressed as triangles).  A cell's surface crosses
+ * exactly its edges whose two samples differ, one vertex per crossing edge.
+ * The paper gives no configuration table, so the configurations are fixed by
+ * a face rule, evaluated here cell by cell:
+ *   - on each cell face, the crossing edges of the face are joined in pairs by
+ *     segments: two crossing edges by one segment; four (two diagonal inside
+ *     corners) by two segments, each cutting off one inside corner;
+ *   - a segment runs from one crossing edge to the other so that, seen from
+ *     outside the cell, the inside part of the face lies on its right;
+ *   - the segments chain into closed loops (each crossing edge lies on two
+ *     faces).  Each loop is cut into a fan of triangles (v0, v_i, v_i+1),
+ *     facing away from the occupied corners, from the apex v0: the first
+ *     vertex, in loop order from the smallest cell-edge number, that lies on
+ *     no face the loop crosses twice (a loop can cross a face with four
+ *     crossing edges twice; a fan diagonal between two vertices of one face
+ *     would lie in that face, where the neighbouring cell may put one too).
+ * Cell corners: b = dx + 2 dy + 4 dz.  Cell edges: 4 a + u + 2 v along axis a,
+ * with (u, v) the corner coordinates on the other two axes in increasing axis
+ * order.  Triangles are listed by cell in linear order (x fastest), loops by
+ * their smallest edge, with vertices as indices into `keys` (the lattice's
+ * crossing edges, ascending).  Writes at most max_tris triangles; returns
+ * the count, or -1 if a crossing edge is missing from `keys`.
+ */
+static void cell_edge_ends(int e, int c0[3], int c1[3])
+{
+    const int a = e / 4, u = e & 1, v = (e >> 1) & 1;
+    const int o1 = a == 0 ? 1 : 0, o2 = a == 2 ? 1 : 2;   /* the other axes, increasing */
+    c0[a] = 0;
+    c1[a] = 1;
+    c0[o1] = c1[o1] = u;
+    c0[o2] = c1[o2] = v;
+}
+
+/* next[e] = the edge a segment leads to from crossing edge e, or -1. */
+static void cell_segments(const int inside[8], int next[12])
+{
+    for (int e = 0; e < 12; ++e)
+        next[e] = -1;
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s) {
+            /* the face's edges and their crossings */
+            int fe[4], nf = 0;
+            for (int e = 0; e < 12; ++e) {
+                int c0[3], c1[3];
+                cell_edge_ends(e, c0, c1);
+                if (e / 4 != a && c0[a] == s)
+                    fe[nf++] = e;
+            }
+            int cross[4], nc = 0;
+            for (int q = 0; q < 4; ++q) {
+                int c0[3], c1[3];
+                cell_edge_ends(fe[q], c0, c1);
+                const int b0 = c0[0] + 2 * c0[1] + 4 * c0[2], b1 = c1[0] + 2 * c1[1] + 4 * c1[2];
+                if (inside[b0] != inside[b1])
+                    cross[nc++] = fe[q];
+            }
+            if (nc == 0)
+                continue;
+            /* pairs of crossing edges and an inside corner for each pair */
+            int pa[2], pb[2], pin[2][3], np = 0;
+            if (nc == 2) {
+                pa[0] = cross[0];
+                pb[0] = cross[1];
+                int found = 0;
+                for (int b = 0; b < 8 && !found; ++b) {
+                    const int c[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+                    if (c[a] == s && inside[b]) {
+                        for (int d = 0; d < 3; ++d)
+                            pin[0][d] = c[d];
+                        found = 1;
+                    }
+                }
+                np = 1;
+            } else { /* four: cut off each inside corner of the face */
+                for (int b = 0; b < 8; ++b) {
+                    const int c[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+                    if (c[a] != s || !inside[b])
+                        continue;
+                    int m = 0, two[2];
+                    for (int q = 0; q < 4; ++q) {
+                        int c0[3], c1[3];
+                        cell_edge_ends(cross[q], c0, c1);
+                        int at0 = 1, at1 = 1;
+                        for (int d = 0; d < 3; ++d) {
+                            at0 &= c0[d] == c[d];
+                            at1 &= c1[d] == c[d];
+                        }
+                        if (at0 || at1)
+                            two[m++] = cross[q];
+                    }
+                    pa[np] = two[0];
+                    pb[np] = two[1];
+                    for (int d = 0; d < 3; ++d)
+                        pin[np][d] = c[d];
+                    ++np;
+                }
+            }
+            /* orientation: with doubled coordinates, inside on the right seen
+             * from outside means ((M2 - M1) x (P - M1)) . n < 0, n = the face's
+             * outward normal */
+            for (int q = 0; q < np; ++q) {
+                int a0[3], a1[3], b0[3], b1[3];
+                cell_edge_ends(pa[q], a0, a1);
+                cell_edge_ends(pb[q], b0, b1);
+                long M1[3], M2[3], P[3];
+                for (int d = 0; d < 3; ++d) {
+                    M1[d] = a0[d] + a1[d];
+                    M2[d] = b0[d] + b1[d];
+                    P[d] = 2 * pin[q][d];
+                }
+                const long u[3] = {M2[0] - M1[0], M2[1] - M1[1], M2[2] - M1[2]};
+                const long w[3] = {P[0] - M1[0], P[1] - M1[1], P[2] - M1[2]};
+                const long cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
+                                    u[0] * w[1] - u[1] * w[0]};
+                const long dot = cr[a] * (s ? 1 : -1);
+                if (dot < 0)
+                    next[pa[q]] = pb[q];
+                else
+                    next[pb[q]] = pa[q];
+            }
+        }
+}
+
+/* The two faces (2 a + s: axis a, side s) cell edge e lies on. */
+static void edge_faces(int e, int f[2])
+{
+    int c0[3], c1[3];
+    cell_edge_ends(e, c0, c1);
+    int m = 0;
+    for (int a = 0; a < 3; ++a)
+        if (a != e / 4)
+            f[m++] = 2 * a + c0[a];
+}
+
+/* The face two cell edges share, or -1. */
+static int common_face(int e1, int e2)
+{
+    int f1[2], f2[2];
+    edge_faces(e1, f1);
+    edge_faces(e2, f2);
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+            if (f1[p] == f2[q])
+                return f1[p];
+    return -1;
+}
+
+static int64_t find_key(const uint32_t *keys, int64_t n, uint32_t key)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] == key)
+            return mid;
+        if (keys[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+int64_t orc_mesh(const int32_t *n, const uint8_t *occ, const uint32_t *keys, int64_t n_keys,
+                 uint32_t *tris, int64_t max_tris)
+{
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    int64_t T = 0;
+    for (int64_t k = 0; k + 1 < nz; ++k)
+        for (int64_t j = 0; j + 1 < ny; ++j)
+            for (int64_t i = 0; i + 1 < nx; ++i) {
+                int inside[8], any = 0, all = 1;
+                for (int b = 0; b < 8; ++b) {
+                    const int64_t lin = (i + (b & 1)) + nx * ((j + ((b >> 1) & 1)) + ny * (k + ((b >> 2) & 1)));
+                    inside[b] = occ[lin] != 0;
+                    any |= inside[b];
+                    all &= inside[b];
+                }
+                if (!any || all)
+                    continue;
+                int next[12], seen[12] = {0};
+                cell_segments(inside, next);
+                for (int e = 0; e < 12; ++e) {
+                    if (next[e] < 0 || seen[e])
+                        continue;
+                    int loop[12], m = 0;
+                    for (int x = e; !seen[x]; x = next[x]) {
+                        seen[x] = 1;
+                        loop[m++] = x;
+                    }
+                    /* faces crossed twice by this loop: a segment lies on
+                     * the face common to its two edges */
+                    int face_segs[6] = {0};
+                    for (int q = 0; q < m; ++q) {
+                        const int f = common_face(loop[q], loop[(q + 1) % m]);
+                        if (f >= 0)
+                            ++face_segs[f];
+                    }
+                    int apex = 0;
+                    for (int q = 0; q < m; ++q) {
+                        int fa[2];
+                        edge_faces(loop[q], fa);
+                        if (face_segs[fa[0]] < 2 && face_segs[fa[1]] < 2) {
+                            apex = q;
+                            break;
+                        }
+                    }
+                    int rot[12];
+                    for (int q = 0; q < m; ++q)
+                        rot[q] = loop[(apex + q) % m];
+                    for (int q = 0; q < m; ++q)
+                        loop[q] = rot[q];
+                    int64_t idx[12];
+                    for (int q = 0; q < m; ++q) {
+                        int c0[3], c1[3];
+                        cell_edge_ends(loop[q], c0, c1);
+                        const int64_t lin = (i + c0[0]) + nx * ((j + c0[1]) + ny * (k + c0[2]));
+                        idx[q] = find_key(keys, n_keys, (uint32_t)(3 * lin + loop[q] / 4));
+                        if (idx[q] < 0)
+                            return -1;
+                    }
+                    for (int q = 1; q + 1 < m; ++q) {
+                        if (T < max_tris) {
+                            tris[3 * T + 0] = (uint32_t)idx[0];
+                            tris[3 * T + 1] = (uint32_t)idx[q];
+                            tris[3 * T + 2] = (uint32_t)idx[q + 1];
+                        }
+                        ++T;
+                    }
+                }
+            }
+    return T;
+}
