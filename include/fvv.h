@@ -270,6 +270,36 @@ fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint8_t
                      uint32_t *d_sils, const fvv_frame_out *out, hipEvent_t *events,
                      hipStream_t stream);
 
+/* Triangles of the isosurface over the cells of one lattice (Sec. II-C: with
+ * a vertex on every crossing edge, the surface follows the marching-cubes
+ * configurations, expressed as triangles).  A cell's surface crosses exactly
+ * its edges whose two samples differ, one vertex per crossing edge.  The
+ * configurations (the paper gives no table) follow a face rule: on each cell
+ * face the crossing edges are joined by segments (with two diagonal occupied
+ * corners each is cut off alone), oriented with the face's occupied part on
+ * their right seen from outside the cell; the segments chain into loops, each
+ * cut into a fan of triangles (v0, v_i, v_i+1) from the first vertex, in loop
+ * order from its smallest cell edge, that lies on no face the loop crosses
+ * twice.  Triangles face away from the occupied side and the surface is
+ * closed wherever it does not reach the lattice's border.  Cell corners are
+ * b = dx + 2 dy + 4 dz, cell edges 4 a + u + 2 v (axis a; u, v the corner
+ * coordinates on the other two axes in increasing order).
+ *   d_occ:    occupancy of `grid` (device, x fastest), as for fvv_surface;
+ *   d_keys:   its crossing edges, ascending (fvv_surface's output), the first
+ *             min(*d_n_keys, max_keys) of them valid (*d_n_keys device);
+ *   d_tris:   out, uint32 [max_tris][3]: indices into d_keys (so into the
+ *             exit points), by cell in linear order (x fastest), loops by
+ *             their smallest cell edge;
+ *   d_n_tris: out (device), the triangle count.
+ * More than max_tris triangles, or a crossing edge missing from the keys
+ * (truncated keys), set the ECAPACITY flag (a missing vertex is written as
+ * 0xffffffff).  EINVAL on NULL pointers, zero capacities, empty dims, or a
+ * lattice beyond 0x55555555 samples or the context's work-item scratch
+ * (about max_fine samples). */
+fvv_status fvv_mesh(fvv_ctx *ctx, const fvv_grid *grid, const uint8_t *d_occ,
+                    const uint32_t *d_keys, const uint32_t *d_n_keys, uint32_t max_keys,
+                    uint32_t *d_tris, uint32_t max_tris, uint32_t *d_n_tris, hipStream_t stream);
+
 /* ---------------------------------------------------------------- soft hull
  * A differentiable relative of the binary hull of Sec. II-B-1 (not in the
  * paper), for refining silhouette logits and camera poses by gradient descent.

@@ -7,8 +7,8 @@ without a GPU, raises.
 
 Names follow the C ABI: ``pack_silhouettes``, ``carve``, ``label``,
 ``roi_grids``, ``surface``, ``carve_batched`` (+ ``carve_batched_graph``,
-``tune_carve_batched``), ``frame``, ``frame_graph``, ``soft_forward`` and
-``soft_backward``, as methods of :class:`Context` (which owns the library's
+``tune_carve_batched``), ``frame``, ``frame_graph``, ``mesh``,
+``soft_forward`` and ``soft_backward``, as methods of :class:`Context` (which owns the library's
 device scratch).  The tile autotuner of the batched carve is
 :mod:`paper_1903_11785_amd.autotune`; the soft hull's autograd functions are in
 :mod:`paper_1903_11785_amd.soft`.
@@ -133,6 +133,7 @@ def _load():
                                            i32),
         "fvv_tune_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), u32, i32,
                                     C.POINTER(C.c_float), C.POINTER(u32), P], i32),
+        "fvv_mesh": ([P, C.POINTER(GridC), P, P, P, u32, P, u32, P, P], i32),
         "fvv_soft_forward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P, P,
                               P], i32),
         "fvv_soft_backward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P,
@@ -357,6 +358,20 @@ class Context:
                                           C.byref(best), C.c_void_p(_stream(stream))),
             "fvv_tune_carve_batched")
         return int(best.value), [float(v) for v in ms]
+
+    def mesh(self, grid: Grid, occ, keys, n_keys, max_tris: int = 1 << 22, tris=None,
+             n_tris=None, stream=None):
+        """Marching-cubes triangles (uint32 [max_tris][3] indices into keys) of
+        one lattice; returns (tris, n_tris) device tensors."""
+        import torch
+        if tris is None:
+            tris = torch.empty((max_tris, 3), dtype=torch.int32, device=occ.device)
+        if n_tris is None:
+            n_tris = torch.zeros(1, dtype=torch.int32, device=occ.device)
+        _ok(self.L.fvv_mesh(self.h, C.byref(grid.c()), _ptr(occ), _ptr(keys), _ptr(n_keys),
+                            int(keys.numel()), _ptr(tris), int(tris.shape[0]), _ptr(n_tris),
+                            C.c_void_p(_stream(stream))), "fvv_mesh")
+        return tris, n_tris
 
     def soft_forward(self, grid: Grid, cams, W: int, H: int, logits, target=None, occ=None,
                      loss=None, stream=None):

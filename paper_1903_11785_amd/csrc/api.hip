@@ -193,7 +193,7 @@ void fvv_destroy(fvv_ctx* ctx) {
     void* ptrs[] = {ctx->d_status, ctx->d_counter, ctx->d_rowbits, ctx->d_rowmask, ctx->d_rmpre,
                     ctx->d_rows, ctx->d_rs, ctx->d_x0, ctx->d_x1, ctx->d_rrow, ctx->d_runP,
                     ctx->d_stats,
-                    ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc,
+                    ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc, ctx->d_mesh_table,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
                     ctx->d_point_off_single, ctx->d_counts_single};
     for (void* p : ptrs)
@@ -259,6 +259,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_prefix, c->job_cap)
     A(d_job_pad, c->job_cap * FVV_MAX_CAMS)
     A(d_soft_acc, FVV_MAX_CAMS * 6)
+    A(d_mesh_table, 1)
     A(d_job_single, 1)
     A(d_cams, FVV_MAX_CAMS)
     A(d_finebits, c->bit_cap)
@@ -272,6 +273,11 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        MeshTable tbl;
+        build_mesh_table(&tbl);
+        e = hipMemcpy(c->d_mesh_table, &tbl, sizeof(tbl), hipMemcpyHostToDevice);
+    }
     // scratch the kernels expect cleared (they clear it again after use)
     if (e == hipSuccess)
         e = hipMemset(c->d_status, 0, sizeof(uint32_t));
@@ -410,6 +416,22 @@ fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_job
         return FVV_EINVAL;
     return dev(launch_carve_batched(ctx, d_jobs, n_jobs, d_cams, d_sils, d_occ_out, nullptr,
                                     tile_of(tile), persistent_blocks(ctx, tile), false, stream));
+}
+
+fvv_status fvv_mesh(fvv_ctx* ctx, const fvv_grid* grid, const uint8_t* d_occ,
+                    const uint32_t* d_keys, const uint32_t* d_n_keys, uint32_t max_keys,
+                    uint32_t* d_tris, uint32_t max_tris, uint32_t* d_n_tris, hipStream_t stream) {
+    if (!ctx || !grid || !d_occ || !d_keys || !d_n_keys || !d_tris || !d_n_tris || max_keys < 1 ||
+        max_tris < 1)
+        return FVV_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (grid->dims[a] < 1)
+            return FVV_EINVAL;
+    // keys 3*lin+axis and cell indices stay 32-bit; the work items fit the scratch
+    if (grid_samples(*grid) > (int64_t)0x55555555 || mesh_items(*grid) > ctx->item_cap)
+        return FVV_EINVAL;
+    return dev(launch_mesh(ctx, *grid, d_occ, d_keys, d_n_keys, max_keys, d_tris, max_tris,
+                           d_n_tris, stream));
 }
 
 // ------------------------------------------------------------------ soft hull

@@ -383,6 +383,8 @@ __device__ __forceinline__ int upper_job(F off, int n, uint64_t x) {
     return lo;
 }
 
+struct MeshTable;
+
 }  // namespace fvv
 
 // ------------------------------------------------------------------ context
@@ -408,6 +410,7 @@ struct fvv_ctx {
     fvv::JobPrefix* d_prefix;    // per job (max(max_jobs, max_rois) + 1)
     float* d_job_pad;            // rounding pad per (job, camera) of a batched carve
     double* d_soft_acc;          // soft hull: per camera sum g and sum (R X) x g
+    fvv::MeshTable* d_mesh_table;  // marching-cubes configurations (built at creation)
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
     fvv_camera* d_cams;          // camera table of fvv_frame
     uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)
@@ -475,6 +478,18 @@ struct SoftCamSet {
 struct SoftJacobians {
     double Jl[FVV_MAX_CAMS][9];
 };
+
+// Marching-cubes configurations: triangles per corner pattern (at most 5)
+// and their cell edges (4 a + u + 2 v).
+struct MeshTable {
+    uint8_t count[256];
+    uint8_t edge[256][15];
+};
+void build_mesh_table(MeshTable* t);
+int64_t mesh_items(const fvv_grid& g);
+hipError_t launch_mesh(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, const uint32_t* keys,
+                       const uint32_t* n_keys, uint32_t max_keys, uint32_t* tris,
+                       uint32_t max_tris, uint32_t* n_tris, hipStream_t s);
 
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);

@@ -1,0 +1,186 @@
+"""GPU parity of the marching-cubes triangles (fvv_mesh) against the oracle
+(oracle.mesh): the triangle arrays are integer results and must be identical
+(same triangles, same order, same vertex order) on random grids with ragged
+sizes, the tiny scene's ROIs through the surface pass, and a volleyball
+frame's ROIs as the frame leaves them; plus degenerate lattices and
+capacity overflows."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fvv():
+    import paper_1903_11785_amd as fvv
+    return fvv
+
+
+@pytest.fixture(scope="module")
+def ctx(fvv):
+    c = fvv.Context(max_coarse=5_000_000, max_fine=1 << 28, max_rois=4096, max_points=1 << 23,
+                    max_jobs=4096)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def grid_for(fvv, dims):
+    return fvv.Grid(origin=(0.0, 0.0, 0.0), h=np.float32(0.01), lo=(0, 0, 0), dims=tuple(dims))
+
+
+def gpu_mesh(fvv, ctx, occ, keys, max_tris=1 << 20):
+    import torch
+    nz, ny, nx = occ.shape
+    k = dev(keys.astype(np.uint32).view(np.int32) if keys.size else np.zeros(1, np.int32))
+    nk = torch.tensor([keys.size], dtype=torch.int32, device="cuda")
+    tris, n = ctx.mesh(grid_for(fvv, (nx, ny, nz)), dev(occ), k[:max(keys.size, 1)], nk,
+                       max_tris=max_tris)
+    n = int(n.cpu()[0])
+    return tris[:min(n, max_tris)].cpu().numpy().view(np.uint32), n
+
+
+@pytest.mark.parametrize("shape,p,seed", [((9, 8, 7), 0.45, 0), ((37, 29, 23), 0.5, 1),
+                                          ((64, 17, 33), 0.3, 2), ((5, 70, 3), 0.6, 3),
+                                          ((2, 2, 2), 0.5, 4)])
+def test_random_grids_match_oracle(fvv, ctx, shape, p, seed):
+    rng = np.random.default_rng(seed)
+    occ = (rng.uniform(size=shape) < p).astype(np.uint8)
+    keys = oracle.edges(occ)
+    ref = oracle.mesh(occ, keys)
+    got, n = gpu_mesh(fvv, ctx, occ, keys)
+    assert n == len(ref)
+    np.testing.assert_array_equal(got, ref)
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_every_cell_configuration(fvv, ctx):
+    """All 256 corner patterns, each in its own cell of one lattice (cells
+    separated by empty layers), against the oracle."""
+    occ = np.zeros((3 * 4 + 1, 3 * 8 + 1, 3 * 8 + 1), np.uint8)
+    for case in range(256):
+        ci, cj, ck = case % 8, (case // 8) % 8, case // 64
+        for b in range(8):
+            if (case >> b) & 1:
+                occ[3 * ck + 1 + ((b >> 2) & 1), 3 * cj + 1 + ((b >> 1) & 1), 3 * ci + 1 + (b & 1)] = 1
+    keys = oracle.edges(occ)
+    ref = oracle.mesh(occ, keys)
+    got, n = gpu_mesh(fvv, ctx, occ, keys)
+    assert n == len(ref)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_tiny_scene_rois_through_the_surface_pass(fvv, ctx, scene_cache):
+    """The tiny scene's fine ROIs carved on the GPU, their crossing edges from
+    fvv_surface, then fvv_mesh on the device keys: equal to the oracle."""
+    import torch
+    sc = scene_cache(scenes.CFG_TINY, 2)
+    r = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                     sc.t_nb, sc.n_steps)
+    sils = ctx.pack_silhouettes(dev(sc.masks))
+    for lat, occ_ref in zip(r.fine, r.occ_fine):
+        grid = fvv.Grid(origin=tuple(np.float32(lat.origin)), h=np.float32(lat.h), lo=tuple(lat.lo),
+                        dims=tuple(lat.dims))
+        occ = ctx.carve(sc.P32, sc.W, sc.H, sils, grid)
+        keys, xyz, n_pts = ctx.surface(grid, occ, sc.P32, sc.W, sc.H, sils, n_steps=sc.n_steps)
+        tris, n_t = ctx.mesh(grid, occ, keys, n_pts)
+        n_t = int(n_t.cpu()[0])
+        ref_keys = oracle.edges(occ_ref)
+        ref = oracle.mesh(occ_ref, ref_keys)
+        assert n_t == len(ref)
+        np.testing.assert_array_equal(tris[:n_t].cpu().numpy().view(np.uint32), ref)
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_volleyball_frame_rois(fvv, ctx, scene_cache):
+    """The ROIs of a volleyball frame as fvv_frame leaves them (fine
+    occupancy and ROI-major keys), meshed ROI by ROI."""
+    import torch
+    sc = scene_cache(scenes.CFG_VOLLEYBALL, 0)
+    coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
+    params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
+                              sc.n_steps)
+    bufs = fvv.FrameBuffers(coarse, 256, 1 << 26, 1 << 22)
+    N, H, W = sc.masks.shape
+    sils = torch.zeros((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+    ctx.frame(params, sils, bufs, masks=dev(sc.masks))
+    torch.cuda.synchronize()
+    assert ctx.check() == fvv.FVV_OK
+    K = int(bufs.counts.cpu()[0])
+    jobs = bufs.jobs_host(K)
+    off = bufs.point_off.cpu().numpy().view(np.uint32)
+    checked = 0
+    for t in range(0, K, 3):           # every third ROI (the oracle is single-threaded per ROI)
+        g = jobs[t]
+        dims = tuple(int(v) for v in g["dims"])
+        grid = fvv.Grid(origin=tuple(g["origin"]), h=g["h"], lo=tuple(int(v) for v in g["lo"]),
+                        dims=dims)
+        o = int(g["out_offset"])
+        occ = bufs.occ_fine[o:o + int(np.prod(dims))]
+        k0, k1 = int(off[t]), int(off[t + 1])
+        keys = bufs.keys[k0:k1]
+        nk = torch.tensor([k1 - k0], dtype=torch.int32, device="cuda")
+        tris, n_t = ctx.mesh(grid, occ, keys, nk)
+        n_t = int(n_t.cpu()[0])
+        occ_h = occ.cpu().numpy().reshape(dims[2], dims[1], dims[0])
+        keys_h = keys.cpu().numpy().view(np.uint32)
+        np.testing.assert_array_equal(keys_h, oracle.edges(occ_h))
+        ref = oracle.mesh(occ_h, keys_h)
+        assert n_t == len(ref)
+        np.testing.assert_array_equal(tris[:n_t].cpu().numpy().view(np.uint32), ref)
+        checked += 1
+    assert checked >= 4
+    assert ctx.check() == fvv.FVV_OK
+
+
+@pytest.mark.parametrize("shape,fill", [((1, 5, 6), 0.5), ((6, 1, 5), 0.5), ((4, 5, 6), 0.0),
+                                        ((4, 5, 6), 1.0)])
+def test_degenerate_lattices(fvv, ctx, shape, fill):
+    rng = np.random.default_rng(0)
+    occ = (rng.uniform(size=shape) < fill).astype(np.uint8)
+    keys = oracle.edges(occ)
+    got, n = gpu_mesh(fvv, ctx, occ, keys)
+    assert n == len(oracle.mesh(occ, keys)) == 0
+
+
+def test_capacity_overflow_and_truncated_keys(fvv, ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    occ = (rng.uniform(size=(20, 21, 22)) < 0.5).astype(np.uint8)
+    keys = oracle.edges(occ)
+    ref = oracle.mesh(occ, keys)
+    # fewer slots than triangles: the first ones written, count complete, flag set
+    got, n = gpu_mesh(fvv, ctx, occ, keys, max_tris=len(ref) // 3)
+    assert n == len(ref)
+    np.testing.assert_array_equal(got, ref[:len(ref) // 3])
+    assert ctx.check() == fvv.FVV_ECAPACITY
+    # keys cut short: vertices beyond them are missing, the flag is set
+    kk = dev(keys.view(np.int32))
+    nk = torch.tensor([keys.size], dtype=torch.int32, device="cuda")
+    g = grid_for(fvv, occ.shape[::-1])
+    tris, n_t = ctx.mesh(g, dev(occ), kk[:keys.size // 2], nk)
+    assert int(n_t.cpu()[0]) == len(ref)
+    assert ctx.check() == fvv.FVV_ECAPACITY
+    assert ctx.check() == fvv.FVV_OK
+
+
+def test_invalid_mesh_arguments(fvv, ctx):
+    import torch
+    occ = dev(np.zeros((4, 4, 4), np.uint8))
+    keys = torch.zeros(4, dtype=torch.int32, device="cuda")
+    nk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    bad_grid = fvv.Grid(origin=(0.0, 0.0, 0.0), h=np.float32(0.01), lo=(0, 0, 0), dims=(0, 4, 4))
+    with pytest.raises(fvv.FvvError) as e:
+        ctx.mesh(bad_grid, occ, keys, nk)
+    assert e.value.status == fvv.FVV_EINVAL
+    big = fvv.Grid(origin=(0.0, 0.0, 0.0), h=np.float32(0.01), lo=(0, 0, 0), dims=(2048, 2048, 512))
+    with pytest.raises(fvv.FvvError) as e:
+        ctx.mesh(big, occ, keys, nk)
+    assert e.value.status == fvv.FVV_EINVAL
