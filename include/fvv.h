@@ -255,6 +255,13 @@ typedef struct {
     uint32_t max_rois;
     int64_t max_fine;
     uint32_t max_points;
+    /* optional marching-cubes triangles of every ROI (as fvv_mesh, vertex
+     * indices into d_keys / d_xyz of the frame): NULL d_tris for none.
+     * d_tri_off: [max_rois + 1], the ROI's first triangle, [K] the total
+     * (clamped to 2^32 - 1, ECAPACITY past max_tris). */
+    uint32_t *d_tris;
+    uint32_t *d_tri_off;
+    uint32_t max_tris;
 } fvv_frame_out;
 
 /* Enqueue the whole frame on `stream`.  d_masks: the frame's uint8
@@ -291,11 +298,13 @@ fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint8_t
  *             exit points), by cell in linear order (x fastest), loops by
  *             their smallest cell edge;
  *   d_n_tris: out (device), the triangle count.
- * More than max_tris triangles, or a crossing edge missing from the keys
- * (truncated keys), set the ECAPACITY flag (a missing vertex is written as
- * 0xffffffff).  EINVAL on NULL pointers, zero capacities, empty dims, or a
- * lattice beyond 0x55555555 samples or the context's work-item scratch
- * (about max_fine samples). */
+ * More than max_tris triangles (the first max_tris are written, the count is
+ * complete), or a crossing edge missing from the keys (truncated keys, or keys
+ * that are not this occupancy's crossing edges), set the ECAPACITY flag; a
+ * missing vertex is written as 0xffffffff.  EINVAL on NULL pointers, zero
+ * capacities, empty dims, or a lattice beyond 0x55555555 samples or whose fine
+ * bitmap exceeds the context's (as for fvv_surface).  Uses the context's
+ * scratch: calls on one context must not overlap. */
 fvv_status fvv_mesh(fvv_ctx *ctx, const fvv_grid *grid, const uint8_t *d_occ,
                     const uint32_t *d_keys, const uint32_t *d_n_keys, uint32_t max_keys,
                     uint32_t *d_tris, uint32_t max_tris, uint32_t *d_n_tris, hipStream_t stream);

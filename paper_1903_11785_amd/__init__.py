@@ -86,7 +86,8 @@ class FrameOut(C.Structure):
     _fields_ = [("d_occ_coarse", C.c_void_p), ("d_labels", C.c_void_p), ("d_rois", C.c_void_p),
                 ("d_jobs", C.c_void_p), ("d_occ_fine", C.c_void_p), ("d_keys", C.c_void_p),
                 ("d_xyz", C.c_void_p), ("d_point_off", C.c_void_p), ("d_counts", C.c_void_p),
-                ("max_rois", C.c_uint32), ("max_fine", C.c_int64), ("max_points", C.c_uint32)]
+                ("max_rois", C.c_uint32), ("max_fine", C.c_int64), ("max_points", C.c_uint32),
+                ("d_tris", C.c_void_p), ("d_tri_off", C.c_void_p), ("max_tris", C.c_uint32)]
 
 
 ROI_DTYPE = np.dtype([("lo", "<i4", 3), ("hi", "<i4", 3), ("count", "<u4"), ("min_index", "<u4")])
@@ -446,7 +447,7 @@ class FrameBuffers:
     """Device outputs of one frame (caller-owned torch tensors)."""
 
     def __init__(self, coarse: Grid, max_rois: int = 256, max_fine: int = 1 << 26,
-                 max_points: int = 1 << 22, device: str = "cuda"):
+                 max_points: int = 1 << 22, device: str = "cuda", max_tris: int = 0):
         import torch
         z = lambda shape, dt: torch.zeros(shape, dtype=dt, device=device)
         self.occ_coarse = z(coarse.shape, torch.uint8)
@@ -458,10 +459,17 @@ class FrameBuffers:
         self.xyz = z((max_points, 3), torch.float32)
         self.point_off = z(max_rois + 1, torch.int32)
         self.counts = z(4, torch.int32)
+        # marching-cubes triangles of the ROIs (vertex indices into keys / xyz),
+        # when max_tris > 0
+        self.tris = z((max_tris, 3), torch.int32) if max_tris > 0 else None
+        self.tri_off = z(max_rois + 1, torch.int32) if max_tris > 0 else None
         self.max_rois, self.max_fine, self.max_points = max_rois, max_fine, max_points
+        self.max_tris = max_tris
         self.c = FrameOut(_ptr(self.occ_coarse), _ptr(self.labels), _ptr(self.rois),
                           _ptr(self.jobs), _ptr(self.occ_fine), _ptr(self.keys), _ptr(self.xyz),
-                          _ptr(self.point_off), _ptr(self.counts), max_rois, max_fine, max_points)
+                          _ptr(self.point_off), _ptr(self.counts), max_rois, max_fine, max_points,
+                          _ptr(self.tris) if self.tris is not None else None,
+                          _ptr(self.tri_off) if self.tri_off is not None else None, max_tris)
 
     def jobs_host(self, n: int) -> np.ndarray:
         return self.jobs[:n].cpu().numpy().reshape(-1).view(JOB_DTYPE)

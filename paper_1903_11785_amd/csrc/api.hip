@@ -195,7 +195,8 @@ void fvv_destroy(fvv_ctx* ctx) {
                     ctx->d_stats,
                     ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc, ctx->d_mesh_table,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
-                    ctx->d_point_off_single, ctx->d_counts_single};
+                    ctx->d_word_edges, ctx->d_tri_cnt, ctx->d_point_off_single,
+                    ctx->d_counts_single};
     for (void* p : ptrs)
         if (p)
             hipFree(p);
@@ -203,6 +204,10 @@ void fvv_destroy(fvv_ctx* ctx) {
         hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join)
         hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_fine)
+        hipEventDestroy(ctx->ev_fine);
+    if (ctx->ev_edges)
+        hipEventDestroy(ctx->ev_edges);
     if (ctx->side)
         hipStreamDestroy(ctx->side);
     delete ctx;
@@ -264,6 +269,8 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_cams, FVV_MAX_CAMS)
     A(d_finebits, c->bit_cap)
     A(d_item_cnt, c->item_cap)
+    A(d_word_edges, c->bit_cap)
+    A(d_tri_cnt, c->item_cap)
     A(d_point_off_single, 2)
     A(d_counts_single, 4)
 #undef A
@@ -273,6 +280,10 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_fine, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_edges, hipEventDisableTiming);
     if (e == hipSuccess) {
         MeshTable tbl;
         build_mesh_table(&tbl);
@@ -402,9 +413,12 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
     job.height = cs.H;
     hipError_t e = launch_surface_prepare_single(ctx, job, d_occ_fine, stream);
     if (e == hipSuccess)
-        e = launch_surface(ctx, ctx->d_job_single, ctx->d_counts_single + 3, 1, d_occ_fine, cs,
-                           d_sils, n_steps, d_keys, d_xyz, max_points, ctx->d_point_off_single,
-                           d_n_points, nullptr, stream);
+        e = launch_edges(ctx, ctx->d_job_single, ctx->d_counts_single + 3, d_keys, d_xyz,
+                         max_points, ctx->d_point_off_single, d_n_points, true, false, stream);
+    if (e == hipSuccess)
+        e = launch_bisect(ctx, ctx->d_job_single, ctx->d_counts_single + 3,
+                          ctx->d_point_off_single, cs, d_sils, n_steps, d_keys, d_xyz, max_points,
+                          stream);
     return dev(e);
 }
 
@@ -427,8 +441,8 @@ fvv_status fvv_mesh(fvv_ctx* ctx, const fvv_grid* grid, const uint8_t* d_occ,
     for (int a = 0; a < 3; ++a)
         if (grid->dims[a] < 1)
             return FVV_EINVAL;
-    // keys 3*lin+axis and cell indices stay 32-bit; the work items fit the scratch
-    if (grid_samples(*grid) > (int64_t)0x55555555 || mesh_items(*grid) > ctx->item_cap)
+    // keys 3*lin+axis stay 32-bit; the lattice's fine bitmap fits the scratch
+    if (grid_samples(*grid) > (int64_t)0x55555555 || fine_bitmap_words(*grid) > ctx->bit_cap)
         return FVV_EINVAL;
     return dev(launch_mesh(ctx, *grid, d_occ, d_keys, d_n_keys, max_keys, d_tris, max_tris,
                            d_n_tris, stream));
@@ -478,6 +492,9 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         !o->d_keys || !o->d_xyz || !o->d_point_off || !o->d_counts || o->max_rois < 1 ||
         o->max_rois > ctx->lim.max_rois || o->max_fine < 1 || o->max_fine > ctx->lim.max_fine ||
         o->max_points < 1)
+        return FVV_EINVAL;
+    const bool mesh = o->d_tris != nullptr;
+    if (mesh && (!o->d_tri_off || o->max_tris < 1))
         return FVV_EINVAL;
     if (grid_samples(p->coarse) > ctx->lim.max_coarse)
         return FVV_EINVAL;
@@ -545,15 +562,35 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (e == hipSuccess)
         e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, ctx->side);
     if (e == hipSuccess)
-        e = hipEventRecord(ctx->ev_join, ctx->side);
-    if (e == hipSuccess)
         e = launch_carve_frame(ctx, o->d_jobs, cs, d_sils, o->d_occ_fine, ctx->d_finebits, ft,
                                blocks, stream);
     mark(4);
+    // the mesh also runs on the side branch: its count once the fine bitmaps
+    // are there, its triangles once the crossing edges are, beside the exit
+    // points
+    const uint32_t* n_jobs = o->d_counts + 3;
+    if (mesh && e == hipSuccess)
+        e = hipEventRecord(ctx->ev_fine, stream);
+    if (mesh && e == hipSuccess)
+        e = hipStreamWaitEvent(ctx->side, ctx->ev_fine, 0);
+    if (mesh && e == hipSuccess)
+        e = launch_mesh_count(ctx, o->d_jobs, n_jobs, ctx->side);
     if (e == hipSuccess)
-        e = launch_surface(ctx, o->d_jobs, o->d_counts + 3, o->max_rois, o->d_occ_fine, cs, d_sils,
-                           p->n_steps, o->d_keys, o->d_xyz, o->max_points, o->d_point_off,
-                           o->d_counts + 2, events ? events[5] : nullptr, stream);
+        e = launch_edges(ctx, o->d_jobs, n_jobs, o->d_keys, o->d_xyz, o->max_points,
+                         o->d_point_off, o->d_counts + 2, true, mesh, stream);
+    mark(5);
+    if (mesh && e == hipSuccess)
+        e = hipEventRecord(ctx->ev_edges, stream);
+    if (mesh && e == hipSuccess)
+        e = hipStreamWaitEvent(ctx->side, ctx->ev_edges, 0);
+    if (mesh && e == hipSuccess)
+        e = launch_mesh_write(ctx, o->d_jobs, n_jobs, o->d_keys, o->d_counts + 2, o->max_points,
+                              false, o->d_tris, o->max_tris, o->d_tri_off, nullptr, ctx->side);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_join, ctx->side);
+    if (e == hipSuccess)
+        e = launch_bisect(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, p->n_steps,
+                          o->d_keys, o->d_xyz, o->max_points, stream);
     if (e == hipSuccess)
         e = hipStreamWaitEvent(stream, ctx->ev_join, 0);
     mark(6);

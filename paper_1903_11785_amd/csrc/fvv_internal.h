@@ -383,6 +383,43 @@ __device__ __forceinline__ int upper_job(F off, int n, uint64_t x) {
     return lo;
 }
 
+// Crossing edges of one fine-bitmap word as the compaction lays them out: the
+// masks by axis (bit b flags the edge from sample 64 q + b of the word's row)
+// and the key-list position of the word's first edge (clamped to 2^32 - 1).
+// An edge's position is then first + the edges of lower bits + the lower axes
+// at its own bit.
+struct alignas(32) WordEdges {
+    uint64_t ex, ey, ez;
+    uint32_t first;
+    uint32_t pad;
+};
+
+// Item offsets of the jobs in LDS (when they fit) for the item -> job search
+// of the passes over fine-bitmap words.
+constexpr int kJobTable = 1024;
+
+struct ItemJobs {
+    const JobPrefix* pre;
+    const uint32_t* lds;   // item_off of jobs 0..nj, or nullptr
+    int nj;
+    __device__ int job_of(uint32_t item) const {
+        if (lds)
+            return upper_job([&](int m) { return (uint64_t)lds[m]; }, nj, item);
+        return upper_job([&](int m) { return (uint64_t)pre[m].item_off; }, nj, item);
+    }
+    __device__ uint32_t first_item(int j) const { return lds ? lds[j] : pre[j].item_off; }
+};
+
+__device__ __forceinline__ ItemJobs load_item_jobs(const JobPrefix* __restrict__ pre, int nj,
+                                                   uint32_t* table) {
+    const bool fit = nj < kJobTable;
+    if (fit)
+        for (int j = threadIdx.x; j <= nj; j += kBlock)
+            table[j] = pre[j].item_off;
+    __syncthreads();
+    return ItemJobs{pre, fit ? table : nullptr, nj};
+}
+
 struct MeshTable;
 
 }  // namespace fvv
@@ -415,6 +452,8 @@ struct fvv_ctx {
     fvv_camera* d_cams;          // camera table of fvv_frame
     uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)
     uint32_t* d_item_cnt;        // crossing edges per work item
+    fvv::WordEdges* d_word_edges;  // per fine-bitmap word (bit_cap), for the mesh
+    uint32_t* d_tri_cnt;         // triangles per work item
     uint32_t* d_point_off_single;
     uint32_t* d_counts_single;
     int64_t item_cap;
@@ -424,6 +463,7 @@ struct fvv_ctx {
     // side branch of a frame (work off the critical path), default priority
     hipStream_t side;
     hipEvent_t ev_fork, ev_join;
+    hipEvent_t ev_fine, ev_edges;  // a frame's mesh branch: fine bitmaps, keys ready
 };
 
 namespace fvv {
@@ -486,10 +526,23 @@ struct MeshTable {
     uint8_t edge[256][15];
 };
 void build_mesh_table(MeshTable* t);
-int64_t mesh_items(const fvv_grid& g);
+// Triangles of one lattice (fvv_mesh): its fine bitmap and word edges, then
+// the mesh passes, checking every vertex against keys.
 hipError_t launch_mesh(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, const uint32_t* keys,
                        const uint32_t* n_keys, uint32_t max_keys, uint32_t* tris,
                        uint32_t max_tris, uint32_t* n_tris, hipStream_t s);
+// The mesh passes over the jobs' fine bitmaps (ctx->d_finebits): triangles
+// per work item (needs the bitmaps), then the triangles (needs the word edges
+// of the edge compaction).  tri_off: NULL, or per job its first triangle and
+// at [n_jobs] the total; n_tris: NULL, or the total.  Vertices are positions
+// in the key list; those at or past min(*n_keys, max_keys), or (verify) whose
+// key differs, are 0xffffffff and set the capacity flag.
+hipError_t launch_mesh_count(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                             hipStream_t s);
+hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                             const uint32_t* keys, const uint32_t* n_keys, uint32_t max_keys,
+                             bool verify, uint32_t* tris, uint32_t max_tris, uint32_t* tri_off,
+                             uint32_t* n_tris, hipStream_t s);
 
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);
@@ -500,11 +553,17 @@ hipError_t launch_soft_backward(fvv_ctx* ctx, const SoftCamSet& cams, const Soft
                                 const fvv_grid& g, const float* logits, const float* target,
                                 const float* grad_occ, const double* scale, float* grad_logits,
                                 double* grad_pose, hipStream_t s);
-hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
-                          uint32_t max_jobs, const uint8_t* occ_fine, const CamSet& cams,
-                          const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,
-                          uint32_t max_points, uint32_t* point_off, uint32_t* n_points,
-                          hipEvent_t edges_done, hipStream_t s);
+// Crossing edges of the jobs' fine bitmaps: keys (and xyz's side marks),
+// point_off and n_points when `keys_out`; the word edges of every word when
+// `word_edges`.
+hipError_t launch_edges(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                        uint32_t* keys, float* xyz, uint32_t max_points, uint32_t* point_off,
+                        uint32_t* n_points, bool keys_out, bool word_edges, hipStream_t s);
+// Exit points of the listed edges.
+hipError_t launch_bisect(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                         const uint32_t* point_off, const CamSet& cams, const uint32_t* sils,
+                         int n_steps, const uint32_t* keys, float* xyz, uint32_t max_points,
+                         hipStream_t s);
 // The fine carve of a frame (jobs prepared by the labelling): tiles with
 // tz == 4 classify cameras per box first (rounding pads of `cams`), others
 // take the batched carve.

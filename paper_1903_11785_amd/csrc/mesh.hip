@@ -95,171 +95,284 @@ void build_mesh_table(MeshTable* t) {
 }
 
 // ------------------------------------------------------------------ kernels
-// A work item is kMeshItem consecutive cells (linear order over the
-// (nx-1) x (ny-1) x (nz-1) cells, x fastest), kMeshCellsPerThread per thread.
-// The count pass sums each item's triangles; the write pass adds the counts of
-// the earlier items, scans its threads and writes each thread's cells in order.
-// Cell indices are 32-bit (fvv_mesh bounds the lattice).
-constexpr int kMeshCellsPerThread = 16;
-constexpr int kMeshItem = kBlock * kMeshCellsPerThread;
+// The passes run over the fine bitmaps of the jobs with the work items of the
+// crossing-edge compaction (kEdgeWords words of one lattice, one word per
+// thread).  A word's thread owns the cells whose first corner is one of its
+// samples: bit b is the cell (64 q + b, y, z).  Its corners lie in the rows
+// (y + dy, z + dz), m = dy + 2 dz, at bits b and b + 1 (bit 0 of the next word
+// for b = 63).  Cells in linear order are words in order, then bits in order,
+// so triangles come out by cell in linear order.
 
-struct CellGeom {
-    uint32_t cx, cy, cells;
-    int64_t sy, sz;
+// The four rows of a word's cells: samples x (r) and x + 1 (s) of each, and
+// the cells that have both occupied and empty corners.
+struct CellRows {
+    uint64_t r[4], s[4];
+    uint64_t mixed;
+    int64_t row;       // row index y + ny z of the word
+    int32_t q;         // word within its row
+    bool last;         // the row's last word
 };
 
-// Corner pattern of cell c and its first sample's linear index.
-__device__ __forceinline__ int cell_case(const uint8_t* __restrict__ occ, uint32_t c,
-                                         const CellGeom& cg, int64_t& base) {
-    const uint32_t r = c / cg.cx, i = c - r * cg.cx;
-    const uint32_t k = r / cg.cy, j = r - k * cg.cy;
-    base = (int64_t)i + cg.sy * j + cg.sz * k;
-    const uint8_t* o = occ + base;
-    int cs = (o[0] != 0) | (o[1] != 0) << 1 | (o[cg.sy] != 0) << 2 | (o[cg.sy + 1] != 0) << 3;
-    o += cg.sz;
-    cs |= (o[0] != 0) << 4 | (o[1] != 0) << 5 | (o[cg.sy] != 0) << 6 | (o[cg.sy + 1] != 0) << 7;
+__device__ __forceinline__ CellRows cell_rows(const uint64_t* __restrict__ bits, int64_t w,
+                                              const int32_t* d, int32_t wr) {
+    CellRows c;
+    c.row = w / wr;
+    c.q = (int32_t)(w - c.row * wr);
+    c.last = c.q == wr - 1;
+    c.mixed = 0;
+    const int32_t y = (int32_t)(c.row % d[1]);
+    const int32_t z = (int32_t)(c.row / d[1]);
+    const bool cells = y + 1 < d[1] && z + 1 < d[2];
+    const int64_t slab = (int64_t)wr * d[1];
+    // rows past the lattice are never read: their loads repeat this word
+    const int64_t wm[4] = {w, cells ? w + wr : w, cells ? w + slab : w,
+                           cells ? w + wr + slab : w};
+    uint64_t any = 0, all = ~0ull;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        c.r[m] = bits[wm[m]];
+        const uint64_t nx = c.last ? 0ull : bits[wm[m] + 1];
+        c.s[m] = (c.r[m] >> 1) | (nx << 63);
+        any |= c.r[m] | c.s[m];
+        all &= c.r[m] & c.s[m];
+    }
+    // cell x needs sample x + 1 in the lattice: in the last word bits
+    // [0, nx - 64 q - 1) are cells
+    const int32_t in_last = d[0] - 64 * c.q - 1;
+    const uint64_t cellmask =
+        c.last ? (in_last >= 64 ? ~0ull : ((1ull << in_last) - 1)) : ~0ull;
+    c.mixed = cells ? (any & ~all) & cellmask : 0ull;
+    return c;
+}
+
+// Corner pattern of the cell at bit b (corner dx + 2 dy + 4 dz = dx + 2 m).
+__device__ __forceinline__ int cell_pattern(const CellRows& c, int b) {
+    int cs = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        cs |= (int)((c.r[m] >> b) & 1u) << (2 * m) | (int)((c.s[m] >> b) & 1u) << (2 * m + 1);
     return cs;
 }
 
-__device__ __forceinline__ CellGeom cell_geom(const fvv_grid& g) {
-    CellGeom cg;
-    cg.cx = (uint32_t)(g.dims[0] - 1);
-    cg.cy = (uint32_t)(g.dims[1] - 1);
-    cg.cells = cg.cx * cg.cy * (uint32_t)(g.dims[2] - 1);
-    cg.sy = g.dims[0];
-    cg.sz = (int64_t)g.dims[0] * g.dims[1];
-    return cg;
+__device__ __forceinline__ void load_table(const MeshTable* __restrict__ tbl, MeshTable* s_tbl) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(tbl);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(s_tbl);
+    for (int i = threadIdx.x; i < (int)(sizeof(MeshTable) / 4); i += kBlock)
+        dst[i] = src[i];
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_grid g,
-                                                            const uint8_t* __restrict__ occ,
+__device__ __forceinline__ uint32_t word_triangles(const CellRows& c, const MeshTable& t) {
+    uint32_t n = 0;
+    for (uint64_t b = c.mixed; b; b &= b - 1)
+        n += t.count[cell_pattern(c, __ffsll((unsigned long long)b) - 1)];
+    return n;
+}
+
+// Per work item: its number of triangles.
+__global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_job* __restrict__ jobs,
+                                                            const JobPrefix* __restrict__ pre,
+                                                            const uint32_t* __restrict__ n_jobs_p,
+                                                            const uint64_t* __restrict__ bits,
                                                             const MeshTable* __restrict__ tbl,
-                                                            uint32_t* __restrict__ item_cnt) {
+                                                            uint32_t* __restrict__ tri_cnt) {
+    __shared__ uint32_t table[kJobTable];
     __shared__ uint32_t scratch[kBlock / kWave];
-    const CellGeom cg = cell_geom(g);
-    const uint32_t items = (cg.cells + kMeshItem - 1) / kMeshItem;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+    __shared__ MeshTable s_tbl;
+    load_table(tbl, &s_tbl);
+    const int nj = (int)*n_jobs_p;
+    const ItemJobs ij = load_item_jobs(pre, nj, table);
+    const uint32_t n_items = ij.first_item(nj);
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int jb = ij.job_of(item);
+        const fvv_grid g = jobs[jb].grid;
+        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
         uint32_t n = 0;
-        const uint32_t c0 = it * kMeshItem + threadIdx.x * kMeshCellsPerThread;
-        for (int q = 0; q < kMeshCellsPerThread; ++q)
-            if (c0 + q < cg.cells) {
-                int64_t base;
-                n += tbl->count[cell_case(occ, c0 + q, cg, base)];
-            }
-        uint32_t tot;
-        block_exclusive_sum<kBlock>(n, scratch, &tot);
+        if (w < fine_bitmap_words(g))
+            n = word_triangles(cell_rows(bits + pre[jb].bit_off, w, g.dims, (g.dims[0] + 63) / 64),
+                               s_tbl);
+        uint32_t total;
+        block_exclusive_sum<kBlock>(n, scratch, &total);
         if (threadIdx.x == 0)
-            item_cnt[it] = tot;
-        __syncthreads();
+            tri_cnt[item] = total;
     }
 }
 
-// Index of `key` in keys[0, n) (ascending), or -1.
-__device__ __forceinline__ int64_t key_index(const uint32_t* __restrict__ keys, int64_t n,
-                                             uint32_t key) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return (lo < n && keys[lo] == key) ? lo : -1;
-}
-
+// Per work item: first triangle = the triangles of the earlier items, then a
+// scan over the threads; each thread writes its cells' triangles.  A vertex
+// on cell edge 4 a + u + 2 v has its edge's first sample at (dx, dy, dz) with
+// d_a = 0 and (u, v) on the other two axes; the owning word's WordEdges give
+// its position.  The 12 positions of a cell go through LDS (one column per
+// thread) so that the table's runtime edge numbers index them.
+template <bool kVerify>
 __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
-    const fvv_grid g, const uint8_t* __restrict__ occ, const MeshTable* __restrict__ tbl,
-    const uint32_t* __restrict__ item_cnt, const uint32_t* __restrict__ keys,
+    const fvv_job* __restrict__ jobs, const JobPrefix* __restrict__ pre,
+    const uint32_t* __restrict__ n_jobs_p, const uint64_t* __restrict__ bits,
+    const MeshTable* __restrict__ tbl, const uint32_t* __restrict__ tri_cnt,
+    const WordEdges* __restrict__ wedges, const uint32_t* __restrict__ keys,
     const uint32_t* __restrict__ n_keys_p, uint32_t max_keys, uint32_t* __restrict__ tris,
-    uint32_t max_tris, uint32_t* __restrict__ n_tris, uint32_t* __restrict__ status) {
+    uint32_t max_tris, uint32_t* __restrict__ tri_off, uint32_t* __restrict__ n_tris,
+    uint32_t* __restrict__ status) {
+    __shared__ uint32_t table[kJobTable];
+    __shared__ uint64_t scratch64[kBlock / kWave];
     __shared__ uint32_t scratch[kBlock / kWave];
-    __shared__ uint32_t s_before;
-    const CellGeom cg = cell_geom(g);
-    const uint32_t items = (cg.cells + kMeshItem - 1) / kMeshItem;
+    __shared__ MeshTable s_tbl;
+    __shared__ uint32_t s_pos[12][kBlock];
+    load_table(tbl, &s_tbl);
+    const int nj = (int)*n_jobs_p;
+    const ItemJobs ij = load_item_jobs(pre, nj, table);
+    const uint32_t n_items = ij.first_item(nj);
     const uint32_t nk_all = *n_keys_p;
-    const int64_t nk = nk_all < max_keys ? nk_all : max_keys;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        // triangles of all earlier work items
-        uint32_t part = 0;
-        for (uint32_t p = threadIdx.x; p < it; p += kBlock)
-            part += item_cnt[p];
-        uint32_t before;
-        block_exclusive_sum<kBlock>(part, scratch, &before);
-        if (threadIdx.x == 0)
-            s_before = before;
-        __syncthreads();
-        const uint32_t item_base = s_before;
-        // this thread's cells follow the lower threads' triangles
-        const uint32_t c0 = it * kMeshItem + threadIdx.x * kMeshCellsPerThread;
-        uint32_t n = 0;
-        for (int q = 0; q < kMeshCellsPerThread; ++q)
-            if (c0 + q < cg.cells) {
-                int64_t base;
-                n += tbl->count[cell_case(occ, c0 + q, cg, base)];
-            }
-        uint32_t tot;
-        uint32_t pos = item_base + block_exclusive_sum<kBlock>(n, scratch, &tot);
+    const uint32_t nk = nk_all < max_keys ? nk_all : max_keys;
+    const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
+    if (n_items == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (tri_off)
+            for (int j = 0; j <= nj; ++j)
+                tri_off[j] = 0;
+        if (n_tris)
+            *n_tris = 0;
+    }
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        uint64_t before = 0;
+        for (uint32_t i = threadIdx.x; i < item; i += kBlock)
+            before += tri_cnt[i];
+        uint64_t first;
+        block_exclusive_sum64<kBlock>(before, scratch64, &first);
+        const int jb = ij.job_of(item);
+        const fvv_grid g = jobs[jb].grid;
+        const int32_t wr = (g.dims[0] + 63) / 64;
+        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
+        CellRows c;
+        c.mixed = 0;
+        if (w < fine_bitmap_words(g))
+            c = cell_rows(bits + pre[jb].bit_off, w, g.dims, wr);
+        uint32_t total;
+        const uint32_t ex = block_exclusive_sum<kBlock>(word_triangles(c, s_tbl), scratch, &total);
+        uint64_t pos = first + ex;
         bool missing = false;
-        for (int q = 0; q < kMeshCellsPerThread && n; ++q) {
-            if (c0 + q >= cg.cells)
-                break;
-            int64_t base;
-            const int cs = cell_case(occ, c0 + q, cg, base);
-            const int nt = tbl->count[cs];
-            for (int r = 0; r < nt; ++r, ++pos) {
-                if (pos >= max_tris)
-                    continue;
+        if (c.mixed) {
+            // the owning words: this word (q) and the next (q + 1) of each row
+            const WordEdges* we = wedges + pre[jb].bit_off;
+            const int64_t slab = (int64_t)wr * g.dims[1];
+            WordEdges own[4], nxt[4];
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const int e = tbl->edge[cs][3 * r + v];
-                    const int a = e >> 2, u = e & 1, w = (e >> 1) & 1;
-                    // the edge's first sample: 0 on axis a, (u, w) on the other two
-                    const int dx = a == 0 ? 0 : u;
-                    const int dy = a == 1 ? 0 : (a == 0 ? u : w);
-                    const int dz = a == 2 ? 0 : w;
-                    const int64_t lin = base + dx + cg.sy * dy + cg.sz * dz;
-                    const int64_t ix = key_index(keys, nk, (uint32_t)(3 * lin + a));
-                    missing |= ix < 0;
-                    tris[3 * (int64_t)pos + v] = ix < 0 ? 0xffffffffu : (uint32_t)ix;
+            for (int m = 0; m < 4; ++m) {
+                const int64_t wm = w + (m & 1) * (int64_t)wr + (m >> 1) * slab;
+                own[m] = we[wm];
+                if (!c.last && (c.mixed >> 63))
+                    nxt[m] = we[wm + 1];
+                else
+                    nxt[m] = own[m];
+            }
+            const int64_t nx = g.dims[0], sz = (int64_t)g.dims[0] * g.dims[1];
+            for (uint64_t bm = c.mixed; bm; bm &= bm - 1) {
+                const int b = __ffsll((unsigned long long)bm) - 1;
+                // position of the first edge at each owner (m, dx) and the
+                // x- and y-edge bits there
+                uint32_t R[4][2], xb[4][2], yb[4][2];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const bool over = dx == 1 && b == 63;
+                        const WordEdges& o = over ? nxt[m] : own[m];
+                        const int p = over ? 0 : b + dx;
+                        const uint64_t below = (1ull << p) - 1ull;
+                        R[m][dx] = o.first + (uint32_t)(__popcll(o.ex & below) +
+                                                        __popcll(o.ey & below) +
+                                                        __popcll(o.ez & below));
+                        xb[m][dx] = (uint32_t)((o.ex >> p) & 1u);
+                        yb[m][dx] = (uint32_t)((o.ey >> p) & 1u);
+                    }
+                // cell edge 4 a + u + 2 v: x-edges own (0, u, v), y-edges (u, 0, v),
+                // z-edges (u, v, 0)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        s_pos[0 + u + 2 * v][threadIdx.x] = R[u + 2 * v][0];
+                        s_pos[4 + u + 2 * v][threadIdx.x] = R[2 * v][u] + xb[2 * v][u];
+                        s_pos[8 + u + 2 * v][threadIdx.x] = R[v][u] + xb[v][u] + yb[v][u];
+                    }
+                const int cs = cell_pattern(c, b);
+                const int nt = s_tbl.count[cs];
+                const int64_t lin0 = c.row * nx + 64 * (int64_t)c.q + b;   // corner 0
+                for (int r = 0; r < nt; ++r, ++pos) {
+                    if (pos >= max_tris)
+                        continue;
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        const int e = s_tbl.edge[cs][3 * r + v];
+                        uint32_t ix = s_pos[e][threadIdx.x];
+                        bool bad = ix >= nk;
+                        if (kVerify && !bad) {
+                            const int a = e >> 2, eu = e & 1, ev = (e >> 1) & 1;
+                            const int dx = a == 0 ? 0 : eu;
+                            const int dy = a == 1 ? 0 : (a == 0 ? eu : ev);
+                            const int dz = a == 2 ? 0 : ev;
+                            const int64_t lin = lin0 + dx + nx * dy + sz * dz;
+                            bad = keys[ix] != (uint32_t)(3 * lin + a);
+                        }
+                        missing |= bad;
+                        tris[3 * pos + v] = bad ? 0xffffffffu : ix;
+                    }
                 }
             }
         }
         if (missing)
             atomicOr(status, kFlagCapacity);
-        if (it == items - 1 && threadIdx.x == kBlock - 1) {
-            const uint32_t all = item_base + tot;
-            *n_tris = all;
-            if (all > max_tris)
-                atomicOr(status, kFlagCapacity);
+        if (threadIdx.x == 0) {
+            if (tri_off && item == ij.first_item(jb))
+                tri_off[jb] = clamp(first);
+            if (item + 1 == n_items) {
+                const uint64_t all = first + total;
+                if (tri_off)
+                    tri_off[nj] = clamp(all);
+                if (n_tris)
+                    *n_tris = clamp(all);
+                if (all > max_tris)
+                    atomicOr(status, kFlagCapacity);
+            }
         }
-        __syncthreads();
     }
 }
 
-__global__ void mesh_zero_kernel(uint32_t* __restrict__ n_tris) { *n_tris = 0u; }
+hipError_t launch_mesh_count(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(mesh_count_kernel, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs,
+                       ctx->d_prefix, n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table,
+                       ctx->d_tri_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                             const uint32_t* keys, const uint32_t* n_keys, uint32_t max_keys,
+                             bool verify, uint32_t* tris, uint32_t max_tris, uint32_t* tri_off,
+                             uint32_t* n_tris, hipStream_t s) {
+    auto kernel = verify ? mesh_write_kernel<true> : mesh_write_kernel<false>;
+    hipLaunchKernelGGL(kernel, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
+                       n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table, ctx->d_tri_cnt,
+                       ctx->d_word_edges, keys, n_keys, max_keys, tris, max_tris, tri_off, n_tris,
+                       ctx->d_status);
+    return hipGetLastError();
+}
 
 hipError_t launch_mesh(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, const uint32_t* keys,
                        const uint32_t* n_keys, uint32_t max_keys, uint32_t* tris,
                        uint32_t max_tris, uint32_t* n_tris, hipStream_t s) {
-    const int64_t cells = (int64_t)(g.dims[0] - 1) * (g.dims[1] - 1) * (g.dims[2] - 1);
-    if (cells <= 0) {
-        hipLaunchKernelGGL(mesh_zero_kernel, dim3(1), dim3(1), 0, s, n_tris);
-        return hipGetLastError();
-    }
-    const int64_t items = (cells + kMeshItem - 1) / kMeshItem;
-    const unsigned blocks = (unsigned)(items < (int64_t)ctx->n_cus * 8 ? items : ctx->n_cus * 8);
-    hipLaunchKernelGGL(mesh_count_kernel, dim3(blocks), dim3(kBlock), 0, s, g, occ,
-                       ctx->d_mesh_table, ctx->d_item_cnt);
-    hipLaunchKernelGGL(mesh_write_kernel, dim3(blocks), dim3(kBlock), 0, s, g, occ,
-                       ctx->d_mesh_table, ctx->d_item_cnt, keys, n_keys, max_keys, tris, max_tris,
-                       n_tris, ctx->d_status);
-    return hipGetLastError();
-}
-
-int64_t mesh_items(const fvv_grid& g) {
-    const int64_t cells = (int64_t)(g.dims[0] - 1) * (g.dims[1] - 1) * (g.dims[2] - 1);
-    return cells <= 0 ? 0 : (cells + kMeshItem - 1) / kMeshItem;
+    fvv_job job;
+    memset(&job, 0, sizeof(job));
+    job.grid = g;
+    hipError_t e = launch_surface_prepare_single(ctx, job, occ, s);
+    if (e == hipSuccess)
+        e = launch_edges(ctx, ctx->d_job_single, ctx->d_counts_single + 3, nullptr, nullptr, 0,
+                         nullptr, nullptr, false, true, s);
+    if (e == hipSuccess)
+        e = launch_mesh_count(ctx, ctx->d_job_single, ctx->d_counts_single + 3, s);
+    if (e == hipSuccess)
+        e = launch_mesh_write(ctx, ctx->d_job_single, ctx->d_counts_single + 3, keys, n_keys,
+                              max_keys, true, tris, max_tris, nullptr, n_tris, s);
+    return e;
 }
 
 }  // namespace fvv

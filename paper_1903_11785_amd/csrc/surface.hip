@@ -57,31 +57,6 @@ hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, const
 }
 
 // ------------------------------------------------------------------ crossing edges
-constexpr int kJobTable = 1024;   // jobs whose item offsets a workgroup keeps in LDS
-
-// Item offsets of the jobs in LDS (when they fit) for the item -> job search.
-struct ItemJobs {
-    const JobPrefix* pre;
-    const uint32_t* lds;   // item_off of jobs 0..nj, or nullptr
-    int nj;
-    __device__ int job_of(uint32_t item) const {
-        if (lds)
-            return upper_job([&](int m) { return (uint64_t)lds[m]; }, nj, item);
-        return upper_job([&](int m) { return (uint64_t)pre[m].item_off; }, nj, item);
-    }
-    __device__ uint32_t first_item(int j) const { return lds ? lds[j] : pre[j].item_off; }
-};
-
-__device__ __forceinline__ ItemJobs load_item_jobs(const JobPrefix* __restrict__ pre, int nj,
-                                                   uint32_t* table) {
-    const bool fit = nj < kJobTable;
-    if (fit)
-        for (int j = threadIdx.x; j <= nj; j += kBlock)
-            table[j] = pre[j].item_off;
-    __syncthreads();
-    return ItemJobs{pre, fit ? table : nullptr, nj};
-}
-
 // Crossing-edge masks of word w of a fine bitmap of lattice dims d, wr words
 // per row: bit b of ex / ey / ez flags the edge from sample x = 64*q + b of
 // the word's row along x / y / z (both ends in the lattice, occupancies
@@ -149,7 +124,10 @@ __global__ __launch_bounds__(kBlock) void edge_count_kernel(const fvv_job* __res
 // every thread writes its word's keys.  The first item of a job gives the
 // job's point offset, the last item the total (ECAPACITY past max_points).
 // xyz[3e] carries, until the bisection overwrites it, +1 if the edge's first
-// sample (lin of its key) is occupied and -1 otherwise.
+// sample (lin of its key) is occupied and -1 otherwise.  kKeys: write the keys,
+// xyz marks, offsets and total; kWords: write every word's WordEdges (at the
+// job's bit_off, like the bitmap).
+template <bool kKeys, bool kWords>
 __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __restrict__ jobs,
                                                             const JobPrefix* __restrict__ pre,
                                                             const uint32_t* __restrict__ n_jobs_p,
@@ -160,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
                                                             uint32_t max_points,
                                                             uint32_t* __restrict__ point_off,
                                                             uint32_t* __restrict__ n_points,
+                                                            WordEdges* __restrict__ wedges,
                                                             uint32_t* __restrict__ status) {
     __shared__ uint32_t table[kJobTable];
     __shared__ uint32_t scratch[kBlock / kWave];
@@ -167,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
     const int nj = (int)*n_jobs_p;
     const ItemJobs ij = load_item_jobs(pre, nj, table);
     const uint32_t n_items = ij.first_item(nj);
-    if (n_items == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (kKeys && n_items == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
         for (int j = 0; j <= nj; ++j)
             point_off[j] = 0;
         *n_points = 0;
@@ -190,7 +169,16 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
         uint32_t total;
         const uint32_t ex = block_exclusive_sum<kBlock>(edge_count(m), scratch, &total);
         uint64_t pos = first + ex;
-        if (w < n_words) {
+        if (kWords && w < n_words) {
+            WordEdges we;
+            we.ex = m.ex;
+            we.ey = m.ey;
+            we.ez = m.ez;
+            we.first = (uint32_t)(pos < 0xffffffffull ? pos : 0xffffffffull);
+            we.pad = 0;
+            wedges[pre[jb].bit_off + w] = we;
+        }
+        if (kKeys && w < n_words) {
             const int64_t row = w / wr;
             const uint32_t lin0 =
                 (uint32_t)(row * g.dims[0] + (w - row * wr) * kWave);   // sample of bit 0
@@ -211,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
                 }
             }
         }
-        if (threadIdx.x == 0) {
+        if (kKeys && threadIdx.x == 0) {
             const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
             if (item == ij.first_item(jb))
                 point_off[jb] = clamp(first);
@@ -483,21 +471,27 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
     }
 }
 
-hipError_t launch_surface(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
-                          uint32_t max_jobs, const uint8_t* occ_fine, const CamSet& cams,
-                          const uint32_t* sils, int n_steps, uint32_t* keys, float* xyz,
-                          uint32_t max_points, uint32_t* point_off, uint32_t* n_points,
-                          hipEvent_t edges_done, hipStream_t s) {
-    (void)max_jobs;
-    (void)occ_fine;
+hipError_t launch_edges(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                        uint32_t* keys, float* xyz, uint32_t max_points, uint32_t* point_off,
+                        uint32_t* n_points, bool keys_out, bool word_edges, hipStream_t s) {
+    if (!keys_out && !word_edges)
+        return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)(ctx->n_cus * 8);
     hipLaunchKernelGGL(edge_count_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
                        n_jobs_dev, ctx->d_finebits, ctx->d_item_cnt);
-    hipLaunchKernelGGL(edge_write_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
-                       n_jobs_dev, ctx->d_finebits, ctx->d_item_cnt, keys, xyz, max_points,
-                       point_off, n_points, ctx->d_status);
-    if (edges_done)
-        (void)hipEventRecord(edges_done, s);
+    auto kernel = keys_out ? (word_edges ? edge_write_kernel<true, true>
+                                         : edge_write_kernel<true, false>)
+                           : edge_write_kernel<false, true>;
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix, n_jobs_dev,
+                       ctx->d_finebits, ctx->d_item_cnt, keys, xyz, max_points, point_off,
+                       n_points, ctx->d_word_edges, ctx->d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_bisect(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                         const uint32_t* point_off, const CamSet& cams, const uint32_t* sils,
+                         int n_steps, const uint32_t* keys, float* xyz, uint32_t max_points,
+                         hipStream_t s) {
     if (cams.n <= 16)
         hipLaunchKernelGGL(bisect_kernel<16>, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs,
                            n_jobs_dev, point_off, cams, sils, n_steps, keys, xyz, max_points);

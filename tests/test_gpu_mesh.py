@@ -140,6 +140,83 @@ def test_volleyball_frame_rois(fvv, ctx, scene_cache):
     assert ctx.check() == fvv.FVV_OK
 
 
+def frame_with_mesh(fvv, ctx, sc, graph=False, max_tris=1 << 22, max_points=1 << 22):
+    import torch
+    coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
+    params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
+                              sc.n_steps)
+    bufs = fvv.FrameBuffers(coarse, 256, 1 << 26, max_points, max_tris=max_tris)
+    N, H, W = sc.masks.shape
+    sils = torch.zeros((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+    masks = dev(sc.masks)
+    if graph:
+        g = ctx.frame_graph(params, sils, bufs, masks=masks)
+        for _ in range(3):
+            bufs.tris.fill_(-7)
+            bufs.tri_off.fill_(-7)
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            yield bufs
+        g.close()
+    else:
+        ctx.frame(params, sils, bufs, masks=masks)
+        torch.cuda.synchronize()
+        yield bufs
+
+
+def check_frame_mesh(res, bufs):
+    K = len(res.rois)
+    counts = bufs.counts.cpu().numpy()
+    assert int(counts[3]) == K
+    poff = bufs.point_off.cpu().numpy().view(np.uint32)
+    toff = bufs.tri_off.cpu().numpy().view(np.uint32)
+    tris = bufs.tris.cpu().numpy().view(np.uint32)
+    assert toff[0] == 0
+    for t in range(K):
+        ref = oracle.mesh(res.occ_fine[t], res.keys[t])
+        got = tris[toff[t]:toff[t + 1]]
+        assert len(got) == len(ref), t
+        np.testing.assert_array_equal(got - poff[t], ref)
+    assert int(toff[K]) == sum(len(oracle.mesh(o, k)) for o, k in zip(res.occ_fine, res.keys))
+
+
+@pytest.mark.parametrize("cfg,frame,graph", [(1, 0, False), (1, 1, True), (2, 0, False),
+                                             (2, 1, True), (3, 0, False)])
+def test_frame_mesh_matches_oracle(fvv, ctx, scene_cache, cfg, frame, graph):
+    """The frame's mesh branch (count beside the crossing edges, triangles
+    beside the exit points, on the side stream): per ROI, the triangles less
+    the ROI's point offset equal the oracle's on its fine occupancy and keys;
+    as a graph, on every replay."""
+    sc = scene_cache(cfg, frame)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    for bufs in frame_with_mesh(fvv, ctx, sc, graph=graph):
+        assert ctx.check() == fvv.FVV_OK
+        check_frame_mesh(res, bufs)
+
+
+def test_frame_mesh_capacity(fvv, ctx, scene_cache):
+    sc = scene_cache(1, 0)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    total = sum(len(oracle.mesh(o, k)) for o, k in zip(res.occ_fine, res.keys))
+    for bufs in frame_with_mesh(fvv, ctx, sc, max_tris=total // 2):
+        K = len(res.rois)
+        assert int(bufs.tri_off.cpu().numpy().view(np.uint32)[K]) == total
+        assert ctx.check() == fvv.FVV_ECAPACITY
+    # too few points: vertices past the stored keys are 0xffffffff
+    for bufs in frame_with_mesh(fvv, ctx, sc, max_points=1000):
+        tris = bufs.tris.cpu().numpy().view(np.uint32)
+        K = len(res.rois)
+        n = int(bufs.tri_off.cpu().numpy().view(np.uint32)[K])
+        assert n == total
+        used = tris[:n]
+        assert (used[used != 0xffffffff] < 1000).all() and (used == 0xffffffff).any()
+        assert ctx.check() == fvv.FVV_ECAPACITY
+    assert ctx.check() == fvv.FVV_OK
+
+
 @pytest.mark.parametrize("shape,fill", [((1, 5, 6), 0.5), ((6, 1, 5), 0.5), ((4, 5, 6), 0.0),
                                         ((4, 5, 6), 1.0)])
 def test_degenerate_lattices(fvv, ctx, shape, fill):
