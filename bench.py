@@ -54,6 +54,7 @@ def parse():
                          "and stream each); latency is measured one frame at a time")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-carve leg")
     ap.add_argument("--no-soft", action="store_true", help="skip the soft-hull leg")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the marching-cubes leg")
     ap.add_argument("--batched-reps", type=int, default=10, help="timed batched-carve launches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a known-size "
@@ -275,6 +276,96 @@ def soft_leg(args, fvv, torch):
                     "pose set-up and the copy of the pose gradients to the host"}
 
 
+def mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_fine, max_points,
+             lat_no_mesh_ms):
+    """Marching-cubes triangles of the volleyball frames: (1) the frame graph
+    with its mesh branch (triangle count beside the crossing edges, triangles
+    beside the exit points, on the side stream), one frame at a time, against
+    the same frames without it; (2) fvv_mesh on each ROI of one frame (fine
+    occupancy and keys as the frame left them), timed with HIP events on its
+    stream: bitmap, word edges, count and write passes."""
+    max_tris = 1 << 23
+    bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points, max_tris=max_tris)
+    graphs = [ctx.frame_graph(params, sils, bufs, masks=m) for m in masks]
+    n_tris = []
+    for g in graphs:
+        g.launch()
+        torch.cuda.synchronize()
+        K = int(bufs.counts.cpu()[0])
+        n_tris.append(int(bufs.tri_off[K].cpu()))
+    if ctx.check() != fvv.FVV_OK:
+        raise RuntimeError("mesh exceeded a capacity")
+    steps = max(1, min(args.steps, 100))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        graphs[k % len(graphs)].launch()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    lat = [a.elapsed_time(b) for a, b in ev]
+    for g in graphs:
+        g.close()
+
+    # fvv_mesh, ROI by ROI, on frame 0's outputs
+    graphs0 = ctx.frame_graph(params, sils, bufs, masks=masks[0])
+    graphs0.launch()
+    torch.cuda.synchronize()
+    graphs0.close()
+    K = int(bufs.counts.cpu()[0])
+    jobs = bufs.jobs_host(K)
+    poff = bufs.point_off.cpu().numpy().view(np.uint32)
+    tris = torch.empty((max_tris, 3), dtype=torch.int32, device="cuda")
+    n_t = torch.zeros(1, dtype=torch.int32, device="cuda")
+    calls = []
+    for t in range(K):
+        g = jobs[t]
+        dims = tuple(int(v) for v in g["dims"])
+        grid = fvv.Grid(origin=tuple(g["origin"]), h=g["h"], lo=tuple(int(v) for v in g["lo"]),
+                        dims=dims)
+        o = int(g["out_offset"])
+        occ = bufs.occ_fine[o:o + int(np.prod(dims))]
+        keys = bufs.keys[int(poff[t]):int(poff[t + 1])]
+        nk = torch.tensor([int(poff[t + 1] - poff[t])], dtype=torch.int32, device="cuda")
+        calls.append((grid, occ, keys, nk))
+    per_call = []
+    bytes_total = 0
+    for rep in range(6):
+        ms = []
+        for grid, occ, keys, nk in calls:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.mesh(grid, occ, keys, nk, tris=tris, n_tris=n_t)
+            e1.record()
+            ms.append((e0, e1))
+            if rep == 0:
+                bytes_total += grid.size + 4 * keys.numel() + 12 * int(n_t.cpu()[0])
+        torch.cuda.synchronize()
+        if rep > 0:
+            per_call.append(sum(a.elapsed_time(b) for a, b in ms))
+    if ctx.check() != fvv.FVV_OK:
+        raise RuntimeError("fvv_mesh reported a missing vertex")
+    frame_ms = pct(per_call, 50)
+    achieved = bytes_total / (frame_ms * 1e-3) / 1e9
+    return {
+        "workload": "marching-cubes triangles of the volleyball frames' ROIs",
+        "triangles_per_frame_mean": float(np.mean(n_tris)),
+        "frame_latency_ms_with_mesh": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "frame_latency_ms_without_mesh_p50": lat_no_mesh_ms,
+        "mesh_branch_added_ms_p50": pct(lat, 50) - lat_no_mesh_ms,
+        "fvv_mesh_per_roi": {"rois": K, "ms_per_frame_p50": frame_ms,
+                             "ms_per_roi": frame_ms / max(K, 1),
+                             "roofline": {"bound": "hbm", "achieved": achieved,
+                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": achieved / HBM_PEAK_GBS,
+                                          "bytes_per_frame": bytes_total,
+                                          "traffic": None,
+                                          "note": "compulsory bytes: 1 B occupancy per sample read, "
+                                                  "4 B per key read, 12 B per triangle written; "
+                                                  "six launches per ROI"}},
+    }
+
+
 def soft_cpu_baseline():
     """The soft-hull oracle (float64 PyTorch CPU: forward + autograd) on the
     same scene, timed once."""
@@ -425,6 +516,9 @@ def main():
         "stages_ms": {s: float(np.mean(v)) for s, v in stage_ms.items()},
     }
 
+    if not args.no_mesh:
+        result["mesh"] = mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois,
+                                  max_fine, max_points, pct(lat_ms, 50))
     if not args.no_batched:
         result["batched"] = batched_leg(args, fvv, torch)
     if not args.no_soft:

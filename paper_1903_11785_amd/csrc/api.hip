@@ -574,7 +574,7 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (mesh && e == hipSuccess)
         e = hipStreamWaitEvent(ctx->side, ctx->ev_fine, 0);
     if (mesh && e == hipSuccess)
-        e = launch_mesh_count(ctx, o->d_jobs, n_jobs, ctx->side);
+        e = launch_mesh_count(ctx, o->d_jobs, n_jobs, 0, ctx->side);
     if (e == hipSuccess)
         e = launch_edges(ctx, o->d_jobs, n_jobs, o->d_keys, o->d_xyz, o->max_points,
                          o->d_point_off, o->d_counts + 2, true, mesh, stream);
@@ -585,7 +585,8 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = hipStreamWaitEvent(ctx->side, ctx->ev_edges, 0);
     if (mesh && e == hipSuccess)
         e = launch_mesh_write(ctx, o->d_jobs, n_jobs, o->d_keys, o->d_counts + 2, o->max_points,
-                              false, o->d_tris, o->max_tris, o->d_tri_off, nullptr, ctx->side);
+                              false, o->d_tris, o->max_tris, o->d_tri_off, nullptr, 0,
+                              ctx->side);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev_join, ctx->side);
     if (e == hipSuccess)

@@ -239,6 +239,13 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
     return v;
 }
 
+// LDS-only ordering between the lanes of one wave (the LDS serves a wave's
+// requests in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Exclusive prefix sum over a 256- or 1024-thread block; *total = block sum.
 // `scratch` holds one uint32 per wave.  Contains __syncthreads().
 template <int NT>
@@ -536,13 +543,14 @@ hipError_t launch_mesh(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, cons
 // of the edge compaction).  tri_off: NULL, or per job its first triangle and
 // at [n_jobs] the total; n_tris: NULL, or the total.  Vertices are positions
 // in the key list; those at or past min(*n_keys, max_keys), or (verify) whose
-// key differs, are 0xffffffff and set the capacity flag.
+// key differs, are 0xffffffff and set the capacity flag.  items_hint: the
+// number of work items when the host knows it, else 0.
 hipError_t launch_mesh_count(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
-                             hipStream_t s);
+                             int64_t items_hint, hipStream_t s);
 hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                              const uint32_t* keys, const uint32_t* n_keys, uint32_t max_keys,
                              bool verify, uint32_t* tris, uint32_t max_tris, uint32_t* tri_off,
-                             uint32_t* n_tris, hipStream_t s);
+                             uint32_t* n_tris, int64_t items_hint, hipStream_t s);
 
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);

@@ -97,8 +97,8 @@ void build_mesh_table(MeshTable* t) {
 // ------------------------------------------------------------------ kernels
 // The passes run over the fine bitmaps of the jobs with the work items of the
 // crossing-edge compaction (kEdgeWords words of one lattice, one word per
-// thread).  A word's thread owns the cells whose first corner is one of its
-// samples: bit b is the cell (64 q + b, y, z).  Its corners lie in the rows
+// thread).  A word's cells are those whose first corner is one of its
+// samples: bit b is the cell (64 q + b, y, z), with corners in the rows
 // (y + dy, z + dz), m = dy + 2 dz, at bits b and b + 1 (bit 0 of the next word
 // for b = 63).  Cells in linear order are words in order, then bits in order,
 // so triangles come out by cell in linear order.
@@ -108,20 +108,16 @@ void build_mesh_table(MeshTable* t) {
 struct CellRows {
     uint64_t r[4], s[4];
     uint64_t mixed;
-    int64_t row;       // row index y + ny z of the word
-    int32_t q;         // word within its row
-    bool last;         // the row's last word
 };
 
 __device__ __forceinline__ CellRows cell_rows(const uint64_t* __restrict__ bits, int64_t w,
                                               const int32_t* d, int32_t wr) {
     CellRows c;
-    c.row = w / wr;
-    c.q = (int32_t)(w - c.row * wr);
-    c.last = c.q == wr - 1;
-    c.mixed = 0;
-    const int32_t y = (int32_t)(c.row % d[1]);
-    const int32_t z = (int32_t)(c.row / d[1]);
+    const int64_t row = w / wr;
+    const int32_t q = (int32_t)(w - row * wr);
+    const bool last = q == wr - 1;
+    const int32_t y = (int32_t)(row % d[1]);
+    const int32_t z = (int32_t)(row / d[1]);
     const bool cells = y + 1 < d[1] && z + 1 < d[2];
     const int64_t slab = (int64_t)wr * d[1];
     // rows past the lattice are never read: their loads repeat this word
@@ -131,16 +127,15 @@ __device__ __forceinline__ CellRows cell_rows(const uint64_t* __restrict__ bits,
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         c.r[m] = bits[wm[m]];
-        const uint64_t nx = c.last ? 0ull : bits[wm[m] + 1];
+        const uint64_t nx = last ? 0ull : bits[wm[m] + 1];
         c.s[m] = (c.r[m] >> 1) | (nx << 63);
         any |= c.r[m] | c.s[m];
         all &= c.r[m] & c.s[m];
     }
     // cell x needs sample x + 1 in the lattice: in the last word bits
-    // [0, nx - 64 q - 1) are cells
-    const int32_t in_last = d[0] - 64 * c.q - 1;
-    const uint64_t cellmask =
-        c.last ? (in_last >= 64 ? ~0ull : ((1ull << in_last) - 1)) : ~0ull;
+    // [0, nx - 64 q - 1) are cells (at most 63)
+    const int32_t in_last = d[0] - 64 * q - 1;
+    const uint64_t cellmask = last ? ((1ull << in_last) - 1ull) : ~0ull;
     c.mixed = cells ? (any & ~all) & cellmask : 0ull;
     return c;
 }
@@ -162,7 +157,7 @@ __device__ __forceinline__ void load_table(const MeshTable* __restrict__ tbl, Me
     __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t word_triangles(const CellRows& c, const MeshTable& t) {
+__device__ __forceinline__ uint32_t cell_triangles(const CellRows& c, const MeshTable& t) {
     uint32_t n = 0;
     for (uint64_t b = c.mixed; b; b &= b - 1)
         n += t.count[cell_pattern(c, __ffsll((unsigned long long)b) - 1)];
@@ -179,8 +174,10 @@ __global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_job* __res
     __shared__ uint32_t table[kJobTable];
     __shared__ uint32_t scratch[kBlock / kWave];
     __shared__ MeshTable s_tbl;
-    load_table(tbl, &s_tbl);
     const int nj = (int)*n_jobs_p;
+    if (blockIdx.x >= pre[nj].item_off)    // no item for this workgroup
+        return;
+    load_table(tbl, &s_tbl);
     const ItemJobs ij = load_item_jobs(pre, nj, table);
     const uint32_t n_items = ij.first_item(nj);
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -189,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_job* __res
         const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
         uint32_t n = 0;
         if (w < fine_bitmap_words(g))
-            n = word_triangles(cell_rows(bits + pre[jb].bit_off, w, g.dims, (g.dims[0] + 63) / 64),
+            n = cell_triangles(cell_rows(bits + pre[jb].bit_off, w, g.dims, (g.dims[0] + 63) / 64),
                                s_tbl);
         uint32_t total;
         block_exclusive_sum<kBlock>(n, scratch, &total);
@@ -198,12 +195,26 @@ __global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_job* __res
     }
 }
 
+// A cell listed for the write pass: the lane of its word in the wave, its bit,
+// its corner pattern and its first triangle (relative to the work item).
+constexpr int kCellRecs = 256;   // per wave and pass
+
+__device__ __forceinline__ uint2 cell_rec(int lane, int b, int cs, uint32_t t) {
+    return make_uint2((uint32_t)lane | (uint32_t)b << 6 | (uint32_t)cs << 12, t);
+}
+
 // Per work item: first triangle = the triangles of the earlier items, then a
-// scan over the threads; each thread writes its cells' triangles.  A vertex
-// on cell edge 4 a + u + 2 v has its edge's first sample at (dx, dy, dz) with
-// d_a = 0 and (u, v) on the other two axes; the owning word's WordEdges give
-// its position.  The 12 positions of a cell go through LDS (one column per
-// thread) so that the table's runtime edge numbers index them.
+// scan over the threads gives each word's first triangle.  The words' cells
+// are then spread over the wave's lanes: each lane lists its word's cells
+// (bit, pattern, first triangle) in the wave's LDS records, and every lane
+// takes every 64th record.  A vertex on cell edge 4 a + u + 2 v has its edge's
+// first sample at (dx, dy, dz) with d_a = 0 and (u, v) on the other two axes;
+// the owning word's WordEdges give its position (each word's four owners in
+// rows y..y+1, z..z+1 are staged in LDS; the next word's, needed at b = 63
+// only, are read from memory).  The 12 positions of a cell
+// go through LDS (one column per thread) so that the table's runtime edge
+// numbers index them; a crossing edge whose position is past the keys (or,
+// kVerify, holds another key) becomes 0xffffffff.
 template <bool kVerify>
 __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
     const fvv_job* __restrict__ jobs, const JobPrefix* __restrict__ pre,
@@ -213,25 +224,33 @@ __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
     const uint32_t* __restrict__ n_keys_p, uint32_t max_keys, uint32_t* __restrict__ tris,
     uint32_t max_tris, uint32_t* __restrict__ tri_off, uint32_t* __restrict__ n_tris,
     uint32_t* __restrict__ status) {
+    constexpr int kWaves = kBlock / kWave;
     __shared__ uint32_t table[kJobTable];
-    __shared__ uint64_t scratch64[kBlock / kWave];
-    __shared__ uint32_t scratch[kBlock / kWave];
+    __shared__ uint64_t scratch64[kWaves];
+    __shared__ uint32_t scratch[kWaves];
     __shared__ MeshTable s_tbl;
     __shared__ uint32_t s_pos[12][kBlock];
-    load_table(tbl, &s_tbl);
+    __shared__ uint2 s_rec[kWaves][kCellRecs];
+    __shared__ WordEdges s_own[4][kBlock];   // each word's owners in rows m, this q
     const int nj = (int)*n_jobs_p;
-    const ItemJobs ij = load_item_jobs(pre, nj, table);
-    const uint32_t n_items = ij.first_item(nj);
-    const uint32_t nk_all = *n_keys_p;
-    const uint32_t nk = nk_all < max_keys ? nk_all : max_keys;
-    const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
-    if (n_items == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t items_all = pre[nj].item_off;
+    if (items_all == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
         if (tri_off)
             for (int j = 0; j <= nj; ++j)
                 tri_off[j] = 0;
         if (n_tris)
             *n_tris = 0;
     }
+    if (blockIdx.x >= items_all)           // no item for this workgroup
+        return;
+    load_table(tbl, &s_tbl);
+    const ItemJobs ij = load_item_jobs(pre, nj, table);
+    const uint32_t n_items = ij.first_item(nj);
+    const uint32_t nk_all = *n_keys_p;
+    const uint32_t nk = nk_all < max_keys ? nk_all : max_keys;
+    const int lane = (int)lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         uint64_t before = 0;
         for (uint32_t i = threadIdx.x; i < item; i += kBlock)
@@ -241,83 +260,113 @@ __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
         const int jb = ij.job_of(item);
         const fvv_grid g = jobs[jb].grid;
         const int32_t wr = (g.dims[0] + 63) / 64;
-        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
+        const int64_t w0 = (int64_t)(item - ij.first_item(jb)) * kEdgeWords;   // item's first word
+        const int64_t w = w0 + threadIdx.x;
         CellRows c;
         c.mixed = 0;
         if (w < fine_bitmap_words(g))
             c = cell_rows(bits + pre[jb].bit_off, w, g.dims, wr);
         uint32_t total;
-        const uint32_t ex = block_exclusive_sum<kBlock>(word_triangles(c, s_tbl), scratch, &total);
-        uint64_t pos = first + ex;
+        const uint32_t tri_ex = block_exclusive_sum<kBlock>(cell_triangles(c, s_tbl), scratch, &total);
+        // the wave's cells, listed by word then bit
+        const uint32_t n_cells = (uint32_t)__popcll(c.mixed);
+        const uint32_t cell_in = wave_inclusive_sum(n_cells);
+        const uint32_t cell_ex = cell_in - n_cells;
+        const uint32_t wave_cells = (uint32_t)__builtin_amdgcn_readlane((int)cell_in, kWave - 1);
+        const WordEdges* we = wedges + pre[jb].bit_off;
+        const int64_t slab = (int64_t)wr * g.dims[1];
+        const int64_t nx = g.dims[0], sz = (int64_t)g.dims[0] * g.dims[1];
         bool missing = false;
         if (c.mixed) {
-            // the owning words: this word (q) and the next (q + 1) of each row
-            const WordEdges* we = wedges + pre[jb].bit_off;
-            const int64_t slab = (int64_t)wr * g.dims[1];
-            WordEdges own[4], nxt[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int64_t wm = w + (m & 1) * (int64_t)wr + (m >> 1) * slab;
-                own[m] = we[wm];
-                if (!c.last && (c.mixed >> 63))
-                    nxt[m] = we[wm + 1];
-                else
-                    nxt[m] = own[m];
+            for (int m = 0; m < 4; ++m)
+                s_own[m][threadIdx.x] = we[w + (m & 1) * (int64_t)wr + (m >> 1) * slab];
+        }
+        for (uint32_t base = 0; base < wave_cells; base += kCellRecs) {
+            if (n_cells && cell_ex < base + kCellRecs && cell_ex + n_cells > base) {
+                uint32_t k = cell_ex, t = tri_ex;
+                for (uint64_t bm = c.mixed; bm; bm &= bm - 1, ++k) {
+                    const int b = __ffsll((unsigned long long)bm) - 1;
+                    const int cs = cell_pattern(c, b);
+                    if (k >= base && k < base + kCellRecs)
+                        s_rec[wv][k - base] = cell_rec(lane, b, cs, t);
+                    t += s_tbl.count[cs];
+                }
             }
-            const int64_t nx = g.dims[0], sz = (int64_t)g.dims[0] * g.dims[1];
-            for (uint64_t bm = c.mixed; bm; bm &= bm - 1) {
-                const int b = __ffsll((unsigned long long)bm) - 1;
+            wave_lds_sync();
+            const uint32_t n_here = wave_cells - base < kCellRecs ? wave_cells - base : kCellRecs;
+            for (uint32_t i = lane; i < n_here; i += kWave) {
+                const uint2 rec = s_rec[wv][i];
+                const int src = (int)(rec.x & 63u), b = (int)((rec.x >> 6) & 63u);
+                const int cs = (int)(rec.x >> 12);
+                const int64_t ws = w0 + wv * kWave + src;      // the cell's word
+                const int64_t row = ws / wr;
+                const int32_t q = (int32_t)(ws - row * wr);
                 // position of the first edge at each owner (m, dx) and the
-                // x- and y-edge bits there
+                // x- and y-edge bits there; dx = 1 at b = 63 is the next word's bit 0
                 uint32_t R[4][2], xb[4][2], yb[4][2];
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < 4; ++m) {
+                    const WordEdges own = s_own[m][wv * kWave + src];
+                    uint64_t nex = 0, ney = 0, nez = 0;
+                    uint32_t nfirst = 0;
+                    if (b == 63) {
+                        const WordEdges* t = we + ws + (m & 1) * (int64_t)wr + (m >> 1) * slab + 1;
+                        nex = t->ex;
+                        ney = t->ey;
+                        nez = t->ez;
+                        nfirst = t->first;
+                    }
 #pragma unroll
                     for (int dx = 0; dx < 2; ++dx) {
                         const bool over = dx == 1 && b == 63;
-                        const WordEdges& o = over ? nxt[m] : own[m];
+                        const uint64_t ex = over ? nex : own.ex;
+                        const uint64_t ey = over ? ney : own.ey;
+                        const uint64_t ez = over ? nez : own.ez;
+                        const uint32_t fst = over ? nfirst : own.first;
                         const int p = over ? 0 : b + dx;
                         const uint64_t below = (1ull << p) - 1ull;
-                        R[m][dx] = o.first + (uint32_t)(__popcll(o.ex & below) +
-                                                        __popcll(o.ey & below) +
-                                                        __popcll(o.ez & below));
-                        xb[m][dx] = (uint32_t)((o.ex >> p) & 1u);
-                        yb[m][dx] = (uint32_t)((o.ey >> p) & 1u);
+                        R[m][dx] = fst + (uint32_t)(__popcll(ex & below) + __popcll(ey & below) +
+                                                    __popcll(ez & below));
+                        xb[m][dx] = (uint32_t)((ex >> p) & 1u);
+                        yb[m][dx] = (uint32_t)((ey >> p) & 1u);
                     }
+                }
                 // cell edge 4 a + u + 2 v: x-edges own (0, u, v), y-edges (u, 0, v),
-                // z-edges (u, v, 0)
+                // z-edges (u, v, 0); its corners c0 and c0 + (1 << a)
+                const int64_t lin0 = row * nx + 64 * (int64_t)q + b;   // corner 0
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) {
-                        s_pos[0 + u + 2 * v][threadIdx.x] = R[u + 2 * v][0];
-                        s_pos[4 + u + 2 * v][threadIdx.x] = R[2 * v][u] + xb[2 * v][u];
-                        s_pos[8 + u + 2 * v][threadIdx.x] = R[v][u] + xb[v][u] + yb[v][u];
-                    }
-                const int cs = cell_pattern(c, b);
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 2; ++v) {
+                            const int dx = a == 0 ? 0 : u;
+                            const int dy = a == 1 ? 0 : (a == 0 ? u : v);
+                            const int dz = a == 2 ? 0 : v;
+                            const int m = dy + 2 * dz;
+                            const uint32_t ix = R[m][dx] + (a >= 1 ? xb[m][dx] : 0u) +
+                                                (a >= 2 ? yb[m][dx] : 0u);
+                            const int c0 = dx + 2 * dy + 4 * dz;
+                            const bool crosses = ((cs >> c0) ^ (cs >> (c0 + (1 << a)))) & 1;
+                            bool bad = ix >= nk;
+                            if (kVerify && crosses && !bad)
+                                bad = keys[ix] !=
+                                      (uint32_t)(3 * (lin0 + dx + nx * dy + sz * dz) + a);
+                            missing |= crosses && bad;
+                            s_pos[4 * a + u + 2 * v][threadIdx.x] = bad ? 0xffffffffu : ix;
+                        }
                 const int nt = s_tbl.count[cs];
-                const int64_t lin0 = c.row * nx + 64 * (int64_t)c.q + b;   // corner 0
+                uint64_t pos = first + rec.y;
                 for (int r = 0; r < nt; ++r, ++pos) {
                     if (pos >= max_tris)
                         continue;
 #pragma unroll
-                    for (int v = 0; v < 3; ++v) {
-                        const int e = s_tbl.edge[cs][3 * r + v];
-                        uint32_t ix = s_pos[e][threadIdx.x];
-                        bool bad = ix >= nk;
-                        if (kVerify && !bad) {
-                            const int a = e >> 2, eu = e & 1, ev = (e >> 1) & 1;
-                            const int dx = a == 0 ? 0 : eu;
-                            const int dy = a == 1 ? 0 : (a == 0 ? eu : ev);
-                            const int dz = a == 2 ? 0 : ev;
-                            const int64_t lin = lin0 + dx + nx * dy + sz * dz;
-                            bad = keys[ix] != (uint32_t)(3 * lin + a);
-                        }
-                        missing |= bad;
-                        tris[3 * pos + v] = bad ? 0xffffffffu : ix;
-                    }
+                    for (int v = 0; v < 3; ++v)
+                        tris[3 * pos + v] = s_pos[s_tbl.edge[cs][3 * r + v]][threadIdx.x];
                 }
             }
+            wave_lds_sync();   // the next pass rewrites this wave's records
         }
         if (missing)
             atomicOr(status, kFlagCapacity);
@@ -337,9 +386,17 @@ __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
     }
 }
 
+// Workgroups of the mesh passes: what the CUs hold at once (the write pass's
+// LDS allows two per CU), or fewer when the item count is known.
+static unsigned mesh_grid(const fvv_ctx* ctx, int per_cu, int64_t items_hint) {
+    const int64_t full = (int64_t)ctx->n_cus * per_cu;
+    return (unsigned)(items_hint > 0 && items_hint < full ? items_hint : full);
+}
+
 hipError_t launch_mesh_count(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(mesh_count_kernel, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs,
+                             int64_t items_hint, hipStream_t s) {
+    hipLaunchKernelGGL(mesh_count_kernel, dim3(mesh_grid(ctx, 8, items_hint)), dim3(kBlock), 0, s,
+                       jobs,
                        ctx->d_prefix, n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table,
                        ctx->d_tri_cnt);
     return hipGetLastError();
@@ -348,9 +405,10 @@ hipError_t launch_mesh_count(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* 
 hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                              const uint32_t* keys, const uint32_t* n_keys, uint32_t max_keys,
                              bool verify, uint32_t* tris, uint32_t max_tris, uint32_t* tri_off,
-                             uint32_t* n_tris, hipStream_t s) {
+                             uint32_t* n_tris, int64_t items_hint, hipStream_t s) {
     auto kernel = verify ? mesh_write_kernel<true> : mesh_write_kernel<false>;
-    hipLaunchKernelGGL(kernel, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
+    hipLaunchKernelGGL(kernel, dim3(mesh_grid(ctx, 2, items_hint)), dim3(kBlock), 0, s, jobs,
+                       ctx->d_prefix,
                        n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table, ctx->d_tri_cnt,
                        ctx->d_word_edges, keys, n_keys, max_keys, tris, max_tris, tri_off, n_tris,
                        ctx->d_status);
@@ -367,11 +425,12 @@ hipError_t launch_mesh(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, cons
     if (e == hipSuccess)
         e = launch_edges(ctx, ctx->d_job_single, ctx->d_counts_single + 3, nullptr, nullptr, 0,
                          nullptr, nullptr, false, true, s);
+    const int64_t items = (fine_bitmap_words(g) + kEdgeWords - 1) / kEdgeWords;
     if (e == hipSuccess)
-        e = launch_mesh_count(ctx, ctx->d_job_single, ctx->d_counts_single + 3, s);
+        e = launch_mesh_count(ctx, ctx->d_job_single, ctx->d_counts_single + 3, items, s);
     if (e == hipSuccess)
         e = launch_mesh_write(ctx, ctx->d_job_single, ctx->d_counts_single + 3, keys, n_keys,
-                              max_keys, true, tris, max_tris, nullptr, n_tris, s);
+                              max_keys, true, tris, max_tris, nullptr, n_tris, items, s);
     return e;
 }
 

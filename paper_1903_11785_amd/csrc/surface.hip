@@ -296,13 +296,6 @@ struct EdgeRec {
     int pad_[3];
 };
 
-// LDS-only ordering between the lanes of one wave (the LDS serves a wave's
-// requests in order; this keeps the compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 template <int kCamsCap>
 __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ n_jobs_p,

@@ -49,7 +49,11 @@ def gpu_mesh(fvv, ctx, occ, keys, max_tris=1 << 20):
 
 @pytest.mark.parametrize("shape,p,seed", [((9, 8, 7), 0.45, 0), ((37, 29, 23), 0.5, 1),
                                           ((64, 17, 33), 0.3, 2), ((5, 70, 3), 0.6, 3),
-                                          ((2, 2, 2), 0.5, 4)])
+                                          ((2, 2, 2), 0.5, 4),
+                                          # rows of several bitmap words: cells at bit 63 take
+                                          # their x + 1 corners and edges from the next word
+                                          ((7, 6, 130), 0.5, 5), ((5, 4, 65), 0.5, 6),
+                                          ((4, 5, 128), 0.5, 7), ((3, 3, 200), 0.2, 8)])
 def test_random_grids_match_oracle(fvv, ctx, shape, p, seed):
     rng = np.random.default_rng(seed)
     occ = (rng.uniform(size=shape) < p).astype(np.uint8)
