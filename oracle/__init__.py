@@ -63,6 +63,10 @@ def lib():
         L.orc_bisect.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, f32, p, p, p, p, i64,
                                  C.c_int, p, p]
         L.orc_bisect.restype = i64
+        L.orc_isovalue.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, f32, p, p, p, p, i64, p,
+                                   p]
+        L.orc_line_lambda2.argtypes = [p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_line_lambda2.restype = C.c_double
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
         L.orc_threads.restype = i32
@@ -196,6 +200,31 @@ def bisect(P, sils, W, H, lat: Lattice, occ: np.ndarray, keys: np.ndarray, steps
     if count_tests:
         return xyz[:E].copy(), t[:E].copy(), int(T)
     return xyz[:E].copy(), t[:E].copy()
+
+
+def isovalue(P, sils, W, H, lat: Lattice, occ: np.ndarray, keys: np.ndarray):
+    """The paper's isovalue of every crossing edge (Sec. II-C, Eq. (2)-(3)):
+    lambda (float32, the minimum over cameras of the Bresenham image-space
+    ratio) and the point at that parameter along the edge from its occupied
+    end."""
+    P = np.ascontiguousarray(P, dtype=np.float32).reshape(-1, 12)
+    sils = np.ascontiguousarray(sils, dtype=np.uint32)
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    E = keys.size
+    lam = np.empty(max(E, 1), np.float32)
+    xyz = np.empty((max(E, 1), 3), np.float32)
+    lib().orc_isovalue(P.shape[0], _p(P), W, H, _p(sils), _p(_f3(lat.origin)), np.float32(lat.h),
+                       _p(_i3(lat.lo)), _p(_i3(lat.dims)), _p(occ), _p(keys), E, _p(lam), _p(xyz))
+    return lam[:E].copy(), xyz[:E].copy()
+
+
+def line_lambda2(sil: np.ndarray, W: int, H: int, p_on, p_off) -> float:
+    """lambda_i^2 of Eq. (2) for one camera: the Bresenham line of pixels from
+    p_on to p_off over one packed silhouette [H][ceil(W/32)]."""
+    sil = np.ascontiguousarray(sil, dtype=np.uint32)
+    return float(lib().orc_line_lambda2(_p(sil), W, H, int(p_on[0]), int(p_on[1]), int(p_off[0]),
+                                        int(p_off[1])))
 
 
 def point_inside(P, sils, W, H, X: float, Y: float, Z: float) -> bool:

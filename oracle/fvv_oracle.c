@@ -24,6 +24,11 @@
  *   orc_bisect       Sec. II-C, Eq. (2)-(3): the point where an edge leaves the
  *                    hull, i.e. the first exit over all cameras, located by
  *                    bisection of the 3-D edge parameter.
+ *   orc_isovalue     Sec. II-C, Eq. (2)-(3) as the paper computes them: per
+ *                    camera the last foreground pixel of the Bresenham line
+ *                    from P_on to P_off, the image-space ratio of Eq. (2),
+ *                    the minimum over cameras of Eq. (3).
+ *   orc_mesh         Sec. II-C: marching-cubes triangles over the cells.
  */
 #include <math.h>
 #include <stdint.h>
@@ -401,6 +406,135 @@ int32_t orc_point_inside(int ncam, const float *P, int W, int H, const uint32_t 
 {
     int nt = 0;
     return point_inside(ncam, P, W, H, sils, X, Y, Z, &nt);
+}
+
+/* ------------------------------------------------------------------ isovalue (Bresenham)
+ *
+ * The paper's own isovalue of a crossing edge (Sec. II-C, Eq. (2) and (3)),
+ * with the readings the paper leaves open fixed as follows.  In camera i the
+ * edge's ends project to the pixels P_on (the occupied end's: inside the
+ * image and foreground, since that sample is occupied) and P_off (the exact
+ * floor of its projection, clamped to [-8, dim + 8] on each axis).  The line
+ * of pixels from P_on to P_off is traced with Bresenham's integer algorithm
+ * (all octants: the error term starts at dx - dy and each step moves along x
+ * when twice the error is at least -dy, along y when it is at most dx).  P_i
+ * is the last pixel before the first one that is background or outside the
+ * image, and Eq. (2) gives lambda_i = |P_i - P_on| / |P_off - P_on|; a line
+ * that is foreground to its end gives lambda_i = 1, and a camera that sees
+ * the OFF end behind it (w <= 0) gives lambda_i = 0.  lambda_i^2 is taken as
+ * the double quotient of the two integer squared lengths; Eq. (3)'s minimum is
+ * taken over those, and lambda = (float)sqrt(min).
+ */
+
+/* lambda_i^2 of one camera for the pixel line (x0, y0) -> (x1, y1) over the
+ * silhouette rows `sil` ([H][wpr] words).  A start pixel that is not
+ * foreground gives 0. */
+static double line_lambda2(const uint32_t *sil, int W, int H, int wpr, int x0, int y0, int x1,
+                           int y1)
+{
+    const int fg0 = x0 >= 0 && y0 >= 0 && x0 < W && y0 < H &&
+                    ((sil[(size_t)y0 * wpr + (x0 >> 5)] >> (x0 & 31)) & 1u);
+    if (!fg0)
+        return 0.0;
+    const int dx = abs(x1 - x0), dy = abs(y1 - y0);
+    const int sx = x0 < x1 ? 1 : -1, sy = y0 < y1 ? 1 : -1;
+    int err = dx - dy;
+    int x = x0, y = y0, last_x = x0, last_y = y0;
+    while (x != x1 || y != y1) {
+        const int e2 = 2 * err;
+        if (e2 >= -dy) {
+            err -= dy;
+            x += sx;
+        }
+        if (e2 <= dx) {
+            err += dx;
+            y += sy;
+        }
+        const int fg = x >= 0 && y >= 0 && x < W && y < H &&
+                       ((sil[(size_t)y * wpr + (x >> 5)] >> (x & 31)) & 1u);
+        if (!fg) {
+            const int64_t ax = last_x - x0, ay = last_y - y0;
+            const int64_t bx = x1 - x0, by = y1 - y0;
+            return (double)(ax * ax + ay * ay) / (double)(bx * bx + by * by);
+        }
+        last_x = x;
+        last_y = y;
+    }
+    return 1.0;
+}
+
+double orc_line_lambda2(const uint32_t *sil, int W, int H, int x0, int y0, int x1, int y1)
+{
+    return line_lambda2(sil, W, H, (W + 31) / 32, x0, y0, x1, y1);
+}
+
+/* Pixel index of the quotient a/w on one axis for the line's far end: the
+ * exact floor, clamped to [-8, dim + 8]. */
+static int far_pixel(float a, float w, int dim)
+{
+    double q = floor((double)a / (double)w);
+    if (q < -8.0)
+        q = -8.0;
+    if (q > (double)dim + 8.0)
+        q = (double)dim + 8.0;
+    return (int)q;
+}
+
+void orc_isovalue(int ncam, const float *P, int W, int H, const uint32_t *sils, const float *o,
+                  float h, const int32_t *lo, const int32_t *n, const uint8_t *occ,
+                  const uint32_t *keys, int64_t E, float *lambda, float *xyz)
+{
+    const int wpr = (W + 31) / 32;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t lin = keys[e] / 3;
+        const int axis = (int)(keys[e] % 3);
+        const int64_t i = lin % n[0], j = (lin / n[0]) % n[1], k = lin / ((int64_t)n[0] * n[1]);
+        const int64_t stride = axis == 0 ? 1 : (axis == 1 ? n[0] : (int64_t)n[0] * n[1]);
+        const int32_t g[3] = {lo[0] + (int32_t)i, lo[1] + (int32_t)j, lo[2] + (int32_t)k};
+        const int p_on = occ[lin] != 0;
+        (void)stride;
+        const int32_t g_on = p_on ? g[axis] : g[axis] + 1;
+        const int32_t g_off = p_on ? g[axis] + 1 : g[axis];
+        const float d = p_on ? 1.0f : -1.0f;
+        float X_on[3], X_off[3];
+        for (int a = 0; a < 3; ++a)
+            X_on[a] = X_off[a] = lattice_coord(g[a], h, o[a]);
+        X_on[axis] = lattice_coord(g_on, h, o[axis]);
+        X_off[axis] = lattice_coord(g_off, h, o[axis]);
+
+        double best = 1.0;
+        for (int c = 0; c < ncam; ++c) {
+            const float *p = P + 12 * c;
+            const float *X = X_on;
+            const float a0 = fmaf(p[2], X[2], fmaf(p[1], X[1], fmaf(p[0], X[0], p[3])));
+            const float b0 = fmaf(p[6], X[2], fmaf(p[5], X[1], fmaf(p[4], X[0], p[7])));
+            const float w0 = fmaf(p[10], X[2], fmaf(p[9], X[1], fmaf(p[8], X[0], p[11])));
+            X = X_off;
+            const float a1 = fmaf(p[2], X[2], fmaf(p[1], X[1], fmaf(p[0], X[0], p[3])));
+            const float b1 = fmaf(p[6], X[2], fmaf(p[5], X[1], fmaf(p[4], X[0], p[7])));
+            const float w1 = fmaf(p[10], X[2], fmaf(p[9], X[1], fmaf(p[8], X[0], p[11])));
+            double l2;
+            if (!(w1 > 0.0f))
+                l2 = 0.0;
+            else
+                l2 = line_lambda2(sils + (size_t)c * H * wpr, W, H, wpr, far_pixel(a0, w0, W),
+                                  far_pixel(b0, w0, H), far_pixel(a1, w1, W),
+                                  far_pixel(b1, w1, H));
+            if (l2 < best)
+                best = l2;
+        }
+        const float lam = (float)sqrt(best);
+        lambda[e] = lam;
+        if (xyz) {
+            float c3[3];
+            for (int a = 0; a < 3; ++a)
+                c3[a] = X_on[a];
+            c3[axis] = fmaf((float)g_on + d * lam, h, o[axis]);
+            for (int a = 0; a < 3; ++a)
+                xyz[3 * e + a] = c3[a];
+        }
+    }
 }
 
 /* Threads the OpenMP loops above use. */
