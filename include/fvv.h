@@ -309,6 +309,37 @@ fvv_status fvv_mesh(fvv_ctx *ctx, const fvv_grid *grid, const uint8_t *d_occ,
                     const uint32_t *d_keys, const uint32_t *d_n_keys, uint32_t max_keys,
                     uint32_t *d_tris, uint32_t max_tris, uint32_t *d_n_tris, hipStream_t stream);
 
+/* The paper's own isovalue of crossing edges (Sec. II-C, Eq. (2)-(3)), for
+ * comparison with the exit points of fvv_surface (which bisect the 3-D edge
+ * parameter against the occupancy test).  In camera i the edge's two samples
+ * project to pixels P_on (the occupied sample's) and P_off -- the exact floor
+ * of each fp32 projection (the occupancy test's), P_off clamped to
+ * [-8, dim + 8] -- and the line of pixels from P_on to P_off is traced with
+ * Bresenham's integer algorithm (all octants: error term dx - dy, a step
+ * along x when twice the error is at least -dy, along y when it is at most
+ * dx).  P_i is the last pixel before the first one that is background or off
+ * the image; lambda_i = |P_i - P_on| / |P_off - P_on| (Eq. (2)), 1 when the
+ * line is foreground to its end, 0 when P_on is not foreground or either
+ * sample is behind the camera.  lambda = min over cameras (Eq. (3)), taken on
+ * lambda_i^2 as the IEEE double quotient of the integer squared lengths, then
+ * rounded to float from its square root.
+ *   d_occ, cams, d_sils: the lattice's occupancy and the cameras, as for
+ *             fvv_surface (n_cams at most the context's max_cams);
+ *   d_keys:   crossing edges 3*lin+axis of `grid` (fvv_surface's output), the
+ *             first min(*d_n_keys, max_keys) of them used (*d_n_keys device);
+ *   d_lambda: out, float [max_keys]: lambda per key (NaN for a key that names
+ *             no edge of the lattice);
+ *   d_xyz:    out (or NULL), float [max_keys][3]: the point at lambda along
+ *             the edge from its occupied sample, the axis coordinate as
+ *             fmaf(g_on + d*lambda, h, origin) (d = +-1 toward the other
+ *             sample), the other two the lattice values.
+ * EINVAL on NULL pointers, zero max_keys, an invalid grid or camera set, or a
+ * lattice beyond 0x55555555 samples.  No context scratch is used. */
+fvv_status fvv_isovalue(fvv_ctx *ctx, const fvv_grid *grid, const uint8_t *d_occ, int32_t n_cams,
+                        const fvv_camera *cams, const uint32_t *d_sils, const uint32_t *d_keys,
+                        const uint32_t *d_n_keys, uint32_t max_keys, float *d_lambda,
+                        float *d_xyz, hipStream_t stream);
+
 /* ---------------------------------------------------------------- soft hull
  * A differentiable relative of the binary hull of Sec. II-B-1 (not in the
  * paper), for refining silhouette logits and camera poses by gradient descent.

@@ -135,6 +135,8 @@ def _load():
         "fvv_tune_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), u32, i32,
                                     C.POINTER(C.c_float), C.POINTER(u32), P], i32),
         "fvv_mesh": ([P, C.POINTER(GridC), P, P, P, u32, P, u32, P, P], i32),
+        "fvv_isovalue": ([P, C.POINTER(GridC), P, i32, C.POINTER(Camera), P, P, P, u32, P, P, P],
+                         i32),
         "fvv_soft_forward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P, P,
                               P], i32),
         "fvv_soft_backward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P,
@@ -373,6 +375,22 @@ class Context:
                             int(keys.numel()), _ptr(tris), int(tris.shape[0]), _ptr(n_tris),
                             C.c_void_p(_stream(stream))), "fvv_mesh")
         return tris, n_tris
+
+    def isovalue(self, grid: Grid, occ, P: np.ndarray, W: int, H: int, sils, keys, n_keys,
+                 lam=None, xyz=None, stream=None):
+        """The paper's Bresenham isovalue (lambda, and the point there) of the
+        first n_keys keys; returns (lam, xyz) device tensors."""
+        import torch
+        cams = make_cameras(P, W, H)
+        m = int(keys.numel())
+        if lam is None:
+            lam = torch.empty(m, dtype=torch.float32, device=occ.device)
+        if xyz is None:
+            xyz = torch.empty((m, 3), dtype=torch.float32, device=occ.device)
+        _ok(self.L.fvv_isovalue(self.h, C.byref(grid.c()), _ptr(occ), len(cams), cams, _ptr(sils),
+                                _ptr(keys), _ptr(n_keys), m, _ptr(lam), _ptr(xyz),
+                                C.c_void_p(_stream(stream))), "fvv_isovalue")
+        return lam, xyz
 
     def soft_forward(self, grid: Grid, cams, W: int, H: int, logits, target=None, occ=None,
                      loss=None, stream=None):

@@ -448,6 +448,20 @@ fvv_status fvv_mesh(fvv_ctx* ctx, const fvv_grid* grid, const uint8_t* d_occ,
                            d_n_tris, stream));
 }
 
+fvv_status fvv_isovalue(fvv_ctx* ctx, const fvv_grid* grid, const uint8_t* d_occ, int32_t n_cams,
+                        const fvv_camera* cams, const uint32_t* d_sils, const uint32_t* d_keys,
+                        const uint32_t* d_n_keys, uint32_t max_keys, float* d_lambda,
+                        float* d_xyz, hipStream_t stream) {
+    if (!ctx || !d_occ || !d_sils || !d_keys || !d_n_keys || !d_lambda || max_keys < 1 ||
+        !cams_ok(ctx, n_cams, cams) || !grid_ok(grid, kMaxIndex))
+        return FVV_EINVAL;
+    if (grid_samples(*grid) > (int64_t)0x55555555)
+        return FVV_EINVAL;
+    const CamSet cs = make_camset(n_cams, cams);
+    return dev(launch_isovalue(ctx, *grid, d_occ, cs, d_sils, d_keys, d_n_keys, max_keys, d_lambda,
+                               d_xyz, stream));
+}
+
 // ------------------------------------------------------------------ soft hull
 fvv_status fvv_soft_forward(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams,
                             const fvv_soft_camera* cams, int32_t width, int32_t height,

@@ -552,6 +552,11 @@ hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* 
                              bool verify, uint32_t* tris, uint32_t max_tris, uint32_t* tri_off,
                              uint32_t* n_tris, int64_t items_hint, hipStream_t s);
 
+// The paper's Bresenham isovalue of the first min(*n_keys, max_keys) keys.
+hipError_t launch_isovalue(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, const CamSet& cams,
+                           const uint32_t* sils, const uint32_t* keys, const uint32_t* n_keys,
+                           uint32_t max_keys, float* lambda, float* xyz, hipStream_t s);
+
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);
 hipError_t launch_soft_forward(fvv_ctx* ctx, const SoftCamSet& cams, const fvv_grid& g,
