@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-carve leg")
     ap.add_argument("--no-soft", action="store_true", help="skip the soft-hull leg")
     ap.add_argument("--no-mesh", action="store_true", help="skip the marching-cubes leg")
+    ap.add_argument("--no-isovalue", action="store_true",
+                    help="skip the Bresenham-isovalue leg")
     ap.add_argument("--batched-reps", type=int, default=10, help="timed batched-carve launches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a known-size "
@@ -276,6 +278,32 @@ def soft_leg(args, fvv, torch):
                     "pose set-up and the copy of the pose gradients to the host"}
 
 
+def graph_ms(torch, enqueue, reps):
+    """GPU time of the calls enqueue(stream) makes, captured once as a graph
+    on a side stream (so host-side marshalling is not timed) and replayed reps
+    times between HIP events; the first replay is a warm-up."""
+    enqueue()                                    # eager once (warm-up, lazy set-up)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            enqueue(side)
+    torch.cuda.current_stream().wait_stream(side)
+    out = []
+    for r in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        if r > 0:
+            out.append(e0.elapsed_time(e1))
+    del g
+    return out
+
+
 def mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_fine, max_points,
              lat_no_mesh_ms):
     """Marching-cubes triangles of the volleyball frames: (1) the frame graph
@@ -328,21 +356,16 @@ def mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_f
         keys = bufs.keys[int(poff[t]):int(poff[t + 1])]
         nk = torch.tensor([int(poff[t + 1] - poff[t])], dtype=torch.int32, device="cuda")
         calls.append((grid, occ, keys, nk))
-    per_call = []
     bytes_total = 0
-    for rep in range(6):
-        ms = []
+    for grid, occ, keys, nk in calls:
+        ctx.mesh(grid, occ, keys, nk, tris=tris, n_tris=n_t)
+        bytes_total += grid.size + 4 * keys.numel() + 12 * int(n_t.cpu()[0])
+
+    def all_rois(stream=None):
         for grid, occ, keys, nk in calls:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            ctx.mesh(grid, occ, keys, nk, tris=tris, n_tris=n_t)
-            e1.record()
-            ms.append((e0, e1))
-            if rep == 0:
-                bytes_total += grid.size + 4 * keys.numel() + 12 * int(n_t.cpu()[0])
-        torch.cuda.synchronize()
-        if rep > 0:
-            per_call.append(sum(a.elapsed_time(b) for a, b in ms))
+            ctx.mesh(grid, occ, keys, nk, tris=tris, n_tris=n_t, stream=stream)
+
+    per_call = graph_ms(torch, all_rois, reps=6)
     if ctx.check() != fvv.FVV_OK:
         raise RuntimeError("fvv_mesh reported a missing vertex")
     frame_ms = pct(per_call, 50)
@@ -362,7 +385,101 @@ def mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_f
                                           "traffic": None,
                                           "note": "compulsory bytes: 1 B occupancy per sample read, "
                                                   "4 B per key read, 12 B per triangle written; "
-                                                  "six launches per ROI"}},
+                                                  "six launches per ROI, the frame's calls "
+                                                  "captured as one graph"}},
+    }
+
+
+def isovalue_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_fine,
+                 max_points, frame0, exit_points_ms):
+    """The paper's Bresenham isovalue (fvv_isovalue) on every ROI of one
+    volleyball frame, on the frame's own fine occupancy and keys, timed with
+    HIP events around each call, beside the frame's exit-point bisection; and
+    how far lambda lies from the bisection's t* on the same edges."""
+    bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
+    g = ctx.frame_graph(params, sils, bufs, masks=masks[0])
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    K = int(bufs.counts.cpu()[0])
+    jobs = bufs.jobs_host(K)
+    poff = bufs.point_off.cpu().numpy().view(np.uint32)
+    N = frame0.P32.shape[0]
+    calls = []
+    for t in range(K):
+        j = jobs[t]
+        dims = tuple(int(v) for v in j["dims"])
+        grid = fvv.Grid(origin=tuple(j["origin"]), h=j["h"], lo=tuple(int(v) for v in j["lo"]),
+                        dims=dims)
+        o = int(j["out_offset"])
+        keys = bufs.keys[int(poff[t]):int(poff[t + 1])]
+        nk = torch.tensor([keys.numel()], dtype=torch.int32, device="cuda")
+        lam = torch.empty(keys.numel(), dtype=torch.float32, device="cuda")
+        xyz = torch.empty((keys.numel(), 3), dtype=torch.float32, device="cuda")
+        calls.append((grid, bufs.occ_fine[o:o + int(np.prod(dims))], keys, nk, lam, xyz))
+    def all_rois(stream=None):
+        for grid, occ, keys, nk, lam, xyz in calls:
+            ctx.isovalue(grid, occ, frame0.P32, frame0.W, frame0.H, sils, keys, nk, lam=lam,
+                         xyz=xyz, stream=stream)
+
+    per_frame = graph_ms(torch, all_rois, reps=6)
+    # lambda against t* (the bisection's bracket midpoint, from its point)
+    E = int(poff[K])
+    keys_h = bufs.keys[:E].cpu().numpy().view(np.uint32)
+    xyz_h = bufs.xyz[:E].cpu().numpy()
+    lam_h = np.concatenate([c[4].cpu().numpy() for c in calls])
+    diffs = []
+    for t in range(K):
+        j = jobs[t]
+        a, b = int(poff[t]), int(poff[t + 1])
+        k = keys_h[a:b]
+        nx, ny = int(j["dims"][0]), int(j["dims"][1])
+        lin, axis = k // 3, k % 3
+        gi = np.stack([lin % nx, (lin // nx) % ny, lin // (nx * ny)], 1) + np.asarray(j["lo"])
+        occ = calls[t][1].cpu().numpy()
+        on_first = occ[lin] != 0
+        g_on = gi[np.arange(k.size), axis] + np.where(on_first, 0, 1)
+        x_on = np.asarray(j["origin"], np.float64)[axis] + g_on * float(j["h"])
+        tstar = np.abs(xyz_h[a:b][np.arange(k.size), axis] - x_on) / float(j["h"])
+        diffs.append(lam_h[a:b] - tstar)
+    d = np.concatenate(diffs) if diffs else np.zeros(1)
+    # the whole frame with the Bresenham estimator in place of the bisection
+    pb = fvv.frame_params(frame0.P32, frame0.W, frame0.H, coarse, frame0.hc_um, frame0.hf_um,
+                          frame0.t_np, frame0.t_nb, frame0.n_steps,
+                          coarse_tile=fvv.tile(64, 1), fine_tile=params.fine_tile,
+                          exit_estimator=fvv.EXIT_BRESENHAM)
+    gb = [ctx.frame_graph(pb, sils, bufs, masks=m) for m in masks]
+    for gg in gb:
+        gg.launch()
+    torch.cuda.synchronize()
+    if ctx.check() != fvv.FVV_OK:
+        raise RuntimeError("frame with the Bresenham estimator exceeded a capacity")
+    lat_b = []
+    for k in range(max(1, min(args.steps, 100))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gb[k % len(gb)].launch()
+        e1.record()
+        e1.synchronize()
+        lat_b.append(e0.elapsed_time(e1))
+    for gg in gb:
+        gg.close()
+    ms = pct(per_frame, 50)
+    bytes_per_frame = E * (4 + 1 + 16) + E * N * 8
+    achieved = bytes_per_frame / (ms * 1e-3) / 1e9
+    return {
+        "workload": "Bresenham isovalue (Eq. (2)-(3)) of one volleyball frame's crossing edges",
+        "edges": E, "rois": K, "ms_per_frame_p50": ms, "edges_per_s": E / (ms * 1e-3),
+        "exit_points_bisection_stage_ms": exit_points_ms,
+        "frame_latency_ms_bresenham_estimator": {"p50": pct(lat_b, 50), "p99": pct(lat_b, 99)},
+        "lambda_minus_tstar": {"mean": float(d.mean()), "mean_abs": float(np.abs(d).mean()),
+                               "p90_abs": float(np.percentile(np.abs(d), 90))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_frame": int(bytes_per_frame),
+                     "traffic": None,
+                     "note": "per edge 4 B key + 1 B occupancy + 16 B out, per (edge, camera) "
+                             "two 4 B silhouette words (start and one step); one launch per ROI, "
+                             "the frame's calls captured as one graph"},
     }
 
 
@@ -519,6 +636,10 @@ def main():
     if not args.no_mesh:
         result["mesh"] = mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois,
                                   max_fine, max_points, pct(lat_ms, 50))
+    if not args.no_isovalue:
+        result["isovalue"] = isovalue_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
+                                          max_rois, max_fine, max_points, sc0,
+                                          float(np.mean(stage_ms_frame["exit_points"][0])))
     if not args.no_batched:
         result["batched"] = batched_leg(args, fvv, torch)
     if not args.no_soft:

@@ -240,7 +240,13 @@ typedef struct {
     uint32_t t_np, t_nb;
     int32_t n_steps;
     fvv_tile coarse_tile, fine_tile;
+    /* how the exit points are found: FVV_EXIT_BISECTION (n_steps bisection
+     * steps against the occupancy test, as fvv_surface) or FVV_EXIT_BRESENHAM
+     * (the paper's image-space isovalue, as fvv_isovalue) */
+    int32_t exit_estimator;
 } fvv_frame_params;
+#define FVV_EXIT_BISECTION 0
+#define FVV_EXIT_BRESENHAM 1
 
 typedef struct {
     uint8_t *d_occ_coarse;

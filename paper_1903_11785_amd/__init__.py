@@ -30,6 +30,7 @@ FRAME_EVENTS = 7
 STAGES = ("pack", "coarse_carve", "label", "fine_carve", "edges", "exit_points")
 
 FVV_OK, FVV_EINVAL, FVV_ECAPACITY, FVV_EDEVICE, FVV_ENOMEM = 0, -1, -2, -3, -4
+EXIT_BISECTION, EXIT_BRESENHAM = 0, 1
 
 
 class FvvError(RuntimeError):
@@ -79,7 +80,7 @@ class FrameParams(C.Structure):
     _fields_ = [("n_cams", C.c_int32), ("cams", Camera * MAX_CAMS), ("coarse", GridC),
                 ("hc_um", C.c_int64), ("hf_um", C.c_int64), ("t_np", C.c_uint32),
                 ("t_nb", C.c_uint32), ("n_steps", C.c_int32), ("coarse_tile", Tile),
-                ("fine_tile", Tile)]
+                ("fine_tile", Tile), ("exit_estimator", C.c_int32)]
 
 
 class FrameOut(C.Structure):
@@ -447,7 +448,10 @@ class FrameGraph:
 
 def frame_params(P: np.ndarray, W: int, H: int, coarse: Grid, hc_um: int, hf_um: int,
                  t_np: int = 8, t_nb: int = 0xFFFFFFFF, n_steps: int = 8,
-                 coarse_tile: Optional[Tile] = None, fine_tile: Optional[Tile] = None) -> FrameParams:
+                 coarse_tile: Optional[Tile] = None, fine_tile: Optional[Tile] = None,
+                 exit_estimator: int = 0) -> FrameParams:
+    """exit_estimator: EXIT_BISECTION (0) or EXIT_BRESENHAM (1, the paper's
+    image-space isovalue)."""
     p = FrameParams()
     cams = make_cameras(P, W, H)
     p.n_cams = len(cams)
@@ -458,6 +462,7 @@ def frame_params(P: np.ndarray, W: int, H: int, coarse: Grid, hc_um: int, hf_um:
     p.t_np, p.t_nb, p.n_steps = int(t_np), int(t_nb), int(n_steps)
     p.coarse_tile = coarse_tile if coarse_tile is not None else tile(64, 1)
     p.fine_tile = fine_tile if fine_tile is not None else tile(64, 4)
+    p.exit_estimator = int(exit_estimator)
     return p
 
 

@@ -500,7 +500,8 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         !grid_ok(&p->coarse, kMaxIndex) || p->hc_um < 1 || p->hf_um < 1 ||
         p->hc_um > kMaxSpacingUm || p->hf_um > kMaxSpacingUm || p->t_np > p->t_nb ||
         p->n_steps < 1 || p->n_steps > FVV_MAX_STEPS || !tile_ok(&p->coarse_tile) ||
-        !tile_ok(&p->fine_tile))
+        !tile_ok(&p->fine_tile) ||
+        (p->exit_estimator != FVV_EXIT_BISECTION && p->exit_estimator != FVV_EXIT_BRESENHAM))
         return FVV_EINVAL;
     if (!o->d_occ_coarse || !o->d_labels || !o->d_rois || !o->d_jobs || !o->d_occ_fine ||
         !o->d_keys || !o->d_xyz || !o->d_point_off || !o->d_counts || o->max_rois < 1 ||
@@ -603,7 +604,10 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
                               ctx->side);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev_join, ctx->side);
-    if (e == hipSuccess)
+    if (e == hipSuccess && p->exit_estimator == FVV_EXIT_BRESENHAM)
+        e = launch_isovalue_jobs(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, o->d_keys,
+                                 o->d_xyz, o->max_points, stream);
+    else if (e == hipSuccess)
         e = launch_bisect(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, p->n_steps,
                           o->d_keys, o->d_xyz, o->max_points, stream);
     if (e == hipSuccess)

@@ -556,6 +556,12 @@ hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* 
 hipError_t launch_isovalue(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, const CamSet& cams,
                            const uint32_t* sils, const uint32_t* keys, const uint32_t* n_keys,
                            uint32_t max_keys, float* lambda, float* xyz, hipStream_t s);
+// The same for a frame's edges (ROI-major keys, per-job offsets), in place of
+// the bisection: xyz gets the points at lambda.
+hipError_t launch_isovalue_jobs(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+                                const uint32_t* point_off, const CamSet& cams,
+                                const uint32_t* sils, const uint32_t* keys, float* xyz,
+                                uint32_t max_points, hipStream_t s);
 
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);

@@ -193,3 +193,60 @@ def test_invalid_isovalue_arguments(fvv, ctx, scene_cache):
     with pytest.raises(fvv.FvvError) as e:
         ctx.isovalue(good, occ, sc.P32[:0], sc.W, sc.H, sils, keys, nk)      # no camera
     assert e.value.status == fvv.FVV_EINVAL
+
+
+@pytest.mark.parametrize("cfg,frame,graph", [(scenes.CFG_TINY, 0, False), (scenes.CFG_TINY, 1, True),
+                                             (scenes.CFG_VOLLEYBALL, 0, False),
+                                             (scenes.CFG_VOLLEYBALL, 1, True),
+                                             (scenes.CFG_JUDO, 0, False)])
+def test_frame_with_the_bresenham_estimator(fvv, ctx, scene_cache, cfg, frame, graph):
+    """fvv_frame with exit_estimator = EXIT_BRESENHAM: every exit point equals
+    the oracle's isovalue point on the oracle's own fine occupancy and keys
+    (one launch over all ROIs in place of the bisection); as a graph, on
+    every replay."""
+    import torch
+    sc = scene_cache(cfg, frame)
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    hs = oracle.pack(sc.masks)
+    ref = [oracle.isovalue(sc.P32, hs, sc.W, sc.H, lat, occ, keys)[1]
+           for lat, occ, keys in zip(res.fine, res.occ_fine, res.keys)]
+    coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
+    params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
+                              sc.n_steps, exit_estimator=fvv.EXIT_BRESENHAM)
+    bufs = fvv.FrameBuffers(coarse, 256, 1 << 26, 1 << 22)
+    N, H, W = sc.masks.shape
+    sils = torch.zeros((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+    masks = dev(sc.masks)
+    runs = 3 if graph else 1
+    g = ctx.frame_graph(params, sils, bufs, masks=masks) if graph else None
+    for _ in range(runs):
+        bufs.xyz.fill_(-1.0)
+        torch.cuda.synchronize()
+        if graph:
+            g.launch()
+        else:
+            ctx.frame(params, sils, bufs, masks=masks)
+        torch.cuda.synchronize()
+        assert ctx.check() == fvv.FVV_OK
+        poff = bufs.point_off.cpu().numpy().view(np.uint32)
+        xyz = bufs.xyz.cpu().numpy()
+        assert int(bufs.counts.cpu()[3]) == len(ref)
+        for t, r in enumerate(ref):
+            got = xyz[poff[t]:poff[t + 1]]
+            np.testing.assert_array_equal(got.view(np.uint32), r.view(np.uint32))
+    if g is not None:
+        g.close()
+
+
+def test_frame_rejects_an_unknown_estimator(fvv, ctx, scene_cache):
+    import torch
+    sc = scene_cache(scenes.CFG_TINY, 0)
+    coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
+    params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, exit_estimator=2)
+    bufs = fvv.FrameBuffers(coarse, 16, 1 << 22, 1 << 16)
+    N, H, W = sc.masks.shape
+    sils = torch.zeros((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+    with pytest.raises(fvv.FvvError) as e:
+        ctx.frame(params, sils, bufs, masks=dev(sc.masks))
+    assert e.value.status == fvv.FVV_EINVAL
