@@ -67,6 +67,8 @@ def lib():
                                    p]
         L.orc_line_lambda2.argtypes = [p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.orc_line_lambda2.restype = C.c_double
+        L.orc_depth.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, i64, p]
+        L.orc_visibility.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, i64, p, f32, p]
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
         L.orc_threads.restype = i32
@@ -225,6 +227,32 @@ def line_lambda2(sil: np.ndarray, W: int, H: int, p_on, p_off) -> float:
     sil = np.ascontiguousarray(sil, dtype=np.uint32)
     return float(lib().orc_line_lambda2(_p(sil), W, H, int(p_on[0]), int(p_on[1]), int(p_off[0]),
                                         int(p_off[1])))
+
+
+def depth(P, W: int, H: int, xyz: np.ndarray, tris: np.ndarray) -> np.ndarray:
+    """Depth images float32 [N][H][W] of a triangle mesh (Sec. II-D-1, Eq. (4)):
+    per pixel the minimum camera-plane distance of the triangles covering it,
+    +inf where none does."""
+    P = np.ascontiguousarray(P, dtype=np.float32).reshape(-1, 12)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    tris = np.ascontiguousarray(tris, dtype=np.uint32).reshape(-1, 3)
+    out = np.empty((P.shape[0], H, W), np.float32)
+    lib().orc_depth(P.shape[0], _p(P), W, H, _p(xyz), _p(tris), tris.shape[0], _p(out))
+    return out
+
+
+def visibility(P, W: int, H: int, xyz: np.ndarray, tris: np.ndarray, depth_images: np.ndarray,
+               t_v: float) -> np.ndarray:
+    """uint32 [T]: bit c set when triangle m is visible in camera c (Sec.
+    II-D-2: in view, and not farther than the depth image by more than t_v)."""
+    P = np.ascontiguousarray(P, dtype=np.float32).reshape(-1, 12)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    tris = np.ascontiguousarray(tris, dtype=np.uint32).reshape(-1, 3)
+    D = np.ascontiguousarray(depth_images, dtype=np.float32)
+    vis = np.empty(max(tris.shape[0], 1), np.uint32)
+    lib().orc_visibility(P.shape[0], _p(P), W, H, _p(xyz), _p(tris), tris.shape[0], _p(D),
+                         np.float32(t_v), _p(vis))
+    return vis[:tris.shape[0]].copy()
 
 
 def point_inside(P, sils, W, H, X: float, Y: float, Z: float) -> bool:

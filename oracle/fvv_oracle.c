@@ -29,6 +29,10 @@
  *                    from P_on to P_off, the image-space ratio of Eq. (2),
  *                    the minimum over cameras of Eq. (3).
  *   orc_mesh         Sec. II-C: marching-cubes triangles over the cells.
+ *   orc_depth        Sec. II-D-1, Eq. (4): per camera, the minimum over the
+ *                    triangles covering a pixel of their distance.
+ *   orc_visibility   Sec. II-D-2: a triangle is occluded in a camera when its
+ *                    distance exceeds the depth image by more than T_v.
  */
 #include <math.h>
 #include <stdint.h>
@@ -421,7 +425,7 @@ int32_t orc_point_inside(int ncam, const float *P, int W, int H, const uint32_t 
  * is the last pixel before the first one that is background or outside the
  * image, and Eq. (2) gives lambda_i = |P_i - P_on| / |P_off - P_on|; a line
  * that is foreground to its end gives lambda_i = 1, and a camera that sees
- * the OFF end behind it (w <= 0) gives lambda_i = 0.  lambda_i^2 is taken as
+ * either end behind it (w <= 0) gives lambda_i = 0.  lambda_i^2 is taken as
  * the double quotient of the two integer squared lengths; Eq. (3)'s minimum is
  * taken over those, and lambda = (float)sqrt(min).
  */
@@ -515,7 +519,7 @@ void orc_isovalue(int ncam, const float *P, int W, int H, const uint32_t *sils, 
             const float b1 = fmaf(p[6], X[2], fmaf(p[5], X[1], fmaf(p[4], X[0], p[7])));
             const float w1 = fmaf(p[10], X[2], fmaf(p[9], X[1], fmaf(p[8], X[0], p[11])));
             double l2;
-            if (!(w1 > 0.0f))
+            if (!(w0 > 0.0f) || !(w1 > 0.0f))
                 l2 = 0.0;
             else
                 l2 = line_lambda2(sils + (size_t)c * H * wpr, W, H, wpr, far_pixel(a0, w0, W),
@@ -534,6 +538,131 @@ void orc_isovalue(int ncam, const float *P, int W, int H, const uint32_t *sils, 
             for (int a = 0; a < 3; ++a)
                 xyz[3 * e + a] = c3[a];
         }
+    }
+}
+
+/* ------------------------------------------------------------------ depth and visibility
+ *
+ * Sec. II-D.  Readings of what the paper leaves open:
+ *   - a triangle's distance is the camera-plane distance (the projection's
+ *     third row, w) of its centroid G = ((v0 + v1) + v2) / 3, per component
+ *     in fp32: one value per (triangle, camera);
+ *   - the 2-D triangle has the vertices (a/w, b/w) of the three projections
+ *     (IEEE fp32 division); it covers pixel (x, y) when the pixel centre
+ *     (x + 0.5, y + 0.5) lies on the same side of its three edges, i.e. the
+ *     three edge functions (x1 - x0)(py - y0) - (y1 - y0)(px - x0), evaluated
+ *     in fp32 in that order, are all >= 0 or all <= 0; triangles with a vertex
+ *     at w <= 0, or of zero area (the first edge's function at the third
+ *     vertex is 0), cover nothing;
+ *   - Eq. (4): the depth image holds the minimum covering distance, +inf
+ *     where nothing covers the pixel;
+ *   - visibility: the centroid's projection (a_G/w_G, b_G/w_G) falls in pixel
+ *     p (floor of each coordinate); the triangle is visible in the camera when
+ *     w_G > 0, p lies inside the image and d - depth[p] <= T_v (fp32).
+ * Triangles index a vertex array of exit points (xyz).
+ */
+
+/* Projection rows of camera P at X: a, b, w (the occupancy test's order). */
+static void project3(const float *p, const float *X, float *a, float *b, float *w)
+{
+    *a = fmaf(p[2], X[2], fmaf(p[1], X[1], fmaf(p[0], X[0], p[3])));
+    *b = fmaf(p[6], X[2], fmaf(p[5], X[1], fmaf(p[4], X[0], p[7])));
+    *w = fmaf(p[10], X[2], fmaf(p[9], X[1], fmaf(p[8], X[0], p[11])));
+}
+
+/* Camera-plane distance of the triangle's centroid and its projection. */
+static void triangle_centroid(const float *p, const float *xyz, const uint32_t *t, float *u,
+                              float *v, float *w)
+{
+    float G[3], a, b;
+    for (int k = 0; k < 3; ++k)
+        G[k] = ((xyz[3 * (size_t)t[0] + k] + xyz[3 * (size_t)t[1] + k]) +
+                xyz[3 * (size_t)t[2] + k]) / 3.0f;
+    project3(p, G, &a, &b, w);
+    *u = a / *w;
+    *v = b / *w;
+}
+
+static float edge_fn(float x0, float y0, float x1, float y1, float px, float py)
+{
+    return (x1 - x0) * (py - y0) - (y1 - y0) * (px - x0);
+}
+
+void orc_depth(int ncam, const float *P, int W, int H, const float *xyz, const uint32_t *tris,
+               int64_t T, float *depth)
+{
+    const size_t npx = (size_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < ncam; ++c) {
+        float *D = depth + (size_t)c * npx;
+        for (size_t q = 0; q < npx; ++q)
+            D[q] = INFINITY;
+        const float *p = P + 12 * c;
+        for (int64_t m = 0; m < T; ++m) {
+            const uint32_t *t = tris + 3 * m;
+            float u[3], v[3], w[3];
+            int front = 1;
+            for (int k = 0; k < 3; ++k) {
+                float a, b;
+                project3(p, xyz + 3 * (size_t)t[k], &a, &b, &w[k]);
+                if (!(w[k] > 0.0f))
+                    front = 0;
+                u[k] = a / w[k];
+                v[k] = b / w[k];
+            }
+            if (!front)
+                continue;
+            if (edge_fn(u[0], v[0], u[1], v[1], u[2], v[2]) == 0.0f)
+                continue;                       /* zero area */
+            float gu, gv, d;
+            triangle_centroid(p, xyz, t, &gu, &gv, &d);
+            (void)gu;
+            (void)gv;
+            /* pixels whose centres could be inside (the edge test decides) */
+            float lo_u = fminf(u[0], fminf(u[1], u[2])), hi_u = fmaxf(u[0], fmaxf(u[1], u[2]));
+            float lo_v = fminf(v[0], fminf(v[1], v[2])), hi_v = fmaxf(v[0], fmaxf(v[1], v[2]));
+            if (!(hi_u >= 0.0f && hi_v >= 0.0f && lo_u < (float)W && lo_v < (float)H))
+                continue;
+            const int x0 = lo_u < 0.0f ? 0 : (int)lo_u;
+            const int y0 = lo_v < 0.0f ? 0 : (int)lo_v;
+            const int x1 = hi_u >= (float)(W - 1) ? W - 1 : (int)hi_u;
+            const int y1 = hi_v >= (float)(H - 1) ? H - 1 : (int)hi_v;
+            for (int y = y0; y <= y1; ++y)
+                for (int x = x0; x <= x1; ++x) {
+                    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+                    const float e0 = edge_fn(u[0], v[0], u[1], v[1], px, py);
+                    const float e1 = edge_fn(u[1], v[1], u[2], v[2], px, py);
+                    const float e2 = edge_fn(u[2], v[2], u[0], v[0], px, py);
+                    const int in = (e0 >= 0.0f && e1 >= 0.0f && e2 >= 0.0f) ||
+                                   (e0 <= 0.0f && e1 <= 0.0f && e2 <= 0.0f);
+                    if (in && d < D[(size_t)y * W + x])
+                        D[(size_t)y * W + x] = d;
+                }
+        }
+    }
+}
+
+void orc_visibility(int ncam, const float *P, int W, int H, const float *xyz,
+                    const uint32_t *tris, int64_t T, const float *depth, float t_v,
+                    uint32_t *vis)
+{
+    const size_t npx = (size_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < T; ++m) {
+        uint32_t mask = 0;
+        for (int c = 0; c < ncam; ++c) {
+            float u, v, d;
+            triangle_centroid(P + 12 * c, xyz, tris + 3 * m, &u, &v, &d);
+            if (!(d > 0.0f))
+                continue;
+            const float fx = floorf(u), fy = floorf(v);
+            if (!(fx >= 0.0f && fy >= 0.0f && fx < (float)W && fy < (float)H))
+                continue;
+            const float D = depth[(size_t)c * npx + (size_t)fy * W + (size_t)fx];
+            if (d - D <= t_v)
+                mask |= 1u << c;
+        }
+        vis[m] = mask;
     }
 }
 
