@@ -67,8 +67,8 @@ def lib():
                                    p]
         L.orc_line_lambda2.argtypes = [p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.orc_line_lambda2.restype = C.c_double
-        L.orc_depth.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, i64, p]
-        L.orc_visibility.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, i64, p, f32, p]
+        L.orc_depth.argtypes = [C.c_int, p, C.c_int, C.c_int, p, i64, p, i64, p]
+        L.orc_visibility.argtypes = [C.c_int, p, C.c_int, C.c_int, p, i64, p, i64, p, f32, p]
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
         L.orc_threads.restype = i32
@@ -237,7 +237,8 @@ def depth(P, W: int, H: int, xyz: np.ndarray, tris: np.ndarray) -> np.ndarray:
     xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
     tris = np.ascontiguousarray(tris, dtype=np.uint32).reshape(-1, 3)
     out = np.empty((P.shape[0], H, W), np.float32)
-    lib().orc_depth(P.shape[0], _p(P), W, H, _p(xyz), _p(tris), tris.shape[0], _p(out))
+    lib().orc_depth(P.shape[0], _p(P), W, H, _p(xyz), xyz.shape[0], _p(tris), tris.shape[0],
+                    _p(out))
     return out
 
 
@@ -250,8 +251,8 @@ def visibility(P, W: int, H: int, xyz: np.ndarray, tris: np.ndarray, depth_image
     tris = np.ascontiguousarray(tris, dtype=np.uint32).reshape(-1, 3)
     D = np.ascontiguousarray(depth_images, dtype=np.float32)
     vis = np.empty(max(tris.shape[0], 1), np.uint32)
-    lib().orc_visibility(P.shape[0], _p(P), W, H, _p(xyz), _p(tris), tris.shape[0], _p(D),
-                         np.float32(t_v), _p(vis))
+    lib().orc_visibility(P.shape[0], _p(P), W, H, _p(xyz), xyz.shape[0], _p(tris), tris.shape[0],
+                         _p(D), np.float32(t_v), _p(vis))
     return vis[:tris.shape[0]].copy()
 
 

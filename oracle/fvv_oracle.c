@@ -555,7 +555,10 @@ void orc_isovalue(int ncam, const float *P, int W, int H, const uint32_t *sils, 
  *     at w <= 0, or of zero area (the first edge's function at the third
  *     vertex is 0), cover nothing;
  *   - Eq. (4): the depth image holds the minimum covering distance, +inf
- *     where nothing covers the pixel;
+ *     where nothing covers the pixel; a triangle whose centroid distance is
+ *     not positive covers nothing;
+ *   - a triangle naming a vertex past the vertex count (such as the mesh's
+ *     0xffffffff for a missing vertex) covers nothing and is invisible;
  *   - visibility: the centroid's projection (a_G/w_G, b_G/w_G) falls in pixel
  *     p (floor of each coordinate); the triangle is visible in the camera when
  *     w_G > 0, p lies inside the image and d - depth[p] <= T_v (fp32).
@@ -588,8 +591,8 @@ static float edge_fn(float x0, float y0, float x1, float y1, float px, float py)
     return (x1 - x0) * (py - y0) - (y1 - y0) * (px - x0);
 }
 
-void orc_depth(int ncam, const float *P, int W, int H, const float *xyz, const uint32_t *tris,
-               int64_t T, float *depth)
+void orc_depth(int ncam, const float *P, int W, int H, const float *xyz, int64_t n_vertices,
+               const uint32_t *tris, int64_t T, float *depth)
 {
     const size_t npx = (size_t)W * H;
 #pragma omp parallel for schedule(static)
@@ -600,6 +603,8 @@ void orc_depth(int ncam, const float *P, int W, int H, const float *xyz, const u
         const float *p = P + 12 * c;
         for (int64_t m = 0; m < T; ++m) {
             const uint32_t *t = tris + 3 * m;
+            if (t[0] >= n_vertices || t[1] >= n_vertices || t[2] >= n_vertices)
+                continue;
             float u[3], v[3], w[3];
             int front = 1;
             for (int k = 0; k < 3; ++k) {
@@ -618,6 +623,8 @@ void orc_depth(int ncam, const float *P, int W, int H, const float *xyz, const u
             triangle_centroid(p, xyz, t, &gu, &gv, &d);
             (void)gu;
             (void)gv;
+            if (!(d > 0.0f))
+                continue;
             /* pixels whose centres could be inside (the edge test decides) */
             float lo_u = fminf(u[0], fminf(u[1], u[2])), hi_u = fmaxf(u[0], fmaxf(u[1], u[2]));
             float lo_v = fminf(v[0], fminf(v[1], v[2])), hi_v = fmaxf(v[0], fmaxf(v[1], v[2]));
@@ -643,13 +650,18 @@ void orc_depth(int ncam, const float *P, int W, int H, const float *xyz, const u
 }
 
 void orc_visibility(int ncam, const float *P, int W, int H, const float *xyz,
-                    const uint32_t *tris, int64_t T, const float *depth, float t_v,
-                    uint32_t *vis)
+                    int64_t n_vertices, const uint32_t *tris, int64_t T, const float *depth,
+                    float t_v, uint32_t *vis)
 {
     const size_t npx = (size_t)W * H;
 #pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < T; ++m) {
         uint32_t mask = 0;
+        const uint32_t *t = tris + 3 * m;
+        if (t[0] >= n_vertices || t[1] >= n_vertices || t[2] >= n_vertices) {
+            vis[m] = 0;
+            continue;
+        }
         for (int c = 0; c < ncam; ++c) {
             float u, v, d;
             triangle_centroid(P + 12 * c, xyz, tris + 3 * m, &u, &v, &d);

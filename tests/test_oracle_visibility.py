@@ -9,7 +9,8 @@ oracle.visibility; Sec. II-D, Eq. (4)).
     centroid's pixel is covered by the near one and T_v is below the gap, and
     visible when T_v exceeds it (self-occlusion ignored), the near one always;
   - triangles outside the image or behind the camera are invisible and leave
-    no depth; a zero-area triangle leaves no depth;
+    no depth; a zero-area triangle leaves no depth; a triangle naming a
+    vertex past the vertex count is skipped;
   - the depth image does not depend on the order of the triangles;
   - a closed sphere mesh seen from outside: triangles well behind the
     sphere's centre (camera-plane distance beyond it by 0.3 r) are occluded,
@@ -126,6 +127,13 @@ def test_out_of_view_behind_and_degenerate():
     assert np.isinf(D).all()
     vis = oracle.visibility(P, W, H, xyz, tris, D, 0.1)
     assert vis[0] == 0 and vis[1] == 0
+    # a triangle naming a missing vertex (the mesh writes 0xffffffff) is skipped
+    good = tri_at([(10.5, 10.5), (30.5, 12.5), (20.5, 30.5)], 2.0)
+    t2 = np.array([[0, 1, 2], [0, 1, 0xffffffff], [3, 1, 2]], np.uint32)
+    D2 = oracle.depth(P, W, H, good, t2)
+    np.testing.assert_array_equal(D2, oracle.depth(P, W, H, good, t2[:1]))
+    vis2 = oracle.visibility(P, W, H, good, t2, D2, 0.1)
+    assert vis2.tolist() == [1, 0, 0]
 
 
 def sphere_mesh(n=28, r=0.25, h=0.02):
