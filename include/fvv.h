@@ -346,6 +346,38 @@ fvv_status fvv_isovalue(fvv_ctx *ctx, const fvv_grid *grid, const uint8_t *d_occ
                         const uint32_t *d_n_keys, uint32_t max_keys, float *d_lambda,
                         float *d_xyz, hipStream_t stream);
 
+/* Depth images and visibility of a triangle mesh (Sec. II-D, Eq. (4)) in
+ * every camera.  Readings of what the paper leaves open:
+ *   - a triangle's distance is the camera-plane distance (the projection's
+ *     third row, w) of its centroid ((v0 + v1) + v2) / 3 (fp32);
+ *   - it covers pixel (x, y) when the pixel centre (x + 0.5, y + 0.5) lies on
+ *     the same side of the three edges of the projected triangle (vertices
+ *     (a/w, b/w), IEEE fp32 division): the edge functions
+ *     (x1 - x0)(py - y0) - (y1 - y0)(px - x0), in fp32 in that order, all
+ *     >= 0 or all <= 0.  Triangles with a vertex at w <= 0, of zero area (the
+ *     first edge's function at the third vertex is 0), with a non-positive
+ *     centroid distance, or naming a vertex at or past the vertex count (the
+ *     mesh's 0xffffffff) cover nothing;
+ *   - Eq. (4): a pixel's depth is the minimum distance of the triangles
+ *     covering it, +inf where none does;
+ *   - a triangle is visible in camera c when its centroid's distance is
+ *     positive, the centroid projects into pixel (floor(a/w), floor(b/w))
+ *     inside the image, and distance - depth there <= t_v (fp32).
+ *   d_xyz:   vertices, float [max_vertices][3] (e.g. the exit points), the
+ *            first min(*d_n_vertices, max_vertices) valid (*d_n_vertices
+ *            device);
+ *   d_tris:  uint32 [max_tris][3] vertex indices (fvv_mesh's output), the
+ *            first min(*d_n_tris, max_tris) used;
+ *   d_depth: out, float [n_cams][H][W], every pixel written;
+ *   d_vis:   out, uint32 [max_tris]: bit c set when the triangle is visible in
+ *            camera c (the first min(*d_n_tris, max_tris) written).
+ * EINVAL on NULL pointers, zero capacities, an invalid camera set or a
+ * non-finite t_v.  No context scratch is used. */
+fvv_status fvv_visibility(fvv_ctx *ctx, int32_t n_cams, const fvv_camera *cams,
+                          const float *d_xyz, const uint32_t *d_n_vertices, uint32_t max_vertices,
+                          const uint32_t *d_tris, const uint32_t *d_n_tris, uint32_t max_tris,
+                          float t_v, float *d_depth, uint32_t *d_vis, hipStream_t stream);
+
 /* ---------------------------------------------------------------- soft hull
  * A differentiable relative of the binary hull of Sec. II-B-1 (not in the
  * paper), for refining silhouette logits and camera poses by gradient descent.

@@ -138,6 +138,8 @@ def _load():
         "fvv_mesh": ([P, C.POINTER(GridC), P, P, P, u32, P, u32, P, P], i32),
         "fvv_isovalue": ([P, C.POINTER(GridC), P, i32, C.POINTER(Camera), P, P, P, u32, P, P, P],
                          i32),
+        "fvv_visibility": ([P, i32, C.POINTER(Camera), P, P, u32, P, P, u32, C.c_float, P, P, P],
+                           i32),
         "fvv_soft_forward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P, P,
                               P], i32),
         "fvv_soft_backward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P,
@@ -392,6 +394,23 @@ class Context:
                                 _ptr(keys), _ptr(n_keys), m, _ptr(lam), _ptr(xyz),
                                 C.c_void_p(_stream(stream))), "fvv_isovalue")
         return lam, xyz
+
+    def visibility(self, P: np.ndarray, W: int, H: int, xyz, n_vertices, tris, n_tris,
+                   t_v: float, depth=None, vis=None, stream=None):
+        """Depth images float [N][H][W] and per-triangle visibility masks (bit c:
+        visible in camera c) of the mesh (xyz vertices, tris indices; the
+        counts are device int32 tensors of one element)."""
+        import torch
+        cams = make_cameras(P, W, H)
+        if depth is None:
+            depth = torch.empty((len(cams), H, W), dtype=torch.float32, device=xyz.device)
+        if vis is None:
+            vis = torch.empty(tris.shape[0], dtype=torch.int32, device=xyz.device)
+        _ok(self.L.fvv_visibility(self.h, len(cams), cams, _ptr(xyz), _ptr(n_vertices),
+                                  int(xyz.shape[0]), _ptr(tris), _ptr(n_tris), int(tris.shape[0]),
+                                  float(t_v), _ptr(depth), _ptr(vis),
+                                  C.c_void_p(_stream(stream))), "fvv_visibility")
+        return depth, vis
 
     def soft_forward(self, grid: Grid, cams, W: int, H: int, logits, target=None, occ=None,
                      loss=None, stream=None):

@@ -462,6 +462,18 @@ fvv_status fvv_isovalue(fvv_ctx* ctx, const fvv_grid* grid, const uint8_t* d_occ
                                d_xyz, stream));
 }
 
+fvv_status fvv_visibility(fvv_ctx* ctx, int32_t n_cams, const fvv_camera* cams,
+                          const float* d_xyz, const uint32_t* d_n_vertices, uint32_t max_vertices,
+                          const uint32_t* d_tris, const uint32_t* d_n_tris, uint32_t max_tris,
+                          float t_v, float* d_depth, uint32_t* d_vis, hipStream_t stream) {
+    if (!ctx || !d_xyz || !d_n_vertices || !d_tris || !d_n_tris || !d_depth || !d_vis ||
+        max_vertices < 1 || max_tris < 1 || !isfinite(t_v) || !cams_ok(ctx, n_cams, cams))
+        return FVV_EINVAL;
+    const CamSet cs = make_camset(n_cams, cams);
+    return dev(launch_visibility(ctx, cs, d_xyz, d_n_vertices, max_vertices, d_tris, d_n_tris,
+                                 max_tris, t_v, d_depth, d_vis, stream));
+}
+
 // ------------------------------------------------------------------ soft hull
 fvv_status fvv_soft_forward(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams,
                             const fvv_soft_camera* cams, int32_t width, int32_t height,

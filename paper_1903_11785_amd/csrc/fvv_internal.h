@@ -563,6 +563,13 @@ hipError_t launch_isovalue_jobs(fvv_ctx* ctx, const fvv_job* jobs, const uint32_
                                 const uint32_t* sils, const uint32_t* keys, float* xyz,
                                 uint32_t max_points, hipStream_t s);
 
+// Depth images (cleared, then the triangles' minimum distances) and the
+// triangles' visibility masks.
+hipError_t launch_visibility(fvv_ctx* ctx, const CamSet& cams, const float* xyz,
+                             const uint32_t* n_vert, uint32_t max_vert, const uint32_t* tris,
+                             const uint32_t* n_tris, uint32_t max_tris, float t_v, float* depth,
+                             uint32_t* vis, hipStream_t s);
+
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);
 hipError_t launch_soft_forward(fvv_ctx* ctx, const SoftCamSet& cams, const fvv_grid& g,
