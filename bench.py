@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-mesh", action="store_true", help="skip the marching-cubes leg")
     ap.add_argument("--no-isovalue", action="store_true",
                     help="skip the Bresenham-isovalue leg")
+    ap.add_argument("--no-visibility", action="store_true",
+                    help="skip the depth-image and visibility leg")
     ap.add_argument("--batched-reps", type=int, default=10, help="timed batched-carve launches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a known-size "
@@ -483,6 +485,53 @@ def isovalue_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, m
     }
 
 
+def visibility_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_fine,
+                   max_points, frame0, t_v=0.1):
+    """Depth images and visibility (Sec. II-D) of one volleyball frame's mesh
+    (the frame's exit points and marching-cubes triangles) in its cameras,
+    the call captured as a graph and replayed between HIP events."""
+    bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points, max_tris=1 << 22)
+    g = ctx.frame_graph(params, sils, bufs, masks=masks[0])
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    K = int(bufs.counts.cpu()[0])
+    n_t = bufs.tri_off[K:K + 1]
+    n_p = bufs.counts[2:3]
+    N = frame0.P32.shape[0]
+    depth = torch.empty((N, frame0.H, frame0.W), dtype=torch.float32, device="cuda")
+    vis = torch.empty(bufs.tris.shape[0], dtype=torch.int32, device="cuda")
+
+    def call(stream=None):
+        ctx.visibility(frame0.P32, frame0.W, frame0.H, bufs.xyz, n_p, bufs.tris, n_t, t_v,
+                       depth=depth, vis=vis, stream=stream)
+
+    ms_all = graph_ms(torch, call, reps=8)
+    if ctx.check() != fvv.FVV_OK:
+        raise RuntimeError("visibility leg reported an error")
+    T = int(n_t.cpu()[0])
+    covered = int(torch.isfinite(depth).sum())
+    v = vis[:T].cpu().numpy().view(np.uint32)
+    seen = np.unpackbits(v.view(np.uint8)).reshape(-1, 32).sum(1) if T else np.zeros(1)
+    ms = pct(ms_all, 50)
+    px = N * frame0.W * frame0.H
+    bytes_ = 4 * px + 4 * covered + T * (12 + 36 + 4 + 4 * N)
+    achieved = bytes_ / (ms * 1e-3) / 1e9
+    return {
+        "workload": "depth images (Eq. (4)) and visibility of one volleyball frame's mesh in its "
+                    "16 cameras at 1920x1080, T_v = 0.1 m",
+        "triangles": T, "cameras": N, "covered_pixels": covered,
+        "ms_per_frame_p50": ms, "triangle_cameras_per_s": T * N / (ms * 1e-3),
+        "cameras_seeing_a_triangle_mean": float(seen.mean()),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_frame": int(bytes_),
+                     "traffic": None,
+                     "note": "4 B per depth pixel cleared, 4 B per covered pixel written, per "
+                             "triangle 12 B indices + 36 B vertices + 4 B mask + 4 B of depth "
+                             "per camera; three kernels"},
+    }
+
+
 def soft_cpu_baseline():
     """The soft-hull oracle (float64 PyTorch CPU: forward + autograd) on the
     same scene, timed once."""
@@ -640,6 +689,9 @@ def main():
         result["isovalue"] = isovalue_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                           max_rois, max_fine, max_points, sc0,
                                           float(np.mean(stage_ms_frame["exit_points"][0])))
+    if not args.no_visibility:
+        result["visibility"] = visibility_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
+                                              max_rois, max_fine, max_points, sc0)
     if not args.no_batched:
         result["batched"] = batched_leg(args, fvv, torch)
     if not args.no_soft:
