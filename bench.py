@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-baseline time budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fine-tile", default="64x4", help="TXxTZ of the fine carve")
+    ap.add_argument("--coarse-tile", default="64x1",
+                    help="TXxTZ of the coarse carve (depth 4 culls cameras per tile, which at "
+                         "coarse spacings costs more than it saves)")
     ap.add_argument("--in-flight", type=int, default=2,
                     help="frames in flight for the throughput figure (one context, buffer set "
                          "and stream each); latency is measured one frame at a time")
@@ -95,6 +98,12 @@ BATCHED_KERNEL = {"kernel": "carve_batched_culled_kernel",
                               "paper_1903_11785_amd/csrc/fvv_internal.h"],
                   "traffic": "profiles/carve_batched_culled_kernel_batched_traffic.json",
                   "tile": [16, 16, 4]}
+
+
+VIS_KERNELS = {"kernel": "depth_clear_kernel + depth_raster_kernel + visibility_kernel",
+               "sources": ["paper_1903_11785_amd/csrc/visibility.hip",
+                           "paper_1903_11785_amd/csrc/fvv_internal.h"],
+               "traffic": "profiles/visibility_volleyball_traffic.json"}
 
 
 def stored_traffic(k):
@@ -448,7 +457,7 @@ def isovalue_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, m
     # the whole frame with the Bresenham estimator in place of the bisection
     pb = fvv.frame_params(frame0.P32, frame0.W, frame0.H, coarse, frame0.hc_um, frame0.hf_um,
                           frame0.t_np, frame0.t_nb, frame0.n_steps,
-                          coarse_tile=fvv.tile(64, 1), fine_tile=params.fine_tile,
+                          coarse_tile=params.coarse_tile, fine_tile=params.fine_tile,
                           exit_estimator=fvv.EXIT_BRESENHAM)
     gb = [ctx.frame_graph(pb, sils, bufs, masks=m) for m in masks]
     for gg in gb:
@@ -525,7 +534,7 @@ def visibility_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois,
         "cameras_seeing_a_triangle_mean": float(seen.mean()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "bytes_per_frame": int(bytes_),
-                     "traffic": None,
+                     "traffic": stored_traffic(VIS_KERNELS),
                      "note": "4 B per depth pixel cleared, 4 B per covered pixel written, per "
                              "triangle 12 B indices + 36 B vertices + 4 B mask + 4 B of depth "
                              "per camera; three kernels"},
@@ -568,8 +577,10 @@ def main():
     ctx = fvv.Context(max_cams=N, max_w=W, max_h=H, max_coarse=coarse.size, max_fine=max_fine,
                       max_rois=max_rois, max_points=max_points, max_jobs=max_rois)
     tx, tz = (int(v) for v in args.fine_tile.split("x"))
+    ctx_, ctz = (int(v) for v in args.coarse_tile.split("x"))
     params = fvv.frame_params(sc0.P32, W, H, coarse, sc0.hc_um, sc0.hf_um, sc0.t_np, sc0.t_nb,
-                              sc0.n_steps, coarse_tile=fvv.tile(64, 1), fine_tile=fvv.tile(tx, tz))
+                              sc0.n_steps, coarse_tile=fvv.tile(ctx_, ctz),
+                              fine_tile=fvv.tile(tx, tz))
     masks = [torch.from_numpy(sc.masks).cuda() for sc in frames]
     sils = torch.empty((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
     bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
@@ -673,7 +684,7 @@ def main():
                    "rois_per_frame_mean": float(np.mean(rois)),
                    "fine_voxels_per_frame_mean": float(np.mean(fine_vox)),
                    "surface_points_per_frame_mean": float(np.mean(points)),
-                   "fine_tile": [tx, 256 // tx, tz]},
+                   "fine_tile": [tx, 256 // tx, tz], "coarse_tile": [ctx_, 256 // ctx_, ctz]},
         "in_flight": n_slots,
         "value_one_frame_at_a_time": total_fine / wall_seq,
         "latency_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99), "mean": float(np.mean(lat_ms))},

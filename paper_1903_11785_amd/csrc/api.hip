@@ -339,7 +339,7 @@ fvv_status fvv_carve(fvv_ctx* ctx, int32_t n_cams, const fvv_camera* cams, const
     if (!ctx || !d_sils || !d_occ || !cams_ok(ctx, n_cams, cams) || !grid_ok(grid, kMaxIndex) ||
         !tile_ok(tile))
         return FVV_EINVAL;
-    const CamSet cs = make_camset(n_cams, cams);
+    const CamSet cs = make_camset(n_cams, cams, grid);   // pads over the lattice's box
     return dev(launch_carve(cs, d_sils, *grid, tile_of(tile), d_occ, nullptr, stream));
 }
 

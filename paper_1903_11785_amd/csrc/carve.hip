@@ -618,7 +618,9 @@ __device__ __forceinline__ void classify_tile(const Cams& cams, const uint32_t* 
 // One culled tile (first sample i0, j0, k0).  tile_off (uniform): a camera
 // rejects the whole tile, which
 // is written as zeros with no other work; tile_mixed: the cameras left to
-// classify per sub-block (cameras outside it accept the whole tile).  Every
+// classify per sub-block (cameras outside it accept the whole tile).  rb:
+// nothing (words null), a fine bitmap (rows of whole words written), or the
+// labelling's row bitmap (rowmask set: bits ORed in, rows marked).  Every
 // LDS read of a tile happens before its last barrier except the s_occ reads
 // of the output pass, and the next tile writes s_occ only after two barriers,
 // so consecutive tiles need no barrier between them.
@@ -703,7 +705,7 @@ __device__ __forceinline__ void carve_tile_culled(const Cams& cams,
     const int i = i0 + lx, j = j0 + ly;
     const bool vxy = i < g.dims[0] && j < g.dims[1];
     uint8_t* const o = out + ((uint64_t)k0 * plane + (uint64_t)j * (uint64_t)g.dims[0] + i);
-    if (tile_off && !rb.words) {
+    if (tile_off && (!rb.words || rb.rowmask)) {   // zeros; a label bitmap gets no bits
         const int nzr = min(TZ, g.dims[2] - k0);
         if (vxy)
             for (int rr = 0; rr < nzr; ++rr)
@@ -722,15 +724,51 @@ __device__ __forceinline__ void carve_tile_culled(const Cams& cams,
         const int q = lane_id() / TX;
         const uint64_t bits = TX == 64 ? m : (m >> (q * TX)) & ((1ull << (TX & 63)) - 1);
         if (rb.words && lx == 0 && j < g.dims[1] && k < g.dims[2]) {
-            uint64_t* word = rb.words + ((int64_t)j + (int64_t)g.dims[1] * k) * rb.wr + (i0 >> 6);
-            if (TX == 64)
+            const int64_t row = (int64_t)j + (int64_t)g.dims[1] * k;
+            uint64_t* word = rb.words + row * rb.wr + (i0 >> 6);
+            if (rb.rowmask) {
+                // the labelling's row bitmap (all-zero before the carve): OR in
+                // the set bits and mark the row
+                if (bits) {
+                    atomicOr((unsigned long long*)word, (unsigned long long)(bits << (i0 & 63)));
+                    atomicOr((unsigned long long*)&rb.rowmask[row >> 6], 1ull << (row & 63));
+                }
+            } else if (TX == 64) {
                 *word = bits;
-            else if (TX == 32)
+            } else if (TX == 32) {
                 reinterpret_cast<uint32_t*>(word)[(i0 >> 5) & 1] = (uint32_t)bits;
-            else
+            } else {
                 reinterpret_cast<uint16_t*>(word)[(i0 >> 4) & 3] = (uint16_t)bits;
+            }
         }
     }
+}
+
+// One lattice with camera culling (tiles of depth 4): one tile per workgroup,
+// the whole-tile classification by the first wave, then the sub-block culling
+// of carve_tile_culled.  The camera set's rounding pads must hold over the
+// lattice's box (infinite pads leave every camera mixed).
+template <int TX>
+__global__ __launch_bounds__(kBlock) void carve_culled_kernel(const CamSet cams,
+                                                              const uint32_t* __restrict__ sils,
+                                                              const fvv_grid g,
+                                                              uint8_t* __restrict__ occ,
+                                                              const RowBits rb) {
+    __shared__ uint32_t s_cls[2];
+    int i0, j0, k0;
+    tile_origin<TX>(g, blockIdx.x, i0, j0, k0);
+    if (threadIdx.x < kWave) {
+        uint32_t rej, mix;
+        classify_tile<TX>(cams, sils, g, i0, j0, k0, rej, mix);
+        if (threadIdx.x == 0) {
+            s_cls[0] = rej;
+            s_cls[1] = mix;
+        }
+    }
+    __syncthreads();
+    const uint32_t rej = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_cls[0]);
+    const uint32_t mix = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_cls[1]);
+    carve_tile_culled<TX>(cams, sils, g, i0, j0, k0, occ, rb, rej != 0, mix);
 }
 
 // The fine carve of a frame: a static, XCD-aware partition of the tiles of
@@ -908,6 +946,19 @@ hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid
     if (tiles > 0x7fffffffull)
         return hipErrorInvalidValue;
     const RowBits rb = rows ? *rows : RowBits{};
+    if (t.tz == 4) {                      // camera culling per tile and per 4x4x4 sub-block
+#define X(TXV)                                                                                \
+        if (t.tx == TXV) {                                                                    \
+            hipLaunchKernelGGL((carve_culled_kernel<TXV>), dim3((unsigned)tiles), dim3(kBlock), \
+                               0, s, cams, sils, g, occ, rb);                                 \
+            return hipGetLastError();                                                         \
+        }
+        X(64)
+        X(32)
+        X(16)
+#undef X
+        return hipErrorInvalidValue;
+    }
 #define X(TXV, TZV)                                                                           \
     if (t.tx == TXV && t.tz == TZV) {                                                         \
         if (rows)                                                                             \
