@@ -28,8 +28,43 @@ def fvv():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("fvv_carve", "fvv_label", "fvv_surface", "fvv_roi_grids", "fvv_carve_batched",
-                 "fvv_frame", "fvv_pack_silhouettes"):
+                 "fvv_frame", "fvv_pack_silhouettes", "fvv_mesh", "fvv_isovalue",
+                 "fvv_visibility", "fvv_soft_forward", "fvv_soft_backward"):
         assert must in names
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the
+    C compiler gives the header's structs (host-only compile of a probe)."""
+    import ctypes as C
+    import json
+    import shutil
+    import subprocess
+    import paper_1903_11785_amd as fvv
+    cxx = "/opt/rocm/bin/amdclang++"
+    if not os.path.exists(cxx):
+        cxx = shutil.which("hipcc")
+    assert cxx, "no HIP host compiler"
+    exe = tmp_path / "abi_layout"
+    subprocess.check_call([cxx, "-x", "hip", "--cuda-host-only", "-std=c++17",
+                           f"-I{os.path.join(ROOT, 'include')}",
+                           os.path.join(ROOT, "tests", "abi_layout.cpp"), "-o", str(exe)])
+    got = json.loads(subprocess.check_output([str(exe)]).decode())
+    structs = {"fvv_camera": fvv.Camera, "fvv_grid": fvv.GridC, "fvv_roi": fvv.Roi,
+               "fvv_job": fvv.Job, "fvv_limits": fvv.Limits, "fvv_tile": fvv.Tile,
+               "fvv_frame_params": fvv.FrameParams, "fvv_frame_out": fvv.FrameOut,
+               "fvv_soft_camera": fvv.SoftCamera}
+    checked = 0
+    for key, value in got.items():
+        if key == "end":
+            continue
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(structs[t], f).offset == value, key
+        else:
+            assert C.sizeof(structs[key]) == value, key
+        checked += 1
+    assert checked > 40
 
 
 def test_library_exports_every_declared_symbol(fvv):
