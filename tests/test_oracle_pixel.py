@@ -77,7 +77,7 @@ def test_lattice_size_matches_printed_counts():
     n = int(np.prod(dims))
     assert n == 23_328_000
     assert round(n / 1e7, 1) == sp["voxels_tested_printed"] / 1e7
-    # dense/sparse occupancy ratio printed as "around 15-fold": (50/20)^3 = 15.6
+    # the paper gives the dense/sparse occupancy ratio as about 15: (50/20)^3 = 15.6
     dn = g["dense_hull"]
     assert abs((sp["voxel_um"] / dn["voxel_um"]) ** 3 - dn["occupied_ratio_printed"]) < 1.0
     assert abs(dn["voxels_occupied_printed"] / sp["voxels_occupied_printed"] - dn["occupied_ratio_printed"]) < 1.0
