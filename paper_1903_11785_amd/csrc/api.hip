@@ -547,7 +547,10 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     const CamSet cs = make_camset(p->n_cams, p->cams, &wide);
     const float h_fine = (float)((double)p->hf_um * 1e-6);
     const TileShape ct = tile_of(&p->coarse_tile), ft = tile_of(&p->fine_tile);
-    const int blocks = persistent_blocks(ctx, &p->fine_tile);
+    // the fine carve's workgroups: the tile's count, else 16 per CU (a frame's
+    // ~3e3 tiles as single-tile workgroups; measured faster than 8 or 24 per CU)
+    const int blocks = p->fine_tile.persistent_blocks > 0 ? p->fine_tile.persistent_blocks
+                                                          : ctx->n_cus * 16;
     auto mark = [&](int i) {
         if (events)
             (void)hipEventRecord(events[i], stream);
