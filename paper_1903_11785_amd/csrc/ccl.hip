@@ -130,6 +130,91 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         dcams[c] = cam;
     }
     const uint32_t K = K_all < max_rois ? K_all : max_rois;
+    auto fine_lattice = [&](uint32_t t, fvv_grid& fg) -> int64_t {
+        int32_t lo[3], hi[3];
+        box(t, lo, hi);
+        int64_t V = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t A = (int64_t)fj.coarse.lo[a] + lo[a] - 1;
+            const int64_t B = (int64_t)fj.coarse.lo[a] + hi[a] + 1;
+            int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um);
+            int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um);
+            const int64_t fmin = ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um);
+            const int64_t fmax = floor_div_pos(
+                ((int64_t)fj.coarse.lo[a] + fj.coarse.dims[a] - 1) * fj.hc_um, fj.hf_um);
+            f0 = f0 < fmin ? fmin : f0;
+            f1 = f1 > fmax ? fmax : f1;
+            fg.origin[a] = fj.coarse.origin[a];
+            fg.lo[a] = (int32_t)f0;
+            fg.dims[a] = (int32_t)(f1 - f0 + 1);
+            V *= (f1 - f0 + 1);
+        }
+        fg.h = fj.h_fine;
+        return V;
+    };
+    auto write_job = [&](uint32_t t, const fvv_grid& fg, uint64_t off) {
+        fvv_job j;
+        j.grid = fg;
+        j.cam_base = 0;
+        j.n_cams = fj.cams.n;
+        j.width = fj.cams.W;
+        j.height = fj.cams.H;
+        j.sil_base = 0;
+        j.out_offset = (int64_t)off;
+        fj.jobs[t] = j;
+    };
+    auto finish = [&](uint32_t n, uint64_t vox, uint64_t tiles, uint64_t items) {
+        pre[n].tile_off = tiles;
+        pre[n].item_off = (uint32_t)items;
+        fj.counts[0] = K_all;
+        fj.counts[1] = (uint32_t)(vox > 0xffffffffull ? 0xffffffffull : vox);
+        fj.counts[3] = n;
+        counter[0] = 0;
+        counter[1] = grab_size(tiles, fj.blocks);
+        counter[2] = n;
+        if (n < K_all)
+            atomicOr(status, kFlagCapacity);
+    };
+    if (K <= (uint32_t)kWave) {
+        // one wave's worth of ROIs (a frame's usual case): the layout in the
+        // first wave with wave scans, no workgroup barriers
+        if (threadIdx.x < kWave) {
+            const uint32_t t = threadIdx.x;
+            fvv_grid fg{};
+            const int64_t V = t < K ? fine_lattice(t, fg) : 0;
+            const uint64_t words = t < K ? (uint64_t)fine_bitmap_words(fg) : 0;
+            const uint64_t inc_v = wave_inclusive_sum64((uint64_t)V);
+            const uint64_t inc_b = wave_inclusive_sum64(words);
+            const uint64_t off = inc_v - (uint64_t)V, boff = inc_b - words;
+            // the carried ROIs are the prefix before the first one that does not fit
+            const bool bad = t < K && (off + (uint64_t)V > (uint64_t)fj.max_fine ||
+                                       V > kMaxKeyedSamples || boff + words > (uint64_t)fj.bit_cap);
+            const uint64_t bad_lanes = __ballot(bad);
+            const uint32_t n = bad_lanes ? (uint32_t)(__ffsll((unsigned long long)bad_lanes) - 1) : K;
+            const bool fits = t < n;
+            const uint64_t tiles = fits ? tiles_of_grid(fg, fj.tile_x, fj.tile_z) : 0;
+            const uint64_t items = fits ? (words + kEdgeWords - 1) / kEdgeWords : 0;
+            const uint64_t inc_t = wave_inclusive_sum64(tiles);
+            const uint64_t inc_i = wave_inclusive_sum64(items);
+            if (fits) {
+                write_job(t, fg, off);
+                pre[t].tile_off = inc_t - tiles;
+                pre[t].bit_off = boff;
+                pre[t].item_off = (uint32_t)(inc_i - items);
+            }
+            auto lane64 = [](uint64_t v, int l) {
+                return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l)
+                        << 32) |
+                       (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+            };
+            const uint64_t vox = n ? lane64(inc_v, (int)n - 1) : 0;
+            const uint64_t all_t = lane64(inc_t, kWave - 1), all_i = lane64(inc_i, kWave - 1);
+            if (t == 0)
+                finish(n, vox, all_t, all_i);
+        }
+        return;
+    }
     if (threadIdx.x == 0) {
         c_vox = c_bits = c_tiles = c_items = 0;
         e_vox = e_tiles = e_items = 0;
@@ -138,30 +223,8 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
     __syncthreads();
     for (uint32_t base = 0; base < K; base += NT) {
         const uint32_t t = base + threadIdx.x;
-        fvv_grid fg;
-        int64_t V = 0;
-        if (t < K) {
-            int32_t lo[3], hi[3];
-            box(t, lo, hi);
-            V = 1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int64_t A = (int64_t)fj.coarse.lo[a] + lo[a] - 1;
-                const int64_t B = (int64_t)fj.coarse.lo[a] + hi[a] + 1;
-                int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um);
-                int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um);
-                const int64_t fmin = ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um);
-                const int64_t fmax = floor_div_pos(
-                    ((int64_t)fj.coarse.lo[a] + fj.coarse.dims[a] - 1) * fj.hc_um, fj.hf_um);
-                f0 = f0 < fmin ? fmin : f0;
-                f1 = f1 > fmax ? fmax : f1;
-                fg.origin[a] = fj.coarse.origin[a];
-                fg.lo[a] = (int32_t)f0;
-                fg.dims[a] = (int32_t)(f1 - f0 + 1);
-                V *= (f1 - f0 + 1);
-            }
-            fg.h = fj.h_fine;
-        }
+        fvv_grid fg{};
+        const int64_t V = t < K ? fine_lattice(t, fg) : 0;
         const uint64_t words = t < K ? (uint64_t)fine_bitmap_words(fg) : 0;
         uint64_t tot_v, tot_b;
         const uint64_t ex_v = block_exclusive_sum64<NT>((uint64_t)V, scratch, &tot_v);
@@ -181,15 +244,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         const uint64_t ex_t = block_exclusive_sum64<NT>(tiles, scratch, &tot_t);
         const uint64_t ex_i = block_exclusive_sum64<NT>(items, scratch, &tot_i);
         if (fits) {
-            fvv_job j;
-            j.grid = fg;
-            j.cam_base = 0;
-            j.n_cams = fj.cams.n;
-            j.width = fj.cams.W;
-            j.height = fj.cams.H;
-            j.sil_base = 0;
-            j.out_offset = (int64_t)off;
-            fj.jobs[t] = j;
+            write_job(t, fg, off);
             pre[t].tile_off = c_tiles + ex_t;
             pre[t].bit_off = boff;
             pre[t].item_off = (uint32_t)(c_items + ex_i);
@@ -210,19 +265,8 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         if (n < base + NT)
             break;
     }
-    if (threadIdx.x == 0) {
-        const uint32_t n = carried;
-        pre[n].tile_off = e_tiles;
-        pre[n].item_off = (uint32_t)e_items;
-        fj.counts[0] = K_all;
-        fj.counts[1] = (uint32_t)(e_vox > 0xffffffffull ? 0xffffffffull : e_vox);
-        fj.counts[3] = n;
-        counter[0] = 0;
-        counter[1] = grab_size(e_tiles, fj.blocks);
-        counter[2] = n;
-        if (n < K_all)
-            atomicOr(status, kFlagCapacity);
-    }
+    if (threadIdx.x == 0)
+        finish(carried, e_vox, e_tiles, e_items);
 }
 
 // ------------------------------------------------------------------ run labelling

@@ -483,6 +483,37 @@ def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
     compare_frame(fvv, sc, bufs, res)
 
 
+def many_balls_scene():
+    """72 separate balls (r = 0.1 m, 6 x 6 x 2 on a 0.55 m grid) seen by 8 cameras of
+    the tiny ring: 72 ROIs, more than one wave's worth for the fine-job layout."""
+    rig = scenes.tiny_rig(8)
+    ells = [scenes.Ellipsoid(center=np.array([(i - 2.5) * 0.55, (j - 2.5) * 0.55, z]),
+                             Q=np.eye(3), axes=np.full(3, 0.1))
+            for i in range(6) for j in range(6) for z in (-0.45, 0.45)]
+    lo, hi = np.array([-2.0, -2.0, -1.0]), np.array([2.0, 2.0, 1.0])
+    return scenes.Scene(name="many", cfg=0, frame=0, cams=rig, masks=scenes.render_masks(rig, ells),
+                        ellipsoids=ells, vol_lo=lo, vol_hi=hi, origin=lo.astype(np.float32),
+                        hc_um=62500, hf_um=20000, coarse_dims=(64, 64, 32))
+
+
+def test_frame_with_more_rois_than_a_wave(fvv, ctx):
+    sc = many_balls_scene()
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    assert len(res.rois) == 72
+    _, bufs, _ = run_frame(fvv, ctx, sc)
+    assert ctx.check() == fvv.FVV_OK
+    compare_frame(fvv, sc, bufs, res)
+    # fewer ROI slots than components: the first ones carried, the flag set
+    _, bufs, _ = run_frame(fvv, ctx, sc, max_rois=60)
+    counts = host(bufs.counts)
+    assert int(counts[0]) == 72 and int(counts[3]) == 60
+    jobs = bufs.jobs_host(60)
+    for t in range(60):
+        assert tuple(jobs[t]["lo"]) == res.fine[t].lo and tuple(jobs[t]["dims"]) == res.fine[t].dims
+    assert ctx.check() == fvv.FVV_ECAPACITY
+
+
 _frame_oracle = {}
 
 
