@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--stage-reps", type=int, default=20, help="eager runs per frame for the stage split")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-baseline time budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds-one-core", type=float, default=6.0,
+                    help="budget of the oracle timed on one host thread (0 skips it)")
+    ap.add_argument("--no-gather", action="store_true", help="skip the gather-ceiling leg")
+    ap.add_argument("--no-h2d", action="store_true",
+                    help="skip the frame latency that includes the silhouettes' host copy")
     ap.add_argument("--fine-tile", default="64x4", help="TXxTZ of the fine carve")
     ap.add_argument("--coarse-tile", default="64x1",
                     help="TXxTZ of the coarse carve (depth 4 culls cameras per tile, which at "
@@ -125,6 +130,103 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, np.float64), q))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_one_core(frames, budget_s):
+    """The oracle on one host thread, on the same frames, until the budget is spent."""
+    import oracle
+    prev = oracle.set_threads(1)
+    try:
+        done_vox, spent, n = 0, 0.0, 0
+        while spent < budget_s and n < 200:
+            sc = frames[n % len(frames)]
+            t0 = time.perf_counter()
+            r = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims,
+                             sc.t_np, sc.t_nb, sc.n_steps)
+            spent += time.perf_counter() - t0
+            done_vox += r.fine_voxels
+            n += 1
+        cores = oracle.threads()
+    finally:
+        oracle.set_threads(prev)
+    return {"value": done_vox / spent, "unit": "fine voxels/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{n} whole volleyball-like frames on one host thread, {spent:.1f} s"}
+
+
+def gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests):
+    """The gather ceiling of the fine carve: BW_g, the rate at which the GPU
+    serves 4-byte words from a table the size of the frame's packed
+    silhouettes (coalesced within a wave, random wave offsets, all CUs), and
+    R_g = BW_g / (1 B + 4 B x mean tests per voxel) fine voxels/s; achieved =
+    fine voxels per frame / fine-carve stage time."""
+    table = sils.reshape(-1)
+    ctx.gather_peak(table, reps=2)
+    words = max(ctx.gather_peak(table, reps=20) for _ in range(3))
+    bw = 4.0 * words
+    out = {"table_bytes": int(table.numel()) * 4, "bw_g_GBs": bw / 1e9,
+           "kernel": "gather_peak_kernel (one coalesced 256 B wave read per step, global loads)"}
+    if tests:
+        t_mean = float(np.mean([tests[f]["tests_fine"] / tests[f]["vox"] for f in tests]))
+        vox = float(np.mean([fine_vox[f] for f in tests]))
+        ms = float(np.mean([carve_ms[f] for f in tests]))
+        r_g = bw / (1.0 + 4.0 * t_mean)
+        achieved = vox / (ms * 1e-3)
+        out.update({"tests_per_voxel": t_mean, "r_g_voxels_per_s": r_g,
+                    "achieved_voxels_per_s": achieved, "frac": achieved / r_g})
+    return out
+
+
+def h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_fine, max_points,
+            fine_vox):
+    """Frame latency including the host-to-device copy of the packed
+    silhouettes: each frame's packed words sit in pinned host memory; a step is
+    the copy into the device buffer then the frame graph without the packing
+    step, between HIP events on one stream, one frame at a time (as the frame
+    latency without the copy is taken)."""
+    host = []
+    bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
+    for m in masks:
+        ctx.frame(params, sils, bufs, masks=m)
+        torch.cuda.synchronize()
+        h = torch.empty(sils.shape, dtype=sils.dtype, pin_memory=True)
+        h.copy_(sils)
+        host.append(h)
+    g = ctx.frame_graph(params, sils, bufs)
+    st = torch.cuda.Stream()
+    K = min(args.steps, 200)
+    for k in range(min(args.warmup, 10)):
+        with torch.cuda.stream(st):
+            sils.copy_(host[k % len(host)], non_blocking=True)
+        g.launch(st)
+    torch.cuda.synchronize()
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for k in range(K):
+        with torch.cuda.stream(st):
+            e0[k].record(st)
+            sils.copy_(host[k % len(host)], non_blocking=True)
+        g.launch(st)
+        e1[k].record(st)
+        st.synchronize()
+        if k < len(host) and int(bufs.counts[1].item()) != fine_vox[k]:
+            raise RuntimeError("frame from host-copied silhouettes differs")
+    lat = [a.elapsed_time(b) for a, b in zip(e0, e1)][len(host):]
+    return {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
+                           "max": float(np.max(lat))},
+            "copied_bytes": int(sils.numel()) * 4, "frames": len(lat),
+            "note": "packed silhouettes copied from pinned host memory, then the frame graph"}
+
+
 def cpu_baseline(frames, budget_s):
     """The oracle as it stands, on the same frames, until the budget is spent."""
     import oracle
@@ -141,7 +243,7 @@ def cpu_baseline(frames, budget_s):
                                   "tests_surface": r.tests_surface}
         n += 1
     return {"value": done_vox / spent, "unit": "fine voxels/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n} whole volleyball-like frames (same inputs as the GPU steps), "
                       f"{spent:.1f} s of oracle time on host CPU"}, tests
 
@@ -711,9 +813,19 @@ def main():
         if not args.no_cpu_baseline:
             result["soft_hull"]["cpu_baseline"] = soft_cpu_baseline()
 
+    if not args.no_h2d:
+        result["latency_with_h2d"] = h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
+                                             max_rois, max_fine, max_points, fine_vox)
+
     tests = {}
     if not args.no_cpu_baseline:
         result["cpu_baseline"], tests = cpu_baseline(frames, args.cpu_seconds)
+        if args.cpu_seconds_one_core > 0:
+            result["cpu_baseline_one_core"] = cpu_one_core(frames, args.cpu_seconds_one_core)
+    if not args.no_gather:
+        carve_ms = [float(np.mean(stage_ms_frame[KERNELS["fine_carve"]["stage"]][f]))
+                    for f in range(len(masks))]
+        result["gather_roofline"] = gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests)
 
     # Rooflines (HBM, algorithmic bytes per launch / stage time of the eager
     # runs, whose events bracket the kernel on its stream):

@@ -378,6 +378,18 @@ fvv_status fvv_visibility(fvv_ctx *ctx, int32_t n_cams, const fvv_camera *cams,
                           const uint32_t *d_tris, const uint32_t *d_n_tris, uint32_t max_tris,
                           float t_v, float *d_depth, uint32_t *d_vis, hipStream_t stream);
 
+/* A measurement aid, not part of the path: the rate at which the GPU serves
+ * 4-byte words from the device table d_table (n_words >= 64 words, e.g. a
+ * frame's packed silhouettes), read coalesced within each wave (64
+ * consecutive words) at pseudo-random wave offsets -- the gather ceiling of
+ * the carve.  One untimed launch, then `reps` launches between HIP events on
+ * `stream`; *words_per_s receives the words read per second.  d_sink: device
+ * scratch of at least 16384 * 256 uint32 (written).  EINVAL on NULL pointers,
+ * n_words < 64 or reps outside [1, 1000]. */
+fvv_status fvv_gather_peak(fvv_ctx *ctx, const uint32_t *d_table, uint32_t n_words,
+                           uint32_t *d_sink, int32_t reps, double *words_per_s,
+                           hipStream_t stream);
+
 /* ---------------------------------------------------------------- soft hull
  * A differentiable relative of the binary hull of Sec. II-B-1 (not in the
  * paper), for refining silhouette logits and camera poses by gradient descent.

@@ -72,6 +72,8 @@ def lib():
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
         L.orc_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = i32
         _lib = L
     return _lib
 
@@ -92,6 +94,11 @@ def _f3(v) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> int:
+    """Sets the OpenMP threads of later oracle calls; returns the previous count."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def floor_div(a: float, w: float) -> int:

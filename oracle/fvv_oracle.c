@@ -691,6 +691,20 @@ int32_t orc_threads(void)
 #endif
 }
 
+/* Sets the threads later parallel loops use (n >= 1); returns the previous count. */
+int32_t orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    int32_t prev = omp_get_max_threads();
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ mesh */
 
 /*

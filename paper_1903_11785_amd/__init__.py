@@ -140,6 +140,7 @@ def _load():
                          i32),
         "fvv_visibility": ([P, i32, C.POINTER(Camera), P, P, u32, P, P, u32, C.c_float, P, P, P],
                            i32),
+        "fvv_gather_peak": ([P, P, u32, P, i32, C.POINTER(C.c_double), P], i32),
         "fvv_soft_forward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P, P,
                               P], i32),
         "fvv_soft_backward": ([P, C.POINTER(GridC), i32, C.POINTER(SoftCamera), i32, i32, P, P, P,
@@ -411,6 +412,16 @@ class Context:
                                   float(t_v), _ptr(depth), _ptr(vis),
                                   C.c_void_p(_stream(stream))), "fvv_visibility")
         return depth, vis
+
+    def gather_peak(self, table, reps: int = 20, stream=None) -> float:
+        """Words per second the GPU serves from the device table (a measurement
+        aid for the carve's gather roofline)."""
+        import torch
+        sink = torch.empty(16384 * 256, dtype=torch.int32, device=table.device)
+        out = C.c_double()
+        _ok(self.L.fvv_gather_peak(self.h, _ptr(table), int(table.numel()), _ptr(sink), int(reps),
+                                   C.byref(out), C.c_void_p(_stream(stream))), "fvv_gather_peak")
+        return out.value
 
     def soft_forward(self, grid: Grid, cams, W: int, H: int, logits, target=None, occ=None,
                      loss=None, stream=None):

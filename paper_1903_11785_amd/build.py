@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfvv.so")
 SOURCES = ["carve.hip", "ccl.hip", "surface.hip", "isovalue.hip", "mesh.hip", "visibility.hip",
-           "soft.hip", "api.hip"]
+           "soft.hip", "measure.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -474,6 +474,38 @@ fvv_status fvv_visibility(fvv_ctx* ctx, int32_t n_cams, const fvv_camera* cams,
                                  max_tris, t_v, d_depth, d_vis, stream));
 }
 
+fvv_status fvv_gather_peak(fvv_ctx* ctx, const uint32_t* d_table, uint32_t n_words,
+                           uint32_t* d_sink, int32_t reps, double* words_per_s,
+                           hipStream_t stream) {
+    if (!ctx || !d_table || !d_sink || !words_per_s || n_words < 64 || reps < 1 || reps > 1000)
+        return FVV_EINVAL;
+    const uint32_t blocks = (uint32_t)(ctx->n_cus * 64 < 16384 ? ctx->n_cus * 64 : 16384);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return FVV_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return FVV_EDEVICE;
+    }
+    fvv_status st = dev(launch_gather_peak(ctx, d_table, n_words, d_sink, blocks, stream));
+    if (st == FVV_OK)
+        st = dev(hipEventRecord(e0, stream));
+    for (int32_t r = 0; r < reps && st == FVV_OK; ++r)
+        st = dev(launch_gather_peak(ctx, d_table, n_words, d_sink, blocks, stream));
+    if (st == FVV_OK)
+        st = dev(hipEventRecord(e1, stream));
+    if (st == FVV_OK)
+        st = dev(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    if (st == FVV_OK)
+        st = dev(hipEventElapsedTime(&ms, e0, e1));
+    if (st == FVV_OK)
+        *words_per_s = (double)gather_peak_words(blocks) * reps / ((double)ms * 1e-3);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return st;
+}
+
 // ------------------------------------------------------------------ soft hull
 fvv_status fvv_soft_forward(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams,
                             const fvv_soft_camera* cams, int32_t width, int32_t height,

@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("fvv_carve", "fvv_label", "fvv_surface", "fvv_roi_grids", "fvv_carve_batched",
                  "fvv_frame", "fvv_pack_silhouettes", "fvv_mesh", "fvv_isovalue",
-                 "fvv_visibility", "fvv_soft_forward", "fvv_soft_backward"):
+                 "fvv_visibility", "fvv_gather_peak", "fvv_soft_forward", "fvv_soft_backward"):
         assert must in names
 
 
