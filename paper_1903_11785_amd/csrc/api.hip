@@ -8,6 +8,7 @@
 #include <new>
 
 #include "fvv_internal.h"
+#include "measure.h"
 
 using namespace fvv;
 

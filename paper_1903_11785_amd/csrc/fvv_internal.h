@@ -570,12 +570,6 @@ hipError_t launch_visibility(fvv_ctx* ctx, const CamSet& cams, const float* xyz,
                              const uint32_t* n_tris, uint32_t max_tris, float t_v, float* depth,
                              uint32_t* vis, hipStream_t s);
 
-// The gather-rate measurement: blocks x kBlock lanes each read
-// gather_peak_words(blocks) / (blocks x kBlock) words of `table`.
-hipError_t launch_gather_peak(fvv_ctx* ctx, const uint32_t* table, uint32_t n_words,
-                              uint32_t* sink, uint32_t blocks, hipStream_t s);
-uint64_t gather_peak_words(uint32_t blocks);
-
 bool make_soft_cams(int n, int W, int H, const fvv_soft_camera* in, SoftCamSet* cs,
                     SoftJacobians* jac);
 hipError_t launch_soft_forward(fvv_ctx* ctx, const SoftCamSet& cams, const fvv_grid& g,

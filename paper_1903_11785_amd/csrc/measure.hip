@@ -3,7 +3,7 @@
 // silhouettes, read coalesced within a wave (one word per lane, 64
 // consecutive words) at pseudo-random wave offsets -- the fastest any carve
 // could fetch silhouette words from that table.  Not part of the path.
-#include "fvv_internal.h"
+#include "measure.h"
 
 namespace fvv {
 
