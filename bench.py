@@ -37,6 +37,12 @@ WORKLOAD = ("volleyball-like frame: 16 cams 1920x1080, 12 players x 5 ellipsoids
             "coarse 100 mm (180x90x40), fine 10 mm in ROIs, 8-step edge bisection")
 METRIC = "fine voxels carved/s + frame latency p50/p99 (16 cams 1080p, 12 ROIs)"
 HBM_PEAK_GBS = 8000.0
+# VALU ceiling of the exact test: 256 CUs x 4 SIMDs x 16 fp32 lanes x 2.4 GHz
+# of non-packed issue (packed fp32 is not used), and the issue slots of one
+# (sample, camera) test in this library's gfx950 code: 45 VALU instructions,
+# one of them a quarter-rate v_rcp_f32 (48 slots).
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+VALU_SLOTS_PER_TEST = 48
 
 
 def parse():
@@ -167,8 +173,10 @@ def gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests):
     """The gather ceiling of the fine carve: BW_g, the rate at which the GPU
     serves 4-byte words from a table the size of the frame's packed
     silhouettes (coalesced within a wave, random wave offsets, all CUs), and
-    R_g = BW_g / (1 B + 4 B x mean tests per voxel) fine voxels/s; achieved =
-    fine voxels per frame / fine-carve stage time."""
+    R_g = BW_g / (1 B + 4 B x mean tests per voxel) fine voxels/s; beside it
+    the VALU ceiling of testing every voxel in camera order with the exact
+    test, R_valu = VALU lane rate / (issue slots per test x mean tests per
+    voxel).  achieved = fine voxels per frame / fine-carve stage time."""
     table = sils.reshape(-1)
     ctx.gather_peak(table, reps=2)
     words = max(ctx.gather_peak(table, reps=20) for _ in range(3))
@@ -180,9 +188,12 @@ def gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests):
         vox = float(np.mean([fine_vox[f] for f in tests]))
         ms = float(np.mean([carve_ms[f] for f in tests]))
         r_g = bw / (1.0 + 4.0 * t_mean)
+        r_valu = VALU_LANE_PEAK / (VALU_SLOTS_PER_TEST * t_mean)
         achieved = vox / (ms * 1e-3)
         out.update({"tests_per_voxel": t_mean, "r_g_voxels_per_s": r_g,
-                    "achieved_voxels_per_s": achieved, "frac": achieved / r_g})
+                    "r_valu_voxels_per_s": r_valu, "achieved_voxels_per_s": achieved,
+                    "frac": achieved / r_g, "frac_binding": achieved / min(r_g, r_valu),
+                    "binding": "valu" if r_valu < r_g else "gather"})
     return out
 
 
