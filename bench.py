@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--cpu-seconds-one-core", type=float, default=6.0,
                     help="budget of the oracle timed on one host thread (0 skips it)")
     ap.add_argument("--no-gather", action="store_true", help="skip the gather-ceiling leg")
+    ap.add_argument("--no-judo", action="store_true", help="skip the judo-frame leg")
+    ap.add_argument("--judo-frames", type=int, default=2, help="distinct judo frames cycled")
+    ap.add_argument("--judo-steps", type=int, default=50, help="timed judo frames")
     ap.add_argument("--no-h2d", action="store_true",
                     help="skip the frame latency that includes the silhouettes' host copy")
     ap.add_argument("--fine-tile", default="64x4", help="TXxTZ of the fine carve")
@@ -236,6 +239,83 @@ def h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois, max_fi
                            "max": float(np.max(lat))},
             "copied_bytes": int(sils.numel()) * 4, "frames": len(lat),
             "note": "packed silhouettes copied from pinned host memory, then the frame graph"}
+
+
+JUDO_WORKLOAD = ("judo-like frame: 24 cams 3840x2160, 1-2 touching pairs, 10x10x3 m mat, "
+                 "coarse 40 mm, fine 5 mm")
+
+
+def judo_leg(args, fvv, torch, cpu):
+    """The larger configuration: judo-like frames through the whole path, one
+    frame at a time as a HIP graph between HIP events (latency p50/p99 and
+    fine voxels carved per second of frame time), with the oracle timed on
+    one frame on all host threads."""
+    import scenes
+    frames = [scenes.make_scene(scenes.CFG_JUDO, f) for f in range(max(1, args.judo_frames))]
+    sc0 = frames[0]
+    N, H, W = sc0.masks.shape
+    coarse = fvv.Grid(origin=tuple(sc0.origin), h=sc0.hc, lo=(0, 0, 0), dims=sc0.coarse_dims)
+    max_rois, max_fine, max_points = 256, 1 << 27, 1 << 23
+    ctx = fvv.Context(max_cams=N, max_w=W, max_h=H, max_coarse=coarse.size, max_fine=max_fine,
+                      max_rois=max_rois, max_points=max_points, max_jobs=max_rois)
+    try:
+        tx, tz = (int(v) for v in args.fine_tile.split("x"))
+        ctx_, ctz = (int(v) for v in args.coarse_tile.split("x"))
+        params = fvv.frame_params(sc0.P32, W, H, coarse, sc0.hc_um, sc0.hf_um, sc0.t_np,
+                                  sc0.t_nb, sc0.n_steps, coarse_tile=fvv.tile(ctx_, ctz),
+                                  fine_tile=fvv.tile(tx, tz))
+        masks = [torch.from_numpy(sc.masks).cuda() for sc in frames]
+        sils = torch.empty((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+        bufs = fvv.FrameBuffers(coarse, max_rois, max_fine, max_points)
+        fine, rois, points = [], [], []
+        for m in masks:
+            ctx.frame(params, sils, bufs, masks=m)
+            torch.cuda.synchronize()
+            if ctx.check() != fvv.FVV_OK:
+                raise RuntimeError("judo frame exceeded a capacity")
+            c = bufs.counts.cpu().numpy()
+            rois.append(int(c[0]))
+            fine.append(int(c[1]))
+            points.append(int(c[2]))
+        graphs = [ctx.frame_graph(params, sils, bufs, masks=m) for m in masks]
+        for k in range(5):
+            graphs[k % len(graphs)].launch()
+        torch.cuda.synchronize()
+        K = max(1, args.judo_steps)
+        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        for k in range(K):
+            e0[k].record()
+            graphs[k % len(graphs)].launch()
+            e1[k].record()
+        torch.cuda.synchronize()
+        lat = [a.elapsed_time(b) for a, b in zip(e0, e1)]
+        done = sum(fine[k % len(graphs)] for k in range(K))
+        out = {"workload": JUDO_WORKLOAD, "frames": len(frames), "steps": K,
+               "rois_per_frame_mean": float(np.mean(rois)),
+               "fine_voxels_per_frame_mean": float(np.mean(fine)),
+               "surface_points_per_frame_mean": float(np.mean(points)),
+               "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
+                              "mean": float(np.mean(lat))},
+               "fine_voxels_per_s_one_frame_at_a_time": done / (sum(lat) * 1e-3)}
+        for g in graphs:
+            g.close()
+        del graphs, bufs, masks, sils
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        r = oracle.frame(sc0.masks, sc0.P32, sc0.origin, sc0.hc_um, sc0.hf_um, sc0.coarse_dims,
+                         sc0.t_np, sc0.t_nb, sc0.n_steps)
+        t = time.perf_counter() - t0
+        if r.fine_voxels != fine[0]:
+            raise RuntimeError("judo frame: oracle and GPU fine voxel counts differ")
+        out["cpu_baseline"] = {"value": r.fine_voxels / t, "unit": "fine voxels/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"one judo-like frame, {t:.2f} s"}
+    return out
 
 
 def cpu_baseline(frames, budget_s):
@@ -824,6 +904,8 @@ def main():
         if not args.no_cpu_baseline:
             result["soft_hull"]["cpu_baseline"] = soft_cpu_baseline()
 
+    if not args.no_judo:
+        result["judo"] = judo_leg(args, fvv, torch, not args.no_cpu_baseline)
     if not args.no_h2d:
         result["latency_with_h2d"] = h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                              max_rois, max_fine, max_points, fine_vox)
