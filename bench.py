@@ -184,7 +184,22 @@ def gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests):
     ctx.gather_peak(table, reps=2)
     words = max(ctx.gather_peak(table, reps=20) for _ in range(3))
     bw = 4.0 * words
+    # BW_hbm: a plain 1 GiB device-to-device copy (read + write bytes over its time)
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    bw_hbm = 10 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3)
+    del a, b
     out = {"table_bytes": int(table.numel()) * 4, "bw_g_GBs": bw / 1e9,
+           "bw_hbm_GBs": bw_hbm / 1e9,
            "kernel": "gather_peak_kernel (one coalesced 256 B wave read per step, global loads)"}
     if tests:
         t_mean = float(np.mean([tests[f]["tests_fine"] / tests[f]["vox"] for f in tests]))
