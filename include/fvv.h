@@ -383,9 +383,11 @@ fvv_status fvv_visibility(fvv_ctx *ctx, int32_t n_cams, const fvv_camera *cams,
  * frame's packed silhouettes), read coalesced within each wave (64
  * consecutive words) at pseudo-random wave offsets -- the gather ceiling of
  * the carve.  One untimed launch, then `reps` launches between HIP events on
- * `stream`; *words_per_s receives the words read per second.  d_sink: device
- * scratch of at least 16384 * 256 uint32 (written).  EINVAL on NULL pointers,
- * n_words < 64 or reps outside [1, 1000]. */
+ * `stream`; the call waits for them on the host and *words_per_s receives the
+ * words read per second.  d_table is only read (caller-owned); d_sink: device
+ * scratch of at least 16384 * 256 uint32, caller-owned, overwritten with lane
+ * sums.  EINVAL on NULL pointers, n_words < 64 or reps outside [1, 1000];
+ * EDEVICE on a HIP error. */
 fvv_status fvv_gather_peak(fvv_ctx *ctx, const uint32_t *d_table, uint32_t n_words,
                            uint32_t *d_sink, int32_t reps, double *words_per_s,
                            hipStream_t stream);
