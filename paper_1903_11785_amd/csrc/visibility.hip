@@ -6,11 +6,11 @@
 // its centroid projects into the image and its distance exceeds the depth
 // there by at most T_v.
 //
-// Depth: one thread per (camera, triangle), cameras outermost so that a
-// wave's triangles (listed cell by cell) touch neighbouring pixels; the
-// minimum is an atomicMin on the float's bits (the distances are positive,
-// so their bit patterns order like the values and the result does not
-// depend on the order of the updates).  Visibility: one thread per triangle
+// Depth: one thread per triangle, its vertices loaded once and rastered in
+// every camera in turn (a wave's triangles, listed cell by cell, touch
+// neighbouring pixels of each image); the minimum is an atomicMin on the
+// float's bits (the distances are positive, so their bit patterns order like
+// the values and the result does not depend on the order of the updates).  Visibility: one thread per triangle
 // over all cameras, one mask word each.  All arithmetic is fp32 in a fixed
 // order with IEEE division, as the reading defines it.
 #include <algorithm>
@@ -70,6 +70,51 @@ __device__ __forceinline__ float edge_fn(float x0, float y0, float x1, float y1,
     return (x1 - x0) * (py - y0) - (y1 - y0) * (px - x0);
 }
 
+// The pixels of one triangle (vertices V) in one camera: skipped when a vertex
+// is behind the camera, the projected area is zero, the centroid's distance is
+// not positive or the box misses the image; else atomicMin of the distance's
+// bits into each covered pixel of the camera's depth image D.
+__device__ __forceinline__ void raster_one(const float* p, const float V[3][3], int W, int H,
+                                           uint32_t* __restrict__ D) {
+    float u[3], v[3];
+    bool front = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float a, b, w;
+        project3(p, V[k], a, b, w);
+        front &= w > 0.0f;
+        u[k] = a / w;
+        v[k] = b / w;
+    }
+    if (!front || edge_fn(u[0], v[0], u[1], v[1], u[2], v[2]) == 0.0f)
+        return;
+    float gu, gv, d;
+    centroid(p, V, gu, gv, d);
+    if (!(d > 0.0f))
+        return;
+    const float lo_u = fminf(u[0], fminf(u[1], u[2])), hi_u = fmaxf(u[0], fmaxf(u[1], u[2]));
+    const float lo_v = fminf(v[0], fminf(v[1], v[2])), hi_v = fmaxf(v[0], fmaxf(v[1], v[2]));
+    if (!(hi_u >= 0.0f && hi_v >= 0.0f && lo_u < (float)W && lo_v < (float)H))
+        return;
+    // pixels whose centres could be inside (the edge test decides)
+    const int x0 = lo_u < 0.0f ? 0 : (int)lo_u;
+    const int y0 = lo_v < 0.0f ? 0 : (int)lo_v;
+    const int x1 = hi_u >= (float)(W - 1) ? W - 1 : (int)hi_u;
+    const int y1 = hi_v >= (float)(H - 1) ? H - 1 : (int)hi_v;
+    const uint32_t dbits = __float_as_uint(d);
+    for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) {
+            const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+            const float e0 = edge_fn(u[0], v[0], u[1], v[1], px, py);
+            const float e1 = edge_fn(u[1], v[1], u[2], v[2], px, py);
+            const float e2 = edge_fn(u[2], v[2], u[0], v[0], px, py);
+            const bool in = (e0 >= 0.0f && e1 >= 0.0f && e2 >= 0.0f) ||
+                            (e0 <= 0.0f && e1 <= 0.0f && e2 <= 0.0f);
+            if (in)
+                atomicMin(&D[(size_t)y * W + x], dbits);
+        }
+}
+
 __global__ __launch_bounds__(kBlock) void depth_raster_kernel(
     const CamSet cams, const float* __restrict__ xyz, const uint32_t* __restrict__ n_vert_p,
     uint32_t max_vert, const uint32_t* __restrict__ tris, const uint32_t* __restrict__ n_tris_p,
@@ -78,53 +123,13 @@ __global__ __launch_bounds__(kBlock) void depth_raster_kernel(
     const uint32_t nv = nv_all < max_vert ? nv_all : max_vert;
     const uint32_t T = nt_all < max_tris ? nt_all : max_tris;
     const int W = cams.W, H = cams.H;
-    const uint64_t pairs = (uint64_t)T * cams.n;
-    for (uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x; q < pairs;
-         q += (uint64_t)gridDim.x * kBlock) {
-        const int c = (int)(q / T);
-        const uint32_t m = (uint32_t)(q - (uint64_t)c * T);
+    for (uint64_t mm = (uint64_t)blockIdx.x * kBlock + threadIdx.x; mm < T;
+         mm += (uint64_t)gridDim.x * kBlock) {
         float V[3][3];
-        if (!load_triangle(xyz, tris, m, nv, V))
+        if (!load_triangle(xyz, tris, (uint32_t)mm, nv, V))
             continue;
-        const float* p = cams.P[c];
-        float u[3], v[3];
-        bool front = true;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float a, b, w;
-            project3(p, V[k], a, b, w);
-            front &= w > 0.0f;
-            u[k] = a / w;
-            v[k] = b / w;
-        }
-        if (!front || edge_fn(u[0], v[0], u[1], v[1], u[2], v[2]) == 0.0f)
-            continue;
-        float gu, gv, d;
-        centroid(p, V, gu, gv, d);
-        if (!(d > 0.0f))
-            continue;
-        const float lo_u = fminf(u[0], fminf(u[1], u[2])), hi_u = fmaxf(u[0], fmaxf(u[1], u[2]));
-        const float lo_v = fminf(v[0], fminf(v[1], v[2])), hi_v = fmaxf(v[0], fmaxf(v[1], v[2]));
-        if (!(hi_u >= 0.0f && hi_v >= 0.0f && lo_u < (float)W && lo_v < (float)H))
-            continue;
-        // pixels whose centres could be inside (the edge test decides)
-        const int x0 = lo_u < 0.0f ? 0 : (int)lo_u;
-        const int y0 = lo_v < 0.0f ? 0 : (int)lo_v;
-        const int x1 = hi_u >= (float)(W - 1) ? W - 1 : (int)hi_u;
-        const int y1 = hi_v >= (float)(H - 1) ? H - 1 : (int)hi_v;
-        uint32_t* D = depth + (size_t)c * W * H;
-        const uint32_t dbits = __float_as_uint(d);
-        for (int y = y0; y <= y1; ++y)
-            for (int x = x0; x <= x1; ++x) {
-                const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-                const float e0 = edge_fn(u[0], v[0], u[1], v[1], px, py);
-                const float e1 = edge_fn(u[1], v[1], u[2], v[2], px, py);
-                const float e2 = edge_fn(u[2], v[2], u[0], v[0], px, py);
-                const bool in = (e0 >= 0.0f && e1 >= 0.0f && e2 >= 0.0f) ||
-                                (e0 <= 0.0f && e1 <= 0.0f && e2 <= 0.0f);
-                if (in)
-                    atomicMin(&D[(size_t)y * W + x], dbits);
-            }
+        for (int c = 0; c < cams.n; ++c)
+            raster_one(cams.P[c], V, W, H, depth + (size_t)c * W * H);
     }
 }
 
@@ -165,9 +170,9 @@ hipError_t launch_visibility(fvv_ctx* ctx, const CamSet& cams, const float* xyz,
     hipLaunchKernelGGL(depth_clear_kernel,
                        dim3((unsigned)std::min<int64_t>(((int64_t)n + kBlock - 1) / kBlock, cap)),
                        dim3(kBlock), 0, s, reinterpret_cast<uint32_t*>(depth), n);
-    const int64_t pairs = (int64_t)max_tris * cams.n;
     hipLaunchKernelGGL(depth_raster_kernel,
-                       dim3((unsigned)std::min<int64_t>((pairs + kBlock - 1) / kBlock, cap)),
+                       dim3((unsigned)std::min<int64_t>(((int64_t)max_tris + kBlock - 1) / kBlock,
+                                                        cap)),
                        dim3(kBlock), 0, s, cams, xyz, n_vert, max_vert, tris, n_tris, max_tris,
                        reinterpret_cast<uint32_t*>(depth));
     hipLaunchKernelGGL(visibility_kernel,
