@@ -58,6 +58,7 @@ def parse():
                     help="budget of the oracle timed on one host thread (0 skips it)")
     ap.add_argument("--no-gather", action="store_true", help="skip the gather-ceiling leg")
     ap.add_argument("--no-judo", action="store_true", help="skip the judo-frame leg")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-rig leg")
     ap.add_argument("--judo-frames", type=int, default=2, help="distinct judo frames cycled")
     ap.add_argument("--judo-steps", type=int, default=50, help="timed judo frames")
     ap.add_argument("--no-h2d", action="store_true",
@@ -260,13 +261,17 @@ JUDO_WORKLOAD = ("judo-like frame: 24 cams 3840x2160, 1-2 touching pairs, 10x10x
                  "coarse 40 mm, fine 5 mm")
 
 
-def judo_leg(args, fvv, torch, cpu):
-    """The larger configuration: judo-like frames through the whole path, one
-    frame at a time as a HIP graph between HIP events (latency p50/p99 and
-    fine voxels carved per second of frame time), with the oracle timed on
-    one frame on all host threads."""
+TINY_WORKLOAD = ("tiny rig: 4 cams 320x240, 2 ellipsoids, 4x4x2 m, coarse 62.5 mm (64x64x32), fine 20 mm; "
+                 "seeds 0-7, one frame each")
+
+
+def config_leg(args, fvv, torch, cpu, cfg, n_frames, steps, workload, cpu_frames):
+    """Another configuration through the whole path: its frames one at a time
+    as a HIP graph between HIP events (latency p50/p99 and fine voxels carved
+    per second of frame time), with the oracle timed on its first cpu_frames
+    frames on all host threads."""
     import scenes
-    frames = [scenes.make_scene(scenes.CFG_JUDO, f) for f in range(max(1, args.judo_frames))]
+    frames = [scenes.make_scene(cfg, f) for f in range(max(1, n_frames))]
     sc0 = frames[0]
     N, H, W = sc0.masks.shape
     coarse = fvv.Grid(origin=tuple(sc0.origin), h=sc0.hc, lo=(0, 0, 0), dims=sc0.coarse_dims)
@@ -287,7 +292,7 @@ def judo_leg(args, fvv, torch, cpu):
             ctx.frame(params, sils, bufs, masks=m)
             torch.cuda.synchronize()
             if ctx.check() != fvv.FVV_OK:
-                raise RuntimeError("judo frame exceeded a capacity")
+                raise RuntimeError("frame exceeded a capacity")
             c = bufs.counts.cpu().numpy()
             rois.append(int(c[0]))
             fine.append(int(c[1]))
@@ -296,7 +301,7 @@ def judo_leg(args, fvv, torch, cpu):
         for k in range(5):
             graphs[k % len(graphs)].launch()
         torch.cuda.synchronize()
-        K = max(1, args.judo_steps)
+        K = max(1, steps)
         e0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
         e1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
         for k in range(K):
@@ -306,7 +311,7 @@ def judo_leg(args, fvv, torch, cpu):
         torch.cuda.synchronize()
         lat = [a.elapsed_time(b) for a, b in zip(e0, e1)]
         done = sum(fine[k % len(graphs)] for k in range(K))
-        out = {"workload": JUDO_WORKLOAD, "frames": len(frames), "steps": K,
+        out = {"workload": workload, "frames": len(frames), "steps": K,
                "rois_per_frame_mean": float(np.mean(rois)),
                "fine_voxels_per_frame_mean": float(np.mean(fine)),
                "surface_points_per_frame_mean": float(np.mean(points)),
@@ -321,15 +326,20 @@ def judo_leg(args, fvv, torch, cpu):
         ctx.close()
     if cpu:
         import oracle
-        t0 = time.perf_counter()
-        r = oracle.frame(sc0.masks, sc0.P32, sc0.origin, sc0.hc_um, sc0.hf_um, sc0.coarse_dims,
-                         sc0.t_np, sc0.t_nb, sc0.n_steps)
-        t = time.perf_counter() - t0
-        if r.fine_voxels != fine[0]:
-            raise RuntimeError("judo frame: oracle and GPU fine voxel counts differ")
-        out["cpu_baseline"] = {"value": r.fine_voxels / t, "unit": "fine voxels/s",
+        n_cpu = min(len(frames), max(1, cpu_frames))
+        done, t = 0, 0.0
+        for f in range(n_cpu):
+            sc = frames[f]
+            t0 = time.perf_counter()
+            r = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims,
+                             sc.t_np, sc.t_nb, sc.n_steps)
+            t += time.perf_counter() - t0
+            if r.fine_voxels != fine[f]:
+                raise RuntimeError("oracle and GPU fine voxel counts differ")
+            done += r.fine_voxels
+        out["cpu_baseline"] = {"value": done / t, "unit": "fine voxels/s",
                                "cores": oracle.threads(), "kind": "oracle",
-                               "sample": f"one judo-like frame, {t:.2f} s"}
+                               "sample": f"{n_cpu} frame(s) of this configuration, {t:.2f} s"}
     return out
 
 
@@ -428,10 +438,34 @@ def batched_leg(args, fvv, torch):
         per_ms.append(e0.elapsed_time(e1))
     identical = bool(torch.equal(out, per))
     del pg, per
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the ROIs of the first 4 frames, all host threads; its
+        # occupancies must equal the batched launch's bytes
+        import oracle
+        sel = [q for q, b in enumerate(boxes) if b.frame < 4]
+        host_sils = {f: oracle.pack(scs[f].masks) for f in range(4)}
+        done, spent = 0, 0.0
+        for q in sel:
+            b = boxes[q]
+            lat = oracle.Lattice(origin=np.asarray(scs[b.frame].origin, np.float32),
+                                 h=np.float32(scs[b.frame].hf), lo=tuple(b.lo), dims=tuple(b.dims))
+            t0 = time.perf_counter()
+            ref, _ = oracle.carve(scs[b.frame].P32, host_sils[b.frame], W, H, lat)
+            spent += time.perf_counter() - t0
+            o = offs[q]
+            got = out[o:o + lat.size].cpu().numpy()
+            if not np.array_equal(got, ref.reshape(-1)):
+                raise RuntimeError("batched carve differs from the oracle")
+            done += lat.size
+        cpu = {"value": done / spent, "unit": "samples/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"the {len(sel)} ROIs of the first 4 frames ({done} samples), {spent:.2f} s"}
     ctx.close()
     b_ms, p_ms = pct(ms, 50), pct(per_ms, 50)
     achieved = total / (b_ms * 1e-3) / 1e9
     return {
+        "cpu_baseline": cpu,
         "workload": BATCHED_WORKLOAD, "rois": len(boxes), "samples": int(total),
         "tile": [t.tx, t.ty, t.tz, t.persistent_blocks], "tuner_key": tuned["key"],
         "tuner_ms": {f"{tx}x{256 // tx}x{tz}/{blk}": round(m, 4)
@@ -920,7 +954,11 @@ def main():
             result["soft_hull"]["cpu_baseline"] = soft_cpu_baseline()
 
     if not args.no_judo:
-        result["judo"] = judo_leg(args, fvv, torch, not args.no_cpu_baseline)
+        result["judo"] = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_JUDO,
+                                    args.judo_frames, args.judo_steps, JUDO_WORKLOAD, 1)
+    if not args.no_tiny:
+        result["tiny"] = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_TINY,
+                                    8, 50, TINY_WORKLOAD, 8)
     if not args.no_h2d:
         result["latency_with_h2d"] = h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                              max_rois, max_fine, max_points, fine_vox)
