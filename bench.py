@@ -803,7 +803,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build. "
+        print("bench.py: this path runs on one GPU; more than one GPU is not supported. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
