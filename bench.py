@@ -67,10 +67,10 @@ def parse():
     ap.add_argument("--coarse-tile", default="64x1",
                     help="TXxTZ of the coarse carve (depth 4 culls cameras per tile, which at "
                          "coarse spacings costs more than it saves)")
-    ap.add_argument("--in-flight", type=int, default=4,
+    ap.add_argument("--in-flight", type=int, default=6,
                     help="frames in flight for the throughput figure (one context, buffer set "
-                         "and stream each; 4 = the GPU's hardware queues per process); latency "
-                         "is measured one frame at a time")
+                         "and stream each; even counts map evenly onto the process's 4 hardware "
+                         "queues); latency is measured one frame at a time")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-carve leg")
     ap.add_argument("--no-soft", action="store_true", help="skip the soft-hull leg")
     ap.add_argument("--no-mesh", action="store_true", help="skip the marching-cubes leg")
