@@ -69,6 +69,7 @@ def lib():
         L.orc_line_lambda2.restype = C.c_double
         L.orc_depth.argtypes = [C.c_int, p, C.c_int, C.c_int, p, i64, p, i64, p]
         L.orc_visibility.argtypes = [C.c_int, p, C.c_int, C.c_int, p, i64, p, i64, p, f32, p]
+        L.orc_edge_point.argtypes = [p, f32, p, p, p, C.c_uint32, f32, p]
         L.orc_point_inside.argtypes = [C.c_int, p, C.c_int, C.c_int, p, f32, f32, f32]
         L.orc_point_inside.restype = i32
         L.orc_threads.restype = i32
@@ -261,6 +262,17 @@ def visibility(P, W: int, H: int, xyz: np.ndarray, tris: np.ndarray, depth_image
     lib().orc_visibility(P.shape[0], _p(P), W, H, _p(xyz), xyz.shape[0], _p(tris), tris.shape[0],
                          _p(D), np.float32(t_v), _p(vis))
     return vis[:tris.shape[0]].copy()
+
+
+def edge_point(lat: Lattice, occ: np.ndarray, key: int, t: float) -> np.ndarray:
+    """The world point (float32 xyz) at parameter t of crossing edge `key` of
+    the lattice, from its occupied end (t = 0) toward the other, formed as the
+    bisection forms its test points."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    out = np.empty(3, np.float32)
+    lib().orc_edge_point(_p(_f3(lat.origin)), np.float32(lat.h), _p(_i3(lat.lo)),
+                         _p(_i3(lat.dims)), _p(occ), int(key), np.float32(t), _p(out))
+    return out
 
 
 def point_inside(P, sils, W, H, X: float, Y: float, Z: float) -> bool:

@@ -348,15 +348,36 @@ int64_t orc_edges(const int32_t *n, const uint8_t *occ, uint32_t *keys, int64_t 
 }
 
 /*
- * Where each crossing edge leaves the hull.  The edge runs from its ON
- * endpoint (parameter 0) to its OFF endpoint (parameter 1) along one lattice
- * axis.  Each of `steps` bisection steps tests the midpoint m of the current
- * bracket [lo, hi] against all cameras (the occupancy test of orc_carve): an
- * inside midpoint moves lo up, an outside one moves hi down.  This locates the
- * first exit over all cameras, the minimum over cameras of Eq. (3), at the
- * resolution 2^-steps.  Output: t* = (lo+hi)/2 and the world point there,
- * with the axis coordinate computed as fmaf(g_on + d*t*, h, o) (d = +1 or -1
- * toward the OFF endpoint) and the other two coordinates as lattice values.
+ * The world point at parameter t of a crossing edge (Sec. II-C).  The edge
+ * key 3*lin+axis names the lattice edge from sample lin to its neighbour
+ * along `axis`; parameter 0 is its ON endpoint (the occupied one), 1 its OFF
+ * endpoint.  The axis coordinate is fmaf(g_on + d*t, h, o) with d = +1 or -1
+ * toward the OFF endpoint; the other two are lattice values.
+ */
+static void edge_point(const float *o, float h, const int32_t *lo, const int32_t *n,
+                       const uint8_t *occ, uint32_t key, float t, float *xyz)
+{
+    int64_t lin = key / 3;
+    int axis = (int)(key % 3);
+    int64_t i = lin % n[0], j = (lin / n[0]) % n[1], k = lin / ((int64_t)n[0] * n[1]);
+    int32_t g[3] = {lo[0] + (int32_t)i, lo[1] + (int32_t)j, lo[2] + (int32_t)k};
+    int p_on = occ[lin] != 0;
+    int32_t g_on = p_on ? g[axis] : g[axis] + 1;
+    float d = p_on ? 1.0f : -1.0f;
+    for (int a = 0; a < 3; ++a)
+        xyz[a] = lattice_coord(g[a], h, o[a]);
+    float q = (float)g_on + d * t;
+    xyz[axis] = fmaf(q, h, o[axis]);
+}
+
+/*
+ * Where each crossing edge leaves the hull.  Each of `steps` bisection steps
+ * tests the point at the midpoint m of the current bracket [lo, hi] of the
+ * edge parameter (edge_point) against all cameras (the occupancy test of
+ * orc_carve): an inside midpoint moves lo up, an outside one moves hi down.
+ * This locates the first exit over all cameras, the minimum over cameras of
+ * Eq. (3), at the resolution 2^-steps.  Output: t* = (lo+hi)/2 and the world
+ * point there.
  */
 int64_t orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
                    const float *o, float h, const int32_t *lo, const int32_t *n,
@@ -366,26 +387,11 @@ int64_t orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
     int64_t tests = 0;
 #pragma omp parallel for schedule(static) reduction(+ : tests)
     for (int64_t e = 0; e < E; ++e) {
-        int64_t lin = keys[e] / 3;
-        int axis = (int)(keys[e] % 3);
-        int64_t i = lin % n[0], j = (lin / n[0]) % n[1], k = lin / ((int64_t)n[0] * n[1]);
-        int64_t stride = axis == 0 ? 1 : (axis == 1 ? n[0] : (int64_t)n[0] * n[1]);
-        int32_t g[3] = {lo[0] + (int32_t)i, lo[1] + (int32_t)j, lo[2] + (int32_t)k};
-        int p_on = occ[lin] != 0;
-        int q_on = occ[lin + stride] != 0;
-        (void)q_on;
-        int32_t g_on = p_on ? g[axis] : g[axis] + 1;
-        float d = p_on ? 1.0f : -1.0f;
-
         float c[3];
-        for (int a = 0; a < 3; ++a)
-            c[a] = lattice_coord(g[a], h, o[a]);
-
         float tlo = 0.0f, thi = 1.0f;
         for (int s = 0; s < steps; ++s) {
             float m = 0.5f * (tlo + thi);
-            float q = (float)g_on + d * m;
-            c[axis] = fmaf(q, h, o[axis]);
+            edge_point(o, h, lo, n, occ, keys[e], m, c);
             int nt = 0;
             if (point_inside(ncam, P, W, H, sils, c[0], c[1], c[2], &nt))
                 tlo = m;
@@ -394,14 +400,18 @@ int64_t orc_bisect(int ncam, const float *P, int W, int H, const uint32_t *sils,
             tests += nt;
         }
         float t = 0.5f * (tlo + thi);
-        float q = (float)g_on + d * t;
-        c[axis] = fmaf(q, h, o[axis]);
-        xyz[3 * e + 0] = c[0];
-        xyz[3 * e + 1] = c[1];
-        xyz[3 * e + 2] = c[2];
+        edge_point(o, h, lo, n, occ, keys[e], t, xyz + 3 * e);
         tstar[e] = t;
     }
     return tests;
+}
+
+/* The point of edge `key` at parameter t, as orc_bisect forms it (for checks
+ * of the bisection's brackets). */
+void orc_edge_point(const float *o, float h, const int32_t *lo, const int32_t *n,
+                    const uint8_t *occ, uint32_t key, float t, float *xyz)
+{
+    edge_point(o, h, lo, n, occ, key, t, xyz);
 }
 
 /* Single world point against all cameras (for checks of the occupancy test). */

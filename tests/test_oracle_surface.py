@@ -11,6 +11,8 @@ Exit points (Sec. II-C, Eq. (2)-(3), first exit over all cameras):
         of a background pixel in at least one;
   P-S3  the point lies outside the solid eroded by the pixel footprint.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -240,29 +242,62 @@ def test_ps3_points_outside_eroded_solid(scene_cache, cfg, frame):
             assert not np.any(np.einsum('ni,ij,nj->n', d, e.M, d) <= s * s)
 
 
-def test_bisection_brackets_are_consistent(scene_cache):
-    """The reported point's parameter is a dyadic midpoint (2k+1)/2^(S+1) and
-    the bracket ends it implies test inside / outside as bisection requires."""
+@pytest.mark.parametrize("cfg,frame", [(1, 0), (1, 3)])
+def test_bisection_brackets_are_consistent(scene_cache, cfg, frame):
+    """Sec. II-C, Eq. (3): bisection keeps the exit inside its bracket.  The
+    reported parameter is a dyadic midpoint (2k+1)/2^(S+1), so the final
+    bracket is [t* - 2^-(S+1), t* + 2^-(S+1)]; its lower end is 0 or a point
+    the occupancy test finds inside, its upper end 1 or a point it finds
+    outside (points formed exactly as the bisection forms them)."""
+    sc = scene_cache(cfg, frame)
+    res = _surface(sc)
+    S = sc.n_steps
+    half = np.float32(2.0 ** -(S + 1))
+    checked = 0
+    for lat, occ, keys, t in zip(res.fine, res.occ_fine, res.keys, res.tstar):
+        k = t.astype(np.float64) * 2.0 ** (S + 1)
+        assert np.all(k == np.round(k)) and np.all(np.round(k) % 2 == 1)
+        for e in range(0, keys.size, max(1, keys.size // 300)):
+            lo, hi = t[e] - half, t[e] + half
+            if lo > 0:
+                X = oracle.edge_point(lat, occ, int(keys[e]), lo)
+                assert oracle.point_inside(sc.P32, res.sils, sc.W, sc.H, *X), (e, lo)
+            if hi < 1:
+                X = oracle.edge_point(lat, occ, int(keys[e]), hi)
+                assert not oracle.point_inside(sc.P32, res.sils, sc.W, sc.H, *X), (e, hi)
+            checked += 1
+    assert checked > 100
+
+
+def test_edge_point_ends_are_the_lattice_samples(scene_cache):
+    """The edge point at t = 0 is the occupied endpoint and at t = 1 the other
+    one, each coordinate the lattice value fma((float)g, h, o) rounded once."""
     sc = scene_cache(1, 0)
     res = _surface(sc)
-    sils = res.sils
-    lat, occ, keys, t = res.fine[0], res.occ_fine[0], res.keys[0], res.tstar[0]
-    k = t.astype(np.float64) * 512
-    assert np.all(np.abs(k - np.round(k)) == 0) and np.all(np.round(k) % 2 == 1)
+    lat, occ, keys = res.fine[0], res.occ_fine[0], res.keys[0]
     nx, ny, _ = lat.dims
-    for e in range(0, keys.size, max(1, keys.size // 200)):
+    flat = occ.reshape(-1)
+    for e in range(0, keys.size, max(1, keys.size // 100)):
         lin, axis = divmod(int(keys[e]), 3)
-        g = [lat.lo[0] + lin % nx, lat.lo[1] + (lin // nx) % ny, lat.lo[2] + lin // (nx * ny)]
-        p_on = occ.reshape(-1)[lin] != 0
-        g_on = g[axis] + (0 if p_on else 1)
-        d = np.float32(1 if p_on else -1)
-        for tt, want in ((t[e] - np.float32(1 / 512), True), (t[e] + np.float32(1 / 512), False)):
-            if tt <= 0 or tt >= 1:
-                continue
-            c = [np.float32(np.float32(gv) * lat.h + lat.origin[a]) for a, gv in enumerate(g)]
-            q = np.float32(np.float32(g_on) + d * np.float32(tt))
-            c[axis] = np.float32(np.float64(q) * np.float64(lat.h) + np.float64(lat.origin[axis]))
-            assert oracle.point_inside(sc.P32, sils, sc.W, sc.H, *c) in (want, not want)
+        g = np.array([lin % nx, (lin // nx) % ny, lin // (nx * ny)])
+        g2 = g.copy()
+        g2[axis] += 1
+        on, off = (g, g2) if flat[lin] else (g2, g)
+        for t, s in ((0.0, on), (1.0, off)):
+            want = [_fma32(lat.lo[a] + int(s[a]), lat.h, lat.origin[a]) for a in range(3)]
+            assert np.array_equal(oracle.edge_point(lat, occ, int(keys[e]), t),
+                                  np.array(want, np.float32))
+
+
+def _fma32(g, h, o) -> np.float32:
+    """float32 fma((float)g, h, o): the exact value g*h + o correctly rounded
+    (to nearest, ties to even) to float32."""
+    v = Fraction(float(np.float32(g))) * Fraction(float(np.float32(h))) + \
+        Fraction(float(np.float32(o)))
+    x = np.float32(float(v))
+    cands = [np.nextafter(x, np.float32(-np.inf)), x, np.nextafter(x, np.float32(np.inf))]
+    return min(cands, key=lambda c: (abs(Fraction(float(c)) - v),
+                                     int(np.array(c, np.float32).view(np.uint32)) & 1))
 
 
 def test_bisection_test_count_bounds(scene_cache):
