@@ -382,8 +382,11 @@ def test_batched_skips_invalid_jobs(fvv, ctx):
 def test_batched_full_workload(fvv, ctx):
     """The batched workload at full size (64 frames x 12 uneven ROIs at 1 cm,
     2.9e9 samples) in the launch the benchmark times: the graph of the culled
-    batched carve equals 768 per-ROI fvv_carve launches byte for byte, and
-    sampled sub-boxes of every 16th ROI equal the oracle."""
+    batched carve equals 768 per-ROI fvv_carve launches of the unculled carve
+    (depth-2 tiles test every camera at every sample, so they share no
+    classification code with the culled kernels) byte for byte, every ROI of
+    the first four frames (48 ROIs, 1.7e8 samples) equals the oracle byte for
+    byte, and sampled sub-boxes of every 16th ROI of the others equal it too."""
     import torch
     scs, boxes = scenes.batched_rois()
     P_all, sils, cams_dev, jobs, jobs_d, total = batched_inputs(fvv, ctx, scs, boxes)
@@ -396,19 +399,37 @@ def test_batched_full_workload(fvv, ctx):
     g.close()
     assert ctx.check() == fvv.FVV_OK
     per = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    unculled = fvv.tile(64, 2)
     for t, b in enumerate(boxes):
         s = scs[b.frame]
         o = int(jobs[t]["out_offset"])
         n = int(np.prod(b.dims))
         grid = fvv.Grid(origin=tuple(np.float32(s.origin)), h=np.float32(s.hf), lo=tuple(b.lo),
                         dims=tuple(b.dims))
-        ctx.carve(s.P32, W, H, sils[b.frame * 4:(b.frame + 1) * 4], grid, out=per[o:o + n])
+        ctx.carve(s.P32, W, H, sils[b.frame * 4:(b.frame + 1) * 4], grid, tile_=unculled,
+                  out=per[o:o + n])
     torch.cuda.synchronize()
+    assert ctx.check() == fvv.FVV_OK
     assert torch.equal(out, per)
     del per
+    # every ROI of frames 0-3 against the oracle, whole
+    packed = {}
+    for t, b in enumerate(boxes):
+        if b.frame >= 4:
+            continue
+        s = scs[b.frame]
+        if b.frame not in packed:
+            packed[b.frame] = oracle.pack(s.masks)
+        lat = oracle.Lattice(origin=s.origin, h=s.hf, lo=tuple(b.lo), dims=tuple(b.dims))
+        ref, _ = oracle.carve(s.P32, packed[b.frame], W, H, lat)
+        o = int(jobs[t]["out_offset"])
+        got = host(out[o:o + lat.size]).reshape(ref.shape)
+        assert np.array_equal(got, ref), f"ROI {t} (frame {b.frame}) differs from the oracle"
     rng = np.random.default_rng(11)
     for t in range(0, len(boxes), 16):
         b = boxes[t]
+        if b.frame < 4:
+            continue
         s = scs[b.frame]
         nx, ny, nz = b.dims
         sub = (min(16, nx), min(16, ny), min(8, nz))
