@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-gather", action="store_true", help="skip the gather-ceiling leg")
     ap.add_argument("--no-judo", action="store_true", help="skip the judo-frame leg")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-rig leg")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper-shaped volleyball and the 2 mm judo legs")
     ap.add_argument("--judo-frames", type=int, default=2, help="distinct judo frames cycled")
     ap.add_argument("--judo-steps", type=int, default=50, help="timed judo frames")
     ap.add_argument("--no-h2d", action="store_true",
@@ -180,7 +182,7 @@ def gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests):
     R_g = BW_g / (1 B + 4 B x mean tests per voxel) fine voxels/s; beside it
     the VALU ceiling of testing every voxel in camera order with the exact
     test, R_valu = VALU lane rate / (issue slots per test x mean tests per
-    voxel).  achieved = fine voxels per frame / fine-carve stage time."""
+    voxel).  achieved = fine voxels per frame / fine-carve kernel time."""
     table = sils.reshape(-1)
     ctx.gather_peak(table, reps=2)
     words = max(ctx.gather_peak(table, reps=20) for _ in range(3))
@@ -264,18 +266,26 @@ JUDO_WORKLOAD = ("judo-like frame: 24 cams 3840x2160, 1-2 touching pairs, 10x10x
 TINY_WORKLOAD = ("tiny rig: 4 cams 320x240, 2 ellipsoids, 4x4x2 m, coarse 62.5 mm (64x64x32), fine 20 mm; "
                  "seeds 0-7, one frame each")
 
+PAPER_V_WORKLOAD = ("the paper's volleyball shape: 10 cams 3840x2160 (f ~3000 px), 14 players, "
+                    "18x18x9 m, coarse 50 mm (360x360x180), fine 20 mm")
 
-def config_leg(args, fvv, torch, cpu, cfg, n_frames, steps, workload, cpu_frames):
+JUDO_FINE_WORKLOAD = ("judo-like frame at 2 mm: 24 cams 3840x2160, 10x10x3 m, coarse 40 mm, "
+                      "fine 2 mm (~1.9e8 fine samples in 6 ROIs)")
+
+
+def config_leg(args, fvv, torch, cpu, cfg, n_frames, steps, workload, cpu_frames,
+               max_fine=1 << 27, stage_reps=0):
     """Another configuration through the whole path: its frames one at a time
     as a HIP graph between HIP events (latency p50/p99 and fine voxels carved
     per second of frame time), with the oracle timed on its first cpu_frames
-    frames on all host threads."""
+    frames on all host threads; with stage_reps, also the per-stage split and
+    the two big kernels' own times from eager runs with the frame's events."""
     import scenes
     frames = [scenes.make_scene(cfg, f) for f in range(max(1, n_frames))]
     sc0 = frames[0]
     N, H, W = sc0.masks.shape
     coarse = fvv.Grid(origin=tuple(sc0.origin), h=sc0.hc, lo=(0, 0, 0), dims=sc0.coarse_dims)
-    max_rois, max_fine, max_points = 256, 1 << 27, 1 << 23
+    max_rois, max_points = 256, 1 << 23
     ctx = fvv.Context(max_cams=N, max_w=W, max_h=H, max_coarse=coarse.size, max_fine=max_fine,
                       max_rois=max_rois, max_points=max_points, max_jobs=max_rois)
     try:
@@ -320,6 +330,23 @@ def config_leg(args, fvv, torch, cpu, cfg, n_frames, steps, workload, cpu_frames
                "fine_voxels_per_s_one_frame_at_a_time": done / (sum(lat) * 1e-3)}
         for g in graphs:
             g.close()
+        if stage_reps > 0:
+            st = {k: [] for k in fvv.STAGES}
+            kt = {k: [] for k in fvv.FRAME_KERNELS}
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(fvv.FRAME_EVENTS)]
+            for rep in range(stage_reps + 1):
+                for m in masks:
+                    ctx.frame(params, sils, bufs, masks=m, events=ev)
+                    torch.cuda.synchronize()
+                    if rep == 0:
+                        continue
+                    for i, k in enumerate(fvv.STAGES):
+                        st[k].append(ev[i].elapsed_time(ev[i + 1]))
+                    for q, k in enumerate(fvv.FRAME_KERNELS):
+                        kt[k].append(ev[fvv.FRAME_STAGE_EVENTS + 2 * q].elapsed_time(
+                            ev[fvv.FRAME_STAGE_EVENTS + 2 * q + 1]))
+            out["stages_ms"] = {k: float(np.mean(v)) for k, v in st.items()}
+            out["kernels_ms"] = {k: float(np.mean(v)) for k, v in kt.items()}
         del graphs, bufs, masks, sils
     finally:
         torch.cuda.synchronize()
@@ -524,12 +551,47 @@ def soft_leg(args, fvv, torch):
         torch.cuda.synchronize()
         out[name] = (time.perf_counter() - t0_) * 1e3 / reps
     V = int(np.prod(s.dims))
+    # the library's forward (fused L2 loss) and adjoint calls alone: ten calls
+    # captured in a graph, replayed between events, per call
+    cams = hull.cameras(w, t)
+    Ld = L.detach()
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    gl = torch.empty_like(Ld)
+    gp = torch.empty((N, 6), dtype=torch.float64, device="cuda")
+    scale = torch.ones(1, dtype=torch.float64, device="cuda")
+
+    def fwd(stream=None):
+        for _ in range(10):
+            ctx.soft_forward(grid, cams, s.W, s.H, Ld, target=target, loss=loss, stream=stream)
+
+    def bwd(stream=None):
+        for _ in range(10):
+            ctx.soft_backward(grid, cams, s.W, s.H, Ld, gl, gp, target=target, scale=scale,
+                              stream=stream)
+
+    f_ms = pct(graph_ms(torch, fwd, 11), 50) / 10
+    b_ms = pct(graph_ms(torch, bwd, 11), 50) / 10
     ctx.close()
+    # algorithmic bytes: forward, per sample 4 B of target read and per (sample,
+    # camera) the four bilinear taps' 4 B logits; adjoint, per sample 4 B of
+    # target and per (sample, camera) the four taps read and four 4 B logit
+    # gradients added (the pose sums are per camera)
+    f_bytes = V * (4 + 16 * N)
+    b_bytes = V * (4 + 32 * N)
+    rl = {}
+    for name, ms, by, kern in (("forward", f_ms, f_bytes, "soft_fwd_kernel"),
+                               ("backward", b_ms, b_bytes, "soft_bwd_kernel + soft_pose_kernel")):
+        achieved = by / (ms * 1e-3) / 1e9
+        rl[name] = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "bytes_per_call": int(by), "call_ms": ms}
     return {"workload": SOFT_WORKLOAD, "samples": V, "cameras": N,
             "forward_ms": out["forward_ms"], "forward_backward_ms": out["forward_backward_ms"],
             "samples_per_s_forward_backward": V / (out["forward_backward_ms"] * 1e-3),
             "note": "wall time per call through the autograd function, including the host-side "
-                    "pose set-up and the copy of the pose gradients to the host"}
+                    "pose set-up and the copy of the pose gradients to the host",
+            "kernel_call_ms": {"forward": f_ms, "backward": b_ms},
+            "roofline": rl["backward"], "rooflines": rl}
 
 
 def graph_ms(torch, enqueue, reps):
@@ -832,6 +894,9 @@ def main():
     fine_vox, rois, points = [], [], []
     stage_ms = {s: [] for s in fvv.STAGES}
     stage_ms_frame = {s: [[] for _ in masks] for s in fvv.STAGES}
+    # the kernels' own execution times (events that take the kernel's start and
+    # end, on the stream the kernel runs on)
+    kernel_ms_frame = {k: [[] for _ in masks] for k in fvv.FRAME_KERNELS}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(fvv.FRAME_EVENTS)]
     for f, m in enumerate(masks):
         for rep in range(max(1, args.stage_reps)):
@@ -842,6 +907,9 @@ def main():
                     dt = ev[i].elapsed_time(ev[i + 1])
                     stage_ms[s].append(dt)
                     stage_ms_frame[s][f].append(dt)
+                for q, k in enumerate(fvv.FRAME_KERNELS):
+                    e0 = ev[fvv.FRAME_STAGE_EVENTS + 2 * q]
+                    kernel_ms_frame[k][f].append(e0.elapsed_time(ev[fvv.FRAME_STAGE_EVENTS + 2 * q + 1]))
         if ctx.check() != fvv.FVV_OK:
             raise RuntimeError("frame exceeded a capacity")
         c = bufs.counts.cpu().numpy()
@@ -959,6 +1027,19 @@ def main():
     if not args.no_tiny:
         result["tiny"] = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_TINY,
                                     8, 50, TINY_WORKLOAD, 8)
+    if not args.no_paper:
+        # the paper's own volleyball shape, with its Table II times (1st volleyball
+        # sequence, steps B-1 to C, GTX 1080 Ti) beside it as context
+        pv = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_PAPER_V, 2, 50,
+                        PAPER_V_WORKLOAD, 1, stage_reps=5)
+        pv["paper_table_ii_ms"] = {"hardware": "GTX 1080 Ti", "sequence": "1st volleyball",
+                                   "B1_sparse_hull": 0.54, "B2_noise_filter_roi": 21.49,
+                                   "B3_dense_hull": 1.23, "C_polygonization": 3.90,
+                                   "B1_to_C": 27.16}
+        result["paper_volleyball"] = pv
+        result["judo_fine"] = config_leg(args, fvv, torch, not args.no_cpu_baseline,
+                                         scenes.CFG_JUDO_FINE, 1, 10, JUDO_FINE_WORKLOAD, 1,
+                                         max_fine=1 << 28, stage_reps=3)
     if not args.no_h2d:
         result["latency_with_h2d"] = h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                              max_rois, max_fine, max_points, fine_vox)
@@ -968,34 +1049,43 @@ def main():
         result["cpu_baseline"], tests = cpu_baseline(frames, args.cpu_seconds)
         if args.cpu_seconds_one_core > 0:
             result["cpu_baseline_one_core"] = cpu_one_core(frames, args.cpu_seconds_one_core)
+    result["kernels_ms"] = {k: float(np.mean([np.mean(v) for v in kernel_ms_frame[k]]))
+                            for k in fvv.FRAME_KERNELS}
     if not args.no_gather:
-        carve_ms = [float(np.mean(stage_ms_frame[KERNELS["fine_carve"]["stage"]][f]))
-                    for f in range(len(masks))]
+        carve_ms = [float(np.mean(kernel_ms_frame["fine_carve"][f])) for f in range(len(masks))]
         result["gather_roofline"] = gather_leg(ctx, torch, sils, fine_vox, carve_ms, tests)
 
-    # Rooflines (HBM, algorithmic bytes per launch / stage time of the eager
-    # runs, whose events bracket the kernel on its stream):
+    # Rooflines of the two big kernels, from their own execution times (events
+    # taken at each kernel's start and end on its stream, eager runs):
     #   fine carve:  per fine voxel 1 B of occupancy written, plus one 4-byte
     #                silhouette word per (voxel, camera) test of the index-order
     #                early exit (counted by the oracle on the same frames);
     #   exit points: per crossing edge 16 B written (key, xyz), plus one 4-byte
     #                word per (point, camera) test of the index-order early exit.
-    # The kernel with the longer stage is the dominant one, reported as
-    # "roofline"; both are listed under "rooflines".
+    # Both are gathers of 4-byte words from the cache-resident silhouettes, so
+    # the bound is the measured gather rate BW_g (the fine carve's fraction of it
+    # is its fraction of R_g = BW_g / (1 + 4 t)); hbm_frac is the same bytes
+    # over the HBM peak.  The kernel with the longer time is "roofline".
     if tests:
+        bw_g = result.get("gather_roofline", {}).get("bw_g_GBs")
         rl = {}
         for k, spec in KERNELS.items():
-            ms = float(np.mean([np.mean(stage_ms_frame[spec["stage"]][f]) for f in tests]))
+            ms = float(np.mean([np.mean(kernel_ms_frame[k][f]) for f in tests]))
             if k == "fine_carve":
                 per = np.mean([tests[f]["vox"] + 4 * tests[f]["tests_fine"] for f in tests])
             else:
                 per = np.mean([16 * tests[f]["edges"] + 4 * tests[f]["tests_surface"] for f in tests])
             achieved = per / (ms * 1e-3) / 1e9
-            rl[k] = {"kernel": spec["kernel"], "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(k), "bytes_per_launch": float(per),
-                     "stage_ms": ms}
-        dominant = max(rl, key=lambda k: rl[k]["stage_ms"])
+            if bw_g:
+                entry = {"kernel": spec["kernel"], "bound": "gather", "achieved": achieved,
+                         "peak": bw_g, "unit": "GB/s", "frac": achieved / bw_g}
+            else:
+                entry = {"kernel": spec["kernel"], "bound": "hbm", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+            entry.update({"traffic": stored_traffic(k), "bytes_per_launch": float(per),
+                          "kernel_ms": ms, "hbm_frac": achieved / HBM_PEAK_GBS})
+            rl[k] = entry
+        dominant = max(rl, key=lambda k: rl[k]["kernel_ms"])
         result["roofline"] = rl[dominant]
         result["rooflines"] = rl
     print(json.dumps(result))

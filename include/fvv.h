@@ -273,12 +273,17 @@ typedef struct {
 /* Enqueue the whole frame on `stream`.  d_masks: the frame's uint8
  * silhouettes [n_cams][H][W], packed into d_sils first; or NULL when d_sils
  * already holds the packed silhouettes.  events: NULL, or FVV_FRAME_EVENTS
- * HIP events recorded on `stream` at the start and after each stage (pack,
- * coarse carve, labelling, fine jobs + fine carve, crossing edges, exit
- * points) -- a per-stage timing of the frame.  EINVAL as the individual calls,
+ * HIP events: the first FVV_FRAME_STAGE_EVENTS are recorded on `stream` at
+ * the start and after each stage (pack, coarse carve, labelling, fine jobs +
+ * fine carve, crossing edges, exit points) -- a per-stage timing of the
+ * frame; the last four take the start and end times of the fine-carve kernel
+ * and of the exit-point kernel themselves (hipExtLaunchKernel), so their
+ * differences are the two kernels' execution times.  Events must be NULL
+ * while the stream is captured into a graph.  EINVAL as the individual calls,
  * and for spacings hc_um or hf_um above 2^28.  Calls on one context must not
  * overlap (they share its scratch). */
-#define FVV_FRAME_EVENTS 7
+#define FVV_FRAME_STAGE_EVENTS 7
+#define FVV_FRAME_EVENTS 11
 fvv_status fvv_frame(fvv_ctx *ctx, const fvv_frame_params *params, const uint8_t *d_masks,
                      uint32_t *d_sils, const fvv_frame_out *out, hipEvent_t *events,
                      hipStream_t stream);

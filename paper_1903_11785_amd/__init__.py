@@ -26,8 +26,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfvv.so")
 MAX_CAMS = 32
 MAX_STEPS = 12
-FRAME_EVENTS = 7
+FRAME_STAGE_EVENTS = 7
+FRAME_EVENTS = 11
 STAGES = ("pack", "coarse_carve", "label", "fine_carve", "edges", "exit_points")
+# events FRAME_STAGE_EVENTS + 2 i, + 2 i + 1: start and end of kernel i itself
+FRAME_KERNELS = ("fine_carve", "exit_points")
 
 FVV_OK, FVV_EINVAL, FVV_ECAPACITY, FVV_EDEVICE, FVV_ENOMEM = 0, -1, -2, -3, -4
 EXIT_BISECTION, EXIT_BRESENHAM = 0, 1
@@ -442,7 +445,9 @@ class Context:
               stream=None):
         """The whole path for one frame.  masks (uint8 [N][H][W], optional) are
         packed into sils first.  events: optional list of FRAME_EVENTS
-        torch.cuda.Event(enable_timing=True), recorded between the stages."""
+        torch.cuda.Event(enable_timing=True): the first FRAME_STAGE_EVENTS are
+        recorded between the stages, the others take the start and end times
+        of the FRAME_KERNELS kernels themselves."""
         ev = None
         if events is not None:
             assert len(events) == FRAME_EVENTS

@@ -46,11 +46,13 @@ bool grid_ok(const fvv_grid* g, int32_t index_limit) {
     return grid_samples(*g) <= kMaxSamples;
 }
 
-bool cams_ok(const fvv_ctx* ctx, int32_t n, const fvv_camera* cams) {
-    if (!cams || n < 1 || n > FVV_MAX_CAMS || n > ctx->lim.max_cams)
+// Cameras within the limits max_cams, max_w, max_h: same image size, finite P.
+bool cams_within(int32_t max_cams, int32_t max_w, int32_t max_h, int32_t n,
+                 const fvv_camera* cams) {
+    if (!cams || n < 1 || n > FVV_MAX_CAMS || n > max_cams)
         return false;
     const int32_t W = cams[0].width, H = cams[0].height;
-    if (W < 1 || H < 1 || W > ctx->lim.max_w || H > ctx->lim.max_h)
+    if (W < 1 || H < 1 || W > max_w || H > max_h)
         return false;
     for (int c = 0; c < n; ++c) {
         if (cams[c].width != W || cams[c].height != H)
@@ -60,6 +62,10 @@ bool cams_ok(const fvv_ctx* ctx, int32_t n, const fvv_camera* cams) {
                 return false;
     }
     return true;
+}
+
+bool cams_ok(const fvv_ctx* ctx, int32_t n, const fvv_camera* cams) {
+    return cams_within(ctx->lim.max_cams, ctx->lim.max_w, ctx->lim.max_h, n, cams);
 }
 
 CamSet make_camset(int32_t n, const fvv_camera* cams, const fvv_grid* box = nullptr) {
@@ -131,6 +137,40 @@ bool soft_args_ok(fvv_ctx* ctx, const fvv_grid* grid, int32_t n_cams, const fvv_
            grid_ok(grid, kMaxIndex);
 }
 
+// The passes of fvv_surface on one lattice with the given scratch: its job
+// and fine bitmap, the crossing edges, the exit points.
+hipError_t launch_surface_single(const SurfaceScratch& sc, const fvv_job& job,
+                                 const uint8_t* d_occ_fine, const CamSet& cs,
+                                 const uint32_t* d_sils, int32_t n_steps, uint32_t* d_keys,
+                                 float* d_xyz, uint32_t max_points, uint32_t* d_n_points,
+                                 hipStream_t stream) {
+    hipError_t e = launch_surface_prepare_single(sc, job, d_occ_fine, stream);
+    // the exit points' pixel windows come from the tiled silhouettes, when the
+    // scratch holds them
+    const bool tiled = sc.tiles && tiled_sil_words(cs.n, cs.W, cs.H) <= sc.tile_cap;
+    if (e == hipSuccess && tiled)
+        e = launch_tile_sils(cs.n, cs.W, cs.H, d_sils, sc.tiles, stream);
+    if (e == hipSuccess)
+        e = launch_edges(sc, sc.job_single, sc.counts_single + 3, d_keys, d_xyz, max_points,
+                         sc.point_off_single, d_n_points, true, false, stream);
+    if (e == hipSuccess)
+        e = launch_bisect(sc.n_cus, sc.job_single, sc.counts_single + 3, sc.point_off_single, cs,
+                          d_sils, tiled ? sc.tiles : nullptr, n_steps, d_keys, d_xyz, max_points,
+                          stream);
+    return e;
+}
+
+// Argument checks of fvv_surface on one lattice (the limits
+// of the cameras and of the lattice's fine bitmap are the caller's).
+bool surface_args_ok(const fvv_grid* roi, const uint8_t* d_occ_fine, int32_t n_cams,
+                     const fvv_camera* cams, const uint32_t* d_sils, int32_t n_steps,
+                     const uint32_t* d_keys, const float* d_xyz, uint32_t max_points,
+                     const uint32_t* d_n_points) {
+    return d_occ_fine && d_sils && d_keys && d_xyz && d_n_points && max_points >= 1 &&
+           n_steps >= 1 && n_steps <= FVV_MAX_STEPS && cams && n_cams >= 1 &&
+           grid_ok(roi, 1 << (23 - n_steps)) && grid_samples(*roi) <= 1431655765LL;
+}
+
 // Capture what `record` enqueues on a fresh stream into an instantiated graph.
 template <typename F>
 fvv_status capture_graph(fvv_graph** out, F record) {
@@ -197,7 +237,7 @@ void fvv_destroy(fvv_ctx* ctx) {
                     ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc, ctx->d_mesh_table,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
                     ctx->d_word_edges, ctx->d_tri_cnt, ctx->d_point_off_single,
-                    ctx->d_counts_single};
+                    ctx->d_counts_single, ctx->d_tsils, ctx->d_rho};
     for (void* p : ptrs)
         if (p)
             hipFree(p);
@@ -209,6 +249,10 @@ void fvv_destroy(fvv_ctx* ctx) {
         hipEventDestroy(ctx->ev_fine);
     if (ctx->ev_edges)
         hipEventDestroy(ctx->ev_edges);
+    if (ctx->ev_packed)
+        hipEventDestroy(ctx->ev_packed);
+    if (ctx->ev_tiled)
+        hipEventDestroy(ctx->ev_tiled);
     if (ctx->side)
         hipStreamDestroy(ctx->side);
     delete ctx;
@@ -274,6 +318,8 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_tri_cnt, c->item_cap)
     A(d_point_off_single, 2)
     A(d_counts_single, 4)
+    A(d_tsils, tiled_sil_words(lim->max_cams, lim->max_w, lim->max_h))
+    A(d_rho, c->job_cap * FVV_MAX_CAMS * kRhoPer)
 #undef A
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
@@ -285,6 +331,10 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         e = hipEventCreateWithFlags(&c->ev_fine, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&c->ev_edges, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_packed, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_tiled, hipEventDisableTiming);
     if (e == hipSuccess) {
         MeshTable tbl;
         build_mesh_table(&tbl);
@@ -398,12 +448,11 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
                        int32_t n_cams, const fvv_camera* cams, const uint32_t* d_sils,
                        int32_t n_steps, uint32_t* d_keys, float* d_xyz, uint32_t max_points,
                        uint32_t* d_n_points, hipStream_t stream) {
-    if (!ctx || !d_occ_fine || !d_sils || !d_keys || !d_xyz || !d_n_points || max_points < 1 ||
-        n_steps < 1 || n_steps > FVV_MAX_STEPS || !cams_ok(ctx, n_cams, cams) ||
-        !grid_ok(roi, 1 << (23 - n_steps)))
+    if (!ctx || !surface_args_ok(roi, d_occ_fine, n_cams, cams, d_sils, n_steps, d_keys, d_xyz,
+                                 max_points, d_n_points) ||
+        !cams_ok(ctx, n_cams, cams))
         return FVV_EINVAL;
-    if (grid_samples(*roi) > ctx->lim.max_fine || grid_samples(*roi) > 1431655765LL ||
-        fine_bitmap_words(*roi) > ctx->bit_cap)
+    if (grid_samples(*roi) > ctx->lim.max_fine || fine_bitmap_words(*roi) > ctx->bit_cap)
         return FVV_EINVAL;
     const CamSet cs = make_camset(n_cams, cams, roi);
     fvv_job job;
@@ -412,15 +461,8 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
     job.n_cams = n_cams;
     job.width = cs.W;
     job.height = cs.H;
-    hipError_t e = launch_surface_prepare_single(ctx, job, d_occ_fine, stream);
-    if (e == hipSuccess)
-        e = launch_edges(ctx, ctx->d_job_single, ctx->d_counts_single + 3, d_keys, d_xyz,
-                         max_points, ctx->d_point_off_single, d_n_points, true, false, stream);
-    if (e == hipSuccess)
-        e = launch_bisect(ctx, ctx->d_job_single, ctx->d_counts_single + 3,
-                          ctx->d_point_off_single, cs, d_sils, n_steps, d_keys, d_xyz, max_points,
-                          stream);
-    return dev(e);
+    return dev(launch_surface_single(surface_scratch(ctx), job, d_occ_fine, cs, d_sils, n_steps,
+                                     d_keys, d_xyz, max_points, d_n_points, stream));
 }
 
 fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_jobs,
@@ -588,11 +630,23 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         if (events)
             (void)hipEventRecord(events[i], stream);
     };
+    // the kernels' own start and end times: fine carve, exit points
+    auto kev = [&](int i) -> hipEvent_t { return events ? events[FVV_FRAME_STAGE_EVENTS + i] : nullptr; };
     hipError_t e = hipSuccess;
     mark(0);
     if (d_masks)
         e = launch_pack(p->n_cams, cs.W, cs.H, d_masks, d_sils, stream);
     mark(1);
+    // the tiled silhouettes of the fine carve and the exit points, on the side
+    // branch beside the coarse carve and the labelling
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_packed, stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(ctx->side, ctx->ev_packed, 0);
+    if (e == hipSuccess)
+        e = launch_tile_sils(p->n_cams, cs.W, cs.H, d_sils, ctx->d_tsils, ctx->side);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_tiled, ctx->side);
     // the coarse carve also fills the labelling's row bitmap
     const RowBits rb = row_bits(ctx, p->coarse);
     if (e == hipSuccess)
@@ -612,6 +666,7 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     fj.tile_z = ft.tz;
     fj.blocks = (uint32_t)blocks;
     fj.bit_cap = ctx->bit_cap;
+    fj.rho = ctx->d_rho;
     if (e == hipSuccess)
         e = launch_label(ctx, p->coarse, o->d_occ_coarse, nullptr, p->t_np, p->t_nb, o->d_rois,
                          o->max_rois, o->d_counts + 0, true, &fj, stream);
@@ -625,8 +680,10 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (e == hipSuccess)
         e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, ctx->side);
     if (e == hipSuccess)
-        e = launch_carve_frame(ctx, o->d_jobs, cs, d_sils, o->d_occ_fine, ctx->d_finebits, ft,
-                               blocks, stream);
+        e = hipStreamWaitEvent(stream, ctx->ev_tiled, 0);
+    if (e == hipSuccess)
+        e = launch_carve_frame(ctx, o->d_jobs, cs, d_sils, ctx->d_tsils, o->d_occ_fine,
+                               ctx->d_finebits, ft, blocks, stream, kev(0), kev(1));
     mark(4);
     // the mesh also runs on the side branch: its count once the fine bitmaps
     // are there, its triangles once the crossing edges are, beside the exit
@@ -639,7 +696,7 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (mesh && e == hipSuccess)
         e = launch_mesh_count(ctx, o->d_jobs, n_jobs, 0, ctx->side);
     if (e == hipSuccess)
-        e = launch_edges(ctx, o->d_jobs, n_jobs, o->d_keys, o->d_xyz, o->max_points,
+        e = launch_edges(surface_scratch(ctx), o->d_jobs, n_jobs, o->d_keys, o->d_xyz, o->max_points,
                          o->d_point_off, o->d_counts + 2, true, mesh, stream);
     mark(5);
     if (mesh && e == hipSuccess)
@@ -654,10 +711,11 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = hipEventRecord(ctx->ev_join, ctx->side);
     if (e == hipSuccess && p->exit_estimator == FVV_EXIT_BRESENHAM)
         e = launch_isovalue_jobs(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, o->d_keys,
-                                 o->d_xyz, o->max_points, stream);
+                                 o->d_xyz, o->max_points, stream, kev(2), kev(3));
     else if (e == hipSuccess)
-        e = launch_bisect(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, p->n_steps,
-                          o->d_keys, o->d_xyz, o->max_points, stream);
+        e = launch_bisect(ctx->n_cus, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils,
+                          ctx->d_tsils, p->n_steps, o->d_keys, o->d_xyz,
+                          o->max_points, stream, kev(2), kev(3));
     if (e == hipSuccess)
         e = hipStreamWaitEvent(stream, ctx->ev_join, 0);
     mark(6);

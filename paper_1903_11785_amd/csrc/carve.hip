@@ -106,6 +106,47 @@ hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ tiled silhouettes
+// The silhouettes in 8 x 8-pixel blocks, one uint64 per block: pixel (x, y) at
+// bit 8 (y & 7) + (x & 7) of block (x / 8, y / 8); blocks row-major per camera,
+// block (bx, by) of camera c at c * tpc + by * tpr + bx with tpr = ceil(W / 8)
+// and tpc = tpr * ceil(H / 8).  Pixels past the image are 0.  A pixel rectangle
+// of up to 9 x 9 pixels lies in at most 2 x 2 blocks.  One thread per block,
+// from the packed rows (whose padding bits are 0).
+__global__ __launch_bounds__(kBlock) void tile_sils_kernel(const uint32_t* __restrict__ sils,
+                                                           int n, int H, int wpr, int tpr,
+                                                           int tph, uint64_t* __restrict__ tiles) {
+    const int64_t total = (int64_t)n * tph * tpr;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t cb = idx / tpr;                  // camera * tph + block row
+        const int bx = (int)(idx - cb * tpr);
+        const int c = (int)(cb / tph), by = (int)(cb - (int64_t)c * tph);
+        const uint32_t* col = sils + (int64_t)c * H * wpr + (bx >> 2);
+        const int sh = 8 * (bx & 3);
+        uint64_t v = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int y = 8 * by + r;
+            if (y < H)
+                v |= (uint64_t)((col[(int64_t)y * wpr] >> sh) & 0xffu) << (8 * r);
+        }
+        tiles[idx] = v;
+    }
+}
+
+
+hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,
+                            hipStream_t s) {
+    const int wpr = (W + 31) / 32, tpr = (W + 7) / 8, tph = (H + 7) / 8;
+    const int64_t total = (int64_t)n * tph * tpr;
+    int64_t blocks = (total + kBlock - 1) / kBlock;
+    blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
+    hipLaunchKernelGGL(tile_sils_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, sils, n, H,
+                       wpr, tpr, tph, tiles);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ carving tile
 constexpr int log2_of(int v) { return v <= 1 ? 0 : 1 + log2_of(v / 2); }
 
@@ -273,9 +314,9 @@ __device__ __forceinline__ bool job_ok(const fvv_job& j) {
            j.out_offset >= 0;
 }
 
-// Prefix sums of tile counts over a host-given job table; resets the work
-// counter.  counter[0] = next work item, [1] = tiles per item, [2] = jobs.
-// A job out of range gets no tiles and raises the job flag.
+// Prefix sums of tile and tile-row counts over a host-given job table; resets
+// the work counter.  counter[0] = next work item, [1] = tiles per item,
+// [2] = jobs.  A job out of range gets no tiles and raises the job flag.
 template <int TX, int TZ>
 __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* __restrict__ jobs,
                                                                  uint32_t n_jobs,
@@ -284,32 +325,42 @@ __global__ __launch_bounds__(kBlock) void batched_prepare_kernel(const fvv_job* 
                                                                  uint32_t* __restrict__ status,
                                                                  uint32_t blocks) {
     __shared__ uint64_t scratch[kBlock / kWave];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0)
+    __shared__ uint64_t carry, carry_rows;
+    if (threadIdx.x == 0) {
         carry = 0;
+        carry_rows = 0;
+    }
     __syncthreads();
     for (uint32_t base = 0; base < n_jobs; base += kBlock) {
         uint32_t j = base + threadIdx.x;
-        uint64_t t = 0;
+        uint64_t t = 0, rows = 0;
         if (j < n_jobs) {
-            if (job_ok(jobs[j]))
+            if (job_ok(jobs[j])) {
                 t = tiles_of_grid(jobs[j].grid, TX, TZ);
-            else
+                rows = t / (uint64_t)((jobs[j].grid.dims[0] + TX - 1) / TX);
+            } else {
                 atomicOr(status, kFlagJob);
+            }
         }
-        uint64_t tot;
-        uint64_t ex = block_exclusive_sum64<kBlock>(t, scratch, &tot);
-        uint64_t c0 = carry;
-        if (j < n_jobs)
+        uint64_t tot, tot_rows;
+        const uint64_t ex = block_exclusive_sum64<kBlock>(t, scratch, &tot);
+        const uint64_t ex_rows = block_exclusive_sum64<kBlock>(rows, scratch, &tot_rows);
+        const uint64_t c0 = carry, r0 = carry_rows;
+        if (j < n_jobs) {
             pre[j].tile_off = c0 + ex;
+            pre[j].row_off = r0 + ex_rows;
+        }
         __syncthreads();
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             carry = c0 + tot;
+            carry_rows = r0 + tot_rows;
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         uint64_t total = carry;
         pre[n_jobs].tile_off = total;
+        pre[n_jobs].row_off = carry_rows;
         counter[0] = 0;
         counter[1] = grab_size(total, blocks);
         counter[2] = n_jobs;
@@ -771,24 +822,377 @@ __global__ __launch_bounds__(kBlock) void carve_culled_kernel(const CamSet cams,
     carve_tile_culled<TX>(cams, sils, g, i0, j0, k0, occ, rb, rej != 0, mix);
 }
 
+// Any and all of the pixels [cx0, cx1] x [cy0, cy1] (inside the image) of one
+// camera's tiled silhouette tc, when the rectangle lies in at most 2 x 2
+// blocks; false (nothing examined) when it spans more.
+__device__ __forceinline__ bool rect_any_all_tiled(const uint64_t* __restrict__ tc, int tpr,
+                                                   int cx0, int cx1, int cy0, int cy1, bool& any,
+                                                   bool& all) {
+    const int bx0 = cx0 >> 3, bx1 = cx1 >> 3, by0 = cy0 >> 3, by1 = cy1 >> 3;
+    if (bx1 - bx0 > 1 || by1 - by0 > 1)
+        return false;
+    uint64_t v[4], m[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int bx = bx0 + (d & 1), by = by0 + (d >> 1);
+        const bool on = bx <= bx1 && by <= by1;
+        // the rectangle's columns and rows within the block (already inside
+        // [0, 7] for a block the rectangle touches; clamped for the others)
+        const int c0 = min(max(cx0 - 8 * bx, 0), 7), c1 = min(max(cx1 - 8 * bx, 0), 7);
+        const int r0 = min(max(cy0 - 8 * by, 0), 7), r1 = min(max(cy1 - 8 * by, 0), 7);
+        const uint64_t cols = (uint64_t)((2u << c1) - (1u << c0)) * 0x0101010101010101ull;
+        const uint64_t rows = (~0ull >> (8 * (7 - r1))) & (~0ull << (8 * r0));
+        m[d] = on ? cols & rows : 0ull;
+        v[d] = 0;
+        if (on)
+            v[d] = tc[(int64_t)by * tpr + bx];
+    }
+    any = false;
+    all = true;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        any |= (v[d] & m[d]) != 0ull;
+        all &= (v[d] & m[d]) == m[d];
+    }
+    return true;
+}
+
+// Classification of one camera for the box of samples with world corners lo,
+// hi: reject (no foreground pixel in the padded rectangle), accept (inside the
+// image and all foreground) or mixed (also for rectangles of more than 2 x 2
+// tiled blocks).  cam: P (12 floats) and the rounding pad.  The corners'
+// projection rows are the chains of three fmas in the order z, y, x (the
+// rounding pad bounds a chain's error in any order), so the (y, z) partial
+// sums are shared by the two corners on x.
+__device__ __forceinline__ int classify_box_tiled(const float* cam, int W, int H,
+                                                  const uint64_t* __restrict__ tc, int tpr,
+                                                  const float* lo, const float* hi) {
+    const float pad = cam[12];
+    if (!(pad < 1.0f))
+        return kCullMixed;
+    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float Y = (k & 1) ? hi[1] : lo[1], Z = (k & 2) ? hi[2] : lo[2];
+        const float ayz = __builtin_fmaf(cam[1], Y, __builtin_fmaf(cam[2], Z, cam[3]));
+        const float byz = __builtin_fmaf(cam[5], Y, __builtin_fmaf(cam[6], Z, cam[7]));
+        const float wyz = __builtin_fmaf(cam[9], Y, __builtin_fmaf(cam[10], Z, cam[11]));
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float X = e ? hi[0] : lo[0];
+            const float a = __builtin_fmaf(cam[0], X, ayz);
+            const float b = __builtin_fmaf(cam[4], X, byz);
+            const float w = __builtin_fmaf(cam[8], X, wyz);
+            const float r = __builtin_amdgcn_rcpf(w);
+            const float qa = a * r, qb = b * r;
+            x0 = fminf(x0, qa);
+            x1 = fmaxf(x1, qa);
+            y0 = fminf(y0, qb);
+            y1 = fmaxf(y1, qb);
+        }
+    }
+    int cx0, cx1, cy0, cy1;
+    bool inside;
+    const int r0 = rect_of_bounds(x0, x1, y0, y1, pad, W, H, cx0, cx1, cy0, cy1, inside);
+    if (r0 >= 0)
+        return r0;
+    bool any, all;
+    if (!rect_any_all_tiled(tc, tpr, cx0, cx1, cy0, cy1, any, all))
+        return kCullMixed;
+    if (!any)
+        return kCullReject;
+    return (inside && all) ? kCullAccept : kCullMixed;
+}
+
+// The pixel of camera P (12 floats) for the point (X, Y, Z) as the occupancy
+// test floors it (sil_test up to the silhouette word): px, py, and whether
+// w > 0 and the pixel lies in the W x H image.
+__device__ __forceinline__ bool point_pixel_exact(const float* __restrict__ P, float X, float Y,
+                                                  float Z, int W, int H, int& px, int& py) {
+    const float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
+    const float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
+    const float w =
+        __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
+    const float r = __builtin_amdgcn_rcpf(w);
+    float qa = a * r, qb = b * r;
+    const bool tiny = w > 0.0f && w < 0x1p-64f;
+    if (__builtin_expect(__ballot(tiny) != 0, 0)) {
+        if (tiny) {
+            qa = a / w;
+            qb = b / w;
+        }
+    }
+    qa = __builtin_amdgcn_fmed3f(qa, -4.0f, (float)W + 4.0f);
+    qb = __builtin_amdgcn_fmed3f(qb, -4.0f, (float)H + 4.0f);
+    px = exact_floor(a, w, qa);
+    py = exact_floor(b, w, qb);
+    return (w > 0.0f) & ((unsigned)px < (unsigned)W) & ((unsigned)py < (unsigned)H);
+}
+
+// The pixels of the rectangle [cx0, cx0 + 7] x [cy0, cy0 + 7] of one camera's
+// tiled silhouette tc as one 64-bit window, bit 8 r + c = pixel (cx0 + c,
+// cy0 + r), from the up to 2 x 2 blocks around its corner (nx, ny: whether the
+// rectangle's last column / row, cx1 / cy1, lie in the next block; pixels past
+// the image are 0).  Rows are shifted up by cy0 % 8, then each row's pixels
+// right by cx0 % 8 with the next block's pixels shifted in.
+__device__ __forceinline__ uint64_t tiled_window(const uint64_t* __restrict__ tc, int tpr,
+                                                 int cx0, int cy0, bool nx, bool ny, bool on) {
+    const uint64_t* tb = tc + (int64_t)(cy0 >> 3) * tpr + (cx0 >> 3);
+    uint64_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    if (on)
+        b0 = tb[0];
+    if (on && nx)
+        b1 = tb[1];
+    if (on && ny)
+        b2 = tb[tpr];
+    if (on && nx && ny)
+        b3 = tb[tpr + 1];
+    const int ox = cx0 & 7, oy = 8 * (cy0 & 7);
+    const uint64_t t0 = oy ? (b0 >> oy) | (b2 << (64 - oy)) : b0;
+    const uint64_t t1 = oy ? (b1 >> oy) | (b3 << (64 - oy)) : b1;
+    const uint64_t lo = (uint64_t)(0xffu >> ox) * 0x0101010101010101ull;
+    return ((t0 >> ox) & lo) | (ox ? (t1 << (8 - ox)) & ~lo : 0ull);
+}
+
+// A (sub-block, camera) pair's window as the tests read it: the pixels, and
+// the window's corner pixel (x | y << 16), or kNoWindow when the camera's
+// rectangle is larger than 8 x 8 pixels (its tests then load packed words).
+constexpr uint32_t kNoWindow = 0xffffffffu;
+
+struct PairWindow {
+    uint64_t bits;
+    uint32_t org;
+    uint32_t pad_;
+};
+
+// One 16 x 4 x 4 block of a fine lattice by one wave (first sample bi0, bj0,
+// k0; bi0 is a multiple of 16), without workgroup barriers:
+//   1. classification: lane (q, c) = (lane / 16, lane % 16) classifies camera
+//      cb + c for the 4 x 4 x 4 sub-block q of the block.  The rectangle
+//      [floor(c - r), floor(c + r)] around the rcp quotient c of the
+//      sub-block's centre, with the job's radius r for the camera (which
+//      bounds how far any point of a 4 x 4 x 4 box moves from its centre's
+//      projection, widened by the rounding pad), holds the pixel of every
+//      sample of the sub-block.  Clamped to the image: no pixel left -> the
+//      camera rejects every sample; otherwise, at most 8 x 8 pixels, the
+//      rectangle's pixels as a window from the tiled silhouettes: none set ->
+//      reject; all set and the rectangle inside the image -> accept; else
+//      mixed, the window kept for the tests.  Larger rectangles are tested
+//      from the tiled blocks when they span at most 2 x 2 of them (no
+//      window), else count as mixed.
+//   2. tests: lane = sample (x, y, z) = (lane % 4, lane / 4 % 4, lane / 16)
+//      of each sub-block no camera rejects; each pass tests one mixed camera
+//      for each of the four sub-blocks (uniform branches), the pixel's bit
+//      read from the pair's window (every in-image sample pixel lies in the
+//      clamped rectangle) or, without one, from the packed rows.
+//   3. output: the occupancy bytes, and the block's 16 bits of each fine-bitmap
+//      row word.
+// cam_lds: per camera P and the rounding pad; rho: the job's radii per camera
+// (kRhoPer floats); win: this wave's LDS windows [4][FVV_MAX_CAMS].
+__device__ __forceinline__ void carve_block16(const CamSet& cams, const float (*cam_lds)[13],
+                                              const float* __restrict__ rho,
+                                              PairWindow (*win)[FVV_MAX_CAMS],
+                                              const uint32_t* __restrict__ sils,
+                                              const uint64_t* __restrict__ tiles, int tpr,
+                                              int64_t tpc, const fvv_grid& g, int bi0, int bj0,
+                                              int k0, uint8_t* __restrict__ out,
+                                              const RowBits& fb) {
+    const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
+    if (bj0 >= ny)
+        return;                                    // no row of the block is in the lattice
+    const int lane = lane_id();
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int64_t cam_words = (int64_t)cams.H * cams.wpr;
+    uint64_t occ[4] = {0ull, 0ull, 0ull, 0ull};
+    if (bi0 < nx) {
+        // 1. classification
+        const int q = lane >> 4, cl = lane & 15;
+        const int si0 = bi0 + 4 * q;
+        const bool sb_on = si0 < nx;
+        float lo[3], hi[3];
+        box_corners(g, min(si0, nx - 1), min(si0 + 3, nx - 1), bj0, min(bj0 + 3, ny - 1), k0,
+                    min(k0 + 3, nz - 1), lo, hi);
+        const float Xc = 0.5f * (lo[0] + hi[0]), Yc = 0.5f * (lo[1] + hi[1]);
+        const float Zc = 0.5f * (lo[2] + hi[2]);
+        uint32_t rej[4] = {0u, 0u, 0u, 0u}, mix[4] = {0u, 0u, 0u, 0u};
+        for (int cb = 0; cb < cams.n; cb += 16) {
+            const int c = cb + cl;
+            const bool on = sb_on && c < cams.n;
+            const int cc = on ? c : 0;
+            const float* P = cam_lds[cc];
+            const float rx = rho[cc * kRhoPer + 0], ry = rho[cc * kRhoPer + 1];
+            const float a = __builtin_fmaf(P[2], Zc, __builtin_fmaf(P[1], Yc, __builtin_fmaf(P[0], Xc, P[3])));
+            const float b = __builtin_fmaf(P[6], Zc, __builtin_fmaf(P[5], Yc, __builtin_fmaf(P[4], Xc, P[7])));
+            const float w = __builtin_fmaf(P[10], Zc, __builtin_fmaf(P[9], Yc, __builtin_fmaf(P[8], Xc, P[11])));
+            const float r = __builtin_amdgcn_rcpf(w);
+            const float W = (float)cams.W, H = (float)cams.H;
+            const float qa = __builtin_amdgcn_fmed3f(a * r, -8.0f, W + 8.0f);
+            const float qb = __builtin_amdgcn_fmed3f(b * r, -8.0f, H + 8.0f);
+            const bool bounded = rx < 64.0f && ry < 64.0f;   // (INFINITY: no bound)
+            const int x0 = (int)__builtin_floorf(qa - (bounded ? rx : 0.0f));
+            const int x1 = (int)__builtin_floorf(qa + (bounded ? rx : 0.0f));
+            const int y0 = (int)__builtin_floorf(qb - (bounded ? ry : 0.0f));
+            const int y1 = (int)__builtin_floorf(qb + (bounded ? ry : 0.0f));
+            const bool inside = x0 >= 0 && y0 >= 0 && x1 < cams.W && y1 < cams.H;
+            const int cx0 = max(x0, 0), cx1 = min(x1, cams.W - 1);
+            const int cy0 = max(y0, 0), cy1 = min(y1, cams.H - 1);
+            const bool off = cx0 > cx1 || cy0 > cy1;
+            const bool small = bounded && !off && cx1 - cx0 <= 7 && cy1 - cy0 <= 7;
+            const uint64_t* tc = tiles + cc * tpc;
+            const uint64_t wv = tiled_window(tc, tpr, small ? cx0 : 0, small ? cy0 : 0,
+                                             (cx1 >> 3) != (cx0 >> 3), (cy1 >> 3) != (cy0 >> 3),
+                                             on && small);
+            const uint64_t cols = (uint64_t)((2u << (cx1 - cx0 & 7)) - 1u) * 0x0101010101010101ull;
+            const uint64_t m = cols & (~0ull >> (8 * (7 - (cy1 - cy0 & 7))));
+            bool any = (wv & m) != 0ull, all = (wv & m) == m;
+            bool known = small;
+            if (__ballot(on && bounded && !off && !small) != 0ull) {
+                // rectangles past a window: any / all from the tiled blocks
+                bool a2 = false, l2 = true;
+                const bool ok2 = on && bounded && !off && !small &&
+                                 rect_any_all_tiled(tc, tpr, cx0, cx1, cy0, cy1, a2, l2);
+                if (ok2) {
+                    any = a2;
+                    all = l2;
+                    known = true;
+                }
+            }
+            int cls = kCullMixed;
+            if (bounded && off)
+                cls = kCullReject;
+            else if (known)
+                cls = !any ? kCullReject : ((inside && all) ? kCullAccept : kCullMixed);
+            if (on && cls == kCullMixed) {
+                PairWindow pw;
+                pw.bits = wv;
+                pw.org = small ? ((uint32_t)cx0 | ((uint32_t)cy0 << 16)) : kNoWindow;
+                pw.pad_ = 0;
+                win[q][c] = pw;
+            }
+            const uint64_t rb = __ballot(on && cls == kCullReject);
+            const uint64_t mb = __ballot(on && cls == kCullMixed);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                rej[s] |= (uint32_t)(rb >> (16 * s)) & 0xffffu;
+                mix[s] |= ((uint32_t)(mb >> (16 * s)) & 0xffffu) << cb;
+            }
+        }
+        wave_lds_sync();   // the windows, written above, are read below by every lane
+        // 2. tests
+        const bool vyz = bj0 + ly < ny && k0 + lz < nz;
+        const float Y = lattice_coord(g.lo[1] + bj0 + ly, g.h, g.origin[1]);
+        const float Z = lattice_coord(g.lo[2] + k0 + lz, g.h, g.origin[2]);
+        float X[4];
+        bool alive[4];
+        uint32_t rest[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int i = bi0 + 4 * s + lx;
+            X[s] = lattice_coord(g.lo[0] + i, g.h, g.origin[0]);
+            alive[s] = vyz && i < nx && rej[s] == 0u;
+            rest[s] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(rej[s] == 0u ? mix[s] : 0u));
+        }
+        while ((rest[0] | rest[1] | rest[2] | rest[3]) != 0u) {
+            int px[4], py[4];
+            bool ok[4], act[4];
+            uint32_t word[4], org[4];
+            uint64_t wbits[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                act[s] = rest[s] != 0u;
+                if (act[s]) {
+                    const int c = __ffs(rest[s]) - 1;
+                    rest[s] &= rest[s] - 1u;
+                    const PairWindow pw = win[s][c];
+                    org[s] = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw.org);
+                    wbits[s] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pw.bits >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pw.bits);
+                    ok[s] = point_pixel_exact(cams.Pc(c), X[s], Y, Z, cams.W, cams.H, px[s],
+                                              py[s]);
+                    word[s] = 0u;
+                    if (org[s] == kNoWindow && ok[s])
+                        word[s] = sils[c * cam_words + py[s] * cams.wpr + (px[s] >> 5)];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                if (act[s]) {
+                    bool in;
+                    if (org[s] != kNoWindow) {
+                        const int ox = (int)(org[s] & 0xffffu), oy = (int)(org[s] >> 16);
+                        in = ok[s] && ((wbits[s] >> ((8 * (py[s] - oy) + (px[s] - ox)) & 63)) & 1ull);
+                    } else {
+                        in = ok[s] && ((word[s] >> (px[s] & 31)) & 1u);
+                    }
+                    alive[s] = alive[s] && in;
+                    if (__ballot(alive[s]) == 0ull)
+                        rest[s] = 0u;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            occ[s] = __ballot(alive[s]);
+        wave_lds_sync();   // the next block rewrites the windows
+    }
+    // 3. output: bytes, lane -> (x, y) = (lane % 16, lane / 16), every z
+    const uint64_t plane = (uint64_t)nx * (uint64_t)ny;
+    {
+        const int x = lane & 15, y = lane >> 4;
+        const int i = bi0 + x, j = bj0 + y;
+        const int s = x >> 2;
+        const uint64_t oq = s == 0 ? occ[0] : s == 1 ? occ[1] : s == 2 ? occ[2] : occ[3];
+        if (i < nx && j < ny) {
+            uint8_t* o = out + ((uint64_t)k0 * plane + (uint64_t)j * (uint64_t)nx + i);
+#pragma unroll
+            for (int z = 0; z < 4; ++z)
+                if (k0 + z < nz)
+                    o[z * plane] = (uint8_t)((oq >> ((x & 3) + 4 * y + 16 * z)) & 1ull);
+        }
+    }
+    // fine bitmap: lane r < 16 -> row (y, z) = (r % 4, r / 4); the block's 16
+    // samples along x are bits (bi0 & 63) .. + 15 of the row's word
+    if (lane < 16) {
+        const int y = lane & 3, z = lane >> 2;
+        const int j = bj0 + y, k = k0 + z;
+        if (j < ny && k < nz) {
+            uint32_t b = 0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                b |= (uint32_t)((occ[s] >> (4 * y + 16 * z)) & 0xfull) << (4 * s);
+            const int64_t row = (int64_t)j + (int64_t)ny * k;
+            reinterpret_cast<uint16_t*>(fb.words + row * fb.wr + (bi0 >> 6))[(bi0 & 63) >> 4] =
+                (uint16_t)b;
+        }
+    }
+}
+
 // The fine carve of a frame: a static, XCD-aware partition of the tiles of
 // all carried ROIs (contiguous tile ranges per XCD keep each L2's share of the
-// silhouettes small); cameras and rounding pads of the frame by value.  Job
-// tables of up to kJobLds ROIs are kept in LDS for the tile -> job search.
+// silhouettes small).  A workgroup takes whole tiles (TX x TY x 4 samples);
+// each of its four waves owns one 16 x 4 x 4 block of the tile (x offset
+// 16 (w mod TX/16), y offset 4 (w div TX/16)) and carves it on its own, with
+// no workgroup barrier (carve_block16).  Job tables of up to kJobLds ROIs and
+// the cameras' matrices and rounding pads are kept in LDS.
 constexpr int kJobLds = 64;
 
 template <int TX>
-__global__ __launch_bounds__(kBlock, 6) void carve_frame_kernel(const fvv_job* __restrict__ jobs,
+__global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* __restrict__ jobs,
                                                              const JobPrefix* __restrict__ pre,
                                                              const uint32_t* __restrict__ counter,
                                                              const CamSet cams,
                                                              const uint32_t* __restrict__ sils,
+                                                             const uint64_t* __restrict__ tiles,
+                                                             const float* __restrict__ rho,
                                                              uint8_t* __restrict__ out,
                                                              uint64_t* __restrict__ finebits) {
+    constexpr int BXN = TX / 16;                     // blocks of a tile along x
+    __shared__ PairWindow s_win[kBlock / kWave][4][FVV_MAX_CAMS];
     __shared__ uint64_t s_tile_off[kJobLds + 1];
     __shared__ uint64_t s_bit_off[kJobLds];
     __shared__ int64_t s_out[kJobLds];
     __shared__ fvv_grid s_grid[kJobLds];
+    __shared__ float s_cam[FVV_MAX_CAMS][13];        // P, then the rounding pad
     const int nj = (int)counter[2];
     const bool lds = nj <= kJobLds;
     if (lds)
@@ -800,9 +1204,17 @@ __global__ __launch_bounds__(kBlock, 6) void carve_frame_kernel(const fvv_job* _
                 s_grid[j] = jobs[j].grid;
             }
         }
+    for (int i = threadIdx.x; i < cams.n * 13; i += kBlock) {
+        const int c = i / 13, e = i - 13 * c;
+        s_cam[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
+    }
     __syncthreads();
     const uint64_t total = lds ? s_tile_off[nj] : pre[nj].tile_off;
     const XcdSlice xs = xcd_slice(total);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int xo = 16 * (wave % BXN), yo = 4 * (wave / BXN);
+    const int tpr = (cams.W + 7) / 8;
+    const int64_t tpc = (int64_t)tpr * ((cams.H + 7) / 8);
     for (uint64_t t = xs.begin + xs.slot; t < xs.end; t += xs.stride) {
         int jb;
         fvv_grid g;
@@ -826,20 +1238,23 @@ __global__ __launch_bounds__(kBlock, 6) void carve_frame_kernel(const fvv_job* _
         fb.wr = (g.dims[0] + 63) / 64;
         int i0, j0, k0;
         tile_origin<TX>(g, t - tile0, i0, j0, k0);
-        carve_tile_culled<TX>(cams, sils, g, i0, j0, k0, out + out_off, fb);
+        carve_block16(cams, s_cam, rho + (int64_t)jb * FVV_MAX_CAMS * kRhoPer, s_win[wave], sils,
+                      tiles, tpr, tpc, g, i0 + xo, j0 + yo, k0, out + out_off, fb);
     }
 }
 
-// The batched carve with camera culling: the tiles of all jobs in a static
+// The batched carve with camera culling: the tile rows (the tiles of one job
+// that share y and z, i.e. all its tiles along x) of all jobs in a static
 // XCD-aware partition; each job's cameras from the device table and its
-// rounding pads from job_pad_kernel.  A workgroup takes runs of four
-// consecutive tiles (x-neighbours, so one workgroup writes 4*TX bytes of each
-// output row and partly written cache lines are few): each wave classifies one
-// tile of the run for its whole box (four latency chains of job, camera and
-// silhouette loads in flight at once), then the workgroup carves the run's
-// tiles one after the other, writing rejected tiles as zeros directly.  Each
-// wave's tiles ascend, so its job index only moves forward (the tile prefix
-// is read from LDS when the job table fits).
+// rounding pads from job_pad_kernel.  A workgroup carves whole tile rows, so
+// it writes every byte of the TY rows x 4 layers of output samples the row
+// covers: each layer's TY sample rows are contiguous in the output, and cache
+// lines are written whole by one workgroup (partly written lines are what
+// costs HBM write traffic here).  Along the row, each wave classifies one
+// tile of a group of four for its whole box (four latency chains of job,
+// camera and silhouette loads in flight at once), then the workgroup carves
+// the group's tiles one after the other, writing rejected tiles as zeros
+// directly.  The tile-row prefix is read from LDS when the job table fits.
 constexpr int kBatchedJobLds = 1024;
 constexpr int kGroup = kBlock / kWave;
 
@@ -849,83 +1264,80 @@ __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
     const uint32_t* __restrict__ counter, const fvv_camera* __restrict__ cams,
     const float* __restrict__ job_pad, const uint32_t* __restrict__ sils,
     uint8_t* __restrict__ out) {
-    __shared__ uint64_t s_tile_off[kLds ? kBatchedJobLds + 1 : 1];
-    __shared__ int32_t s_tile[kGroup][6];      // job, i0, j0, k0, rejecting, mixed cameras
+    constexpr int TY = kBlock / TX;
+    __shared__ uint64_t s_row_off[kLds ? kBatchedJobLds + 1 : 1];
+    __shared__ int32_t s_tile[kGroup][2];      // rejecting, mixed cameras
     const int nj = (int)counter[2];
     if (kLds)
         for (int j = threadIdx.x; j <= nj; j += kBlock)
-            s_tile_off[j] = pre[j].tile_off;
+            s_row_off[j] = pre[j].row_off;
     __syncthreads();
     auto off = [&](int m) -> uint64_t {
         if (kLds)
-            return s_tile_off[m];
-        return pre[m].tile_off;
+            return s_row_off[m];
+        return pre[m].row_off;
     };
     const XcdSlice xs = xcd_slice(off(nj));
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    // runs of kGroup consecutive tiles (x-neighbours, whose rows share cache lines)
-    const uint64_t runs = (xs.end - xs.begin + kGroup - 1) / kGroup;
     int jb = 0;
-    {
-        const uint64_t t = xs.begin + (uint64_t)xs.slot * kGroup + wave;
-        if (t < xs.end)
-            jb = upper_job(off, nj, t);
-    }
-    for (uint64_t run = xs.slot; run < runs; run += xs.stride) {
-        const uint64_t tg = xs.begin + run * kGroup;
-        const uint64_t t = tg + wave;
-        __syncthreads();                       // the previous run is done with s_tile
-        if (t < xs.end) {
-            while (jb + 1 < nj && __builtin_amdgcn_readfirstlane((uint32_t)(off(jb + 1) <= t)))
-                ++jb;
-            const int j = __builtin_amdgcn_readfirstlane(jb);
-            const fvv_job& job = jobs[j];
-            const JobCams jc{cams + job.cam_base, job_pad + (int64_t)j * FVV_MAX_CAMS, job.n_cams,
-                             job.width, job.height, (job.width + 31) / 32};
-            int i0, j0, k0;
-            tile_origin<TX>(job.grid, t - off(j), i0, j0, k0);
-            uint32_t rej, mix;
-            classify_tile<TX>(jc, sils + job.sil_base, job.grid, i0, j0, k0, rej, mix);
-            if (lane_id() == 0) {
-                s_tile[wave][0] = j;
-                s_tile[wave][1] = i0;
-                s_tile[wave][2] = j0;
-                s_tile[wave][3] = k0;
-                s_tile[wave][4] = (int32_t)rej;
-                s_tile[wave][5] = (int32_t)mix;
+    if (xs.begin + xs.slot < xs.end)
+        jb = upper_job(off, nj, xs.begin + xs.slot);
+    for (uint64_t row = xs.begin + xs.slot; row < xs.end; row += xs.stride) {
+        // rows ascend, so the job index only moves forward
+        while (jb + 1 < nj && off(jb + 1) <= row)
+            ++jb;
+        const int j = __builtin_amdgcn_readfirstlane(jb);
+        const fvv_job& job = jobs[j];
+        const fvv_grid g = job.grid;
+        const JobCams jc{cams + job.cam_base, job_pad + (int64_t)j * FVV_MAX_CAMS, job.n_cams,
+                         job.width, job.height, (job.width + 31) / 32};
+        const int ntx = (g.dims[0] + TX - 1) / TX;
+        const int nty = (g.dims[1] + TY - 1) / TY;
+        const uint32_t r = (uint32_t)(row - off(j));
+        const int j0 = (int)(r % (uint32_t)nty) * TY, k0 = (int)(r / (uint32_t)nty) * 4;
+        for (int tx0 = 0; tx0 < ntx; tx0 += kGroup) {
+            __syncthreads();                   // the previous group is done with s_tile
+            if (tx0 + wave < ntx) {
+                uint32_t rej, mix;
+                classify_tile<TX>(jc, sils + job.sil_base, g, (tx0 + wave) * TX, j0, k0, rej,
+                                  mix);
+                if (lane_id() == 0) {
+                    s_tile[wave][0] = (int32_t)rej;
+                    s_tile[wave][1] = (int32_t)mix;
+                }
             }
-        }
-        __syncthreads();
-        for (int w = 0; w < kGroup; ++w) {
-            if (tg + w >= xs.end)
-                break;
-            // uniform values read back from LDS: scalar registers
-            const int j = __builtin_amdgcn_readfirstlane(s_tile[w][0]);
-            const int i0 = __builtin_amdgcn_readfirstlane(s_tile[w][1]);
-            const int j0 = __builtin_amdgcn_readfirstlane(s_tile[w][2]);
-            const int k0 = __builtin_amdgcn_readfirstlane(s_tile[w][3]);
-            const uint32_t rej = (uint32_t)__builtin_amdgcn_readfirstlane(s_tile[w][4]);
-            const uint32_t mix = (uint32_t)__builtin_amdgcn_readfirstlane(s_tile[w][5]);
-            const fvv_job& job = jobs[j];
-            const JobCams jc{cams + job.cam_base, job_pad + (int64_t)j * FVV_MAX_CAMS, job.n_cams,
-                             job.width, job.height, (job.width + 31) / 32};
-            carve_tile_culled<TX>(jc, sils + job.sil_base, job.grid, i0, j0, k0,
-                                  out + job.out_offset, RowBits{}, rej != 0, mix);
+            __syncthreads();
+            for (int w = 0; w < kGroup && tx0 + w < ntx; ++w) {
+                // uniform values read back from LDS: scalar registers
+                const uint32_t rej = (uint32_t)__builtin_amdgcn_readfirstlane(s_tile[w][0]);
+                const uint32_t mix = (uint32_t)__builtin_amdgcn_readfirstlane(s_tile[w][1]);
+                carve_tile_culled<TX>(jc, sils + job.sil_base, g, (tx0 + w) * TX, j0, k0,
+                                      out + job.out_offset, RowBits{}, rej != 0, mix);
+            }
         }
     }
 }
 
 hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& cams,
-                              const uint32_t* sils, uint8_t* out, uint64_t* finebits, TileShape t,
-                              int blocks, hipStream_t s) {
-    if (t.tz != 4)
-        return launch_carve_batched(ctx, jobs, 0, ctx->d_cams, sils, out, finebits, t, blocks,
-                                    true, s);
+                              const uint32_t* sils, const uint64_t* tiles, uint8_t* out,
+                              uint64_t* finebits, TileShape t, int blocks, hipStream_t s,
+                              hipEvent_t k_start, hipEvent_t k_stop) {
+    if (t.tz != 4) {
+        // the persistent carve: the events bracket its launch
+        hipError_t e = k_start ? hipEventRecord(k_start, s) : hipSuccess;
+        if (e == hipSuccess)
+            e = launch_carve_batched(ctx, jobs, 0, ctx->d_cams, sils, out, finebits, t, blocks,
+                                     true, s);
+        if (e == hipSuccess && k_stop)
+            e = hipEventRecord(k_stop, s);
+        return e;
+    }
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;
 #define X(TXV)                                                                                 \
     if (t.tx == TXV) {                                                                         \
-        hipLaunchKernelGGL((carve_frame_kernel<TXV>), dim3(blocks), dim3(kBlock), 0, s, jobs,  \
-                           ctx->d_prefix, ctx->d_counter, cams, sils, out, finebits);          \
+        hipExtLaunchKernelGGL((carve_frame_kernel<TXV>), dim3(blocks), dim3(kBlock), 0, s,     \
+                              k_start, k_stop, 0, jobs, ctx->d_prefix, ctx->d_counter, cams,   \
+                              sils, tiles, ctx->d_rho, out, finebits);                         \
         return hipGetLastError();                                                              \
     }
     X(64) X(32) X(16)

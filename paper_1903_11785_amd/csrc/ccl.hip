@@ -111,6 +111,42 @@ constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
 // longest prefix that fits both), and build the tile and work-item prefixes of
 // the batched carve and the surface passes.  box(t, lo, hi) gives ROI t's
 // coarse box.  counts: [0] K, [1] fine samples, [3] ROIs carried.
+// The radii of every carried job and camera (FrameJobs::rho), one pair per
+// thread, once the jobs are written (counter[2] = carried jobs).
+template <int NT>
+__device__ __forceinline__ void fine_job_radii(const FrameJobs& fj, const uint32_t* counter) {
+    const uint32_t n = counter[2];
+    const int nc = fj.cams.n;
+    for (uint32_t p = threadIdx.x; p < n * (uint32_t)nc; p += NT) {
+        const uint32_t t = p / (uint32_t)nc;
+        const int c = (int)(p - t * (uint32_t)nc);
+        const fvv_grid g = fj.jobs[t].grid;
+        double lo[3], hi[3];
+        grid_box(g, lo, hi);
+        const float pad = fj.cams.pad[c];
+        float* out = fj.rho + ((int64_t)t * FVV_MAX_CAMS + c) * kRhoPer;
+        // half-extents: 1.5 h per axis for a box of 4 samples, 0.5 h along the
+        // axis of an edge; plus the rounding of the lattice coordinates
+        const double h = (double)g.h;
+        double slack = 0.0;
+        for (int a = 0; a < 3; ++a)
+            slack = fmax(slack, fmax(fabs(lo[a]), fabs(hi[a])));
+        slack *= 0x1p-20;
+        const double eb[3] = {1.5 * h + slack, 1.5 * h + slack, 1.5 * h + slack};
+        double ru, rv;
+        box_radius(fj.cams.P[c], lo, hi, eb, &ru, &rv);
+        out[0] = rho_rect(ru, pad);
+        out[1] = rho_rect(rv, pad);
+        for (int a = 0; a < 3; ++a) {
+            double ee[3] = {slack, slack, slack};
+            ee[a] = 0.5 * h + slack;
+            box_radius(fj.cams.P[c], lo, hi, ee, &ru, &rv);
+            out[2 + 2 * a] = rho_rect(ru, pad);
+            out[3 + 2 * a] = rho_rect(rv, pad);
+        }
+    }
+}
+
 template <int NT, typename Box>
 __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, uint32_t K_all,
                                                 uint32_t max_rois, JobPrefix* __restrict__ pre,
@@ -213,6 +249,8 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
             if (t == 0)
                 finish(n, vox, all_t, all_i);
         }
+        __syncthreads();
+        fine_job_radii<NT>(fj, counter);
         return;
     }
     if (threadIdx.x == 0) {
@@ -267,6 +305,8 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
     }
     if (threadIdx.x == 0)
         finish(carried, e_vox, e_tiles, e_items);
+    __syncthreads();
+    fine_job_radii<NT>(fj, counter);
 }
 
 // ------------------------------------------------------------------ run labelling

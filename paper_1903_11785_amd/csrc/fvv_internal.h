@@ -3,6 +3,7 @@
 // kernel file provides to the C ABI layer (api.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -83,6 +84,69 @@ __host__ __device__ inline float rounding_pad(const float* P, int W, int H, cons
     if (!(pad < 0.25))
         return INFINITY;       // too coarse to be useful
     return (float)pad * (1.0f + 0x1p-20f);
+}
+
+// Bounds (pixels, u then v) on how far the real projection of camera P moves
+// within a box of half-extents e (world units) around any point of the world
+// box [lo, hi]: with d = X - C, u(C + d) - u(C) = (A.d - u(C) W.d) / w(C + d),
+// A and W the first three entries of P's first and third rows (the second row
+// for v), u(C) within the range of u over the box's corners (u is monotone
+// along every segment where w > 0) and w at least its minimum over the corners.
+// Double precision, no contraction, with a relative slack; INFINITY where w
+// is not positive over the box.
+__host__ __device__ inline void box_radius(const float* P, const double lo[3], const double hi[3],
+                                           const double e[3], double* ru, double* rv) {
+#pragma clang fp contract(off)
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, wmin = INFINITY;
+    for (int corner = 0; corner < 8; ++corner) {
+        const double X[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1],
+                             (corner & 4) ? hi[2] : lo[2]};
+        double r[3];
+        for (int q = 0; q < 3; ++q) {
+            r[q] = (double)P[4 * q + 3];
+            for (int k = 0; k < 3; ++k)
+                r[q] += (double)P[4 * q + k] * X[k];
+        }
+        wmin = fmin(wmin, r[2]);
+        if (r[2] > 0.0) {
+            umin = fmin(umin, r[0] / r[2]);
+            umax = fmax(umax, r[0] / r[2]);
+            vmin = fmin(vmin, r[1] / r[2]);
+            vmax = fmax(vmax, r[1] / r[2]);
+        }
+    }
+    if (!(wmin > 0.0)) {
+        *ru = INFINITY;
+        *rv = INFINITY;
+        return;
+    }
+    double su = 0.0, sv = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double wk = (double)P[8 + k];
+        su += e[k] * fmax(fabs((double)P[k] - umin * wk), fabs((double)P[k] - umax * wk));
+        sv += e[k] * fmax(fabs((double)P[4 + k] - vmin * wk), fabs((double)P[4 + k] - vmax * wk));
+    }
+    *ru = su / wmin * (1.0 + 1e-9) + 1e-9;
+    *rv = sv / wmin * (1.0 + 1e-9) + 1e-9;
+}
+
+// Radii of a frame's ROI lattices per (job, camera), kRhoPer floats each: the
+// pixel half-widths of the rectangle around the centre projection of a box of
+// 4 x 4 x 4 samples (u, v), then of an edge along axis 0, 1, 2 (u, v each),
+// each already widened by the camera's rounding pad and a margin for the
+// float arithmetic of the rectangle (see rho_rect); INFINITY where no bound.
+constexpr int kRhoPer = 8;
+
+// The float half-width r of a rectangle [floor(c - r), floor(c + r)] around a
+// centre quotient c (an rcp quotient, |c| < 2^13 after clamping) that holds
+// the floored quotient of every point within the real radius `radius` of the
+// centre's real projection: the radius, the rounding pad (which covers the
+// error of both quotients against the real projections) and 2^-8 for the
+// rounding of c -/+ r; rounded up; INFINITY when either is unbounded.
+__host__ __device__ inline float rho_rect(double radius, float pad) {
+    if (!(radius < 1e6) || !(pad < 1.0f))
+        return INFINITY;
+    return (float)(radius + (double)pad + 0x1p-8) * (1.0f + 0x1p-20f);
 }
 
 // Tile of the carving kernels: TX*TY == 256 threads, TZ samples per thread.
@@ -347,6 +411,7 @@ constexpr int kStatsRow = 8;   // per component: count, lo[3], hi[3], smallest l
 struct JobPrefix {
     uint64_t tile_off;   // first tile of the job
     uint64_t bit_off;    // first word of the job's fine bitmap
+    uint64_t row_off;    // first tile row (tiles sharing y and z) of the job (batched carve)
     uint32_t item_off;   // first crossing-edge work item of the job
     uint32_t pad;
 };
@@ -458,6 +523,8 @@ struct fvv_ctx {
     fvv_job* d_job_single;       // the job of a single-ROI fvv_surface call
     fvv_camera* d_cams;          // camera table of fvv_frame
     uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)
+    uint64_t* d_tsils;           // a frame's silhouettes in 8 x 8-pixel blocks
+    float* d_rho;                // a frame's radii per (job, camera), kRhoPer floats each
     uint32_t* d_item_cnt;        // crossing edges per work item
     fvv::WordEdges* d_word_edges;  // per fine-bitmap word (bit_cap), for the mesh
     uint32_t* d_tri_cnt;         // triangles per work item
@@ -471,6 +538,7 @@ struct fvv_ctx {
     hipStream_t side;
     hipEvent_t ev_fork, ev_join;
     hipEvent_t ev_fine, ev_edges;  // a frame's mesh branch: fine bitmaps, keys ready
+    hipEvent_t ev_packed, ev_tiled;  // packed rows ready; tiled silhouettes ready
 };
 
 namespace fvv {
@@ -489,6 +557,7 @@ struct FrameJobs {
     int tile_x, tile_z;
     uint32_t blocks;
     int64_t bit_cap;     // words of the fine bitmap scratch
+    float* rho;          // per (job, camera) radii (kRhoPer floats), written with the jobs
 };
 
 // Launchers (each returns hipSuccess or the launch error).
@@ -561,7 +630,8 @@ hipError_t launch_isovalue(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, 
 hipError_t launch_isovalue_jobs(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                                 const uint32_t* point_off, const CamSet& cams,
                                 const uint32_t* sils, const uint32_t* keys, float* xyz,
-                                uint32_t max_points, hipStream_t s);
+                                uint32_t max_points, hipStream_t s, hipEvent_t k_start = nullptr,
+                                hipEvent_t k_stop = nullptr);
 
 // Depth images (cleared, then the triangles' minimum distances) and the
 // triangles' visibility masks.
@@ -579,25 +649,54 @@ hipError_t launch_soft_backward(fvv_ctx* ctx, const SoftCamSet& cams, const Soft
                                 const fvv_grid& g, const float* logits, const float* target,
                                 const float* grad_occ, const double* scale, float* grad_logits,
                                 double* grad_pose, hipStream_t s);
+// Device scratch of the crossing-edge and exit-point passes: a context's
+// (surface_scratch) or the static array of the allocation-free entry point.
+struct SurfaceScratch {
+    fvv_job* job_single;         // the job of a single lattice
+    JobPrefix* pre;              // per job (at least 2)
+    uint32_t* counts_single;     // [3] = jobs of a single lattice (1)
+    uint32_t* point_off_single;  // 2 entries
+    uint64_t* finebits;          // fine bitmaps of the jobs
+    uint32_t* item_cnt;          // crossing edges per work item
+    WordEdges* word_edges;       // per fine-bitmap word (NULL: never written)
+    uint32_t* status;            // sticky flags
+    uint64_t* tiles;             // silhouettes in 8 x 8-pixel blocks (NULL: none)
+    int64_t tile_cap;            // words at `tiles`
+    int n_cus;
+};
+SurfaceScratch surface_scratch(fvv_ctx* ctx);
 // Crossing edges of the jobs' fine bitmaps: keys (and xyz's side marks),
 // point_off and n_points when `keys_out`; the word edges of every word when
 // `word_edges`.
-hipError_t launch_edges(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+hipError_t launch_edges(const SurfaceScratch& sc, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                         uint32_t* keys, float* xyz, uint32_t max_points, uint32_t* point_off,
                         uint32_t* n_points, bool keys_out, bool word_edges, hipStream_t s);
-// Exit points of the listed edges.
-hipError_t launch_bisect(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+// Exit points of the listed edges.  tiles: the silhouettes in 8 x 8-pixel
+// blocks (launch_tile_sils), or NULL (slower: no pixel windows).
+hipError_t launch_bisect(int n_cus, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                          const uint32_t* point_off, const CamSet& cams, const uint32_t* sils,
-                         int n_steps, const uint32_t* keys, float* xyz, uint32_t max_points,
-                         hipStream_t s);
+                         const uint64_t* tiles, int n_steps, const uint32_t* keys, float* xyz,
+                         uint32_t max_points, hipStream_t s, hipEvent_t k_start = nullptr,
+                         hipEvent_t k_stop = nullptr);
 // The fine carve of a frame (jobs prepared by the labelling): tiles with
 // tz == 4 classify cameras per box first (rounding pads of `cams`), others
 // take the batched carve.
+// k_start, k_stop: NULL, or events that take the kernel's own start and end
+// times (hipExtLaunchKernel).
 hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& cams,
-                              const uint32_t* sils, uint8_t* out, uint64_t* finebits, TileShape t,
-                              int blocks, hipStream_t s);
+                              const uint32_t* sils, const uint64_t* tiles, uint8_t* out,
+                              uint64_t* finebits, TileShape t, int blocks, hipStream_t s,
+                              hipEvent_t k_start = nullptr, hipEvent_t k_stop = nullptr);
+// The silhouettes in 8 x 8-pixel blocks (tile_sils_kernel's layout), from the
+// packed rows.
+hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,
+                            hipStream_t s);
+// Words of the tiled silhouettes of n cameras of W x H pixels.
+inline int64_t tiled_sil_words(int n, int W, int H) {
+    return (int64_t)n * ((W + 7) / 8) * ((H + 7) / 8);
+}
 // The job table and fine bitmap of a single lattice with occupancy occ.
-hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, const uint8_t* occ,
-                                         hipStream_t s);
+hipError_t launch_surface_prepare_single(const SurfaceScratch& sc, const fvv_job& job,
+                                         const uint8_t* occ, hipStream_t s);
 
 }  // namespace fvv

@@ -259,12 +259,13 @@ hipError_t launch_isovalue(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, 
 hipError_t launch_isovalue_jobs(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                                 const uint32_t* point_off, const CamSet& cams,
                                 const uint32_t* sils, const uint32_t* keys, float* xyz,
-                                uint32_t max_points, hipStream_t s) {
+                                uint32_t max_points, hipStream_t s, hipEvent_t k_start,
+                                hipEvent_t k_stop) {
     const int64_t want = ((int64_t)max_points + kBlock - 1) / kBlock;
     const int64_t cap = (int64_t)ctx->n_cus * 8;
-    hipLaunchKernelGGL(isovalue_jobs_kernel, dim3((unsigned)(want < cap ? want : cap)),
-                       dim3(kBlock), 0, s, jobs, n_jobs_dev, point_off, cams, sils, keys, xyz,
-                       max_points);
+    hipExtLaunchKernelGGL(isovalue_jobs_kernel, dim3((unsigned)(want < cap ? want : cap)),
+                          dim3(kBlock), 0, s, k_start, k_stop, 0, jobs, n_jobs_dev, point_off,
+                          cams, sils, keys, xyz, max_points);
     return hipGetLastError();
 }
 

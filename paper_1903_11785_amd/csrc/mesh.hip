@@ -421,9 +421,10 @@ hipError_t launch_mesh(fvv_ctx* ctx, const fvv_grid& g, const uint8_t* occ, cons
     fvv_job job;
     memset(&job, 0, sizeof(job));
     job.grid = g;
-    hipError_t e = launch_surface_prepare_single(ctx, job, occ, s);
+    const SurfaceScratch sc = surface_scratch(ctx);
+    hipError_t e = launch_surface_prepare_single(sc, job, occ, s);
     if (e == hipSuccess)
-        e = launch_edges(ctx, ctx->d_job_single, ctx->d_counts_single + 3, nullptr, nullptr, 0,
+        e = launch_edges(sc, ctx->d_job_single, ctx->d_counts_single + 3, nullptr, nullptr, 0,
                          nullptr, nullptr, false, true, s);
     const int64_t items = (fine_bitmap_words(g) + kEdgeWords - 1) / kEdgeWords;
     if (e == hipSuccess)

@@ -45,14 +45,28 @@ __global__ __launch_bounds__(kBlock) void fine_bitmap_kernel(const uint8_t* __re
         bits[word] = b;
 }
 
-hipError_t launch_surface_prepare_single(fvv_ctx* ctx, const fvv_job& job, const uint8_t* occ,
-                                         hipStream_t s) {
-    hipLaunchKernelGGL(surface_single_kernel, dim3(1), dim3(64), 0, s, job, ctx->d_job_single,
-                       ctx->d_prefix, ctx->d_counts_single);
+SurfaceScratch surface_scratch(fvv_ctx* ctx) {
+    return SurfaceScratch{ctx->d_job_single,
+                          ctx->d_prefix,
+                          ctx->d_counts_single,
+                          ctx->d_point_off_single,
+                          ctx->d_finebits,
+                          ctx->d_item_cnt,
+                          ctx->d_word_edges,
+                          ctx->d_status,
+                          ctx->d_tsils,
+                          tiled_sil_words(ctx->lim.max_cams, ctx->lim.max_w, ctx->lim.max_h),
+                          ctx->n_cus};
+}
+
+hipError_t launch_surface_prepare_single(const SurfaceScratch& sc, const fvv_job& job,
+                                         const uint8_t* occ, hipStream_t s) {
+    hipLaunchKernelGGL(surface_single_kernel, dim3(1), dim3(64), 0, s, job, sc.job_single, sc.pre,
+                       sc.counts_single);
     const int64_t n_words = fine_bitmap_words(job.grid);
     const int64_t blocks = (n_words * kWave + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(fine_bitmap_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, occ,
-                       job.grid.dims[0], (job.grid.dims[0] + 63) / 64, n_words, ctx->d_finebits);
+                       job.grid.dims[0], (job.grid.dims[0] + 63) / 64, n_words, sc.finebits);
     return hipGetLastError();
 }
 
@@ -215,20 +229,65 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
 }
 
 // ------------------------------------------------------------------ exit points
+// Exit points by bisection of the edge parameter against the occupancy test
+// (the AND over all cameras).
+//
+// A camera whose padded pixel rectangle around the whole edge lies inside the
+// image and is all foreground accepts every point of the edge: the projection
+// of a segment is the segment between its ends' projections, and the rounding
+// pad bounds the distance between the real quotient of any point of the
+// lattice's box and the rounded quotient the occupancy test floors (the ends'
+// quotients here come from rcp, whose error the pad also covers).  Such a
+// camera is left out of the edge's bisection.
+//
+// One wave takes 64 edges, one per lane.  Each lane forms, camera after
+// camera (kCullUnroll cameras' silhouette loads in flight together), its
+// edge's padded rectangle; one of at most 8 x 8 pixels inside the image gets
+// the rectangle's pixels as one 64-bit window (bit 8 r + c = pixel (x0 + c,
+// y0 + r) from its top-left corner), built from the 2 x 2 blocks of the tiled
+// silhouettes around it: the camera is dropped when the rectangle is all
+// foreground, else the (edge, camera) pair is listed in LDS with its window.
+// Cameras with larger rectangles are listed without a window.
+// The bisection then runs over the kept pairs in passes of 64: a pair's lane
+// tests its camera at the round's points and ORs the failing points into the
+// edge's LDS word; each edge's lane then advances its bracket.  Every tested
+// point's pixel lies in its pair's rectangle, so a pair with a window reads
+// the pixel from it: the rounds make no memory access but LDS, except for
+// pairs without a window (which load the packed row word, as the plain test).
+// Without tiled silhouettes (tiles NULL) every candidate is kept without a
+// window.  The n_steps bisection steps run two at a time: a round tests the
+// three points lo + (1, 2, 3) w/4 of the bracket [lo, lo + w] and replays the
+// two binary steps from them -- the first step tests the midpoint (2), the
+// second the midpoint of the half it kept (3 if 2 was inside, else 1) -- so
+// the final bracket is exactly that of n_steps binary steps (all points are
+// dyadic, exact in float).  The bracket width w is the same for every edge.
+constexpr int kBisectJobs = 64;    // jobs whose lattices a workgroup keeps in LDS
+constexpr int kWinCap = 256;       // kept pairs per wave with an LDS window
+constexpr int kCullUnroll = 4;     // cull passes whose loads are in flight together
+constexpr uint32_t kNoWindow = 0xffffffffu;
 
-// Whether camera c accepts every point of the edge X0-X1: the pixel rectangle
-// of the edge's projection, widened by cams.pad[c], lies inside the image and
-// is entirely foreground.  The projection of a segment is the segment between
-// the projections of its ends, and pad[c] bounds the distance between the real
-// quotient of any point of the lattice's box and the rounded quotient the
-// occupancy test floors (the ends' quotients here come from rcp, whose error
-// pad[c] also covers).  Rectangles of more than 2 rows or 2 words are not
-// examined (the camera then stays in the bisection).
-__device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
-                                                    const uint32_t* __restrict__ sil,
-                                                    const float* X0, const float* X1) {
-    const float* P = &cams.P[c][0];
-    const float pad = cams.pad[c];
+// An edge as the passes need it: its first sample's coordinates (the sample
+// of its key), the axis coordinate of its second sample, the axis, the ON
+// end's index along it (as float), the direction toward the OFF end, the
+// lattice spacing and origin on that axis, and the bracket start.
+struct EdgeRec {
+    float c[3];
+    float x1;
+    float gq, d, h, o, lo;
+    int axis;
+    int pad_[2];
+};
+
+// The padded pixel rectangle of camera P (rounding pad `pad`) around the
+// segment X0-X1: window origin and size when it lies inside the image and
+// spans at most 8 x 8 pixels (`small`), else small = false.
+struct EdgeRect {
+    int x0, y0, nx, ny;   // top-left pixel, columns - 1, rows - 1
+    bool small;
+};
+
+__device__ __forceinline__ EdgeRect edge_rect(const float* P, float pad, int W, int H,
+                                              const float* X0, const float* X1) {
     float x[2], y[2];
     bool front = true;
 #pragma unroll
@@ -246,55 +305,50 @@ __device__ __forceinline__ bool camera_accepts_edge(const CamSet& cams, int c,
     const float fx1 = __builtin_floorf(fmaxf(x[0], x[1]) + pad);
     const float fy0 = __builtin_floorf(fminf(y[0], y[1]) - pad);
     const float fy1 = __builtin_floorf(fmaxf(y[0], y[1]) + pad);
-    const bool small = front && fx0 >= 0.0f && fy0 >= 0.0f && fx1 < (float)cams.W &&
-                       fy1 < (float)cams.H && fx1 - fx0 <= 31.0f && fy1 - fy0 <= 1.0f;
-    const int x0 = small ? (int)fx0 : 0, x1 = small ? (int)fx1 : 0;
-    const int y0 = small ? (int)fy0 : 0, y1 = small ? (int)fy1 : 0;
-    const int w0 = x0 >> 5, w1 = x1 >> 5;
-    const uint32_t m0 = w0 == w1 ? (2u << (x1 & 31)) - (1u << (x0 & 31)) : 0u - (1u << (x0 & 31));
-    const uint32_t m1 = w0 == w1 ? 0u : (2u << (x1 & 31)) - 1u;
-    // only the words the rectangle covers are loaded, all of them together
-    const uint32_t* r0 = sil + y0 * cams.wpr;
-    const uint32_t* r1 = sil + y1 * cams.wpr;
-    const bool two_w = w1 != w0, two_r = y1 != y0;
-    uint32_t a00 = 0, a01 = 0, a10 = 0, a11 = 0;
-    if (small)
-        a00 = r0[w0];
-    if (small && two_w)
-        a01 = r0[w1];
-    if (small && two_r)
-        a10 = r1[w0];
-    if (small && two_w && two_r)
-        a11 = r1[w1];
-    return small && (a00 & m0) == m0 && (a01 & m1) == m1 && (!two_r || (a10 & m0) == m0) &&
-           (!two_r || (a11 & m1) == m1);
+    EdgeRect r;
+    r.small = front && pad < 1.0f && fx0 >= 0.0f && fy0 >= 0.0f && fx1 < (float)W &&
+              fy1 < (float)H && fx1 - fx0 <= 7.0f && fy1 - fy0 <= 7.0f;
+    r.x0 = r.small ? (int)fx0 : 0;
+    r.y0 = r.small ? (int)fy0 : 0;
+    r.nx = r.small ? (int)fx1 - r.x0 : 0;
+    r.ny = r.small ? (int)fy1 - r.y0 : 0;
+    return r;
 }
 
-// One crossing edge per lane.  Each lane decodes its edge and keeps the
-// cameras that can reject some point of it (the others accept the whole edge;
-// kCullChunk cameras' loads in flight together).  The wave then lists its
-// (edge, kept camera) pairs in LDS and runs the bisection over that list in
-// passes of 64 pairs, so every lane tests one pair per pass however unevenly
-// the kept cameras fall on the edges; a pair's failing points are ORed into
-// its edge's LDS word and each lane then advances its own edge.  The n_steps
-// bisection steps run two at a time: a round tests the three points
-// lo + (1, 2, 3) w/4 of the bracket [lo, lo + w] and replays the two binary
-// steps from them -- the first step tests the midpoint (2), the second the
-// midpoint of the half it kept (3 if 2 was inside, else 1) -- so the final
-// bracket is exactly that of n_steps binary steps (all points are dyadic,
-// exact in float).  The bracket width w is the same for every edge.
-constexpr int kCullChunk = 4;      // cameras whose culling loads are in flight together
-constexpr int kBisectJobs = 64;    // jobs whose lattices a workgroup keeps in LDS
+// The window of rectangle r from the four tiled blocks around its corner
+// (b[0] = block (x0/8, y0/8), b[1] the next along x, b[2] the next along y,
+// b[3] both; absent ones 0): rows shifted up by y0 % 8, then each row's
+// pixels right by x0 % 8 with the next block's pixels shifted in.
+__device__ __forceinline__ uint64_t edge_window(const EdgeRect& r, const uint64_t* b) {
+    const int ox = r.x0 & 7, oy = 8 * (r.y0 & 7);
+    const uint64_t t0 = oy ? (b[0] >> oy) | (b[2] << (64 - oy)) : b[0];
+    const uint64_t t1 = oy ? (b[1] >> oy) | (b[3] << (64 - oy)) : b[1];
+    const uint64_t lo = (uint64_t)(0xffu >> ox) * 0x0101010101010101ull;
+    return ((t0 >> ox) & lo) | ((t1 << ((8 - ox) & 7)) & ~lo & (ox ? ~0ull : 0ull));
+}
 
-// An edge as the pair passes need it: the ON-end sample's coordinates, the
-// axis, the ON end's index along it (as float), the direction toward the OFF
-// end, the lattice spacing and origin on that axis, and the bracket start.
-struct EdgeRec {
-    float c[3];
-    float gq, d, h, o, lo;
-    int axis;
-    int pad_[3];
-};
+// Pixel of camera P for the point X (the occupancy test up to the silhouette
+// word): px, py and whether w > 0 and the pixel lies in the W x H image.
+__device__ __forceinline__ bool point_pixel(const float* P, float X, float Y, float Z, int W,
+                                            int H, int& px, int& py) {
+    const float a = __builtin_fmaf(P[2], Z, __builtin_fmaf(P[1], Y, __builtin_fmaf(P[0], X, P[3])));
+    const float b = __builtin_fmaf(P[6], Z, __builtin_fmaf(P[5], Y, __builtin_fmaf(P[4], X, P[7])));
+    const float w = __builtin_fmaf(P[10], Z, __builtin_fmaf(P[9], Y, __builtin_fmaf(P[8], X, P[11])));
+    const float r = __builtin_amdgcn_rcpf(w);
+    float qa = a * r, qb = b * r;
+    const bool tiny = w > 0.0f && w < 0x1p-64f;
+    if (__builtin_expect(__ballot(tiny) != 0, 0)) {
+        if (tiny) {
+            qa = a / w;
+            qb = b / w;
+        }
+    }
+    qa = __builtin_amdgcn_fmed3f(qa, -4.0f, (float)W + 4.0f);
+    qb = __builtin_amdgcn_fmed3f(qb, -4.0f, (float)H + 4.0f);
+    px = exact_floor(a, w, qa);
+    py = exact_floor(b, w, qb);
+    return (w > 0.0f) & ((unsigned)px < (unsigned)W) & ((unsigned)py < (unsigned)H);
+}
 
 template <int kCamsCap>
 __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __restrict__ jobs,
@@ -302,6 +356,7 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
                                                         const uint32_t* __restrict__ point_off,
                                                         const CamSet cams,
                                                         const uint32_t* __restrict__ sils,
+                                                        const uint64_t* __restrict__ tiles,
                                                         int n_steps,
                                                         const uint32_t* __restrict__ keys,
                                                         float* __restrict__ xyz,
@@ -309,9 +364,11 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
     constexpr int kWaves = kBlock / kWave;
     __shared__ uint32_t s_off[kBisectJobs + 1];
     __shared__ fvv_grid s_grid[kBisectJobs];
-    __shared__ float s_P[kCamsCap][12];
+    __shared__ float s_P[kCamsCap][13];              // P, then the rounding pad
     __shared__ EdgeRec s_rec[kWaves][kWave];
-    __shared__ uint16_t s_pair[kWaves][kWave * kCamsCap];
+    __shared__ uint16_t s_pair[kWaves][kWave * kCamsCap];   // kept (edge, camera) pairs
+    __shared__ uint64_t s_win[kWaves][kWinCap];
+    __shared__ uint32_t s_worg[kWaves][kWinCap];
     __shared__ uint32_t s_fail[kWaves][kWave];
     const int nj = (int)*n_jobs_p;
     const bool lds = nj <= kBisectJobs;
@@ -321,16 +378,22 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
             if (j < nj)
                 s_grid[j] = jobs[j].grid;
         }
-    for (int q = threadIdx.x; q < cams.n * 12; q += kBlock)
-        s_P[q / 12][q % 12] = cams.P[q / 12][q % 12];
+    for (int q = threadIdx.x; q < cams.n * 13; q += kBlock) {
+        const int c = q / 13, e = q - 13 * c;
+        s_P[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
+    }
     __syncthreads();
     const uint32_t total = lds ? s_off[nj] : point_off[nj];
     const uint32_t E = total < max_points ? total : max_points;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
+    const int tpr = (cams.W + 7) / 8;
+    const int64_t tpc = (int64_t)tpr * ((cams.H + 7) / 8);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     EdgeRec* const rec = s_rec[wave];
     uint16_t* const pairs = s_pair[wave];
+    uint64_t* const win = s_win[wave];
+    uint32_t* const worg = s_worg[wave];
     uint32_t* const fails = s_fail[wave];
     // contiguous edge ranges per XCD, in chunks of one block's edges
     const XcdSlice xs = xcd_slice((E + kBlock - 1) / kBlock);
@@ -364,46 +427,70 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
         const float o_axis = axis == 0 ? g.origin[0] : (axis == 1 ? g.origin[1] : g.origin[2]);
         const float c[3] = {lattice_coord(gx, g.h, g.origin[0]), lattice_coord(gy, g.h, g.origin[1]),
                             lattice_coord(gz, g.h, g.origin[2])};
-        const float x1a = lattice_coord(g_axis + 1, g.h, o_axis);
-        const float X0[3] = {c[0], c[1], c[2]};
-        const float X1[3] = {axis == 0 ? x1a : c[0], axis == 1 ? x1a : c[1],
-                             axis == 2 ? x1a : c[2]};
-        // cull: the cameras whose padded rectangle around the edge is not all
-        // foreground stay (the same camera on every lane: scalar loads)
-        uint32_t keep = 0;
-        for (int cb = 0; cb < cams.n; cb += kCullChunk) {
-            bool acc[kCullChunk];
-#pragma unroll
-            for (int u = 0; u < kCullChunk; ++u) {
-                const int cc = min(cb + u, cams.n - 1);
-                acc[u] = camera_accepts_edge(cams, cc, sils + cc * cam_words, X0, X1);
-            }
-#pragma unroll
-            for (int u = 0; u < kCullChunk; ++u)
-                if (cb + u < cams.n && !acc[u])
-                    keep |= 1u << (cb + u);
-        }
-        if (!act)
-            keep = 0;
-        // this lane's edge record and its pairs, listed wave-wide
         EdgeRec& mine = rec[lane];
         mine.c[0] = c[0];
         mine.c[1] = c[1];
         mine.c[2] = c[2];
+        mine.x1 = lattice_coord(g_axis + 1, g.h, o_axis);
         mine.gq = (float)g_on;
         mine.d = d;
         mine.h = g.h;
         mine.o = o_axis;
         mine.lo = 0.0f;
         mine.axis = axis;
-        const uint32_t cnt = (uint32_t)__builtin_popcount(keep);
-        const uint32_t incl = wave_inclusive_sum(cnt);
-        const uint32_t n_pairs = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
-        {
-            uint32_t pos = incl - cnt;
-            for (uint32_t m = keep; m; m &= m - 1)
-                pairs[pos++] = (uint16_t)((lane << 5) | (__ffs(m) - 1));
+        // cull: lane = edge, camera uniform (its matrix in scalar registers),
+        // kCullUnroll cameras' window loads in flight together; the kept
+        // pairs are listed camera by camera
+        const float X0[3] = {c[0], c[1], c[2]};
+        const float X1[3] = {axis == 0 ? mine.x1 : c[0], axis == 1 ? mine.x1 : c[1],
+                             axis == 2 ? mine.x1 : c[2]};
+        uint32_t n_pairs = 0;
+        for (int cb = 0; cb < cams.n; cb += kCullUnroll) {
+            EdgeRect rr[kCullUnroll];
+            uint64_t blk[kCullUnroll][4];
+#pragma unroll
+            for (int u = 0; u < kCullUnroll; ++u) {
+                const int cc = min(cb + u, cams.n - 1);
+                rr[u] = edge_rect(cams.Pc(cc), cams.padc(cc), cams.W, cams.H, X0, X1);
+                rr[u].small = rr[u].small && tiles != nullptr && act;
+                const bool sm = rr[u].small;
+                const int bx = rr[u].x0 >> 3, by = rr[u].y0 >> 3;
+                const bool nx = ((rr[u].x0 + rr[u].nx) >> 3) != bx;
+                const bool ny = ((rr[u].y0 + rr[u].ny) >> 3) != by;
+                const uint64_t* tb = tiles + cc * tpc + (int64_t)by * tpr + bx;
+                blk[u][0] = blk[u][1] = blk[u][2] = blk[u][3] = 0ull;
+                if (sm)
+                    blk[u][0] = tb[0];
+                if (sm && nx)
+                    blk[u][1] = tb[1];
+                if (sm && ny)
+                    blk[u][2] = tb[tpr];
+                if (sm && nx && ny)
+                    blk[u][3] = tb[tpr + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kCullUnroll; ++u) {
+                if (cb + u >= cams.n)
+                    break;
+                const uint64_t wv = edge_window(rr[u], blk[u]);
+                const uint64_t cols = (uint64_t)((2u << rr[u].nx) - 1u) * 0x0101010101010101ull;
+                const uint64_t m = cols & (~0ull >> (8 * (7 - rr[u].ny)));
+                const bool keep = act && !(rr[u].small && (wv & m) == m);
+                const uint64_t kb = __ballot(keep);
+                const uint32_t slot = n_pairs + lane_rank(kb);
+                if (keep) {
+                    pairs[slot] = (uint16_t)((lane << 5) | (cb + u));
+                    if (slot < (uint32_t)kWinCap) {
+                        win[slot] = rr[u].small ? wv : 0ull;
+                        worg[slot] = rr[u].small
+                                         ? ((uint32_t)rr[u].x0 | ((uint32_t)rr[u].y0 << 16))
+                                         : kNoWindow;
+                    }
+                }
+                n_pairs += (uint32_t)__popcll(kb);
+            }
         }
+        wave_lds_sync();
         float lo = 0.0f, w = 1.0f;
         for (int st = 0; st < n_steps; st += 2) {
             const bool two = st + 1 < n_steps;   // uniform
@@ -416,24 +503,43 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
                 const uint32_t pr = pairs[live ? pi : 0];
                 const int el = (int)(pr >> 5), ca = (int)(pr & 31u);
                 const EdgeRec& er = rec[el];
-                float Xp[3], Yp[3], Zp[3];
+                const bool cached = pi < (uint32_t)kWinCap;
+                const uint32_t org = cached ? worg[cached ? pi : 0] : kNoWindow;
+                const uint64_t wv = cached ? win[cached ? pi : 0] : 0ull;
+                const bool has_win = org != kNoWindow;
+                const int ox = (int)(org & 0xffffu), oy = (int)(org >> 16);
+                const float* P = s_P[ca];
+                const uint32_t* sc = sils + ca * cam_words;
+                uint32_t fail = 0u;
+                int px[3], py[3];
+                bool ok[3];
+                uint32_t word[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
+                    const bool on = two || q == 1;
                     const float t = er.lo + (float)(q + 1) * w4;
                     const float ax = __builtin_fmaf(er.gq + er.d * t, er.h, er.o);
-                    Xp[q] = er.axis == 0 ? ax : er.c[0];
-                    Yp[q] = er.axis == 1 ? ax : er.c[1];
-                    Zp[q] = er.axis == 2 ? ax : er.c[2];
+                    const float Xp = er.axis == 0 ? ax : er.c[0];
+                    const float Yp = er.axis == 1 ? ax : er.c[1];
+                    const float Zp = er.axis == 2 ? ax : er.c[2];
+                    ok[q] = false;
+                    word[q] = 0u;
+                    if (on) {
+                        ok[q] = point_pixel(P, Xp, Yp, Zp, cams.W, cams.H, px[q], py[q]);
+                        if (live && ok[q] && !has_win)
+                            word[q] = sc[py[q] * cams.wpr + (px[q] >> 5)];
+                    }
                 }
-                const float* P3[3] = {s_P[ca], s_P[ca], s_P[ca]};
-                const uint32_t* sc = sils + ca * cam_words;
-                const uint32_t* S3[3] = {sc, sc, sc};
-                uint32_t fail;
-                if (two)
-                    fail = ~multi_inside<3>(P3, Xp, Yp, Zp, S3, cams.W, cams.H, cams.wpr) & 7u;
-                else
-                    fail = (~multi_inside<1>(P3, Xp + 1, Yp + 1, Zp + 1, S3, cams.W, cams.H,
-                                             cams.wpr) & 1u) << 1;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const bool on = two || q == 1;
+                    if (!on)
+                        continue;
+                    const int sh = (8 * (py[q] - oy) + (px[q] - ox)) & 63;
+                    const bool in = ok[q] && (has_win ? ((wv >> sh) & 1ull) != 0ull
+                                                      : ((word[q] >> (px[q] & 31)) & 1u) != 0u);
+                    fail |= in ? 0u : (1u << q);
+                }
                 if (live && fail)
                     atomicOr(&fails[el], fail);
             }
@@ -464,34 +570,36 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
     }
 }
 
-hipError_t launch_edges(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+hipError_t launch_edges(const SurfaceScratch& sc, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                         uint32_t* keys, float* xyz, uint32_t max_points, uint32_t* point_off,
                         uint32_t* n_points, bool keys_out, bool word_edges, hipStream_t s) {
-    if (!keys_out && !word_edges)
+    if ((!keys_out && !word_edges) || (word_edges && !sc.word_edges))
         return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)(ctx->n_cus * 8);
-    hipLaunchKernelGGL(edge_count_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix,
-                       n_jobs_dev, ctx->d_finebits, ctx->d_item_cnt);
+    const unsigned blocks = (unsigned)(sc.n_cus * 8);
+    hipLaunchKernelGGL(edge_count_kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, sc.pre,
+                       n_jobs_dev, sc.finebits, sc.item_cnt);
     auto kernel = keys_out ? (word_edges ? edge_write_kernel<true, true>
                                          : edge_write_kernel<true, false>)
                            : edge_write_kernel<false, true>;
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, ctx->d_prefix, n_jobs_dev,
-                       ctx->d_finebits, ctx->d_item_cnt, keys, xyz, max_points, point_off,
-                       n_points, ctx->d_word_edges, ctx->d_status);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, s, jobs, sc.pre, n_jobs_dev,
+                       sc.finebits, sc.item_cnt, keys, xyz, max_points, point_off, n_points,
+                       sc.word_edges, sc.status);
     return hipGetLastError();
 }
 
-hipError_t launch_bisect(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+hipError_t launch_bisect(int n_cus, const fvv_job* jobs, const uint32_t* n_jobs_dev,
                          const uint32_t* point_off, const CamSet& cams, const uint32_t* sils,
-                         int n_steps, const uint32_t* keys, float* xyz, uint32_t max_points,
-                         hipStream_t s) {
+                         const uint64_t* tiles, int n_steps, const uint32_t* keys, float* xyz,
+                         uint32_t max_points, hipStream_t s, hipEvent_t k_start,
+                         hipEvent_t k_stop) {
     if (cams.n <= 16)
-        hipLaunchKernelGGL(bisect_kernel<16>, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s, jobs,
-                           n_jobs_dev, point_off, cams, sils, n_steps, keys, xyz, max_points);
+        hipExtLaunchKernelGGL(bisect_kernel<16>, dim3(n_cus * 8), dim3(kBlock), 0, s, k_start,
+                              k_stop, 0, jobs, n_jobs_dev, point_off, cams, sils, tiles, n_steps,
+                              keys, xyz, max_points);
     else
-        hipLaunchKernelGGL(bisect_kernel<FVV_MAX_CAMS>, dim3(ctx->n_cus * 8), dim3(kBlock), 0, s,
-                           jobs, n_jobs_dev, point_off, cams, sils, n_steps, keys, xyz,
-                           max_points);
+        hipExtLaunchKernelGGL(bisect_kernel<FVV_MAX_CAMS>, dim3(n_cus * 8), dim3(kBlock), 0, s,
+                              k_start, k_stop, 0, jobs, n_jobs_dev, point_off, cams, sils, tiles,
+                              n_steps, keys, xyz, max_points);
     return hipGetLastError();
 }
 

@@ -41,6 +41,9 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 CFG_TINY, CFG_VOLLEYBALL, CFG_JUDO, CFG_BATCHED = 1, 2, 3, 4
+# the paper's own volleyball shape (its lattice sizes and rig), and the judo
+# frame at a fine spacing that fills ~1e8 fine samples
+CFG_PAPER_V, CFG_JUDO_FINE = 5, 6
 UINT32_MAX = 0xFFFFFFFF
 
 
@@ -409,6 +412,38 @@ def scene_judo(frame: int) -> Scene:
                  noisy=True, groups=groups)
 
 
+def scene_paper_volleyball(frame: int) -> Scene:
+    """The shape of the paper's volleyball experiment: an 18 x 18 x 9 m volume,
+    coarse 50 mm (360 x 360 x 180 samples), fine 20 mm, 10 cameras of 3840 x
+    2160 with f about 3000 px, 14 players (7 per half of an 18 x 9 m court
+    in the middle of the volume, spacing >= 1 m)."""
+    lo, hi = np.array([-9.0, -9.0, 0.0]), np.array([9.0, 9.0, 9.0])
+    cams = _court_rig(CFG_PAPER_V, 0, 10, 3840, 2160, 2900.0, 3100.0, lo, hi)   # static rig
+    rng = rng_for(CFG_PAPER_V, frame, 1)
+    ells, groups = [], []
+    for p in _place_players(rng, 7, (0.8, 8.2), (-3.8, 3.8), 1.0):
+        yaw = rng.uniform(0, 2 * np.pi)
+        s = rng.uniform(0.9, 1.1)
+        lift = rng.uniform(0.2, 0.8) if rng.uniform() < 0.25 else 0.0
+        es = player(rng, p, yaw, s, lift)
+        groups.append(list(range(len(ells), len(ells) + len(es))))
+        ells += es
+    return Scene(name="paper_volleyball", cfg=CFG_PAPER_V, frame=frame, cams=cams,
+                 masks=render_masks(cams, ells), ellipsoids=ells, vol_lo=lo, vol_hi=hi,
+                 origin=lo.astype(np.float32), hc_um=50000, hf_um=20000,
+                 coarse_dims=(lattice_dims(18, 50000), lattice_dims(18, 50000),
+                              lattice_dims(9, 50000)),
+                 groups=groups)
+
+
+def scene_judo_fine(frame: int) -> Scene:
+    """The judo frame (rig, players, noise) with 2 mm fine voxels: ~1e8 fine
+    samples in its ROIs."""
+    sc = scene_judo(frame)
+    sc.name, sc.cfg, sc.hf_um = "judo_fine", CFG_JUDO_FINE, 2000
+    return sc
+
+
 def make_scene(cfg: int, frame: int) -> Scene:
     if cfg == CFG_TINY:
         return scene_tiny(frame)
@@ -416,6 +451,10 @@ def make_scene(cfg: int, frame: int) -> Scene:
         return scene_volleyball(frame)
     if cfg == CFG_JUDO:
         return scene_judo(frame)
+    if cfg == CFG_PAPER_V:
+        return scene_paper_volleyball(frame)
+    if cfg == CFG_JUDO_FINE:
+        return scene_judo_fine(frame)
     raise ValueError(f"no single-frame scene for cfg {cfg}")
 
 

@@ -464,7 +464,13 @@ def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, 
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(fvv.FRAME_EVENTS)]
         ctx.frame(params, sils, bufs, masks=masks, events=ev)
         torch.cuda.synchronize()
-        assert all(ev[i].elapsed_time(ev[i + 1]) >= 0 for i in range(fvv.FRAME_EVENTS - 1))
+        assert all(ev[i].elapsed_time(ev[i + 1]) >= 0
+                   for i in range(fvv.FRAME_STAGE_EVENTS - 1))
+        # each kernel's own time lies inside its stage's
+        for q, stage in enumerate(fvv.FRAME_KERNELS):
+            s = fvv.STAGES.index(stage)
+            k0, k1 = ev[fvv.FRAME_STAGE_EVENTS + 2 * q], ev[fvv.FRAME_STAGE_EVENTS + 2 * q + 1]
+            assert 0 < k0.elapsed_time(k1) <= ev[s].elapsed_time(ev[s + 1])
     return None, bufs, sils
 
 
@@ -632,3 +638,25 @@ def test_invalid_arguments_are_rejected(fvv, ctx, scene_cache):
         ctx.surface(good, dev(np.zeros((4, 4, 4), np.uint8)), sc.P32, sc.W, sc.H, sils, n_steps=13)
     with pytest.raises(fvv.FvvError):
         ctx.label(good, dev(np.zeros((4, 4, 4), np.uint8)), t_np=9, t_nb=8)
+
+
+# ------------------------------------------------------------------ paper-shaped frames
+@pytest.mark.parametrize("cfg", [scenes.CFG_PAPER_V, scenes.CFG_JUDO_FINE])
+def test_frame_paper_shapes(fvv, scene_cache, cfg):
+    """The paper's volleyball shape (10 cameras 3840x2160, an 18 x 18 x 9 m volume at
+    50 mm: 360 x 360 x 180 coarse samples, more rows than the labelling keeps in
+    LDS; 20 mm fine) and a judo frame at 2 mm (~1.9e8 fine samples in 6 ROIs, fine
+    bitmaps and job tables at that size) against the oracle, element by element."""
+    sc = scene_cache(cfg, 0)
+    res = oracle_frame(sc, cfg, 0)
+    c = fvv.Context(max_cams=sc.P32.shape[0], max_w=sc.W, max_h=sc.H,
+                    max_coarse=int(np.prod(sc.coarse_dims)), max_fine=1 << 28, max_rois=256,
+                    max_points=1 << 22, max_jobs=256)
+    try:
+        _, bufs, _ = run_frame(fvv, c, sc, max_rois=256, max_fine=1 << 28, max_points=1 << 22)
+        assert c.check() == fvv.FVV_OK
+        compare_frame(fvv, sc, bufs, res)
+        if cfg == scenes.CFG_JUDO_FINE:
+            assert res.fine_voxels > 100_000_000
+    finally:
+        c.close()
