@@ -187,6 +187,32 @@ fvv_status fvv_surface(fvv_ctx *ctx, const fvv_grid *roi, const uint8_t *d_occ_f
                        int32_t n_steps, uint32_t *d_keys, float *d_xyz, uint32_t max_points,
                        uint32_t *d_n_points, hipStream_t stream);
 
+/* Allocation-free variant of fvv_surface, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and kernels as fvv_surface,
+ * without a context.  Its scratch (the lattice's job table, crossing edges per
+ * work item, fine bitmap, and the silhouettes in 8 x 8-pixel blocks when
+ * n_cams * ceil(W / 8) * ceil(H / 8) <= FVV_NOALLOC_TILE_WORDS; larger rigs
+ * take a slower path of the same kernels) is one static device array of about
+ * 16 MiB on each GPU the library runs on, held until the process ends; the
+ * call allocates no device memory and calls no allocating library routine.
+ * Limits: the
+ * lattice's fine bitmap, ny * nz * ceil(nx / 64) words, at most
+ * FVV_NOALLOC_BITMAP_WORDS (else EINVAL); at most FVV_MAX_CAMS cameras of up
+ * to 65536 x 65536 pixels.  Capacity: *d_n_points always receives the edge
+ * count E, and only the first max_points edges are written when E exceeds it;
+ * with no context there is no sticky ECAPACITY, so compare *d_n_points with
+ * max_points.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (several streams or threads) race and must be serialised
+ * by the caller.  EDEVICE when the array's device address cannot be looked up
+ * or a launch fails. */
+#define FVV_NOALLOC_BITMAP_WORDS (1 << 20)
+#define FVV_NOALLOC_TILE_WORDS (1 << 20)
+fvv_status fvv_surface_noalloc(const fvv_grid *roi, const uint8_t *d_occ_fine, int32_t n_cams,
+                               const fvv_camera *cams, const uint32_t *d_sils, int32_t n_steps,
+                               uint32_t *d_keys, float *d_xyz, uint32_t max_points,
+                               uint32_t *d_n_points, hipStream_t stream);
+
 /* Batched fine carving (Sec. II-B-3 over many ROIs, of one or many frames) in
  * ONE persistent launch.  d_jobs: n_jobs jobs (device, <= max_jobs); d_cams:
  * device camera table; output bytes as each job states.  The output is

@@ -130,6 +130,8 @@ def _load():
         "fvv_roi_grids": ([C.POINTER(GridC), i64, i64, C.POINTER(Roi), u32, C.POINTER(GridC)], i32),
         "fvv_surface": ([P, C.POINTER(GridC), P, i32, C.POINTER(Camera), P, i32, P, P, u32, P, P],
                         i32),
+        "fvv_surface_noalloc": ([C.POINTER(GridC), P, i32, C.POINTER(Camera), P, i32, P, P, u32,
+                                 P, P], i32),
         "fvv_carve_batched": ([P, P, u32, P, P, P, C.POINTER(Tile), P], i32),
         "fvv_frame": ([P, C.POINTER(FrameParams), P, P, C.POINTER(FrameOut), P, P], i32),
         "fvv_frame_graph_create": ([P, C.POINTER(FrameParams), P, P, C.POINTER(FrameOut),
@@ -252,6 +254,24 @@ def roi_grids(coarse: Grid, hc_um: int, hf_um: int, rois: np.ndarray) -> List[Gr
 
 
 # ------------------------------------------------------------------ context
+NOALLOC_BITMAP_WORDS = 1 << 20
+
+
+def surface_noalloc(roi: Grid, occ_fine, P: np.ndarray, W: int, H: int, sils, keys, xyz,
+                    n_points, n_steps: int = 8, max_points: Optional[int] = None, stream=None):
+    """fvv_surface_noalloc: Context.surface without a context, into the
+    caller's keys (int32 [max_points]), xyz (float32 [max_points][3]) and
+    n_points (int32 [1]); the library uses its static per-GPU scratch."""
+    cams = make_cameras(P, W, H)
+    if max_points is None:
+        max_points = int(keys.numel())
+    _ok(_load().fvv_surface_noalloc(C.byref(roi.c()), _ptr(occ_fine), len(cams), cams,
+                                    _ptr(sils), int(n_steps), _ptr(keys), _ptr(xyz),
+                                    int(max_points), _ptr(n_points), C.c_void_p(_stream(stream))),
+        "fvv_surface_noalloc")
+    return keys, xyz, n_points
+
+
 class Context:
     """Owns the library's device scratch (all allocated up front)."""
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "fvv_internal.h"
@@ -160,7 +161,7 @@ hipError_t launch_surface_single(const SurfaceScratch& sc, const fvv_job& job,
     return e;
 }
 
-// Argument checks of fvv_surface on one lattice (the limits
+// Argument checks shared by fvv_surface and fvv_surface_noalloc (the limits
 // of the cameras and of the lattice's fine bitmap are the caller's).
 bool surface_args_ok(const fvv_grid* roi, const uint8_t* d_occ_fine, int32_t n_cams,
                      const fvv_camera* cams, const uint32_t* d_sils, int32_t n_steps,
@@ -169,6 +170,72 @@ bool surface_args_ok(const fvv_grid* roi, const uint8_t* d_occ_fine, int32_t n_c
     return d_occ_fine && d_sils && d_keys && d_xyz && d_n_points && max_points >= 1 &&
            n_steps >= 1 && n_steps <= FVV_MAX_STEPS && cams && n_cams >= 1 &&
            grid_ok(roi, 1 << (23 - n_steps)) && grid_samples(*roi) <= 1431655765LL;
+}
+
+// ------------------------------------------------------------------ allocation-free surface
+// The scratch of fvv_surface_noalloc: one array per device, laid out as the
+// SurfaceScratch fields in this order, each at a 256-byte boundary.  Host
+// code never passes `scratch` itself to a kernel (in host code the name is a
+// host-side stand-in); it uses the device address that hipGetSymbolAddress
+// returns for the current device.
+constexpr int64_t kNoAllocItems = FVV_NOALLOC_BITMAP_WORDS / kEdgeWords + 2;
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaJob = 0;
+constexpr size_t kNaPre = kNaJob + round256(sizeof(fvv_job));
+constexpr size_t kNaCounts = kNaPre + round256(2 * sizeof(JobPrefix));
+constexpr size_t kNaPointOff = kNaCounts + round256(4 * sizeof(uint32_t));
+constexpr size_t kNaStatus = kNaPointOff + round256(2 * sizeof(uint32_t));
+constexpr size_t kNaItems = kNaStatus + round256(sizeof(uint32_t));
+constexpr size_t kNaBits = kNaItems + round256((size_t)kNoAllocItems * sizeof(uint32_t));
+constexpr size_t kNaTiles = kNaBits + (size_t)FVV_NOALLOC_BITMAP_WORDS * sizeof(uint64_t);
+constexpr size_t kNaBytes = kNaTiles + (size_t)FVV_NOALLOC_TILE_WORDS * sizeof(uint64_t);
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kNoAllocDevices];   // device address of `scratch` per device
+int g_noalloc_cus[kNoAllocDevices];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+// Device address and CU count of the current device's scratch (looked up
+// once per device, under a lock).
+hipError_t noalloc_scratch(SurfaceScratch* out) {
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess)
+        return e;
+    if (d < 0 || d >= kNoAllocDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[d]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d);
+        if (e != hipSuccess)
+            return e;
+        g_noalloc_cus[d] = cus;
+        g_noalloc_ptr[d] = (unsigned char*)ptr;
+    }
+    unsigned char* p = g_noalloc_ptr[d];
+    out->job_single = (fvv_job*)(p + kNaJob);
+    out->pre = (JobPrefix*)(p + kNaPre);
+    out->counts_single = (uint32_t*)(p + kNaCounts);
+    out->point_off_single = (uint32_t*)(p + kNaPointOff);
+    out->status = (uint32_t*)(p + kNaStatus);
+    out->item_cnt = (uint32_t*)(p + kNaItems);
+    out->finebits = (uint64_t*)(p + kNaBits);
+    out->word_edges = nullptr;
+    out->tiles = (uint64_t*)(p + kNaTiles);
+    out->tile_cap = FVV_NOALLOC_TILE_WORDS;
+    out->n_cus = g_noalloc_cus[d];
+    return hipSuccess;
 }
 
 // Capture what `record` enqueues on a fresh stream into an instantiated graph.
@@ -463,6 +530,29 @@ fvv_status fvv_surface(fvv_ctx* ctx, const fvv_grid* roi, const uint8_t* d_occ_f
     job.height = cs.H;
     return dev(launch_surface_single(surface_scratch(ctx), job, d_occ_fine, cs, d_sils, n_steps,
                                      d_keys, d_xyz, max_points, d_n_points, stream));
+}
+
+fvv_status fvv_surface_noalloc(const fvv_grid* roi, const uint8_t* d_occ_fine, int32_t n_cams,
+                               const fvv_camera* cams, const uint32_t* d_sils, int32_t n_steps,
+                               uint32_t* d_keys, float* d_xyz, uint32_t max_points,
+                               uint32_t* d_n_points, hipStream_t stream) {
+    if (!surface_args_ok(roi, d_occ_fine, n_cams, cams, d_sils, n_steps, d_keys, d_xyz,
+                         max_points, d_n_points) ||
+        !cams_within(FVV_MAX_CAMS, 1 << 16, 1 << 16, n_cams, cams) ||
+        fine_bitmap_words(*roi) > FVV_NOALLOC_BITMAP_WORDS)
+        return FVV_EINVAL;
+    SurfaceScratch sc;
+    if (noalloc_scratch(&sc) != hipSuccess)
+        return FVV_EDEVICE;
+    const CamSet cs = make_camset(n_cams, cams, roi);
+    fvv_job job;
+    memset(&job, 0, sizeof(job));
+    job.grid = *roi;
+    job.n_cams = n_cams;
+    job.width = cs.W;
+    job.height = cs.H;
+    return dev(launch_surface_single(sc, job, d_occ_fine, cs, d_sils, n_steps, d_keys, d_xyz,
+                                     max_points, d_n_points, stream));
 }
 
 fvv_status fvv_carve_batched(fvv_ctx* ctx, const fvv_job* d_jobs, uint32_t n_jobs,
