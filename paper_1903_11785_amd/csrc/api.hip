@@ -303,23 +303,17 @@ void fvv_destroy(fvv_ctx* ctx) {
                     ctx->d_stats,
                     ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc, ctx->d_mesh_table,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
-                    ctx->d_word_edges, ctx->d_tri_cnt, ctx->d_point_off_single,
+                    ctx->d_word_edges, ctx->d_tri_first, ctx->d_point_off_single,
                     ctx->d_counts_single, ctx->d_tsils, ctx->d_rho};
     for (void* p : ptrs)
         if (p)
             hipFree(p);
-    if (ctx->ev_fork)
-        hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join)
         hipEventDestroy(ctx->ev_join);
     if (ctx->ev_fine)
         hipEventDestroy(ctx->ev_fine);
     if (ctx->ev_edges)
         hipEventDestroy(ctx->ev_edges);
-    if (ctx->ev_packed)
-        hipEventDestroy(ctx->ev_packed);
-    if (ctx->ev_tiled)
-        hipEventDestroy(ctx->ev_tiled);
     if (ctx->side)
         hipStreamDestroy(ctx->side);
     delete ctx;
@@ -361,7 +355,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     if (e == hipSuccess)           \
         e = alloc(&c->ptr, (n));
     A(d_status, 1)
-    A(d_counter, 4)
+    A(d_counter, kCounters)
     A(d_rowbits, n_rowbits)
     A(d_rowmask, n_rowmask)
     A(d_rmpre, n_rowmask)
@@ -382,7 +376,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_finebits, c->bit_cap)
     A(d_item_cnt, c->item_cap)
     A(d_word_edges, c->bit_cap)
-    A(d_tri_cnt, c->item_cap)
+    A(d_tri_first, c->item_cap)
     A(d_point_off_single, 2)
     A(d_counts_single, 4)
     A(d_tsils, tiled_sil_words(lim->max_cams, lim->max_w, lim->max_h))
@@ -391,17 +385,11 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess)
         e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&c->ev_fine, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&c->ev_edges, hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&c->ev_packed, hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&c->ev_tiled, hipEventDisableTiming);
     if (e == hipSuccess) {
         MeshTable tbl;
         build_mesh_table(&tbl);
@@ -410,6 +398,8 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     // scratch the kernels expect cleared (they clear it again after use)
     if (e == hipSuccess)
         e = hipMemset(c->d_status, 0, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(c->d_counter, 0, kCounters * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMemset(c->d_rowbits, 0, (size_t)n_rowbits * sizeof(uint64_t));
     if (e == hipSuccess)
@@ -724,19 +714,13 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     auto kev = [&](int i) -> hipEvent_t { return events ? events[FVV_FRAME_STAGE_EVENTS + i] : nullptr; };
     hipError_t e = hipSuccess;
     mark(0);
+    // the packed rows, and the 8 x 8-pixel blocks the fine carve and the exit
+    // points read
     if (d_masks)
-        e = launch_pack(p->n_cams, cs.W, cs.H, d_masks, d_sils, stream);
+        e = launch_pack_tiled(p->n_cams, cs.W, cs.H, d_masks, d_sils, ctx->d_tsils, stream);
+    else
+        e = launch_tile_sils(p->n_cams, cs.W, cs.H, d_sils, ctx->d_tsils, stream);
     mark(1);
-    // the tiled silhouettes of the fine carve and the exit points, on the side
-    // branch beside the coarse carve and the labelling
-    if (e == hipSuccess)
-        e = hipEventRecord(ctx->ev_packed, stream);
-    if (e == hipSuccess)
-        e = hipStreamWaitEvent(ctx->side, ctx->ev_packed, 0);
-    if (e == hipSuccess)
-        e = launch_tile_sils(p->n_cams, cs.W, cs.H, d_sils, ctx->d_tsils, ctx->side);
-    if (e == hipSuccess)
-        e = hipEventRecord(ctx->ev_tiled, ctx->side);
     // the coarse carve also fills the labelling's row bitmap
     const RowBits rb = row_bits(ctx, p->coarse);
     if (e == hipSuccess)
@@ -761,16 +745,10 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = launch_label(ctx, p->coarse, o->d_occ_coarse, nullptr, p->t_np, p->t_nb, o->d_rois,
                          o->max_rois, o->d_counts + 0, true, &fj, stream);
     mark(3);
-    // the grid pass writing labels and the filtered coarse occupancy runs on a
-    // side branch, beside the fine stage, which needs only the ROI table
+    // the grid pass writing labels and the filtered coarse occupancy (on the
+    // same stream: a branch to the side stream and back costs more than it)
     if (e == hipSuccess)
-        e = hipEventRecord(ctx->ev_fork, stream);
-    if (e == hipSuccess)
-        e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-    if (e == hipSuccess)
-        e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, ctx->side);
-    if (e == hipSuccess)
-        e = hipStreamWaitEvent(stream, ctx->ev_tiled, 0);
+        e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, stream);
     if (e == hipSuccess)
         e = launch_carve_frame(ctx, o->d_jobs, cs, d_sils, ctx->d_tsils, o->d_occ_fine,
                                ctx->d_finebits, ft, blocks, stream, kev(0), kev(1));
@@ -797,7 +775,7 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = launch_mesh_write(ctx, o->d_jobs, n_jobs, o->d_keys, o->d_counts + 2, o->max_points,
                               false, o->d_tris, o->max_tris, o->d_tri_off, nullptr, 0,
                               ctx->side);
-    if (e == hipSuccess)
+    if (mesh && e == hipSuccess)
         e = hipEventRecord(ctx->ev_join, ctx->side);
     if (e == hipSuccess && p->exit_estimator == FVV_EXIT_BRESENHAM)
         e = launch_isovalue_jobs(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, o->d_keys,
@@ -806,7 +784,7 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = launch_bisect(ctx->n_cus, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils,
                           ctx->d_tsils, p->n_steps, o->d_keys, o->d_xyz,
                           o->max_points, stream, kev(2), kev(3));
-    if (e == hipSuccess)
+    if (mesh && e == hipSuccess)
         e = hipStreamWaitEvent(stream, ctx->ev_join, 0);
     mark(6);
     return dev(e);

@@ -136,6 +136,76 @@ __global__ __launch_bounds__(kBlock) void tile_sils_kernel(const uint32_t* __res
 }
 
 
+// Both forms at once, straight from the masks, for images whose width is a
+// multiple of 8: one thread per 8 x 8-pixel block reads its 8 rows of 8 bytes
+// (a wave covers 512 contiguous bytes of each row), stores the block's word
+// and the block's byte of each of its 8 packed rows (the row's last block also
+// clears the padding bytes of the row's last word).  k32: every block index
+// fits 32 bits (split by multiply and shifts).
+template <bool k32>
+__global__ __launch_bounds__(kBlock) void pack_tiled_kernel(const uint8_t* __restrict__ masks,
+                                                            int n, int W, int H, int wpr,
+                                                            int tpr, int tph, DivU32 by_tpr,
+                                                            DivU32 by_tph,
+                                                            uint32_t* __restrict__ sils,
+                                                            uint64_t* __restrict__ tiles) {
+    const int64_t total = (int64_t)n * tph * tpr;
+    uint8_t* const rows = reinterpret_cast<uint8_t*>(sils);
+    const int row_bytes = 4 * wpr;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t cb, c;
+        if (k32) {
+            cb = divu32((uint32_t)idx, by_tpr);
+            c = divu32((uint32_t)cb, by_tph);
+        } else {
+            cb = idx / tpr;
+            c = cb / tph;
+        }
+        const int bx = (int)(idx - cb * tpr);
+        const int by = (int)(cb - c * tph);
+        const int y0 = 8 * by;
+        const int nr = min(8, H - y0);
+        const uint8_t* src = masks + ((int64_t)c * H + y0) * W + 8 * bx;
+        uint8_t* dst = rows + ((int64_t)c * H + y0) * row_bytes + bx;
+        uint64_t v = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (r < nr) {
+                const uint2 q = *reinterpret_cast<const uint2*>(src + (int64_t)r * W);
+                const uint32_t b = nonzero_bytes(q.x) | (nonzero_bytes(q.y) << 4);
+                v |= (uint64_t)b << (8 * r);
+                dst[(int64_t)r * row_bytes] = (uint8_t)b;
+                if (bx == tpr - 1)
+                    for (int k = tpr; k < row_bytes; ++k)
+                        dst[(int64_t)r * row_bytes + (k - bx)] = 0;
+            }
+        }
+        tiles[idx] = v;
+    }
+}
+
+hipError_t launch_pack_tiled(int n, int W, int H, const uint8_t* masks, uint32_t* sils,
+                             uint64_t* tiles, hipStream_t s) {
+    if (W % 8 != 0 || reinterpret_cast<uintptr_t>(masks) % 8 != 0) {
+        hipError_t e = launch_pack(n, W, H, masks, sils, s);
+        return e == hipSuccess ? launch_tile_sils(n, W, H, sils, tiles, s) : e;
+    }
+    const int wpr = (W + 31) / 32, tpr = W / 8, tph = (H + 7) / 8;
+    const int64_t total = (int64_t)n * tph * tpr;
+    int64_t blocks = (total + kBlock - 1) / kBlock;
+    blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
+    const DivU32 dx = divu32_magic((uint32_t)tpr), dy = divu32_magic((uint32_t)tph);
+    if (total + (int64_t)blocks * kBlock <= ((int64_t)1 << 32))
+        hipLaunchKernelGGL(pack_tiled_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           masks, n, W, H, wpr, tpr, tph, dx, dy, sils, tiles);
+    else
+        hipLaunchKernelGGL(pack_tiled_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           masks, n, W, H, wpr, tpr, tph, dx, dy, sils, tiles);
+    return hipGetLastError();
+}
+
+
 hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,
                             hipStream_t s) {
     const int wpr = (W + 31) / 32, tpr = (W + 7) / 8, tph = (H + 7) / 8;

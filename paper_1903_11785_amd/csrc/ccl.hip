@@ -133,14 +133,15 @@ __device__ __forceinline__ void fine_job_radii(const FrameJobs& fj, const uint32
             slack = fmax(slack, fmax(fabs(lo[a]), fabs(hi[a])));
         slack *= 0x1p-20;
         const double eb[3] = {1.5 * h + slack, 1.5 * h + slack, 1.5 * h + slack};
+        const BoxProj bp = box_projection(fj.cams.P[c], lo, hi);
         double ru, rv;
-        box_radius(fj.cams.P[c], lo, hi, eb, &ru, &rv);
+        box_radius(fj.cams.P[c], bp, eb, &ru, &rv);
         out[0] = rho_rect(ru, pad);
         out[1] = rho_rect(rv, pad);
         for (int a = 0; a < 3; ++a) {
             double ee[3] = {slack, slack, slack};
             ee[a] = 0.5 * h + slack;
-            box_radius(fj.cams.P[c], lo, hi, ee, &ru, &rv);
+            box_radius(fj.cams.P[c], bp, ee, &ru, &rv);
             out[2 + 2 * a] = rho_rect(ru, pad);
             out[3 + 2 * a] = rho_rect(rv, pad);
         }
@@ -310,6 +311,29 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
 }
 
 // ------------------------------------------------------------------ run labelling
+// Measurement builds (FVV_LABEL_PHASES defined) record, from thread 0 of the
+// labelling workgroup, the real-time clock (100 MHz) at the end of each phase
+// of the last labelling into label_phase_stamps: [0] entry, [1] row mask
+// counted, [2] rows listed, [3] runs cut, [4] runs united, [5] forest
+// flattened and roots numbered, [6] stats, filter and ROI table, [7] labels
+// written and the bitmap cleared, [8] the fine jobs laid out.
+constexpr int kLabelPhases = 9;
+#ifdef FVV_LABEL_PHASES
+__device__ uint64_t label_phase_stamps[kLabelPhases];
+__device__ __forceinline__ void label_stamp(int i) {
+    if (threadIdx.x == 0)
+        label_phase_stamps[i] = __builtin_amdgcn_s_memrealtime();
+}
+// A stamp where no barrier ends the phase: the barrier, then the stamp.
+__device__ __forceinline__ void label_stamp_sync(int i) {
+    __syncthreads();
+    label_stamp(i);
+}
+#else
+__device__ __forceinline__ void label_stamp(int) {}
+__device__ __forceinline__ void label_stamp_sync(int) {}
+#endif
+
 constexpr int kMaskCap = 1024;   // row-mask words held in LDS (grids of up to 65536 rows)
 constexpr int kRowWords = 4;     // row-bitmap words a thread keeps in registers
 
@@ -525,6 +549,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
             m.rows[pos++] = w * 64 + (__ffsll((unsigned long long)b) - 1);
     }
     __syncthreads();
+    label_stamp(2);
     // 2. runs of each row, numbered in raster order: a run starts at a set
     //    bit whose left neighbour is clear and ends at one whose right
     //    neighbour is clear
@@ -590,10 +615,12 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     if (threadIdx.x == 0)
         m.rs[n_rows] = n_runs;
     __syncthreads();
+    label_stamp(3);
     // 3. unite every run with the adjacent runs of its earlier neighbouring rows
     for (int32_t k = threadIdx.x; k < n_runs; k += NT)
         for_each_earlier_adjacent<kLds>(a, m, k, [&](int32_t b) { unite<kLds>(m.P, k, b); });
     __syncthreads();
+    label_stamp(4);
     // 4. flatten, then number the roots in ascending run id.  The walk only
     //    reads: the sole writes now set a node to its root, which keeps every
     //    concurrent walk on course (path halving here could store a
@@ -616,6 +643,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         K_all += (int32_t)total;
     }
     __syncthreads();
+    label_stamp(5);
     // 5. stats, filter, ROI table (stats rows in LDS while the components fit;
     //    the label of each rank follows the rows)
     uint32_t K = 0;
@@ -627,6 +655,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         stats_and_select<kLds, false>(a, m, n_runs, K_all, a.gstats,
                                       a.gstats + (int64_t)kStatsRow * K_all, a.g.rs, scan, &K);
     __syncthreads();
+    label_stamp(6);
     // 6. labels of the occupied samples; the bitmap cleared for the next call
     for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
         const int64_t row_lin = (int64_t)a.nx * m.rows[m.rrow[k]];
@@ -651,6 +680,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     }
     if (kJobs) {
         __syncthreads();
+        label_stamp(7);
         auto box = [&](uint32_t t, int32_t* lo, int32_t* hi) {
             if (lds_stats_ok) {
                 const int32_t* s = lds_stats + (int64_t)kStatsRow * m.rs[t];
@@ -669,6 +699,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
             }
         };
         build_fine_jobs<NT>(fj, box, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);
+        label_stamp_sync(8);
     }
     return true;
 }
@@ -685,6 +716,7 @@ __global__ __launch_bounds__(kLabelThreads) void label_runs_kernel(const LabelAr
     __shared__ int32_t s_P[kRunCap];
     __shared__ int32_t s_stats[kStatsRow * kRootCap + kRootCap];   // rows, then labels
     __shared__ uint32_t s_scan[kLabelThreads / kWave];
+    label_stamp(0);
     const int32_t R = a.ny * a.nz;
     const int32_t n_rm = (R + 63) / 64;
     const bool lds_ok = n_rm <= kMaskCap && a.nx <= 65535;
@@ -703,6 +735,7 @@ __global__ __launch_bounds__(kLabelThreads) void label_runs_kernel(const LabelAr
         n_rows += (int32_t)total;
     }
     __syncthreads();
+    label_stamp(1);
     if (lds_ok && n_rows <= kRowCap) {
         const RunArrays m{s_rm, s_rmpre, s_rows, s_rs, nullptr, nullptr, s_xx, s_rrow, s_P};
         if (label_body<true, kJobs>(a, fj, m, n_rows, s_stats, s_scan))
@@ -801,3 +834,15 @@ hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int
 }
 
 }  // namespace fvv
+
+#ifdef FVV_LABEL_PHASES
+// Measurement builds only: the last labelling's phase stamps to host memory
+// (out: at least 9 entries).
+extern "C" int32_t fvv_label_phase_stamps(uint64_t* out, int32_t n) {
+    if (!out || n < fvv::kLabelPhases)
+        return FVV_EINVAL;
+    const hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(fvv::label_phase_stamps),
+                                             sizeof(uint64_t) * fvv::kLabelPhases);
+    return e == hipSuccess ? FVV_OK : FVV_EDEVICE;
+}
+#endif

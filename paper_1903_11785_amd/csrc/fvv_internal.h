@@ -16,6 +16,10 @@ constexpr int kBlock = 256;              // threads per workgroup everywhere
 constexpr int kEdgeWords = 256;          // fine-bitmap words per crossing-edge work item
 constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits: an output capacity
 constexpr uint32_t kFlagJob = 2u;        // was exceeded; a batched job was out of range
+// Work counters of a context: [0] next work item, [1] tiles per item, [2] jobs
+// (persistent carve); [kCounterMesh] workgroups of the triangle count done.
+constexpr int kCounters = 8;
+constexpr int kCounterMesh = 4;
 
 // Projections of a camera rig passed by value in the kernel arguments.
 // pad[c] bounds, for every point of the lattice box the call works in, how far
@@ -86,18 +90,16 @@ __host__ __device__ inline float rounding_pad(const float* P, int W, int H, cons
     return (float)pad * (1.0f + 0x1p-20f);
 }
 
-// Bounds (pixels, u then v) on how far the real projection of camera P moves
-// within a box of half-extents e (world units) around any point of the world
-// box [lo, hi]: with d = X - C, u(C + d) - u(C) = (A.d - u(C) W.d) / w(C + d),
-// A and W the first three entries of P's first and third rows (the second row
-// for v), u(C) within the range of u over the box's corners (u is monotone
-// along every segment where w > 0) and w at least its minimum over the corners.
-// Double precision, no contraction, with a relative slack; INFINITY where w
-// is not positive over the box.
-__host__ __device__ inline void box_radius(const float* P, const double lo[3], const double hi[3],
-                                           const double e[3], double* ru, double* rv) {
+// The corners' range of u and v and minimum of w (box_radius's first step,
+// shared by the radii of several half-extents over one box).
+struct BoxProj {
+    double umin, umax, vmin, vmax, wmin;
+};
+
+__host__ __device__ inline BoxProj box_projection(const float* P, const double lo[3],
+                                                  const double hi[3]) {
 #pragma clang fp contract(off)
-    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, wmin = INFINITY;
+    BoxProj b{INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY};
     for (int corner = 0; corner < 8; ++corner) {
         const double X[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1],
                              (corner & 4) ? hi[2] : lo[2]};
@@ -107,15 +109,30 @@ __host__ __device__ inline void box_radius(const float* P, const double lo[3], c
             for (int k = 0; k < 3; ++k)
                 r[q] += (double)P[4 * q + k] * X[k];
         }
-        wmin = fmin(wmin, r[2]);
+        b.wmin = fmin(b.wmin, r[2]);
         if (r[2] > 0.0) {
-            umin = fmin(umin, r[0] / r[2]);
-            umax = fmax(umax, r[0] / r[2]);
-            vmin = fmin(vmin, r[1] / r[2]);
-            vmax = fmax(vmax, r[1] / r[2]);
+            b.umin = fmin(b.umin, r[0] / r[2]);
+            b.umax = fmax(b.umax, r[0] / r[2]);
+            b.vmin = fmin(b.vmin, r[1] / r[2]);
+            b.vmax = fmax(b.vmax, r[1] / r[2]);
         }
     }
-    if (!(wmin > 0.0)) {
+    return b;
+}
+
+// Bounds (pixels, u then v) on how far the real projection of camera P moves
+// within a box of half-extents e (world units) around any point of the world
+// box [lo, hi] (b: box_projection over it): with d = X - C,
+// u(C + d) - u(C) = (A.d - u(C) W.d) / w(C + d), A and W the first three
+// entries of P's first and third rows (the second row for v), u(C) within the
+// range of u over the box's corners (u is monotone along every segment where
+// w > 0) and w at least its minimum over the corners.
+// Double precision, no contraction, with a relative slack; INFINITY where w
+// is not positive over the box.
+__host__ __device__ inline void box_radius(const float* P, const BoxProj& b, const double e[3],
+                                           double* ru, double* rv) {
+#pragma clang fp contract(off)
+    if (!(b.wmin > 0.0)) {
         *ru = INFINITY;
         *rv = INFINITY;
         return;
@@ -123,11 +140,11 @@ __host__ __device__ inline void box_radius(const float* P, const double lo[3], c
     double su = 0.0, sv = 0.0;
     for (int k = 0; k < 3; ++k) {
         const double wk = (double)P[8 + k];
-        su += e[k] * fmax(fabs((double)P[k] - umin * wk), fabs((double)P[k] - umax * wk));
-        sv += e[k] * fmax(fabs((double)P[4 + k] - vmin * wk), fabs((double)P[4 + k] - vmax * wk));
+        su += e[k] * fmax(fabs((double)P[k] - b.umin * wk), fabs((double)P[k] - b.umax * wk));
+        sv += e[k] * fmax(fabs((double)P[4 + k] - b.vmin * wk), fabs((double)P[4 + k] - b.vmax * wk));
     }
-    *ru = su / wmin * (1.0 + 1e-9) + 1e-9;
-    *rv = sv / wmin * (1.0 + 1e-9) + 1e-9;
+    *ru = su / b.wmin * (1.0 + 1e-9) + 1e-9;
+    *rv = sv / b.wmin * (1.0 + 1e-9) + 1e-9;
 }
 
 // Radii of a frame's ROI lattices per (job, camera), kRhoPer floats each: the
@@ -527,18 +544,17 @@ struct fvv_ctx {
     float* d_rho;                // a frame's radii per (job, camera), kRhoPer floats each
     uint32_t* d_item_cnt;        // crossing edges per work item
     fvv::WordEdges* d_word_edges;  // per fine-bitmap word (bit_cap), for the mesh
-    uint32_t* d_tri_cnt;         // triangles per work item
+    uint64_t* d_tri_first;       // first triangle of each work item
     uint32_t* d_point_off_single;
     uint32_t* d_counts_single;
     int64_t item_cap;
     int64_t job_cap;
     int64_t bit_cap;
     int n_cus;
-    // side branch of a frame (work off the critical path), default priority
+    // side branch of a frame's mesh (off the critical path), default priority
     hipStream_t side;
-    hipEvent_t ev_fork, ev_join;
+    hipEvent_t ev_join;            // the mesh branch done
     hipEvent_t ev_fine, ev_edges;  // a frame's mesh branch: fine bitmaps, keys ready
-    hipEvent_t ev_packed, ev_tiled;  // packed rows ready; tiled silhouettes ready
 };
 
 namespace fvv {
@@ -691,6 +707,10 @@ hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& c
 // packed rows.
 hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,
                             hipStream_t s);
+// Pack the masks into both forms (packed rows and 8 x 8-pixel blocks) in one
+// pass where the width is a multiple of 8, else by the two kernels in turn.
+hipError_t launch_pack_tiled(int n, int W, int H, const uint8_t* masks, uint32_t* sils,
+                             uint64_t* tiles, hipStream_t s);
 // Words of the tiled silhouettes of n cameras of W x H pixels.
 inline int64_t tiled_sil_words(int n, int W, int H) {
     return (int64_t)n * ((W + 7) / 8) * ((H + 7) / 8);

@@ -164,19 +164,26 @@ __device__ __forceinline__ uint32_t cell_triangles(const CellRows& c, const Mesh
     return n;
 }
 
-// Per work item: its number of triangles.
+// Per work item: its number of triangles.  The last workgroup to finish
+// (counted on `arrived`, zero on entry) turns the counts into each item's
+// first triangle, an exclusive scan in place, and sets `arrived` back to zero.
 __global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_job* __restrict__ jobs,
                                                             const JobPrefix* __restrict__ pre,
                                                             const uint32_t* __restrict__ n_jobs_p,
                                                             const uint64_t* __restrict__ bits,
                                                             const MeshTable* __restrict__ tbl,
-                                                            uint32_t* __restrict__ tri_cnt) {
+                                                            uint64_t* __restrict__ tri_first,
+                                                            uint32_t* __restrict__ arrived) {
     __shared__ uint32_t table[kJobTable];
     __shared__ uint32_t scratch[kBlock / kWave];
+    __shared__ uint64_t scratch64[kBlock / kWave];
     __shared__ MeshTable s_tbl;
+    __shared__ bool s_last;
     const int nj = (int)*n_jobs_p;
-    if (blockIdx.x >= pre[nj].item_off)    // no item for this workgroup
+    const uint32_t items_all = pre[nj].item_off;
+    if (blockIdx.x >= items_all)           // no item for this workgroup
         return;
+    const uint32_t active = gridDim.x < items_all ? gridDim.x : items_all;
     load_table(tbl, &s_tbl);
     const ItemJobs ij = load_item_jobs(pre, nj, table);
     const uint32_t n_items = ij.first_item(nj);
@@ -191,8 +198,31 @@ __global__ __launch_bounds__(kBlock) void mesh_count_kernel(const fvv_job* __res
         uint32_t total;
         block_exclusive_sum<kBlock>(n, scratch, &total);
         if (threadIdx.x == 0)
-            tri_cnt[item] = total;
+            tri_first[item] = total;
     }
+    __threadfence();                        // the counts, before the arrival
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = atomicAdd(arrived, 1u) == active - 1;
+    __syncthreads();
+    if (!s_last)
+        return;
+    __threadfence();                        // every workgroup's counts, after its arrival
+    uint64_t carry = 0;
+    for (uint32_t b0 = 0; b0 < n_items; b0 += kBlock) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint64_t v = i < n_items
+                               ? __hip_atomic_load(tri_first + i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : 0ull;
+        uint64_t all;
+        const uint64_t ex = block_exclusive_sum64<kBlock>(v, scratch64, &all);
+        if (i < n_items)
+            tri_first[i] = carry + ex;
+        carry += all;
+    }
+    if (threadIdx.x == 0)
+        *arrived = 0;
 }
 
 // A cell listed for the write pass: the lane of its word in the wave, its bit,
@@ -203,8 +233,8 @@ __device__ __forceinline__ uint2 cell_rec(int lane, int b, int cs, uint32_t t) {
     return make_uint2((uint32_t)lane | (uint32_t)b << 6 | (uint32_t)cs << 12, t);
 }
 
-// Per work item: first triangle = the triangles of the earlier items, then a
-// scan over the threads gives each word's first triangle.  The words' cells
+// Per work item: its first triangle from the count pass, then a scan over the
+// threads gives each word's first triangle.  The words' cells
 // are then spread over the wave's lanes: each lane lists its word's cells
 // (bit, pattern, first triangle) in the wave's LDS records, and every lane
 // takes every 64th record.  A vertex on cell edge 4 a + u + 2 v has its edge's
@@ -219,14 +249,13 @@ template <bool kVerify>
 __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
     const fvv_job* __restrict__ jobs, const JobPrefix* __restrict__ pre,
     const uint32_t* __restrict__ n_jobs_p, const uint64_t* __restrict__ bits,
-    const MeshTable* __restrict__ tbl, const uint32_t* __restrict__ tri_cnt,
+    const MeshTable* __restrict__ tbl, const uint64_t* __restrict__ tri_first,
     const WordEdges* __restrict__ wedges, const uint32_t* __restrict__ keys,
     const uint32_t* __restrict__ n_keys_p, uint32_t max_keys, uint32_t* __restrict__ tris,
     uint32_t max_tris, uint32_t* __restrict__ tri_off, uint32_t* __restrict__ n_tris,
     uint32_t* __restrict__ status) {
     constexpr int kWaves = kBlock / kWave;
     __shared__ uint32_t table[kJobTable];
-    __shared__ uint64_t scratch64[kWaves];
     __shared__ uint32_t scratch[kWaves];
     __shared__ MeshTable s_tbl;
     __shared__ uint32_t s_pos[12][kBlock];
@@ -252,11 +281,7 @@ __global__ __launch_bounds__(kBlock) void mesh_write_kernel(
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        uint64_t before = 0;
-        for (uint32_t i = threadIdx.x; i < item; i += kBlock)
-            before += tri_cnt[i];
-        uint64_t first;
-        block_exclusive_sum64<kBlock>(before, scratch64, &first);
+        const uint64_t first = tri_first[item];
         const int jb = ij.job_of(item);
         const fvv_grid g = jobs[jb].grid;
         const int32_t wr = (g.dims[0] + 63) / 64;
@@ -398,7 +423,7 @@ hipError_t launch_mesh_count(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* 
     hipLaunchKernelGGL(mesh_count_kernel, dim3(mesh_grid(ctx, 8, items_hint)), dim3(kBlock), 0, s,
                        jobs,
                        ctx->d_prefix, n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table,
-                       ctx->d_tri_cnt);
+                       ctx->d_tri_first, ctx->d_counter + kCounterMesh);
     return hipGetLastError();
 }
 
@@ -409,7 +434,7 @@ hipError_t launch_mesh_write(fvv_ctx* ctx, const fvv_job* jobs, const uint32_t* 
     auto kernel = verify ? mesh_write_kernel<true> : mesh_write_kernel<false>;
     hipLaunchKernelGGL(kernel, dim3(mesh_grid(ctx, 2, items_hint)), dim3(kBlock), 0, s, jobs,
                        ctx->d_prefix,
-                       n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table, ctx->d_tri_cnt,
+                       n_jobs_dev, ctx->d_finebits, ctx->d_mesh_table, ctx->d_tri_first,
                        ctx->d_word_edges, keys, n_keys, max_keys, tris, max_tris, tri_off, n_tris,
                        ctx->d_status);
     return hipGetLastError();

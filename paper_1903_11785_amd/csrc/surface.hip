@@ -240,30 +240,35 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
 // quotients here come from rcp, whose error the pad also covers).  Such a
 // camera is left out of the edge's bisection.
 //
-// One wave takes 64 edges, one per lane.  Each lane forms, camera after
-// camera (kCullUnroll cameras' silhouette loads in flight together), its
-// edge's padded rectangle; one of at most 8 x 8 pixels inside the image gets
-// the rectangle's pixels as one 64-bit window (bit 8 r + c = pixel (x0 + c,
+// A workgroup takes 64 edges at a time.  Its first wave decodes them (one
+// per lane) into LDS records.  The cull then spreads the (edge, camera) pairs
+// over the four waves: wave v takes cameras v, v + 4, ... (each camera's
+// matrix uniform, in scalar registers), lane = edge, kCullUnroll cameras'
+// loads in flight together, so each wave works through a quarter of the rig.
+// A pair's padded rectangle of at most 8 x 8 pixels inside the image gets the
+// rectangle's pixels as one 64-bit window (bit 8 r + c = pixel (x0 + c,
 // y0 + r) from its top-left corner), built from the 2 x 2 blocks of the tiled
 // silhouettes around it: the camera is dropped when the rectangle is all
-// foreground, else the (edge, camera) pair is listed in LDS with its window.
-// Cameras with larger rectangles are listed without a window.
-// The bisection then runs over the kept pairs in passes of 64: a pair's lane
+// foreground, else the pair is appended to the workgroup's LDS list with its
+// window.  Cameras with larger rectangles are listed without a window.
+// The bisection then runs over the kept pairs, 256 at a time: a pair's lane
 // tests its camera at the round's points and ORs the failing points into the
-// edge's LDS word; each edge's lane then advances its bracket.  Every tested
-// point's pixel lies in its pair's rectangle, so a pair with a window reads
-// the pixel from it: the rounds make no memory access but LDS, except for
-// pairs without a window (which load the packed row word, as the plain test).
-// Without tiled silhouettes (tiles NULL) every candidate is kept without a
-// window.  The n_steps bisection steps run two at a time: a round tests the
-// three points lo + (1, 2, 3) w/4 of the bracket [lo, lo + w] and replays the
-// two binary steps from them -- the first step tests the midpoint (2), the
-// second the midpoint of the half it kept (3 if 2 was inside, else 1) -- so
-// the final bracket is exactly that of n_steps binary steps (all points are
-// dyadic, exact in float).  The bracket width w is the same for every edge.
+// edge's LDS word; the first wave then advances each edge's bracket.  Every
+// tested point's pixel lies in its pair's rectangle, so a pair with a window
+// reads the pixel from it: the rounds make no memory access but LDS, except
+// for pairs without a window (which load the packed row word, as the plain
+// test).  Without tiled silhouettes (tiles NULL) every candidate is kept
+// without a window.  The n_steps bisection steps run two at a time: a round
+// tests the three points lo + (1, 2, 3) w/4 of the bracket [lo, lo + w] and
+// replays the two binary steps from them -- the first step tests the midpoint
+// (2), the second the midpoint of the half it kept (3 if 2 was inside, else
+// 1) -- so the final bracket is exactly that of n_steps binary steps (all
+// points are dyadic, exact in float).  The bracket width w is the same for
+// every edge.
 constexpr int kBisectJobs = 64;    // jobs whose lattices a workgroup keeps in LDS
-constexpr int kWinCap = 256;       // kept pairs per wave with an LDS window
-constexpr int kCullUnroll = 4;     // cull passes whose loads are in flight together
+constexpr int kBisectEdges = 64;   // edges per workgroup pass
+constexpr int kWinCap = 512;       // kept pairs per workgroup pass with an LDS window
+constexpr int kCullUnroll = 2;     // cull cameras whose loads are in flight together
 constexpr uint32_t kNoWindow = 0xffffffffu;
 
 // An edge as the passes need it: its first sample's coordinates (the sample
@@ -351,25 +356,26 @@ __device__ __forceinline__ bool point_pixel(const float* P, float X, float Y, fl
 }
 
 template <int kCamsCap>
-__global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __restrict__ jobs,
-                                                        const uint32_t* __restrict__ n_jobs_p,
-                                                        const uint32_t* __restrict__ point_off,
-                                                        const CamSet cams,
-                                                        const uint32_t* __restrict__ sils,
-                                                        const uint64_t* __restrict__ tiles,
-                                                        int n_steps,
-                                                        const uint32_t* __restrict__ keys,
-                                                        float* __restrict__ xyz,
-                                                        uint32_t max_points) {
+__global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restrict__ jobs,
+                                                     const uint32_t* __restrict__ n_jobs_p,
+                                                     const uint32_t* __restrict__ point_off,
+                                                     const CamSet cams,
+                                                     const uint32_t* __restrict__ sils,
+                                                     const uint64_t* __restrict__ tiles,
+                                                     int n_steps,
+                                                     const uint32_t* __restrict__ keys,
+                                                     float* __restrict__ xyz,
+                                                     uint32_t max_points) {
     constexpr int kWaves = kBlock / kWave;
     __shared__ uint32_t s_off[kBisectJobs + 1];
     __shared__ fvv_grid s_grid[kBisectJobs];
     __shared__ float s_P[kCamsCap][13];              // P, then the rounding pad
-    __shared__ EdgeRec s_rec[kWaves][kWave];
-    __shared__ uint16_t s_pair[kWaves][kWave * kCamsCap];   // kept (edge, camera) pairs
-    __shared__ uint64_t s_win[kWaves][kWinCap];
-    __shared__ uint32_t s_worg[kWaves][kWinCap];
-    __shared__ uint32_t s_fail[kWaves][kWave];
+    __shared__ EdgeRec s_rec[kBisectEdges];
+    __shared__ uint16_t s_pair[kBisectEdges * kCamsCap];   // kept (edge, camera) pairs
+    __shared__ uint64_t s_win[kWinCap];
+    __shared__ uint32_t s_worg[kWinCap];
+    __shared__ uint32_t s_fail[kBisectEdges];
+    __shared__ uint32_t s_npairs;
     const int nj = (int)*n_jobs_p;
     const bool lds = nj <= kBisectJobs;
     if (lds)
@@ -390,122 +396,130 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
     const int64_t tpc = (int64_t)tpr * ((cams.H + 7) / 8);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    EdgeRec* const rec = s_rec[wave];
-    uint16_t* const pairs = s_pair[wave];
-    uint64_t* const win = s_win[wave];
-    uint32_t* const worg = s_worg[wave];
-    uint32_t* const fails = s_fail[wave];
-    // contiguous edge ranges per XCD, in chunks of one block's edges
-    const XcdSlice xs = xcd_slice((E + kBlock - 1) / kBlock);
+    // contiguous edge ranges per XCD, in chunks of 64 edges
+    const XcdSlice xs = xcd_slice((E + kBisectEdges - 1) / kBisectEdges);
     for (uint64_t chunk = xs.begin + xs.slot; chunk < xs.end; chunk += xs.stride) {
-        const uint32_t e = (uint32_t)chunk * kBlock + threadIdx.x;
+        const uint32_t e = (uint32_t)chunk * kBisectEdges + lane;   // this lane's edge
         const bool act = e < E;
-        const uint32_t ee = act ? e : E - 1;
-        int jb;
-        fvv_grid g;
-        if (lds) {
-            jb = upper_job([&](int m) { return (uint64_t)s_off[m]; }, nj, ee);
-            g = s_grid[jb];
-        } else {
-            jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, ee);
-            g = jobs[jb].grid;
-        }
-        const uint32_t key = keys[ee];
-        const uint32_t lin = key / 3u;
-        const int axis = (int)(key - 3u * lin);
-        const uint32_t i = lin % (uint32_t)g.dims[0];
-        const uint32_t r = lin / (uint32_t)g.dims[0];
-        const uint32_t j = r % (uint32_t)g.dims[1];
-        const uint32_t k = r / (uint32_t)g.dims[1];
-        // (selects rather than run-time indices into local arrays, which would
-        // put them in scratch memory)
-        const int gx = g.lo[0] + (int)i, gy = g.lo[1] + (int)j, gz = g.lo[2] + (int)k;
-        const int g_axis = axis == 0 ? gx : (axis == 1 ? gy : gz);
-        const bool p_on = xyz[3 * (int64_t)ee] > 0.0f;   // left there by the edge pass
-        const int g_on = g_axis + (p_on ? 0 : 1);
-        const float d = p_on ? 1.0f : -1.0f;
-        const float o_axis = axis == 0 ? g.origin[0] : (axis == 1 ? g.origin[1] : g.origin[2]);
-        const float c[3] = {lattice_coord(gx, g.h, g.origin[0]), lattice_coord(gy, g.h, g.origin[1]),
-                            lattice_coord(gz, g.h, g.origin[2])};
-        EdgeRec& mine = rec[lane];
-        mine.c[0] = c[0];
-        mine.c[1] = c[1];
-        mine.c[2] = c[2];
-        mine.x1 = lattice_coord(g_axis + 1, g.h, o_axis);
-        mine.gq = (float)g_on;
-        mine.d = d;
-        mine.h = g.h;
-        mine.o = o_axis;
-        mine.lo = 0.0f;
-        mine.axis = axis;
-        // cull: lane = edge, camera uniform (its matrix in scalar registers),
-        // kCullUnroll cameras' window loads in flight together; the kept
-        // pairs are listed camera by camera
-        const float X0[3] = {c[0], c[1], c[2]};
-        const float X1[3] = {axis == 0 ? mine.x1 : c[0], axis == 1 ? mine.x1 : c[1],
-                             axis == 2 ? mine.x1 : c[2]};
-        uint32_t n_pairs = 0;
-        for (int cb = 0; cb < cams.n; cb += kCullUnroll) {
-            EdgeRect rr[kCullUnroll];
-            uint64_t blk[kCullUnroll][4];
-#pragma unroll
-            for (int u = 0; u < kCullUnroll; ++u) {
-                const int cc = min(cb + u, cams.n - 1);
-                rr[u] = edge_rect(cams.Pc(cc), cams.padc(cc), cams.W, cams.H, X0, X1);
-                rr[u].small = rr[u].small && tiles != nullptr && act;
-                const bool sm = rr[u].small;
-                const int bx = rr[u].x0 >> 3, by = rr[u].y0 >> 3;
-                const bool nx = ((rr[u].x0 + rr[u].nx) >> 3) != bx;
-                const bool ny = ((rr[u].y0 + rr[u].ny) >> 3) != by;
-                const uint64_t* tb = tiles + cc * tpc + (int64_t)by * tpr + bx;
-                blk[u][0] = blk[u][1] = blk[u][2] = blk[u][3] = 0ull;
-                if (sm)
-                    blk[u][0] = tb[0];
-                if (sm && nx)
-                    blk[u][1] = tb[1];
-                if (sm && ny)
-                    blk[u][2] = tb[tpr];
-                if (sm && nx && ny)
-                    blk[u][3] = tb[tpr + 1];
+        // 1. the edges' records, by the first wave
+        if (wave == 0) {
+            const uint32_t ee = act ? e : E - 1;
+            int jb;
+            fvv_grid g;
+            if (lds) {
+                jb = upper_job([&](int m) { return (uint64_t)s_off[m]; }, nj, ee);
+                g = s_grid[jb];
+            } else {
+                jb = upper_job([&](int m) { return (uint64_t)point_off[m]; }, nj, ee);
+                g = jobs[jb].grid;
             }
+            const uint32_t key = keys[ee];
+            const uint32_t lin = key / 3u;
+            const int axis = (int)(key - 3u * lin);
+            const uint32_t i = lin % (uint32_t)g.dims[0];
+            const uint32_t r = lin / (uint32_t)g.dims[0];
+            const uint32_t j = r % (uint32_t)g.dims[1];
+            const uint32_t k = r / (uint32_t)g.dims[1];
+            // (selects rather than run-time indices into local arrays, which
+            // would put them in scratch memory)
+            const int gx = g.lo[0] + (int)i, gy = g.lo[1] + (int)j, gz = g.lo[2] + (int)k;
+            const int g_axis = axis == 0 ? gx : (axis == 1 ? gy : gz);
+            const bool p_on = xyz[3 * (int64_t)ee] > 0.0f;   // left there by the edge pass
+            const float o_axis = axis == 0 ? g.origin[0] : (axis == 1 ? g.origin[1] : g.origin[2]);
+            EdgeRec mine;
+            mine.c[0] = lattice_coord(gx, g.h, g.origin[0]);
+            mine.c[1] = lattice_coord(gy, g.h, g.origin[1]);
+            mine.c[2] = lattice_coord(gz, g.h, g.origin[2]);
+            mine.x1 = lattice_coord(g_axis + 1, g.h, o_axis);
+            mine.gq = (float)(g_axis + (p_on ? 0 : 1));
+            mine.d = p_on ? 1.0f : -1.0f;
+            mine.h = g.h;
+            mine.o = o_axis;
+            mine.lo = 0.0f;
+            mine.axis = axis;
+            mine.pad_[0] = mine.pad_[1] = 0;
+            s_rec[lane] = mine;
+            if (lane == 0)
+                s_npairs = 0u;
+        }
+        __syncthreads();
+        // 2. cull: lane = edge, wave v the cameras v, v + 4, ...
+        {
+            const EdgeRec& er = s_rec[lane];
+            const float X0[3] = {er.c[0], er.c[1], er.c[2]};
+            const float X1[3] = {er.axis == 0 ? er.x1 : er.c[0], er.axis == 1 ? er.x1 : er.c[1],
+                                 er.axis == 2 ? er.x1 : er.c[2]};
+            for (int cb = wave; cb < cams.n; cb += kWaves * kCullUnroll) {
+                EdgeRect rr[kCullUnroll];
+                uint64_t blk[kCullUnroll][4];
 #pragma unroll
-            for (int u = 0; u < kCullUnroll; ++u) {
-                if (cb + u >= cams.n)
-                    break;
-                const uint64_t wv = edge_window(rr[u], blk[u]);
-                const uint64_t cols = (uint64_t)((2u << rr[u].nx) - 1u) * 0x0101010101010101ull;
-                const uint64_t m = cols & (~0ull >> (8 * (7 - rr[u].ny)));
-                const bool keep = act && !(rr[u].small && (wv & m) == m);
-                const uint64_t kb = __ballot(keep);
-                const uint32_t slot = n_pairs + lane_rank(kb);
-                if (keep) {
-                    pairs[slot] = (uint16_t)((lane << 5) | (cb + u));
-                    if (slot < (uint32_t)kWinCap) {
-                        win[slot] = rr[u].small ? wv : 0ull;
-                        worg[slot] = rr[u].small
-                                         ? ((uint32_t)rr[u].x0 | ((uint32_t)rr[u].y0 << 16))
-                                         : kNoWindow;
+                for (int u = 0; u < kCullUnroll; ++u) {
+                    const int cc = min(cb + u * kWaves, cams.n - 1);
+                    rr[u] = edge_rect(cams.Pc(cc), cams.padc(cc), cams.W, cams.H, X0, X1);
+                    rr[u].small = rr[u].small && tiles != nullptr && act;
+                    const bool sm = rr[u].small;
+                    const int bx = rr[u].x0 >> 3, by = rr[u].y0 >> 3;
+                    const bool nx = ((rr[u].x0 + rr[u].nx) >> 3) != bx;
+                    const bool ny = ((rr[u].y0 + rr[u].ny) >> 3) != by;
+                    const uint64_t* tb = tiles + cc * tpc + (int64_t)by * tpr + bx;
+                    blk[u][0] = blk[u][1] = blk[u][2] = blk[u][3] = 0ull;
+                    if (sm)
+                        blk[u][0] = tb[0];
+                    if (sm && nx)
+                        blk[u][1] = tb[1];
+                    if (sm && ny)
+                        blk[u][2] = tb[tpr];
+                    if (sm && nx && ny)
+                        blk[u][3] = tb[tpr + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < kCullUnroll; ++u) {
+                    const int cc = cb + u * kWaves;
+                    if (cc >= cams.n)
+                        break;
+                    const uint64_t wv = edge_window(rr[u], blk[u]);
+                    const uint64_t cols = (uint64_t)((2u << rr[u].nx) - 1u) * 0x0101010101010101ull;
+                    const uint64_t m = cols & (~0ull >> (8 * (7 - rr[u].ny)));
+                    const bool keep = act && !(rr[u].small && (wv & m) == m);
+                    const uint64_t kb = __ballot(keep);
+                    if (kb == 0ull)
+                        continue;
+                    uint32_t base = 0u;
+                    if (lane == 0)
+                        base = atomicAdd(&s_npairs, (uint32_t)__popcll(kb));
+                    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+                    const uint32_t slot = base + lane_rank(kb);
+                    if (keep) {
+                        s_pair[slot] = (uint16_t)((lane << 5) | cc);
+                        if (slot < (uint32_t)kWinCap) {
+                            s_win[slot] = rr[u].small ? wv : 0ull;
+                            s_worg[slot] = rr[u].small
+                                               ? ((uint32_t)rr[u].x0 | ((uint32_t)rr[u].y0 << 16))
+                                               : kNoWindow;
+                        }
                     }
                 }
-                n_pairs += (uint32_t)__popcll(kb);
             }
         }
-        wave_lds_sync();
+        __syncthreads();
+        const uint32_t n_pairs = s_npairs;
+        // 3. the rounds; the first wave keeps each edge's bracket start
         float lo = 0.0f, w = 1.0f;
         for (int st = 0; st < n_steps; st += 2) {
             const bool two = st + 1 < n_steps;   // uniform
             const float w4 = 0.25f * w;
-            fails[lane] = 0u;
-            wave_lds_sync();
-            for (uint32_t base = 0; base < n_pairs; base += kWave) {
+            if (wave == 0)
+                s_fail[lane] = 0u;
+            __syncthreads();
+            for (uint32_t base = (uint32_t)wave * kWave; base < n_pairs; base += kBlock) {
                 const uint32_t pi = base + (uint32_t)lane;
                 const bool live = pi < n_pairs;
-                const uint32_t pr = pairs[live ? pi : 0];
+                const uint32_t pr = s_pair[live ? pi : 0];
                 const int el = (int)(pr >> 5), ca = (int)(pr & 31u);
-                const EdgeRec& er = rec[el];
+                const EdgeRec& er = s_rec[el];
                 const bool cached = pi < (uint32_t)kWinCap;
-                const uint32_t org = cached ? worg[cached ? pi : 0] : kNoWindow;
-                const uint64_t wv = cached ? win[cached ? pi : 0] : 0ull;
+                const uint32_t org = cached ? s_worg[cached ? pi : 0] : kNoWindow;
+                const uint64_t wv = cached ? s_win[cached ? pi : 0] : 0ull;
                 const bool has_win = org != kNoWindow;
                 const int ox = (int)(org & 0xffffu), oy = (int)(org >> 16);
                 const float* P = s_P[ca];
@@ -541,32 +555,34 @@ __global__ __launch_bounds__(kBlock, 6) void bisect_kernel(const fvv_job* __rest
                     fail |= in ? 0u : (1u << q);
                 }
                 if (live && fail)
-                    atomicOr(&fails[el], fail);
+                    atomicOr(&s_fail[el], fail);
             }
-            wave_lds_sync();
-            const uint32_t f = fails[lane];
-            if (two) {
-                const int idx = !(f & 2u) ? (!(f & 4u) ? 3 : 2) : (!(f & 1u) ? 1 : 0);
-                lo = lo + (float)idx * w4;
-                w = w4;
-            } else {
-                if (!(f & 2u))
+            __syncthreads();
+            if (wave == 0) {
+                const uint32_t f = s_fail[lane];
+                if (two) {
+                    const int idx = !(f & 2u) ? (!(f & 4u) ? 3 : 2) : (!(f & 1u) ? 1 : 0);
+                    lo = lo + (float)idx * w4;
+                } else if (!(f & 2u)) {
                     lo = lo + 2.0f * w4;
-                w = 0.5f * w;
+                }
+                s_rec[lane].lo = lo;
             }
-            mine.lo = lo;
-            wave_lds_sync();
+            w = two ? w4 : 0.5f * w;   // every wave: the width is the same for all edges
+            __syncthreads();
         }
-        if (act) {
+        // 4. the exit point: the final bracket's midpoint
+        if (wave == 0 && act) {
+            const EdgeRec& er = s_rec[lane];
             const float hi = lo + w;
             const float t = 0.5f * (lo + hi);
-            const float q = (float)g_on + d * t;
-            const float ax = __builtin_fmaf(q, g.h, o_axis);
-            xyz[3 * (int64_t)e + 0] = axis == 0 ? ax : c[0];
-            xyz[3 * (int64_t)e + 1] = axis == 1 ? ax : c[1];
-            xyz[3 * (int64_t)e + 2] = axis == 2 ? ax : c[2];
+            const float q = er.gq + er.d * t;
+            const float ax = __builtin_fmaf(q, er.h, er.o);
+            xyz[3 * (int64_t)e + 0] = er.axis == 0 ? ax : er.c[0];
+            xyz[3 * (int64_t)e + 1] = er.axis == 1 ? ax : er.c[1];
+            xyz[3 * (int64_t)e + 2] = er.axis == 2 ? ax : er.c[2];
         }
-        wave_lds_sync();   // the next chunk rewrites this wave's records and pairs
+        __syncthreads();   // the next chunk rewrites the records, pairs and count
     }
 }
 
@@ -593,11 +609,11 @@ hipError_t launch_bisect(int n_cus, const fvv_job* jobs, const uint32_t* n_jobs_
                          uint32_t max_points, hipStream_t s, hipEvent_t k_start,
                          hipEvent_t k_stop) {
     if (cams.n <= 16)
-        hipExtLaunchKernelGGL(bisect_kernel<16>, dim3(n_cus * 8), dim3(kBlock), 0, s, k_start,
+        hipExtLaunchKernelGGL(bisect_kernel<16>, dim3(n_cus * 16), dim3(kBlock), 0, s, k_start,
                               k_stop, 0, jobs, n_jobs_dev, point_off, cams, sils, tiles, n_steps,
                               keys, xyz, max_points);
     else
-        hipExtLaunchKernelGGL(bisect_kernel<FVV_MAX_CAMS>, dim3(n_cus * 8), dim3(kBlock), 0, s,
+        hipExtLaunchKernelGGL(bisect_kernel<FVV_MAX_CAMS>, dim3(n_cus * 16), dim3(kBlock), 0, s,
                               k_start, k_stop, 0, jobs, n_jobs_dev, point_off, cams, sils, tiles,
                               n_steps, keys, xyz, max_points);
     return hipGetLastError();

@@ -445,7 +445,7 @@ def test_batched_full_workload(fvv, ctx):
 
 # ------------------------------------------------------------------ whole frame
 def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, graph=False,
-              pack_first=False, coarse_tile=None, fine_tile=None):
+              pack_first=False, coarse_tile=None, fine_tile=None, sils_fill=0):
     coarse = fvv.Grid(origin=tuple(sc.origin), h=sc.hc, lo=(0, 0, 0), dims=sc.coarse_dims)
     params = fvv.frame_params(sc.P32, sc.W, sc.H, coarse, sc.hc_um, sc.hf_um, sc.t_np, sc.t_nb,
                               sc.n_steps, coarse_tile=coarse_tile, fine_tile=fine_tile)
@@ -453,7 +453,7 @@ def run_frame(fvv, ctx, sc, max_rois=256, max_fine=1 << 26, max_points=1 << 22, 
     import torch
     masks = dev(sc.masks)
     N, H, W = sc.masks.shape
-    sils = torch.zeros((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
+    sils = torch.full((N, H, (W + 31) // 32), sils_fill, dtype=torch.int32, device="cuda")
     if graph:                                  # packing inside the graph
         g = ctx.frame_graph(params, sils, bufs, masks=masks)
         return g, bufs, sils
@@ -505,9 +505,35 @@ def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
     sc = scene_cache(cfg, frame)
     res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
                        sc.t_nb, sc.n_steps)
-    _, bufs, _ = run_frame(fvv, ctx, sc, pack_first=(frame % 2 == 1))
+    _, bufs, sils = run_frame(fvv, ctx, sc, pack_first=(frame % 2 == 1))
     assert ctx.check() == fvv.FVV_OK
     compare_frame(fvv, sc, bufs, res)
+    np.testing.assert_array_equal(host(sils).view(np.uint32), oracle.pack(sc.masks))
+
+
+@pytest.mark.parametrize("width", [312, 316, 320])
+def test_frame_ragged_width(fvv, ctx, scene_cache, width):
+    """Images cut at the right edge: a width of 8k pixels that is not a row of
+    whole 32-bit words (the one-pass packing of rows and 8 x 8 blocks clears
+    the row's padding bytes), one that is not a multiple of 8 (rows and blocks
+    packed in turn) and the full width."""
+    import dataclasses
+    sc = scene_cache(1, 0)
+    masks = np.ascontiguousarray(sc.masks[:, :, :width])
+    # foreground noise along the cut edge, so that the last bits of every row
+    # matter; the silhouette buffer starts all ones, so that every bit the
+    # packing leaves unwritten shows
+    rng = np.random.default_rng(width)
+    masks[:, :, -12:] = (rng.uniform(size=masks[:, :, -12:].shape) < 0.5).astype(np.uint8) * 255
+    sc = dataclasses.replace(sc, masks=masks,
+                             cams=[dataclasses.replace(c, W=width) for c in sc.cams])
+    assert sc.W == width and sc.masks.shape[2] == width
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    _, bufs, sils = run_frame(fvv, ctx, sc, sils_fill=-1)
+    assert ctx.check() == fvv.FVV_OK
+    compare_frame(fvv, sc, bufs, res)
+    np.testing.assert_array_equal(host(sils).view(np.uint32), oracle.pack(sc.masks))
 
 
 def many_balls_scene():
