@@ -861,6 +861,11 @@ def soft_cpu_baseline():
             "cores": torch.get_num_threads(), "sample": "one forward + gradient of the same scene"}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -926,6 +931,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    progress("volleyball frames: stage split done, timing the frame graphs")
     graphs = [ctx.frame_graph(params, sils, bufs, masks=m) for m in masks]
     for k in range(args.warmup):
         graphs[k % len(graphs)].launch()
@@ -1005,29 +1011,37 @@ def main():
     }
 
     if not args.no_mesh:
+        progress("mesh leg")
         result["mesh"] = mesh_leg(args, fvv, torch, ctx, params, masks, sils, coarse, max_rois,
                                   max_fine, max_points, pct(lat_ms, 50))
     if not args.no_isovalue:
+        progress("isovalue leg")
         result["isovalue"] = isovalue_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                           max_rois, max_fine, max_points, sc0,
                                           float(np.mean(stage_ms_frame["exit_points"][0])))
     if not args.no_visibility:
+        progress("visibility leg")
         result["visibility"] = visibility_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                               max_rois, max_fine, max_points, sc0)
     if not args.no_batched:
+        progress("batched leg")
         result["batched"] = batched_leg(args, fvv, torch)
     if not args.no_soft:
+        progress("soft hull leg")
         result["soft_hull"] = soft_leg(args, fvv, torch)
         if not args.no_cpu_baseline:
             result["soft_hull"]["cpu_baseline"] = soft_cpu_baseline()
 
     if not args.no_judo:
+        progress("judo leg")
         result["judo"] = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_JUDO,
                                     args.judo_frames, args.judo_steps, JUDO_WORKLOAD, 1)
     if not args.no_tiny:
+        progress("tiny leg")
         result["tiny"] = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_TINY,
                                     8, 50, TINY_WORKLOAD, 8)
     if not args.no_paper:
+        progress("paper-shaped volleyball and 2 mm judo legs")
         # the paper's own volleyball shape, with its Table II times (1st volleyball
         # sequence, steps B-1 to C, GTX 1080 Ti) beside it as context
         pv = config_leg(args, fvv, torch, not args.no_cpu_baseline, scenes.CFG_PAPER_V, 2, 50,
@@ -1041,11 +1055,13 @@ def main():
                                          scenes.CFG_JUDO_FINE, 1, 10, JUDO_FINE_WORKLOAD, 1,
                                          max_fine=1 << 28, stage_reps=3)
     if not args.no_h2d:
+        progress("host-copy latency leg")
         result["latency_with_h2d"] = h2d_leg(args, fvv, torch, ctx, params, masks, sils, coarse,
                                              max_rois, max_fine, max_points, fine_vox)
 
     tests = {}
     if not args.no_cpu_baseline:
+        progress("oracle baseline")
         result["cpu_baseline"], tests = cpu_baseline(frames, args.cpu_seconds)
         if args.cpu_seconds_one_core > 0:
             result["cpu_baseline_one_core"] = cpu_one_core(frames, args.cpu_seconds_one_core)

@@ -750,7 +750,8 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     if (e == hipSuccess)
         e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, stream);
     if (e == hipSuccess)
-        e = launch_carve_frame(ctx, o->d_jobs, cs, d_sils, ctx->d_tsils, o->d_occ_fine,
+        e = launch_carve_frame(ctx, o->d_jobs, (int)o->max_rois, cs, d_sils, ctx->d_tsils,
+                               o->d_occ_fine,
                                ctx->d_finebits, ft, blocks, stream, kev(0), kev(1));
     mark(4);
     // the mesh also runs on the side branch: its count once the fine bitmaps

@@ -1237,9 +1237,12 @@ __device__ __forceinline__ void carve_block16(const CamSet& cams, const float (*
     }
 }
 
-// The fine carve of a frame: a static, XCD-aware partition of the tiles of
-// all carried ROIs (contiguous tile ranges per XCD keep each L2's share of the
-// silhouettes small).  A workgroup takes whole tiles (TX x TY x 4 samples);
+// The fine carve of a frame: the tiles of all carried ROIs dealt out to the
+// workgroups in turn (tile t to workgroup t mod grid, then t + grid, ...), so
+// every XCD gets an even share of the costly tiles near the surfaces (this
+// measured faster than contiguous tile ranges per XCD, which keep each L2's
+// share of the silhouettes smaller but leave some XCDs with more work).  A
+// workgroup takes whole tiles (TX x TY x 4 samples);
 // each of its four waves owns one 16 x 4 x 4 block of the tile (x offset
 // 16 (w mod TX/16), y offset 4 (w div TX/16)) and carves it on its own, with
 // no workgroup barrier (carve_block16).  Job tables of up to kJobLds ROIs and
@@ -1255,7 +1258,8 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
                                                              const uint64_t* __restrict__ tiles,
                                                              const float* __restrict__ rho,
                                                              uint8_t* __restrict__ out,
-                                                             uint64_t* __restrict__ finebits) {
+                                                             uint64_t* __restrict__ finebits,
+                                                             int job_lds) {
     constexpr int BXN = TX / 16;                     // blocks of a tile along x
     __shared__ PairWindow s_win[kBlock / kWave][4][FVV_MAX_CAMS];
     __shared__ uint64_t s_tile_off[kJobLds + 1];
@@ -1263,24 +1267,25 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
     __shared__ int64_t s_out[kJobLds];
     __shared__ fvv_grid s_grid[kJobLds];
     __shared__ float s_cam[FVV_MAX_CAMS][13];        // P, then the rounding pad
-    const int nj = (int)counter[2];
-    const bool lds = nj <= kJobLds;
-    if (lds)
-        for (int j = threadIdx.x; j <= nj; j += kBlock) {
-            s_tile_off[j] = pre[j].tile_off;
-            if (j < nj) {
-                s_bit_off[j] = pre[j].bit_off;
-                s_out[j] = jobs[j].out_offset;
-                s_grid[j] = jobs[j].grid;
-            }
+    // the job tables of the first job_lds jobs (every job the output can hold,
+    // up to kJobLds), loaded without waiting for the frame's job count
+    for (int j = threadIdx.x; j <= job_lds; j += kBlock) {
+        s_tile_off[j] = pre[j].tile_off;
+        if (j < job_lds) {
+            s_bit_off[j] = pre[j].bit_off;
+            s_out[j] = jobs[j].out_offset;
+            s_grid[j] = jobs[j].grid;
         }
+    }
+    const int nj = (int)counter[2];
+    const bool lds = nj <= job_lds;
     for (int i = threadIdx.x; i < cams.n * 13; i += kBlock) {
         const int c = i / 13, e = i - 13 * c;
         s_cam[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
     }
     __syncthreads();
     const uint64_t total = lds ? s_tile_off[nj] : pre[nj].tile_off;
-    const XcdSlice xs = xcd_slice(total);
+    const XcdSlice xs{0, total, blockIdx.x, gridDim.x};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int xo = 16 * (wave % BXN), yo = 4 * (wave / BXN);
     const int tpr = (cams.W + 7) / 8;
@@ -1388,10 +1393,10 @@ __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
     }
 }
 
-hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& cams,
-                              const uint32_t* sils, const uint64_t* tiles, uint8_t* out,
-                              uint64_t* finebits, TileShape t, int blocks, hipStream_t s,
-                              hipEvent_t k_start, hipEvent_t k_stop) {
+hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
+                              const CamSet& cams, const uint32_t* sils, const uint64_t* tiles,
+                              uint8_t* out, uint64_t* finebits, TileShape t, int blocks,
+                              hipStream_t s, hipEvent_t k_start, hipEvent_t k_stop) {
     if (t.tz != 4) {
         // the persistent carve: the events bracket its launch
         hipError_t e = k_start ? hipEventRecord(k_start, s) : hipSuccess;
@@ -1403,11 +1408,13 @@ hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& c
         return e;
     }
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+    // jobs: max_jobs entries; the prefix table holds at least max_jobs + 1
+    const int job_lds = max_jobs < kJobLds ? max_jobs : kJobLds;
 #define X(TXV)                                                                                 \
     if (t.tx == TXV) {                                                                         \
         hipExtLaunchKernelGGL((carve_frame_kernel<TXV>), dim3(blocks), dim3(kBlock), 0, s,     \
                               k_start, k_stop, 0, jobs, ctx->d_prefix, ctx->d_counter, cams,   \
-                              sils, tiles, ctx->d_rho, out, finebits);                         \
+                              sils, tiles, ctx->d_rho, out, finebits, job_lds);                \
         return hipGetLastError();                                                              \
     }
     X(64) X(32) X(16)

@@ -90,6 +90,29 @@ __device__ __forceinline__ void unite(int32_t* P, int32_t a, int32_t b) {
     }
 }
 
+// Measurement builds (FVV_LABEL_PHASES defined) record, from thread 0 of the
+// labelling workgroup, the real-time clock (100 MHz) at the end of each phase
+// of the last labelling into label_phase_stamps: [0] entry, [1] row mask
+// counted, [2] rows listed, [3] runs cut, [4] runs united, [5] forest
+// flattened and roots numbered, [6] stats, filter and ROI table, [7] labels
+// written and the bitmap cleared, [8] the fine jobs laid out, [9] their radii.
+constexpr int kLabelPhases = 10;
+#ifdef FVV_LABEL_PHASES
+__device__ uint64_t label_phase_stamps[kLabelPhases];
+__device__ __forceinline__ void label_stamp(int i) {
+    if (threadIdx.x == 0)
+        label_phase_stamps[i] = __builtin_amdgcn_s_memrealtime();
+}
+// A stamp where no barrier ends the phase: the barrier, then the stamp.
+__device__ __forceinline__ void label_stamp_sync(int i) {
+    __syncthreads();
+    label_stamp(i);
+}
+#else
+__device__ __forceinline__ void label_stamp(int) {}
+__device__ __forceinline__ void label_stamp_sync(int) {}
+#endif
+
 // ------------------------------------------------------------------ fine jobs of a frame
 // floor(a / b) for b > 0 and |a| < 2^53: the correctly rounded double
 // quotient is within one of the exact one; the integer residual corrects it.
@@ -251,6 +274,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
                 finish(n, vox, all_t, all_i);
         }
         __syncthreads();
+        label_stamp(8);
         fine_job_radii<NT>(fj, counter);
         return;
     }
@@ -307,33 +331,11 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
     if (threadIdx.x == 0)
         finish(carried, e_vox, e_tiles, e_items);
     __syncthreads();
+    label_stamp(8);
     fine_job_radii<NT>(fj, counter);
 }
 
 // ------------------------------------------------------------------ run labelling
-// Measurement builds (FVV_LABEL_PHASES defined) record, from thread 0 of the
-// labelling workgroup, the real-time clock (100 MHz) at the end of each phase
-// of the last labelling into label_phase_stamps: [0] entry, [1] row mask
-// counted, [2] rows listed, [3] runs cut, [4] runs united, [5] forest
-// flattened and roots numbered, [6] stats, filter and ROI table, [7] labels
-// written and the bitmap cleared, [8] the fine jobs laid out.
-constexpr int kLabelPhases = 9;
-#ifdef FVV_LABEL_PHASES
-__device__ uint64_t label_phase_stamps[kLabelPhases];
-__device__ __forceinline__ void label_stamp(int i) {
-    if (threadIdx.x == 0)
-        label_phase_stamps[i] = __builtin_amdgcn_s_memrealtime();
-}
-// A stamp where no barrier ends the phase: the barrier, then the stamp.
-__device__ __forceinline__ void label_stamp_sync(int i) {
-    __syncthreads();
-    label_stamp(i);
-}
-#else
-__device__ __forceinline__ void label_stamp(int) {}
-__device__ __forceinline__ void label_stamp_sync(int) {}
-#endif
-
 constexpr int kMaskCap = 1024;   // row-mask words held in LDS (grids of up to 65536 rows)
 constexpr int kRowWords = 4;     // row-bitmap words a thread keeps in registers
 
@@ -699,7 +701,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
             }
         };
         build_fine_jobs<NT>(fj, box, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);
-        label_stamp_sync(8);
+        label_stamp_sync(9);
     }
     return true;
 }
@@ -837,7 +839,7 @@ hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int
 
 #ifdef FVV_LABEL_PHASES
 // Measurement builds only: the last labelling's phase stamps to host memory
-// (out: at least 9 entries).
+// (out: at least 10 entries).
 extern "C" int32_t fvv_label_phase_stamps(uint64_t* out, int32_t n) {
     if (!out || n < fvv::kLabelPhases)
         return FVV_EINVAL;

@@ -699,10 +699,11 @@ hipError_t launch_bisect(int n_cus, const fvv_job* jobs, const uint32_t* n_jobs_
 // take the batched carve.
 // k_start, k_stop: NULL, or events that take the kernel's own start and end
 // times (hipExtLaunchKernel).
-hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, const CamSet& cams,
-                              const uint32_t* sils, const uint64_t* tiles, uint8_t* out,
-                              uint64_t* finebits, TileShape t, int blocks, hipStream_t s,
-                              hipEvent_t k_start = nullptr, hipEvent_t k_stop = nullptr);
+hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
+                              const CamSet& cams, const uint32_t* sils, const uint64_t* tiles,
+                              uint8_t* out, uint64_t* finebits, TileShape t, int blocks,
+                              hipStream_t s, hipEvent_t k_start = nullptr,
+                              hipEvent_t k_stop = nullptr);
 // The silhouettes in 8 x 8-pixel blocks (tile_sils_kernel's layout), from the
 // packed rows.
 hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,

@@ -22,7 +22,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 PHASES_LIB = os.path.join(HERE, "libfvv_label_phases.so")
 PHASES = ["row mask", "rows listed", "runs cut", "unions", "flatten + root numbers",
-          "stats + Eq. (1) filter + ROIs", "labels + bitmap clear", "fine jobs + radii"]
+          "stats + Eq. (1) filter + ROIs", "labels + bitmap clear", "fine jobs laid out",
+          "fine job radii"]
 TICK_US = 0.01   # the real-time clock runs at 100 MHz
 
 
@@ -53,14 +54,14 @@ def run(frames: int, reps: int) -> dict:
                               sc0.n_steps)
     sils = torch.empty((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
     bufs = fvv.FrameBuffers(coarse, 256, 1 << 26, 1 << 22)
-    stamps = np.zeros(9, np.uint64)
+    stamps = np.zeros(10, np.uint64)
     per = []
     for sc in scs:
         m = torch.from_numpy(sc.masks).cuda()
         for rep in range(reps + 1):
             ctx.frame(params, sils, bufs, masks=m)
             torch.cuda.synchronize()
-            if L.fvv_label_phase_stamps(stamps.ctypes.data, 9) != 0:
+            if L.fvv_label_phase_stamps(stamps.ctypes.data, 10) != 0:
                 raise RuntimeError("no phase stamps")
             if rep:
                 per.append(np.diff(stamps.astype(np.int64)) * TICK_US)
