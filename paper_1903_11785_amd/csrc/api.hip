@@ -155,9 +155,9 @@ hipError_t launch_surface_single(const SurfaceScratch& sc, const fvv_job& job,
         e = launch_edges(sc, sc.job_single, sc.counts_single + 3, d_keys, d_xyz, max_points,
                          sc.point_off_single, d_n_points, true, false, stream);
     if (e == hipSuccess)
-        e = launch_bisect(sc.n_cus, sc.job_single, sc.counts_single + 3, sc.point_off_single, cs,
-                          d_sils, tiled ? sc.tiles : nullptr, n_steps, d_keys, d_xyz, max_points,
-                          stream);
+        e = launch_bisect(sc.n_cus, sc.job_single, 1, sc.counts_single + 3, sc.point_off_single,
+                          cs, d_sils, tiled ? sc.tiles : nullptr, n_steps, d_keys, d_xyz,
+                          max_points, stream);
     return e;
 }
 
@@ -782,9 +782,9 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = launch_isovalue_jobs(ctx, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils, o->d_keys,
                                  o->d_xyz, o->max_points, stream, kev(2), kev(3));
     else if (e == hipSuccess)
-        e = launch_bisect(ctx->n_cus, o->d_jobs, n_jobs, o->d_point_off, cs, d_sils,
-                          ctx->d_tsils, p->n_steps, o->d_keys, o->d_xyz,
-                          o->max_points, stream, kev(2), kev(3));
+        e = launch_bisect(ctx->n_cus, o->d_jobs, (int)o->max_rois, n_jobs, o->d_point_off, cs,
+                          d_sils, ctx->d_tsils, p->n_steps, o->d_keys, o->d_xyz, o->max_points,
+                          stream, kev(2), kev(3));
     if (mesh && e == hipSuccess)
         e = hipStreamWaitEvent(stream, ctx->ev_join, 0);
     mark(6);

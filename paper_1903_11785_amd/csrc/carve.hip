@@ -15,6 +15,8 @@
 // definition.
 #include "fvv_internal.h"
 
+#include <type_traits>
+
 namespace fvv {
 
 constexpr int kCamGroup = 2;
@@ -1058,8 +1060,10 @@ struct PairWindow {
 //   3. output: the occupancy bytes, and the block's 16 bits of each fine-bitmap
 //      row word.
 // cam_lds: per camera P and the rounding pad; rho: the job's radii per camera
-// (kRhoPer floats); win: this wave's LDS windows [4][FVV_MAX_CAMS].
-__device__ __forceinline__ void carve_block16(const CamSet& cams, const float (*cam_lds)[13],
+// (kRhoPer floats); win: this wave's LDS windows [4][FVV_MAX_CAMS].  Returns
+// the number of test passes, and in the high half the (sub-block, camera)
+// tests they made (wave-uniform counts, for measurement builds).
+__device__ __forceinline__ uint32_t carve_block16(const CamSet& cams, const float (*cam_lds)[13],
                                               const float* __restrict__ rho,
                                               PairWindow (*win)[FVV_MAX_CAMS],
                                               const uint32_t* __restrict__ sils,
@@ -1069,7 +1073,8 @@ __device__ __forceinline__ void carve_block16(const CamSet& cams, const float (*
                                               const RowBits& fb) {
     const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
     if (bj0 >= ny)
-        return;                                    // no row of the block is in the lattice
+        return 0u;                                 // no row of the block is in the lattice
+    uint32_t n_pass = 0u, n_test = 0u;
     const int lane = lane_id();
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
@@ -1163,6 +1168,8 @@ __device__ __forceinline__ void carve_block16(const CamSet& cams, const float (*
             rest[s] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(rej[s] == 0u ? mix[s] : 0u));
         }
         while ((rest[0] | rest[1] | rest[2] | rest[3]) != 0u) {
+            ++n_pass;
+            n_test += (rest[0] != 0u) + (rest[1] != 0u) + (rest[2] != 0u) + (rest[3] != 0u);
             int px[4], py[4];
             bool ok[4], act[4];
             uint32_t word[4], org[4];
@@ -1235,7 +1242,18 @@ __device__ __forceinline__ void carve_block16(const CamSet& cams, const float (*
                 (uint16_t)b;
         }
     }
+    return n_pass | (n_test << 16);
 }
+
+// Measurement builds (FVV_CARVE_PROBE defined) record, for the first
+// kProbeWaves waves of the frame's fine carve, the real-time clock (100 MHz)
+// at the wave's entry and exit and its block count, and for its first
+// kProbeIters blocks their start, end, test passes and tests.
+#ifdef FVV_CARVE_PROBE
+constexpr int kProbeWaves = 16384, kProbeIters = 4;
+__device__ uint64_t carve_probe_blocks[kProbeWaves * kProbeIters][3];
+__device__ uint64_t carve_probe_waves[kProbeWaves][3];
+#endif
 
 // The fine carve of a frame: the tiles of all carried ROIs dealt out to the
 // workgroups in turn (tile t to workgroup t mod grid, then t + grid, ...), so
@@ -1260,6 +1278,10 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
                                                              uint8_t* __restrict__ out,
                                                              uint64_t* __restrict__ finebits,
                                                              int job_lds) {
+#ifdef FVV_CARVE_PROBE
+    const uint64_t probe_entry = __builtin_amdgcn_s_memrealtime();
+    uint32_t probe_blocks = 0;
+#endif
     constexpr int BXN = TX / 16;                     // blocks of a tile along x
     __shared__ PairWindow s_win[kBlock / kWave][4][FVV_MAX_CAMS];
     __shared__ uint64_t s_tile_off[kJobLds + 1];
@@ -1284,18 +1306,25 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
         s_cam[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
     }
     __syncthreads();
-    const uint64_t total = lds ? s_tile_off[nj] : pre[nj].tile_off;
-    const XcdSlice xs{0, total, blockIdx.x, gridDim.x};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int xo = 16 * (wave % BXN), yo = 4 * (wave / BXN);
     const int tpr = (cams.W + 7) / 8;
     const int64_t tpc = (int64_t)tpr * ((cams.H + 7) / 8);
+    // the tiles' loop, once with the job tables in LDS and once without (two
+    // copies, so that neither reads its tables through generic pointers)
+    auto tiles_loop = [&](auto in_lds) {
+    uint64_t total;
+    if constexpr (decltype(in_lds)::value)
+        total = s_tile_off[nj];
+    else
+        total = pre[nj].tile_off;
+    const XcdSlice xs{0, total, blockIdx.x, gridDim.x};
     for (uint64_t t = xs.begin + xs.slot; t < xs.end; t += xs.stride) {
         int jb;
         fvv_grid g;
         int64_t out_off;
         uint64_t tile0, bit_off;
-        if (lds) {
+        if constexpr (decltype(in_lds)::value) {
             jb = upper_job([&](int m) { return s_tile_off[m]; }, nj, t);
             g = s_grid[jb];
             out_off = s_out[jb];
@@ -1313,9 +1342,39 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
         fb.wr = (g.dims[0] + 63) / 64;
         int i0, j0, k0;
         tile_origin<TX>(g, t - tile0, i0, j0, k0);
-        carve_block16(cams, s_cam, rho + (int64_t)jb * FVV_MAX_CAMS * kRhoPer, s_win[wave], sils,
-                      tiles, tpr, tpc, g, i0 + xo, j0 + yo, k0, out + out_off, fb);
+#ifdef FVV_CARVE_PROBE
+        const uint64_t t_a = __builtin_amdgcn_s_memrealtime();
+#endif
+        const uint32_t passes_tests =
+            carve_block16(cams, s_cam, rho + (int64_t)jb * FVV_MAX_CAMS * kRhoPer, s_win[wave],
+                          sils, tiles, tpr, tpc, g, i0 + xo, j0 + yo, k0, out + out_off, fb);
+#ifdef FVV_CARVE_PROBE
+        const uint64_t t_b = __builtin_amdgcn_s_memrealtime();
+        const uint32_t pw = blockIdx.x * (kBlock / kWave) + wave;
+        if (lane_id() == 0 && pw < (uint32_t)kProbeWaves && probe_blocks < (uint32_t)kProbeIters) {
+            uint64_t* r = carve_probe_blocks[pw * kProbeIters + probe_blocks];
+            r[0] = t_a;
+            r[1] = t_b;
+            r[2] = passes_tests;
+        }
+        ++probe_blocks;
+#else
+        (void)passes_tests;
+#endif
     }
+    };
+    if (lds)
+        tiles_loop(std::true_type{});
+    else
+        tiles_loop(std::false_type{});
+#ifdef FVV_CARVE_PROBE
+    const uint32_t pw = blockIdx.x * (kBlock / kWave) + wave;
+    if (lane_id() == 0 && pw < (uint32_t)kProbeWaves) {
+        carve_probe_waves[pw][0] = probe_entry;
+        carve_probe_waves[pw][1] = __builtin_amdgcn_s_memrealtime();
+        carve_probe_waves[pw][2] = probe_blocks;
+    }
+#endif
 }
 
 // The batched carve with camera culling: the tile rows (the tiles of one job
@@ -1332,6 +1391,23 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
 // directly.  The tile-row prefix is read from LDS when the job table fits.
 constexpr int kBatchedJobLds = 1024;
 constexpr int kGroup = kBlock / kWave;
+constexpr int kRowRectWords = 8;   // silhouette words per row of a tile row's rectangle
+
+// Zero n bytes from p by the workgroup: 16-byte stores between the first and
+// the last 16-byte boundary, byte stores at the ends.
+__device__ __forceinline__ void zero_span(uint8_t* p, int64_t n) {
+    const int64_t head = (int64_t)((16 - ((uintptr_t)p & 15)) & 15);
+    const int64_t h = head < n ? head : n;
+    if ((int64_t)threadIdx.x < h)
+        p[threadIdx.x] = 0;
+    const int64_t n16 = (n - h) / 16;
+    uint4* q = reinterpret_cast<uint4*>(p + h);
+    for (int64_t i = threadIdx.x; i < n16; i += kBlock)
+        q[i] = make_uint4(0u, 0u, 0u, 0u);
+    const int64_t tail0 = h + 16 * n16;
+    if ((int64_t)threadIdx.x < n - tail0)
+        p[tail0 + threadIdx.x] = 0;
+}
 
 template <int TX, bool kLds>
 __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
@@ -1370,6 +1446,30 @@ __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
         const int nty = (g.dims[1] + TY - 1) / TY;
         const uint32_t r = (uint32_t)(row - off(j));
         const int j0 = (int)(r % (uint32_t)nty) * TY, k0 = (int)(r / (uint32_t)nty) * 4;
+        // the whole row first: a camera that rejects the row's box rejects
+        // every tile of it, and the row's TY x 4 sample rows are written as
+        // zeros, each layer's rows one contiguous span
+        __syncthreads();                       // the previous row is done with s_tile
+        if (wave == 0) {
+            float lo[3], hi[3];
+            box_corners(g, 0, g.dims[0] - 1, j0, min(j0 + TY, g.dims[1]) - 1, k0,
+                        min(k0 + 4, g.dims[2]) - 1, lo, hi);
+            uint32_t rej, mix;
+            classify_box_wave<kRowRectWords>(jc, sils + job.sil_base, (int64_t)jc.H * jc.wpr, lo, hi,
+                                         rej, mix);
+            if (lane_id() == 0)
+                s_tile[0][0] = (int32_t)rej;
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(s_tile[0][0]) != 0) {
+            const int ny = min(j0 + TY, g.dims[1]) - j0;
+            const int64_t span = (int64_t)ny * g.dims[0];            // bytes per layer
+            const int64_t plane = (int64_t)g.dims[0] * g.dims[1];
+            uint8_t* base = out + job.out_offset + (int64_t)j0 * g.dims[0];
+            for (int z = 0; z < 4 && k0 + z < g.dims[2]; ++z)
+                zero_span(base + (int64_t)(k0 + z) * plane, span);
+            continue;
+        }
         for (int tx0 = 0; tx0 < ntx; tx0 += kGroup) {
             __syncthreads();                   // the previous group is done with s_tile
             if (tx0 + wave < ntx) {
@@ -1514,3 +1614,34 @@ hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jo
 }
 
 }  // namespace fvv
+
+#ifdef FVV_CARVE_PROBE
+// Measurement builds only: the fine carve's probe tables to host memory
+// (blocks: kProbeWaves * kProbeIters * 3 words, waves: kProbeWaves * 3), and
+// their clearing before a run.
+extern "C" int32_t fvv_carve_probe_read(uint64_t* blocks, uint64_t* waves) {
+    if (!blocks || !waves)
+        return FVV_EINVAL;
+    hipError_t e = hipMemcpyFromSymbol(blocks, HIP_SYMBOL(fvv::carve_probe_blocks),
+                                       sizeof(fvv::carve_probe_blocks));
+    if (e == hipSuccess)
+        e = hipMemcpyFromSymbol(waves, HIP_SYMBOL(fvv::carve_probe_waves),
+                                sizeof(fvv::carve_probe_waves));
+    return e == hipSuccess ? FVV_OK : FVV_EDEVICE;
+}
+
+extern "C" int32_t fvv_carve_probe_clear() {
+    void* b = nullptr;
+    void* w = nullptr;
+    hipError_t e = hipGetSymbolAddress(&b, HIP_SYMBOL(fvv::carve_probe_blocks));
+    if (e == hipSuccess)
+        e = hipGetSymbolAddress(&w, HIP_SYMBOL(fvv::carve_probe_waves));
+    if (e == hipSuccess)
+        e = hipMemset(b, 0, sizeof(fvv::carve_probe_blocks));
+    if (e == hipSuccess)
+        e = hipMemset(w, 0, sizeof(fvv::carve_probe_waves));
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    return e == hipSuccess ? FVV_OK : FVV_EDEVICE;
+}
+#endif

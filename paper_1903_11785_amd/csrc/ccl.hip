@@ -33,6 +33,10 @@ constexpr int kLabelThreads = 512;
 constexpr int kRowCap = 4096;    // listed rows held in LDS
 constexpr int kRunCap = 6144;    // runs held in LDS
 constexpr int kRootCap = 1024;   // components whose stats are held in LDS
+// Adjacent run pairs listed in LDS before the unions (in the stats rows' room;
+// run ids below 2^16 pack two to a word).
+constexpr int kPairCap = kStatsRow * kRootCap + kRootCap;
+static_assert(kRunCap <= 65536, "run ids of the LDS pair list take 16 bits");
 
 // ------------------------------------------------------------------ union-find
 // Loads and stores of values other threads change concurrently: relaxed
@@ -114,17 +118,23 @@ __device__ __forceinline__ void label_stamp_sync(int) {}
 #endif
 
 // ------------------------------------------------------------------ fine jobs of a frame
-// floor(a / b) for b > 0 and |a| < 2^53: the correctly rounded double
-// quotient is within one of the exact one; the integer residual corrects it.
-__device__ __forceinline__ int64_t floor_div_pos(int64_t a, int64_t b) {
-    int64_t q = (int64_t)__builtin_floor((double)a / (double)b);
-    const int64_t r = a - q * b;
-    q -= (r < 0) ? 1 : 0;
-    q += (r >= b) ? 1 : 0;
+// floor(a / b) for b > 0 and |a| <= 2^53, from binv = 1.0 / b: the double
+// estimate a * binv (two roundings) is within two of the quotient, and two
+// steps of integer residual correction make it exact.
+__device__ __forceinline__ int64_t floor_div_pos(int64_t a, int64_t b, double binv) {
+    int64_t q = (int64_t)__builtin_floor((double)a * binv);
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+        const int64_t r = a - q * b;
+        q -= (r < 0) ? 1 : 0;
+        q += (r >= b) ? 1 : 0;
+    }
     return q;
 }
 
-__device__ __forceinline__ int64_t ceil_div_pos(int64_t a, int64_t b) { return -floor_div_pos(-a, b); }
+__device__ __forceinline__ int64_t ceil_div_pos(int64_t a, int64_t b, double binv) {
+    return -floor_div_pos(-a, b, binv);
+}
 
 constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
 
@@ -190,6 +200,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         dcams[c] = cam;
     }
     const uint32_t K = K_all < max_rois ? K_all : max_rois;
+    const double hf_inv = 1.0 / (double)fj.hf_um;
     auto fine_lattice = [&](uint32_t t, fvv_grid& fg) -> int64_t {
         int32_t lo[3], hi[3];
         box(t, lo, hi);
@@ -198,11 +209,12 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         for (int a = 0; a < 3; ++a) {
             const int64_t A = (int64_t)fj.coarse.lo[a] + lo[a] - 1;
             const int64_t B = (int64_t)fj.coarse.lo[a] + hi[a] + 1;
-            int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um);
-            int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um);
-            const int64_t fmin = ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um);
+            int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um, hf_inv);
+            int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um, hf_inv);
+            const int64_t fmin =
+                ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um, hf_inv);
             const int64_t fmax = floor_div_pos(
-                ((int64_t)fj.coarse.lo[a] + fj.coarse.dims[a] - 1) * fj.hc_um, fj.hf_um);
+                ((int64_t)fj.coarse.lo[a] + fj.coarse.dims[a] - 1) * fj.hc_um, fj.hf_um, hf_inv);
             f0 = f0 < fmin ? fmin : f0;
             f1 = f1 > fmax ? fmax : f1;
             fg.origin[a] = fj.coarse.origin[a];
@@ -618,9 +630,41 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         m.rs[n_rows] = n_runs;
     __syncthreads();
     label_stamp(3);
-    // 3. unite every run with the adjacent runs of its earlier neighbouring rows
-    for (int32_t k = threadIdx.x; k < n_runs; k += NT)
-        for_each_earlier_adjacent<kLds>(a, m, k, [&](int32_t b) { unite<kLds>(m.P, k, b); });
+    // 3. unite every run with the adjacent runs of its earlier neighbouring rows.
+    //    In LDS the adjacent pairs are listed first (in the stats rows, unused
+    //    until step 5), then united one pair per thread, so that no wave waits
+    //    on the neighbour search of some lanes and the unions of others at
+    //    once; pairs past the list's room are united where they are found.
+    if (kLds) {
+        uint32_t* const pairs = reinterpret_cast<uint32_t*>(lds_stats);
+        uint32_t* const n_pairs = scan;            // free until the next scan
+        if (threadIdx.x == 0)
+            *n_pairs = 0u;
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < n_runs; k += NT)
+            for_each_earlier_adjacent<kLds>(a, m, k, [&](int32_t b) {
+                const uint64_t act = __ballot(true);
+                const int leader = __ffsll((unsigned long long)act) - 1;
+                uint32_t base = 0;
+                if (lane_id() == leader)
+                    base = atomicAdd(n_pairs, (uint32_t)__popcll(act));
+                const uint32_t slot =
+                    (uint32_t)__builtin_amdgcn_readlane((int)base, leader) + lane_rank(act);
+                if (slot < (uint32_t)kPairCap)
+                    pairs[slot] = ((uint32_t)k << 16) | (uint32_t)b;
+                else
+                    unite<kLds>(m.P, k, b);
+            });
+        __syncthreads();
+        const uint32_t np = min(*n_pairs, (uint32_t)kPairCap);
+        for (uint32_t q = threadIdx.x; q < np; q += NT) {
+            const uint32_t v = pairs[q];
+            unite<kLds>(m.P, (int32_t)(v >> 16), (int32_t)(v & 0xffffu));
+        }
+    } else {
+        for (int32_t k = threadIdx.x; k < n_runs; k += NT)
+            for_each_earlier_adjacent<kLds>(a, m, k, [&](int32_t b) { unite<kLds>(m.P, k, b); });
+    }
     __syncthreads();
     label_stamp(4);
     // 4. flatten, then number the roots in ascending run id.  The walk only

@@ -111,10 +111,13 @@ __host__ __device__ inline BoxProj box_projection(const float* P, const double l
         }
         b.wmin = fmin(b.wmin, r[2]);
         if (r[2] > 0.0) {
-            b.umin = fmin(b.umin, r[0] / r[2]);
-            b.umax = fmax(b.umax, r[0] / r[2]);
-            b.vmin = fmin(b.vmin, r[1] / r[2]);
-            b.vmax = fmax(b.vmax, r[1] / r[2]);
+            // (one reciprocal per corner: its rounding is far inside the
+            // relative slack box_radius adds)
+            const double rw = 1.0 / r[2];
+            b.umin = fmin(b.umin, r[0] * rw);
+            b.umax = fmax(b.umax, r[0] * rw);
+            b.vmin = fmin(b.vmin, r[1] * rw);
+            b.vmax = fmax(b.vmax, r[1] * rw);
         }
     }
     return b;
@@ -509,6 +512,26 @@ __device__ __forceinline__ ItemJobs load_item_jobs(const JobPrefix* __restrict__
     return ItemJobs{pre, fit ? table : nullptr, nj};
 }
 
+// The job of work item `item` and the first work item of job j, from the
+// LDS table (kLds: `table` is the workgroup's copy) or from the prefixes.
+template <bool kLds>
+__device__ __forceinline__ int item_job(const uint32_t* table, const JobPrefix* __restrict__ pre,
+                                        int nj, uint32_t item) {
+    if constexpr (kLds)
+        return upper_job([&](int m) { return (uint64_t)table[m]; }, nj, item);
+    else
+        return upper_job([&](int m) { return (uint64_t)pre[m].item_off; }, nj, item);
+}
+
+template <bool kLds>
+__device__ __forceinline__ uint32_t item_first(const uint32_t* table,
+                                               const JobPrefix* __restrict__ pre, int j) {
+    if constexpr (kLds)
+        return table[j];
+    else
+        return pre[j].item_off;
+}
+
 struct MeshTable;
 
 }  // namespace fvv
@@ -689,7 +712,7 @@ hipError_t launch_edges(const SurfaceScratch& sc, const fvv_job* jobs, const uin
                         uint32_t* n_points, bool keys_out, bool word_edges, hipStream_t s);
 // Exit points of the listed edges.  tiles: the silhouettes in 8 x 8-pixel
 // blocks (launch_tile_sils), or NULL (slower: no pixel windows).
-hipError_t launch_bisect(int n_cus, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+hipError_t launch_bisect(int n_cus, const fvv_job* jobs, int max_jobs, const uint32_t* n_jobs_dev,
                          const uint32_t* point_off, const CamSet& cams, const uint32_t* sils,
                          const uint64_t* tiles, int n_steps, const uint32_t* keys, float* xyz,
                          uint32_t max_points, hipStream_t s, hipEvent_t k_start = nullptr,

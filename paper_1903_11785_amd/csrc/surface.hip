@@ -13,6 +13,8 @@
 // two steps per round.
 #include "fvv_internal.h"
 
+#include <type_traits>
+
 namespace fvv {
 
 // The single job of fvv_surface, from the kernel arguments.
@@ -117,12 +119,17 @@ __global__ __launch_bounds__(kBlock) void edge_count_kernel(const fvv_job* __res
     __shared__ uint32_t scratch[kBlock / kWave];
     const int nj = (int)*n_jobs_p;
     const ItemJobs ij = load_item_jobs(pre, nj, table);
-    const uint32_t n_items = ij.first_item(nj);
+    // two copies of the loop, with the job table in LDS and without (so that
+    // neither reads it through generic pointers)
+    auto items_loop = [&](auto in_lds) {
+    constexpr bool kLds = decltype(in_lds)::value;
+    const uint32_t n_items = item_first<kLds>(table, pre, nj);
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int jb = ij.job_of(item);
+        const int jb = item_job<kLds>(table, pre, nj, item);
         const fvv_grid g = jobs[jb].grid;
         const int64_t n_words = fine_bitmap_words(g);
-        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
+        const int64_t w =
+            (int64_t)(item - item_first<kLds>(table, pre, jb)) * kEdgeWords + threadIdx.x;
         const int32_t wr = (g.dims[0] + 63) / 64;
         uint32_t c = 0;
         if (w < n_words)
@@ -132,6 +139,11 @@ __global__ __launch_bounds__(kBlock) void edge_count_kernel(const fvv_job* __res
         if (threadIdx.x == 0)
             item_cnt[item] = total;
     }
+    };
+    if (ij.lds)
+        items_loop(std::true_type{});
+    else
+        items_loop(std::false_type{});
 }
 
 // Per work item: first edge = sum of the counts of the items before it; then
@@ -159,7 +171,11 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
     __shared__ uint64_t scratch64[kBlock / kWave];
     const int nj = (int)*n_jobs_p;
     const ItemJobs ij = load_item_jobs(pre, nj, table);
-    const uint32_t n_items = ij.first_item(nj);
+    // two copies of the loop, with the job table in LDS and without (so that
+    // neither reads it through generic pointers)
+    auto items_loop = [&](auto in_lds) {
+    constexpr bool kLds = decltype(in_lds)::value;
+    const uint32_t n_items = item_first<kLds>(table, pre, nj);
     if (kKeys && n_items == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
         for (int j = 0; j <= nj; ++j)
             point_off[j] = 0;
@@ -172,10 +188,11 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
             before += item_cnt[i];
         uint64_t first;
         block_exclusive_sum64<kBlock>(before, scratch64, &first);
-        const int jb = ij.job_of(item);
+        const int jb = item_job<kLds>(table, pre, nj, item);
         const fvv_grid g = jobs[jb].grid;
         const int64_t n_words = fine_bitmap_words(g);
-        const int64_t w = (int64_t)(item - ij.first_item(jb)) * kEdgeWords + threadIdx.x;
+        const int64_t w =
+            (int64_t)(item - item_first<kLds>(table, pre, jb)) * kEdgeWords + threadIdx.x;
         const int32_t wr = (g.dims[0] + 63) / 64;
         EdgeMasks m{0ull, 0ull, 0ull, 0ull};
         if (w < n_words)
@@ -215,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
         }
         if (kKeys && threadIdx.x == 0) {
             const auto clamp = [](uint64_t v) { return (uint32_t)(v < 0xffffffffull ? v : 0xffffffffull); };
-            if (item == ij.first_item(jb))
+            if (item == item_first<kLds>(table, pre, jb))
                 point_off[jb] = clamp(first);
             if (item + 1 == n_items) {
                 const uint64_t all = first + total;
@@ -226,6 +243,11 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
             }
         }
     }
+    };
+    if (ij.lds)
+        items_loop(std::true_type{});
+    else
+        items_loop(std::false_type{});
 }
 
 // ------------------------------------------------------------------ exit points
@@ -365,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                                                      int n_steps,
                                                      const uint32_t* __restrict__ keys,
                                                      float* __restrict__ xyz,
-                                                     uint32_t max_points) {
+                                                     uint32_t max_points, int job_lds) {
     constexpr int kWaves = kBlock / kWave;
     __shared__ uint32_t s_off[kBisectJobs + 1];
     __shared__ fvv_grid s_grid[kBisectJobs];
@@ -376,20 +398,28 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
     __shared__ uint32_t s_worg[kWinCap];
     __shared__ uint32_t s_fail[kBisectEdges];
     __shared__ uint32_t s_npairs;
+    // the point offsets and lattices of the first job_lds jobs (every job the
+    // tables hold, up to kBisectJobs), loaded without waiting for the job count
+    for (int j = threadIdx.x; j <= job_lds; j += kBlock) {
+        s_off[j] = point_off[j];
+        if (j < job_lds)
+            s_grid[j] = jobs[j].grid;
+    }
     const int nj = (int)*n_jobs_p;
-    const bool lds = nj <= kBisectJobs;
-    if (lds)
-        for (int j = threadIdx.x; j <= nj; j += kBlock) {
-            s_off[j] = point_off[j];
-            if (j < nj)
-                s_grid[j] = jobs[j].grid;
-        }
+    const bool lds = nj <= job_lds;
     for (int q = threadIdx.x; q < cams.n * 13; q += kBlock) {
         const int c = q / 13, e = q - 13 * c;
         s_P[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
     }
     __syncthreads();
-    const uint32_t total = lds ? s_off[nj] : point_off[nj];
+    // the chunks' loop, once with the job tables in LDS and once without (two
+    // copies, so that neither reads its tables through generic pointers)
+    auto chunks_loop = [&](auto in_lds) {
+    uint32_t total;
+    if constexpr (decltype(in_lds)::value)
+        total = s_off[nj];
+    else
+        total = point_off[nj];
     const uint32_t E = total < max_points ? total : max_points;
     const int64_t cam_words = (int64_t)cams.H * cams.wpr;
     const int tpr = (cams.W + 7) / 8;
@@ -406,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
             const uint32_t ee = act ? e : E - 1;
             int jb;
             fvv_grid g;
-            if (lds) {
+            if constexpr (decltype(in_lds)::value) {
                 jb = upper_job([&](int m) { return (uint64_t)s_off[m]; }, nj, ee);
                 g = s_grid[jb];
             } else {
@@ -584,6 +614,11 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
         }
         __syncthreads();   // the next chunk rewrites the records, pairs and count
     }
+    };
+    if (lds)
+        chunks_loop(std::true_type{});
+    else
+        chunks_loop(std::false_type{});
 }
 
 hipError_t launch_edges(const SurfaceScratch& sc, const fvv_job* jobs, const uint32_t* n_jobs_dev,
@@ -603,19 +638,21 @@ hipError_t launch_edges(const SurfaceScratch& sc, const fvv_job* jobs, const uin
     return hipGetLastError();
 }
 
-hipError_t launch_bisect(int n_cus, const fvv_job* jobs, const uint32_t* n_jobs_dev,
+hipError_t launch_bisect(int n_cus, const fvv_job* jobs, int max_jobs, const uint32_t* n_jobs_dev,
                          const uint32_t* point_off, const CamSet& cams, const uint32_t* sils,
                          const uint64_t* tiles, int n_steps, const uint32_t* keys, float* xyz,
                          uint32_t max_points, hipStream_t s, hipEvent_t k_start,
                          hipEvent_t k_stop) {
+    // jobs: max_jobs entries, point_off: max_jobs + 1
+    const int job_lds = max_jobs < kBisectJobs ? max_jobs : kBisectJobs;
     if (cams.n <= 16)
         hipExtLaunchKernelGGL(bisect_kernel<16>, dim3(n_cus * 16), dim3(kBlock), 0, s, k_start,
                               k_stop, 0, jobs, n_jobs_dev, point_off, cams, sils, tiles, n_steps,
-                              keys, xyz, max_points);
+                              keys, xyz, max_points, job_lds);
     else
         hipExtLaunchKernelGGL(bisect_kernel<FVV_MAX_CAMS>, dim3(n_cus * 16), dim3(kBlock), 0, s,
                               k_start, k_stop, 0, jobs, n_jobs_dev, point_off, cams, sils, tiles,
-                              n_steps, keys, xyz, max_points);
+                              n_steps, keys, xyz, max_points, job_lds);
     return hipGetLastError();
 }
 
