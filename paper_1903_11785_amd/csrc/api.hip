@@ -745,14 +745,13 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
         e = launch_label(ctx, p->coarse, o->d_occ_coarse, nullptr, p->t_np, p->t_nb, o->d_rois,
                          o->max_rois, o->d_counts + 0, true, &fj, stream);
     mark(3);
-    // the grid pass writing labels and the filtered coarse occupancy (on the
-    // same stream: a branch to the side stream and back costs more than it)
-    if (e == hipSuccess)
-        e = launch_label_write(ctx, p->coarse, o->d_occ_coarse, o->d_labels, stream);
+    // the fine carve; the grid pass writing labels and the filtered coarse
+    // occupancy rides in its launch (a branch to the side stream and back, or
+    // a launch of its own, costs more than the pass)
     if (e == hipSuccess)
         e = launch_carve_frame(ctx, o->d_jobs, (int)o->max_rois, cs, d_sils, ctx->d_tsils,
-                               o->d_occ_fine,
-                               ctx->d_finebits, ft, blocks, stream, kev(0), kev(1));
+                               o->d_occ_fine, ctx->d_finebits, ft, blocks, p->coarse,
+                               o->d_occ_coarse, o->d_labels, stream, kev(0), kev(1));
     mark(4);
     // the mesh also runs on the side branch: its count once the fine bitmaps
     // are there, its triangles once the crossing edges are, beside the exit

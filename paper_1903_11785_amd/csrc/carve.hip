@@ -1277,7 +1277,16 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
                                                              const float* __restrict__ rho,
                                                              uint8_t* __restrict__ out,
                                                              uint64_t* __restrict__ finebits,
-                                                             int job_lds) {
+                                                             int job_lds, LabelWrite lw) {
+    // the workgroups past the carve's write the coarse labels and filtered
+    // occupancy (they start as the carve's tail frees the CUs)
+    if (blockIdx.x >= lw.carve_blocks) {
+        const int64_t stride = (int64_t)(gridDim.x - lw.carve_blocks) * kBlock;
+        for (int64_t v = (int64_t)(blockIdx.x - lw.carve_blocks) * kBlock + threadIdx.x; v < lw.V;
+             v += stride)
+            label_write_sample(lw, v);
+        return;
+    }
 #ifdef FVV_CARVE_PROBE
     const uint64_t probe_entry = __builtin_amdgcn_s_memrealtime();
     uint32_t probe_blocks = 0;
@@ -1318,7 +1327,7 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
         total = s_tile_off[nj];
     else
         total = pre[nj].tile_off;
-    const XcdSlice xs{0, total, blockIdx.x, gridDim.x};
+    const XcdSlice xs{0, total, blockIdx.x, lw.carve_blocks};
     for (uint64_t t = xs.begin + xs.slot; t < xs.end; t += xs.stride) {
         int jb;
         fvv_grid g;
@@ -1496,10 +1505,14 @@ __global__ __launch_bounds__(kBlock, 6) void carve_batched_culled_kernel(
 hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
                               const CamSet& cams, const uint32_t* sils, const uint64_t* tiles,
                               uint8_t* out, uint64_t* finebits, TileShape t, int blocks,
+                              const fvv_grid& coarse, uint8_t* occ_coarse, int32_t* labels,
                               hipStream_t s, hipEvent_t k_start, hipEvent_t k_stop) {
     if (t.tz != 4) {
-        // the persistent carve: the events bracket its launch
-        hipError_t e = k_start ? hipEventRecord(k_start, s) : hipSuccess;
+        // the persistent carve: the events bracket its launch; the labels'
+        // write pass goes first
+        hipError_t e = launch_label_write(ctx, coarse, occ_coarse, labels, s);
+        if (e == hipSuccess && k_start)
+            e = hipEventRecord(k_start, s);
         if (e == hipSuccess)
             e = launch_carve_batched(ctx, jobs, 0, ctx->d_cams, sils, out, finebits, t, blocks,
                                      true, s);
@@ -1508,13 +1521,24 @@ hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
         return e;
     }
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+    // the coarse labels' write pass rides in the same launch, about eight
+    // samples per thread in workgroups after the carve's
+    LabelWrite lw;
+    lw.sample_label = ctx->d_sample_label;
+    lw.occ = occ_coarse;
+    lw.labels = labels;
+    lw.V = (int64_t)coarse.dims[0] * coarse.dims[1] * coarse.dims[2];
+    lw.carve_blocks = (uint32_t)blocks;
+    const int64_t lw_blocks = (lw.V + 8 * kBlock - 1) / (8 * kBlock);
+    const int extra = (int)(lw_blocks < 1 ? 1 : (lw_blocks > 4 * ctx->n_cus ? 4 * ctx->n_cus
+                                                                              : lw_blocks));
     // jobs: max_jobs entries; the prefix table holds at least max_jobs + 1
     const int job_lds = max_jobs < kJobLds ? max_jobs : kJobLds;
 #define X(TXV)                                                                                 \
     if (t.tx == TXV) {                                                                         \
-        hipExtLaunchKernelGGL((carve_frame_kernel<TXV>), dim3(blocks), dim3(kBlock), 0, s,     \
-                              k_start, k_stop, 0, jobs, ctx->d_prefix, ctx->d_counter, cams,   \
-                              sils, tiles, ctx->d_rho, out, finebits, job_lds);                \
+        hipExtLaunchKernelGGL((carve_frame_kernel<TXV>), dim3(blocks + extra), dim3(kBlock), 0, \
+                              s, k_start, k_stop, 0, jobs, ctx->d_prefix, ctx->d_counter, cams, \
+                              sils, tiles, ctx->d_rho, out, finebits, job_lds, lw);            \
         return hipGetLastError();                                                              \
     }
     X(64) X(32) X(16)

@@ -818,14 +818,7 @@ __global__ __launch_bounds__(kBlock) void label_write_kernel(const int32_t* __re
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= V)
         return;
-    if (occ[v]) {
-        const int32_t lab = sample_label[v];
-        labels[v] = lab;
-        if (lab == 0)
-            occ[v] = 0;
-    } else {
-        labels[v] = 0;
-    }
+    label_write_sample(LabelWrite{sample_label, occ, labels, V, 0u}, v);
 }
 
 RowBits row_bits(fvv_ctx* ctx, const fvv_grid& g) {

@@ -599,6 +599,29 @@ struct FrameJobs {
     float* rho;          // per (job, camera) radii (kRhoPer floats), written with the jobs
 };
 
+// The coarse labels' write pass of a frame (after the labelling): per sample
+// v, labels[v] = the sample's component label (0 when unoccupied or filtered
+// out by Eq. (1)) and occ[v] cleared where the label is 0.  carve_blocks: the
+// workgroups of the launch that carve; the rest write labels.
+struct LabelWrite {
+    const int32_t* sample_label;
+    uint8_t* occ;
+    int32_t* labels;
+    int64_t V;
+    uint32_t carve_blocks;
+};
+
+__device__ __forceinline__ void label_write_sample(const LabelWrite& lw, int64_t v) {
+    if (lw.occ[v]) {
+        const int32_t lab = lw.sample_label[v];
+        lw.labels[v] = lab;
+        if (lab == 0)
+            lw.occ[v] = 0;
+    } else {
+        lw.labels[v] = 0;
+    }
+}
+
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils, hipStream_t s);
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g,
@@ -722,9 +745,11 @@ hipError_t launch_bisect(int n_cus, const fvv_job* jobs, int max_jobs, const uin
 // take the batched carve.
 // k_start, k_stop: NULL, or events that take the kernel's own start and end
 // times (hipExtLaunchKernel).
+// The labels' write pass (launch_label_write's work) runs in the same launch.
 hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
                               const CamSet& cams, const uint32_t* sils, const uint64_t* tiles,
                               uint8_t* out, uint64_t* finebits, TileShape t, int blocks,
+                              const fvv_grid& coarse, uint8_t* occ_coarse, int32_t* labels,
                               hipStream_t s, hipEvent_t k_start = nullptr,
                               hipEvent_t k_stop = nullptr);
 // The silhouettes in 8 x 8-pixel blocks (tile_sils_kernel's layout), from the

@@ -288,7 +288,9 @@ __global__ __launch_bounds__(kBlock) void edge_write_kernel(const fvv_job* __res
 // points are dyadic, exact in float).  The bracket width w is the same for
 // every edge.
 constexpr int kBisectJobs = 64;    // jobs whose lattices a workgroup keeps in LDS
-constexpr int kBisectEdges = 64;   // edges per workgroup pass
+constexpr int kBisectEdges = 64;   // edges per workgroup pass (64 or 128)
+constexpr int kHalves = kBisectEdges / kWave;   // waves that own edges
+static_assert(kHalves >= 1 && kHalves <= kBlock / kWave, "edges per pass");
 constexpr int kWinCap = 512;       // kept pairs per workgroup pass with an LDS window
 constexpr int kCullUnroll = 2;     // cull cameras whose loads are in flight together
 constexpr uint32_t kNoWindow = 0xffffffffu;
@@ -426,13 +428,16 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
     const int64_t tpc = (int64_t)tpr * ((cams.H + 7) / 8);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    // contiguous edge ranges per XCD, in chunks of 64 edges
+    // contiguous edge ranges per XCD, in chunks of kBisectEdges edges
     const XcdSlice xs = xcd_slice((E + kBisectEdges - 1) / kBisectEdges);
     for (uint64_t chunk = xs.begin + xs.slot; chunk < xs.end; chunk += xs.stride) {
-        const uint32_t e = (uint32_t)chunk * kBisectEdges + lane;   // this lane's edge
+        // the first kHalves waves own the chunk's edges, 64 each: this lane's
+        // edge in a wave that owns some (its record at s_rec[el])
+        const int el = (wave < kHalves ? wave : 0) * kWave + lane;
+        const uint32_t e = (uint32_t)chunk * kBisectEdges + (uint32_t)el;
         const bool act = e < E;
-        // 1. the edges' records, by the first wave
-        if (wave == 0) {
+        // 1. the edges' records, by the waves that own them
+        if (wave < kHalves) {
             const uint32_t ee = act ? e : E - 1;
             int jb;
             fvv_grid g;
@@ -468,14 +473,17 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
             mine.lo = 0.0f;
             mine.axis = axis;
             mine.pad_[0] = mine.pad_[1] = 0;
-            s_rec[lane] = mine;
-            if (lane == 0)
+            s_rec[el] = mine;
+            if (el == 0)
                 s_npairs = 0u;
         }
         __syncthreads();
-        // 2. cull: lane = edge, wave v the cameras v, v + 4, ...
-        {
-            const EdgeRec& er = s_rec[lane];
+        // 2. cull: lane = edge (the chunk's 64-edge parts in turn), wave v the
+        //    cameras v, v + 4, ...
+        for (int half = 0; half < kHalves; ++half) {
+            const int ec = half * kWave + lane;
+            const bool act_c = (uint32_t)chunk * kBisectEdges + (uint32_t)ec < E;
+            const EdgeRec& er = s_rec[ec];
             const float X0[3] = {er.c[0], er.c[1], er.c[2]};
             const float X1[3] = {er.axis == 0 ? er.x1 : er.c[0], er.axis == 1 ? er.x1 : er.c[1],
                                  er.axis == 2 ? er.x1 : er.c[2]};
@@ -486,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                 for (int u = 0; u < kCullUnroll; ++u) {
                     const int cc = min(cb + u * kWaves, cams.n - 1);
                     rr[u] = edge_rect(cams.Pc(cc), cams.padc(cc), cams.W, cams.H, X0, X1);
-                    rr[u].small = rr[u].small && tiles != nullptr && act;
+                    rr[u].small = rr[u].small && tiles != nullptr && act_c;
                     const bool sm = rr[u].small;
                     const int bx = rr[u].x0 >> 3, by = rr[u].y0 >> 3;
                     const bool nx = ((rr[u].x0 + rr[u].nx) >> 3) != bx;
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                     const uint64_t wv = edge_window(rr[u], blk[u]);
                     const uint64_t cols = (uint64_t)((2u << rr[u].nx) - 1u) * 0x0101010101010101ull;
                     const uint64_t m = cols & (~0ull >> (8 * (7 - rr[u].ny)));
-                    const bool keep = act && !(rr[u].small && (wv & m) == m);
+                    const bool keep = act_c && !(rr[u].small && (wv & m) == m);
                     const uint64_t kb = __ballot(keep);
                     if (kb == 0ull)
                         continue;
@@ -520,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                     base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
                     const uint32_t slot = base + lane_rank(kb);
                     if (keep) {
-                        s_pair[slot] = (uint16_t)((lane << 5) | cc);
+                        s_pair[slot] = (uint16_t)((ec << 5) | cc);
                         if (slot < (uint32_t)kWinCap) {
                             s_win[slot] = rr[u].small ? wv : 0ull;
                             s_worg[slot] = rr[u].small
@@ -533,20 +541,20 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
         }
         __syncthreads();
         const uint32_t n_pairs = s_npairs;
-        // 3. the rounds; the first wave keeps each edge's bracket start
+        // 3. the rounds; the owning waves keep each edge's bracket start
         float lo = 0.0f, w = 1.0f;
         for (int st = 0; st < n_steps; st += 2) {
             const bool two = st + 1 < n_steps;   // uniform
             const float w4 = 0.25f * w;
-            if (wave == 0)
-                s_fail[lane] = 0u;
+            if (wave < kHalves)
+                s_fail[el] = 0u;
             __syncthreads();
             for (uint32_t base = (uint32_t)wave * kWave; base < n_pairs; base += kBlock) {
                 const uint32_t pi = base + (uint32_t)lane;
                 const bool live = pi < n_pairs;
                 const uint32_t pr = s_pair[live ? pi : 0];
-                const int el = (int)(pr >> 5), ca = (int)(pr & 31u);
-                const EdgeRec& er = s_rec[el];
+                const int pe = (int)(pr >> 5), ca = (int)(pr & 31u);
+                const EdgeRec& er = s_rec[pe];
                 const bool cached = pi < (uint32_t)kWinCap;
                 const uint32_t org = cached ? s_worg[cached ? pi : 0] : kNoWindow;
                 const uint64_t wv = cached ? s_win[cached ? pi : 0] : 0ull;
@@ -585,25 +593,25 @@ __global__ __launch_bounds__(kBlock) void bisect_kernel(const fvv_job* __restric
                     fail |= in ? 0u : (1u << q);
                 }
                 if (live && fail)
-                    atomicOr(&s_fail[el], fail);
+                    atomicOr(&s_fail[pe], fail);
             }
             __syncthreads();
-            if (wave == 0) {
-                const uint32_t f = s_fail[lane];
+            if (wave < kHalves) {
+                const uint32_t f = s_fail[el];
                 if (two) {
                     const int idx = !(f & 2u) ? (!(f & 4u) ? 3 : 2) : (!(f & 1u) ? 1 : 0);
                     lo = lo + (float)idx * w4;
                 } else if (!(f & 2u)) {
                     lo = lo + 2.0f * w4;
                 }
-                s_rec[lane].lo = lo;
+                s_rec[el].lo = lo;
             }
             w = two ? w4 : 0.5f * w;   // every wave: the width is the same for all edges
             __syncthreads();
         }
         // 4. the exit point: the final bracket's midpoint
-        if (wave == 0 && act) {
-            const EdgeRec& er = s_rec[lane];
+        if (wave < kHalves && act) {
+            const EdgeRec& er = s_rec[el];
             const float hi = lo + w;
             const float t = 0.5f * (lo + hi);
             const float q = er.gq + er.d * t;

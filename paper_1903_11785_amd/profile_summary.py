@@ -4,6 +4,9 @@
 ``rocprofv3 --kernel-trace --stats --output-format csv`` run) as a table of
 calls, average, minimum and total time per kernel.
 
+``counters``: per kernel, the mean of each counter of one or more counter
+runs (``rocprofv3 --pmc ...``, CSV output) over the kernel's dispatches.
+
 ``traffic``: HBM bytes per launch of one kernel from two counter runs
 (``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``, CSV output), each
 scaled by what the same counter reads for a plain device copy of known size
@@ -112,10 +115,43 @@ def _copy_value(rows):
     return max(vals)
 
 
+def counters(dirs, kernels, command: str) -> str:
+    """Per kernel, the mean of every counter over its dispatches, from one or
+    more counter runs (each a rocprofv3 --pmc run with CSV output)."""
+    per = {}
+    for d in dirs:
+        path = _one("*counter_collection.csv", d)
+        acc = {}
+        names = {}
+        for r in csv.DictReader(open(path)):
+            key = (r.get("Dispatch_Id"), r["Counter_Name"])
+            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+            names[r.get("Dispatch_Id")] = short_name(r["Kernel_Name"])
+        for (did, cn), v in acc.items():
+            per.setdefault(names[did], {}).setdefault(cn, []).append(v)
+    lines = [f"# counters: {command}", "",
+             "kernel | counter | mean per dispatch | dispatches"]
+    for k in kernels:
+        for cn, vs in sorted(per.get(k, {}).items()):
+            lines.append(f"{k} | {cn} | {sum(vs) / len(vs):.6g} | {len(vs)}")
+    return "\n".join(lines) + "\n"
+
+
 def traffic(fetch_dir, write_dir, kernel, sources, copy_mib, workload, command) -> dict:
+    """kernel: one short name, or several joined by ' + ' (a call of several
+    kernels: the sum of their means)."""
     fr, wr = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
-    f_kib, nf = _kernel_mean(fr, kernel)
-    w_kib, nw = _kernel_mean(wr, kernel)
+    f_kib = w_kib = 0.0
+    nf, nw = [], []
+    for k in kernel.split(" + "):
+        f, n1 = _kernel_mean(fr, k)
+        w, n2 = _kernel_mean(wr, k)
+        f_kib += f
+        w_kib += w
+        nf.append(n1)
+        nw.append(n2)
+    nf = nf[0] if len(nf) == 1 else nf
+    nw = nw[0] if len(nw) == 1 else nw
     ref_kib = copy_mib * 1024.0
     f_copy, w_copy = _copy_value(fr), _copy_value(wr)
     f_scale, w_scale = ref_kib / f_copy, ref_kib / w_copy
@@ -161,8 +197,14 @@ def main():
     c.add_argument("--copy-mib", type=int, default=256)
     c.add_argument("--workload", required=True)
     c.add_argument("--command", required=True)
+    q = sub.add_parser("counters")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--kernels", nargs="+", required=True)
+    q.add_argument("--command", required=True)
     a = ap.parse_args()
-    if a.what == "trace":
+    if a.what == "counters":
+        sys.stdout.write(counters(a.dirs, a.kernels, a.command))
+    elif a.what == "trace":
         sys.stdout.write(trace(a.dir, a.command, a.top, a.first, a.first_kernels))
     else:
         json.dump(traffic(a.fetch_dir, a.write_dir, a.kernel, a.sources, a.copy_mib, a.workload,
