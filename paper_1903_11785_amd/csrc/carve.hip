@@ -1247,7 +1247,8 @@ __device__ __forceinline__ uint32_t carve_block16(const CamSet& cams, const floa
 
 // Measurement builds (FVV_CARVE_PROBE defined) record, for the first
 // kProbeWaves waves of the frame's fine carve, the real-time clock (100 MHz)
-// at the wave's entry and exit and its block count, and for its first
+// at the wave's entry and exit, its block count and the time its workgroup's
+// tables took (entry to the barrier after them), and for its first
 // kProbeIters blocks their start, end, test passes and tests.
 #ifdef FVV_CARVE_PROBE
 constexpr int kProbeWaves = 16384, kProbeIters = 4;
@@ -1315,6 +1316,9 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
         s_cam[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
     }
     __syncthreads();
+#ifdef FVV_CARVE_PROBE
+    const uint64_t probe_tables = __builtin_amdgcn_s_memrealtime();
+#endif
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int xo = 16 * (wave % BXN), yo = 4 * (wave / BXN);
     const int tpr = (cams.W + 7) / 8;
@@ -1381,7 +1385,9 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
     if (lane_id() == 0 && pw < (uint32_t)kProbeWaves) {
         carve_probe_waves[pw][0] = probe_entry;
         carve_probe_waves[pw][1] = __builtin_amdgcn_s_memrealtime();
-        carve_probe_waves[pw][2] = probe_blocks;
+        // blocks carved, and (high half) the ticks from entry to the tables'
+        // barrier
+        carve_probe_waves[pw][2] = probe_blocks | ((probe_tables - probe_entry) << 32);
     }
 #endif
 }

@@ -191,7 +191,9 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
     __shared__ uint64_t c_vox, c_bits, c_tiles, c_items;   // running totals over whole chunks
     __shared__ uint64_t e_vox, e_tiles, e_items;           // totals over the carried ROIs
     __shared__ uint32_t carried;
-    for (int c = threadIdx.x; c < fj.cams.n; c += NT) {
+    // the device camera table, by the threads past the first wave (which lays
+    // out the jobs meanwhile)
+    for (int c = (int)threadIdx.x - kWave; c >= 0 && c < fj.cams.n; c += NT - kWave) {
         fvv_camera cam;
         for (int e = 0; e < 12; ++e)
             cam.P[e] = fj.cams.P[c][e];

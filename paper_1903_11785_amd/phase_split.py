@@ -47,7 +47,8 @@ def carve_split(blocks: np.ndarray, waves: np.ndarray) -> dict:
     base = int(wv[:, 0].min())
     ent = (wv[:, 0].astype(np.int64) - base) * TICK_US
     ext = (wv[:, 1].astype(np.int64) - base) * TICK_US
-    n_blk = wv[:, 2].astype(np.int64)
+    n_blk = (wv[:, 2] & 0xffffffff).astype(np.int64)
+    tables = (wv[:, 2] >> 32).astype(np.int64) * TICK_US
     b = blocks.reshape(PROBE_WAVES, PROBE_ITERS, 3)
     used = b[:, :, 0] != 0
     st = (b[:, :, 0].astype(np.int64) - base) * TICK_US
@@ -89,6 +90,7 @@ def carve_split(blocks: np.ndarray, waves: np.ndarray) -> dict:
             "between_blocks": round(float(gaps.sum() / wave_time), 3),
         },
         "before_first_block_us_mean": round(float(first[has].mean()), 2),
+        "of_which_tables_and_barrier_us_mean": round(float(tables[has].mean()), 2),
         "between_blocks_us_mean": round(float(gaps.mean()), 2) if gaps.size else 0.0,
         "wave_entry_us": {"p50": round(float(np.median(ent)), 2), "max": round(float(ent.max()), 2)},
         "busy_fraction_of_span": round(wave_time / (span * 256 * 28), 3),
