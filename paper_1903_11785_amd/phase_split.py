@@ -97,7 +97,7 @@ def carve_split(blocks: np.ndarray, waves: np.ndarray) -> dict:
     }
 
 
-def run(frames: int, reps: int) -> dict:
+def run(frames: int, reps: int, cfg: str = "volleyball") -> dict:
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
     import scenes
@@ -113,16 +113,18 @@ def run(frames: int, reps: int) -> dict:
     L.fvv_carve_probe_clear.argtypes = []
     L.fvv_carve_probe_clear.restype = C.c_int32
     torch.cuda.set_device(0)
-    scs = [scenes.make_scene(scenes.CFG_VOLLEYBALL, f) for f in range(frames)]
+    cfg_id = {"volleyball": scenes.CFG_VOLLEYBALL, "judo": scenes.CFG_JUDO,
+              "paper_volleyball": scenes.CFG_PAPER_V}[cfg]
+    scs = [scenes.make_scene(cfg_id, f) for f in range(frames)]
     sc0 = scs[0]
     N, H, W = sc0.masks.shape
     coarse = fvv.Grid(origin=tuple(sc0.origin), h=sc0.hc, lo=(0, 0, 0), dims=sc0.coarse_dims)
-    ctx = fvv.Context(max_cams=N, max_w=W, max_h=H, max_coarse=coarse.size, max_fine=1 << 26,
-                      max_rois=256, max_points=1 << 22, max_jobs=256)
+    ctx = fvv.Context(max_cams=N, max_w=W, max_h=H, max_coarse=coarse.size, max_fine=1 << 27,
+                      max_rois=256, max_points=1 << 23, max_jobs=256)
     params = fvv.frame_params(sc0.P32, W, H, coarse, sc0.hc_um, sc0.hf_um, sc0.t_np, sc0.t_nb,
                               sc0.n_steps)
     sils = torch.empty((N, H, (W + 31) // 32), dtype=torch.int32, device="cuda")
-    bufs = fvv.FrameBuffers(coarse, 256, 1 << 26, 1 << 22)
+    bufs = fvv.FrameBuffers(coarse, 256, 1 << 27, 1 << 23)
     stamps = np.zeros(N_STAMPS, np.uint64)
     blocks = np.zeros((PROBE_WAVES * PROBE_ITERS, 3), np.uint64)
     waves = np.zeros((PROBE_WAVES, 3), np.uint64)
@@ -148,7 +150,7 @@ def run(frames: int, reps: int) -> dict:
     # the fine carve: the run with the median span
     carve.sort(key=lambda c: c["span_us"])
     return {
-        "workload": f"volleyball, {frames} frames x {reps} runs",
+        "workload": f"{cfg}, {frames} frames x {reps} runs",
         "labelling_us": {p: round(float(v), 2) for p, v in zip(LABEL_PHASES, med)},
         "labelling_total_us": round(float(np.median(label.sum(axis=1))), 2),
         "fine_carve_median_run": carve[len(carve) // 2],
@@ -161,11 +163,12 @@ def main():
     ap.add_argument("--run", action="store_true")
     ap.add_argument("--frames", type=int, default=4)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--cfg", default="volleyball", choices=["volleyball", "judo", "paper_volleyball"])
     a = ap.parse_args()
     if a.build:
         print(build_measure())
     if a.run:
-        print(json.dumps(run(a.frames, a.reps), indent=1))
+        print(json.dumps(run(a.frames, a.reps, a.cfg), indent=1))
 
 
 if __name__ == "__main__":
