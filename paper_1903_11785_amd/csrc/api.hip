@@ -150,7 +150,7 @@ hipError_t launch_surface_single(const SurfaceScratch& sc, const fvv_job& job,
     // scratch holds them
     const bool tiled = sc.tiles && tiled_sil_words(cs.n, cs.W, cs.H) <= sc.tile_cap;
     if (e == hipSuccess && tiled)
-        e = launch_tile_sils(cs.n, cs.W, cs.H, d_sils, sc.tiles, stream);
+        e = launch_tile_sils(cs.n, cs.W, cs.H, d_sils, sc.tiles, nullptr, stream);
     if (e == hipSuccess)
         e = launch_edges(sc, sc.job_single, sc.counts_single + 3, d_keys, d_xyz, max_points,
                          sc.point_off_single, d_n_points, true, false, stream);
@@ -304,7 +304,7 @@ void fvv_destroy(fvv_ctx* ctx) {
                     ctx->d_sample_label, ctx->d_prefix, ctx->d_job_pad, ctx->d_soft_acc, ctx->d_mesh_table,
                     ctx->d_job_single, ctx->d_cams, ctx->d_finebits, ctx->d_item_cnt,
                     ctx->d_word_edges, ctx->d_tri_first, ctx->d_point_off_single,
-                    ctx->d_counts_single, ctx->d_tsils, ctx->d_rho};
+                    ctx->d_counts_single, ctx->d_tsils, ctx->d_sany, ctx->d_rho};
     for (void* p : ptrs)
         if (p)
             hipFree(p);
@@ -380,6 +380,7 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
     A(d_point_off_single, 2)
     A(d_counts_single, 4)
     A(d_tsils, tiled_sil_words(lim->max_cams, lim->max_w, lim->max_h))
+    A(d_sany, sil_any_words(lim->max_cams, lim->max_w, lim->max_h))
     A(d_rho, c->job_cap * FVV_MAX_CAMS * kRhoPer)
 #undef A
     if (e == hipSuccess)
@@ -404,6 +405,10 @@ fvv_status fvv_create(fvv_ctx** out, const fvv_limits* lim) {
         e = hipMemset(c->d_rowbits, 0, (size_t)n_rowbits * sizeof(uint64_t));
     if (e == hipSuccess)
         e = hipMemset(c->d_rowmask, 0, (size_t)n_rowmask * sizeof(uint64_t));
+    if (e == hipSuccess)
+        e = hipMemset(c->d_sany, 0,
+                      (size_t)sil_any_words(lim->max_cams, lim->max_w, lim->max_h) *
+                          sizeof(uint64_t));
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -714,17 +719,27 @@ fvv_status fvv_frame(fvv_ctx* ctx, const fvv_frame_params* p, const uint8_t* d_m
     auto kev = [&](int i) -> hipEvent_t { return events ? events[FVV_FRAME_STAGE_EVENTS + i] : nullptr; };
     hipError_t e = hipSuccess;
     mark(0);
-    // the packed rows, and the 8 x 8-pixel blocks the fine carve and the exit
-    // points read
+    // a large coarse lattice is carved in two passes, the first rejecting
+    // whole boxes by the silhouettes' non-empty blocks (the list of the kept
+    // ones in the labelling's sample-label scratch, unused until the
+    // labelling, which clears their count)
+    const bool two_pass = ct.tz != 4 && (uint64_t)grid_samples(p->coarse) >= kRejectMinSamples;
+    const CarveReject rej{SilAny{ctx->d_sany, sil_any_bw(cs.W), (cs.H + 7) / 8},
+                          reinterpret_cast<uint32_t*>(ctx->d_sample_label),
+                          ctx->d_counter + kCounterBoxes, ctx->n_cus};
+    // the packed rows, the 8 x 8-pixel blocks the fine carve and the exit
+    // points read, and (two passes) which of the blocks are non-empty
+    uint64_t* const sany = two_pass ? ctx->d_sany : nullptr;
     if (d_masks)
-        e = launch_pack_tiled(p->n_cams, cs.W, cs.H, d_masks, d_sils, ctx->d_tsils, stream);
+        e = launch_pack_tiled(p->n_cams, cs.W, cs.H, d_masks, d_sils, ctx->d_tsils, sany, stream);
     else
-        e = launch_tile_sils(p->n_cams, cs.W, cs.H, d_sils, ctx->d_tsils, stream);
+        e = launch_tile_sils(p->n_cams, cs.W, cs.H, d_sils, ctx->d_tsils, sany, stream);
     mark(1);
     // the coarse carve also fills the labelling's row bitmap
     const RowBits rb = row_bits(ctx, p->coarse);
     if (e == hipSuccess)
-        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, &rb, stream);
+        e = launch_carve(cs, d_sils, p->coarse, ct, o->d_occ_coarse, &rb, stream,
+                         two_pass ? &rej : nullptr);
     mark(2);
     // labelling; its selection kernel also lays out the fine jobs of the ROIs
     FrameJobs fj;

@@ -113,11 +113,18 @@ hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils
 // bit 8 (y & 7) + (x & 7) of block (x / 8, y / 8); blocks row-major per camera,
 // block (bx, by) of camera c at c * tpc + by * tpr + bx with tpr = ceil(W / 8)
 // and tpc = tpr * ceil(H / 8).  Pixels past the image are 0.  A pixel rectangle
-// of up to 9 x 9 pixels lies in at most 2 x 2 blocks.  One thread per block,
-// from the packed rows (whose padding bits are 0).
+// of up to 9 x 9 pixels lies in at most 2 x 2 blocks.
+//
+// Both kernels below run one thread per block; with kAny they also OR each
+// non-empty block's bit into its SilAny word (all-zero before).
+
+// From the packed rows (whose padding bits are 0).
+template <bool kAny>
 __global__ __launch_bounds__(kBlock) void tile_sils_kernel(const uint32_t* __restrict__ sils,
                                                            int n, int H, int wpr, int tpr,
-                                                           int tph, uint64_t* __restrict__ tiles) {
+                                                           int tph, int bw,
+                                                           uint64_t* __restrict__ tiles,
+                                                           uint64_t* __restrict__ any) {
     const int64_t total = (int64_t)n * tph * tpr;
     for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * kBlock) {
@@ -134,23 +141,26 @@ __global__ __launch_bounds__(kBlock) void tile_sils_kernel(const uint32_t* __res
                 v |= (uint64_t)((col[(int64_t)y * wpr] >> sh) & 0xffu) << (8 * r);
         }
         tiles[idx] = v;
+        if (kAny && v != 0)
+            atomicOr((unsigned long long*)&any[cb * bw + (bx >> 6)], 1ull << (bx & 63));
     }
 }
 
 
 // Both forms at once, straight from the masks, for images whose width is a
-// multiple of 8: one thread per 8 x 8-pixel block reads its 8 rows of 8 bytes
-// (a wave covers 512 contiguous bytes of each row), stores the block's word
-// and the block's byte of each of its 8 packed rows (the row's last block also
-// clears the padding bytes of the row's last word).  k32: every block index
-// fits 32 bits (split by multiply and shifts).
-template <bool k32>
+// multiple of 8: each block's thread reads its 8 rows of 8 bytes (a wave
+// covers 512 contiguous bytes of each row), stores the block's word and the
+// block's byte of each of its 8 packed rows (the row's last block also clears
+// the padding bytes of the row's last word).  k32: every block index fits 32
+// bits (split by multiply and shifts).
+template <bool k32, bool kAny>
 __global__ __launch_bounds__(kBlock) void pack_tiled_kernel(const uint8_t* __restrict__ masks,
                                                             int n, int W, int H, int wpr,
-                                                            int tpr, int tph, DivU32 by_tpr,
-                                                            DivU32 by_tph,
+                                                            int tpr, int tph, int bw,
+                                                            DivU32 by_tpr, DivU32 by_tph,
                                                             uint32_t* __restrict__ sils,
-                                                            uint64_t* __restrict__ tiles) {
+                                                            uint64_t* __restrict__ tiles,
+                                                            uint64_t* __restrict__ any) {
     const int64_t total = (int64_t)n * tph * tpr;
     uint8_t* const rows = reinterpret_cast<uint8_t*>(sils);
     const int row_bytes = 4 * wpr;
@@ -184,38 +194,108 @@ __global__ __launch_bounds__(kBlock) void pack_tiled_kernel(const uint8_t* __res
             }
         }
         tiles[idx] = v;
+        if (kAny && v != 0)
+            atomicOr((unsigned long long*)&any[cb * bw + (bx >> 6)], 1ull << (bx & 63));
+    }
+}
+
+// The same for images whose width is a multiple of 16 (masks 16-byte
+// aligned): one thread per two horizontally adjacent blocks, 16-byte loads of
+// its 8 rows, the two blocks' words in one 16-byte store and two bytes of
+// each packed row in one 2-byte store.
+template <bool k32, bool kAny>
+__global__ __launch_bounds__(kBlock) void pack_tiled16_kernel(const uint8_t* __restrict__ masks,
+                                                              int n, int W, int H, int wpr,
+                                                              int tpr, int tph, int bw,
+                                                              DivU32 by_tp2, DivU32 by_tph,
+                                                              uint32_t* __restrict__ sils,
+                                                              uint64_t* __restrict__ tiles,
+                                                              uint64_t* __restrict__ any) {
+    const int tp2 = tpr / 2;
+    const int64_t total = (int64_t)n * tph * tp2;
+    uint8_t* const rows = reinterpret_cast<uint8_t*>(sils);
+    const int row_bytes = 4 * wpr;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t cb, c;
+        if (k32) {
+            cb = divu32((uint32_t)idx, by_tp2);
+            c = divu32((uint32_t)cb, by_tph);
+        } else {
+            cb = idx / tp2;
+            c = cb / tph;
+        }
+        const int bx = 2 * (int)(idx - cb * tp2);
+        const int by = (int)(cb - c * tph);
+        const int y0 = 8 * by;
+        const int nr = min(8, H - y0);
+        const uint8_t* src = masks + ((int64_t)c * H + y0) * W + 8 * bx;
+        uint8_t* dst = rows + ((int64_t)c * H + y0) * row_bytes + bx;
+        uint64_t v0 = 0, v1 = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (r < nr) {
+                const uint4 q = *reinterpret_cast<const uint4*>(src + (int64_t)r * W);
+                const uint32_t b0 = nonzero_bytes(q.x) | (nonzero_bytes(q.y) << 4);
+                const uint32_t b1 = nonzero_bytes(q.z) | (nonzero_bytes(q.w) << 4);
+                v0 |= (uint64_t)b0 << (8 * r);
+                v1 |= (uint64_t)b1 << (8 * r);
+                *reinterpret_cast<uint16_t*>(dst + (int64_t)r * row_bytes) =
+                    (uint16_t)(b0 | (b1 << 8));
+                if (bx == tpr - 2)
+                    for (int k = tpr; k < row_bytes; ++k)
+                        dst[(int64_t)r * row_bytes + (k - bx)] = 0;
+            }
+        }
+        *reinterpret_cast<ulonglong2*>(tiles + cb * tpr + bx) = make_ulonglong2(v0, v1);
+        if (kAny && (v0 | v1) != 0)
+            atomicOr((unsigned long long*)&any[cb * bw + (bx >> 6)],
+                     (unsigned long long)((v0 ? 1ull : 0ull) | (v1 ? 2ull : 0ull)) << (bx & 63));
     }
 }
 
 hipError_t launch_pack_tiled(int n, int W, int H, const uint8_t* masks, uint32_t* sils,
-                             uint64_t* tiles, hipStream_t s) {
+                             uint64_t* tiles, uint64_t* any, hipStream_t s) {
     if (W % 8 != 0 || reinterpret_cast<uintptr_t>(masks) % 8 != 0) {
         hipError_t e = launch_pack(n, W, H, masks, sils, s);
-        return e == hipSuccess ? launch_tile_sils(n, W, H, sils, tiles, s) : e;
+        return e == hipSuccess ? launch_tile_sils(n, W, H, sils, tiles, any, s) : e;
     }
-    const int wpr = (W + 31) / 32, tpr = W / 8, tph = (H + 7) / 8;
+    const int wpr = (W + 31) / 32, tpr = W / 8, tph = (H + 7) / 8, bw = sil_any_bw(W);
+    if (W % 16 == 0 && reinterpret_cast<uintptr_t>(masks) % 16 == 0) {
+        const int64_t total = (int64_t)n * tph * (tpr / 2);
+        int64_t blocks = (total + kBlock - 1) / kBlock;
+        blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
+        const DivU32 dx = divu32_magic((uint32_t)(tpr / 2)), dy = divu32_magic((uint32_t)tph);
+        const bool k32 = total + (int64_t)blocks * kBlock <= ((int64_t)1 << 32);
+        auto kernel = k32 ? (any ? pack_tiled16_kernel<true, true> : pack_tiled16_kernel<true, false>)
+                          : (any ? pack_tiled16_kernel<false, true>
+                                 : pack_tiled16_kernel<false, false>);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, masks, n, W, H,
+                           wpr, tpr, tph, bw, dx, dy, sils, tiles, any);
+        return hipGetLastError();
+    }
     const int64_t total = (int64_t)n * tph * tpr;
     int64_t blocks = (total + kBlock - 1) / kBlock;
     blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
     const DivU32 dx = divu32_magic((uint32_t)tpr), dy = divu32_magic((uint32_t)tph);
-    if (total + (int64_t)blocks * kBlock <= ((int64_t)1 << 32))
-        hipLaunchKernelGGL(pack_tiled_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           masks, n, W, H, wpr, tpr, tph, dx, dy, sils, tiles);
-    else
-        hipLaunchKernelGGL(pack_tiled_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           masks, n, W, H, wpr, tpr, tph, dx, dy, sils, tiles);
+    const bool k32 = total + (int64_t)blocks * kBlock <= ((int64_t)1 << 32);
+    auto kernel = k32 ? (any ? pack_tiled_kernel<true, true> : pack_tiled_kernel<true, false>)
+                      : (any ? pack_tiled_kernel<false, true> : pack_tiled_kernel<false, false>);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, masks, n, W, H, wpr,
+                       tpr, tph, bw, dx, dy, sils, tiles, any);
     return hipGetLastError();
 }
 
 
 hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,
-                            hipStream_t s) {
-    const int wpr = (W + 31) / 32, tpr = (W + 7) / 8, tph = (H + 7) / 8;
+                            uint64_t* any, hipStream_t s) {
+    const int wpr = (W + 31) / 32, tpr = (W + 7) / 8, tph = (H + 7) / 8, bw = sil_any_bw(W);
     const int64_t total = (int64_t)n * tph * tpr;
     int64_t blocks = (total + kBlock - 1) / kBlock;
     blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
-    hipLaunchKernelGGL(tile_sils_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, sils, n, H,
-                       wpr, tpr, tph, tiles);
+    hipLaunchKernelGGL(any ? tile_sils_kernel<true> : tile_sils_kernel<false>,
+                       dim3((unsigned)blocks), dim3(kBlock), 0, s, sils, n, H, wpr, tpr, tph, bw,
+                       tiles, any);
     return hipGetLastError();
 }
 
@@ -362,18 +442,6 @@ __device__ __forceinline__ void carve_tile(GetP getP, GetSil sil_of, int ncam, i
             }
         }
     }
-}
-
-// ------------------------------------------------------------------ one lattice
-template <int TX, int TZ, bool kRows>
-__global__ __launch_bounds__(kBlock) void carve_kernel(const CamSet cams,
-                                                       const uint32_t* __restrict__ sils,
-                                                       const fvv_grid g, uint8_t* __restrict__ occ,
-                                                       const RowBits rb) {
-    const int64_t cam_words = (int64_t)cams.H * cams.wpr;
-    carve_tile<TX, TZ, kRows ? kBitsLabel : kBitsNone>([&](int c) { return &cams.P[c][0]; },
-                              [&](int c) { return sils + c * cam_words; }, cams.n, cams.W, cams.H,
-                              cams.wpr, g, blockIdx.x, occ, rb);
 }
 
 // ------------------------------------------------------------------ batched, persistent
@@ -723,6 +791,246 @@ __device__ __forceinline__ void tile_origin(const fvv_grid& g, uint64_t tile, in
     i0 = bx * TX;
     j0 = by * TY;
     k0 = bz * 4;
+}
+
+// ------------------------------------------------------------------ one lattice
+template <int TX, int TZ, bool kRows>
+__global__ __launch_bounds__(kBlock) void carve_kernel(const CamSet cams,
+                                                       const uint32_t* __restrict__ sils,
+                                                       const fvv_grid g, uint8_t* __restrict__ occ,
+                                                       const RowBits rb) {
+    const int64_t cam_words = (int64_t)cams.H * cams.wpr;
+    carve_tile<TX, TZ, kRows ? kBitsLabel : kBitsNone>([&](int c) { return &cams.P[c][0]; },
+                              [&](int c) { return sils + c * cam_words; }, cams.n, cams.W, cams.H,
+                              cams.wpr, g, blockIdx.x, occ, rb);
+}
+
+// Large lattices, most of whose samples lie far from every silhouette, in two
+// passes over boxes of 8 x 8 x 4 samples (compact boxes project to small
+// rectangles, so more of them are rejected whole than flat tiles of the same
+// size): carve_reject_kernel zeroes the occupancy and marks the boxes that no
+// camera rejects whole; carve_kept_kernel carves the marked boxes.
+constexpr int kRejRows = 16;   // block rows of a rectangle read for a rejection
+
+// Whether the camera cam (P, then the rounding pad) sees no foreground pixel
+// in the padded rectangle of the box lo, hi (then no sample of the box is
+// occupied), by one lane: the bounds of the 8 corners' quotients, then the
+// silhouette's non-empty 8 x 8-pixel blocks under the rectangle (sb: this
+// camera's block rows), eight rows at a time until one is non-empty.  A
+// rectangle of more than kRejRows block rows or two words of blocks rejects
+// nothing.
+__device__ __forceinline__ bool cam_rejects_box(const float* cam, int W, int H,
+                                                const uint64_t* __restrict__ sb, int bw,
+                                                const float* lo, const float* hi) {
+    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // the (y, z) partial sums, shared by the two corners on x
+        const float Y = (k & 1) ? hi[1] : lo[1], Z = (k & 2) ? hi[2] : lo[2];
+        const float ayz = __builtin_fmaf(cam[2], Z, __builtin_fmaf(cam[1], Y, cam[3]));
+        const float byz = __builtin_fmaf(cam[6], Z, __builtin_fmaf(cam[5], Y, cam[7]));
+        const float wyz = __builtin_fmaf(cam[10], Z, __builtin_fmaf(cam[9], Y, cam[11]));
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float X = e ? hi[0] : lo[0];
+            const float a = __builtin_fmaf(cam[0], X, ayz);
+            const float b = __builtin_fmaf(cam[4], X, byz);
+            const float w = __builtin_fmaf(cam[8], X, wyz);
+            const float r = __builtin_amdgcn_rcpf(w);
+            x0 = fminf(x0, a * r);
+            x1 = fmaxf(x1, a * r);
+            y0 = fminf(y0, b * r);
+            y1 = fmaxf(y1, b * r);
+        }
+    }
+    int cx0, cx1, cy0, cy1;
+    bool inside;
+    const int st = rect_of_bounds(x0, x1, y0, y1, cam[12], W, H, cx0, cx1, cy0, cy1, inside);
+    if (st >= 0)
+        return st == kCullReject;
+    const int by0 = cy0 >> 3, nby = (cy1 >> 3) - by0 + 1;
+    const int bx0 = cx0 >> 3, bx1 = cx1 >> 3, w0 = bx0 >> 6;
+    if (nby > kRejRows || (bx1 >> 6) - w0 > 1)
+        return false;
+    const bool two = (bx1 >> 6) != w0;
+    const uint64_t m0 = (~0ull << (bx0 & 63)) & (two ? ~0ull : ~0ull >> (63 - (bx1 & 63)));
+    const uint64_t m1 = two ? ~0ull >> (63 - (bx1 & 63)) : 0ull;
+    // each batch's loads in bounds and issued at once: rows past the
+    // rectangle repeat its last row, the second word repeats the first where
+    // there is none
+    const uint64_t* row = sb + (int64_t)by0 * bw + w0;
+    const int w1 = two ? 1 : 0;
+    uint64_t acc = 0ull;
+    for (int r0 = 0; r0 < nby && acc == 0ull; r0 += 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t* rr = row + (int64_t)min(r0 + r, nby - 1) * bw;
+            acc |= (rr[0] & m0) | (rr[w1] & m1);
+        }
+    }
+    return acc == 0ull;
+}
+
+// The boxes of the two-pass carve: nbx x nby x nbz boxes of 8 x 8 x 4 samples,
+// x fastest; with the divisions by nbx and nby.
+struct RejBoxes {
+    uint32_t n, nbx, nby;
+    DivU32 by_nbx, by_nby;
+};
+
+
+__device__ __forceinline__ void rej_box_origin(const RejBoxes& bx, uint32_t b, int& i0, int& j0,
+                                               int& k0) {
+    const uint32_t q = divu32(b, bx.by_nbx), bz = divu32(q, bx.by_nby);
+    i0 = 8 * (int)(b - q * bx.nbx);
+    j0 = 8 * (int)(q - bz * bx.nby);
+    k0 = 4 * (int)bz;
+}
+
+// Zeros over the whole occupancy (16-byte stores between the first and the
+// last 16-byte boundary), then one thread per (box, camera): a workgroup
+// takes per_wg = min(256 / cameras, 64) boxes (cam_of: division by the camera
+// count), each camera that rejects a box marks it in LDS, and the
+// boxes no camera rejects are appended to list (one atomic on *count per
+// workgroup that keeps any; *count is 0 before, order unspecified).
+__global__ __launch_bounds__(kBlock) void carve_reject_kernel(const CamSet cams,
+                                                              const SilAny sa, const fvv_grid g,
+                                                              uint8_t* __restrict__ occ,
+                                                              const RejBoxes boxes, int per_wg,
+                                                              DivU32 cam_of,
+                                                              uint32_t* __restrict__ list,
+                                                              uint32_t* __restrict__ count) {
+    __shared__ float s_cam[FVV_MAX_CAMS][13];
+    __shared__ uint32_t s_rej[kBlock];
+    for (int i = threadIdx.x; i < cams.n * 13; i += kBlock) {
+        const int c = i / 13, e = i - 13 * c;
+        s_cam[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
+    }
+    s_rej[threadIdx.x] = 0u;
+    const uint64_t V = (uint64_t)g.dims[0] * (uint64_t)g.dims[1] * (uint64_t)g.dims[2];
+    const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t nth = (uint64_t)gridDim.x * kBlock;
+    const uint64_t mis = (16u - (uint32_t)(reinterpret_cast<uintptr_t>(occ) & 15u)) & 15u;
+    const uint64_t head = mis < V ? mis : V;
+    const uint64_t n16 = (V - head) >> 4, tail0 = head + (n16 << 4);
+    uint4* const body = reinterpret_cast<uint4*>(occ + head);
+    for (uint64_t i = tid; i < n16; i += nth)
+        body[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid < head)
+        occ[tid] = 0;
+    if (tid < V - tail0)
+        occ[tail0 + tid] = 0;
+    __syncthreads();
+
+    const uint32_t bl = divu32(threadIdx.x, cam_of);
+    const int c = (int)(threadIdx.x - bl * (uint32_t)cams.n);
+    const uint32_t b = blockIdx.x * (uint32_t)per_wg + bl;
+    if (bl < (uint32_t)per_wg && b < boxes.n) {
+        int i0, j0, k0;
+        rej_box_origin(boxes, b, i0, j0, k0);
+        float lo[3], hi[3];
+        box_corners(g, i0, min(i0 + 8, g.dims[0]) - 1, j0, min(j0 + 8, g.dims[1]) - 1, k0,
+                    min(k0 + 4, g.dims[2]) - 1, lo, hi);
+        if (cam_rejects_box(s_cam[c], cams.W, cams.H, sa.bits + (int64_t)c * sa.tph * sa.bw,
+                            sa.bw, lo, hi))
+            s_rej[bl] = 1u;
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {   // per_wg <= 64: the first wave holds every box's flag
+        const uint32_t bb = blockIdx.x * (uint32_t)per_wg + threadIdx.x;
+        const bool kept = threadIdx.x < (unsigned)per_wg && bb < boxes.n && !s_rej[threadIdx.x];
+        const uint64_t km = __ballot(kept);
+        if (km) {
+            uint32_t at = 0u;
+            if (threadIdx.x == 0)
+                at = atomicAdd(count, (uint32_t)__popcll(km));
+            at = (uint32_t)__builtin_amdgcn_readfirstlane((int)at);
+            if (kept)
+                list[at + lane_rank(km)] = bb;
+        }
+    }
+}
+
+// One z layer (8 x 8 samples) of a kept box by one wave: lane (x, y) = (l % 8,
+// l / 8) holds one sample, tested against 16 cameras at a time in one call
+// (cam: matrices and pads in LDS; a camera past the last repeats the last)
+// until it is out or the cameras are; then its occupancy byte and, with
+// kRows, the labelling's row bits (a box row's 8 bits ORed into its word).
+template <bool kRows>
+__device__ __forceinline__ void carve_box_layer(const float (*cam)[13],
+                                                const uint32_t* __restrict__ sils,
+                                                int64_t cam_words, int ncam, int W, int H,
+                                                int wpr, const fvv_grid& g, int i0, int j0, int k,
+                                                uint8_t* __restrict__ out, const RowBits& rb) {
+    const int lane = lane_id();
+    const int i = i0 + (lane & 7), j = j0 + (lane >> 3);
+    bool alive = i < g.dims[0] && j < g.dims[1] && k < g.dims[2];
+    const bool valid = alive;
+    const float X = lattice_coord(g.lo[0] + i, g.h, g.origin[0]);
+    const float Y = lattice_coord(g.lo[1] + j, g.h, g.origin[1]);
+    const float Z = lattice_coord(g.lo[2] + k, g.h, g.origin[2]);
+    for (int c0 = 0; c0 < ncam && __ballot(alive) != 0ull; c0 += 16) {
+        const float* P[16];
+        const uint32_t* S[16];
+        float Xs[16], Ys[16], Zs[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = min(c0 + q, ncam - 1);
+            P[q] = cam[c];
+            S[q] = sils + c * cam_words;
+            Xs[q] = X;
+            Ys[q] = Y;
+            Zs[q] = Z;
+        }
+        alive = alive && multi_inside<16>(P, Xs, Ys, Zs, S, W, H, wpr) == 0xffffu;
+    }
+    if (valid)
+        out[(uint64_t)k * g.dims[0] * (uint64_t)g.dims[1] + (uint64_t)j * g.dims[0] + i] =
+            alive ? 1 : 0;
+    if (kRows) {
+        const uint64_t bits = (__ballot(alive) >> (8 * (lane >> 3))) & 0xffull;
+        if ((lane & 7) == 0 && bits != 0) {
+            const int64_t row = (int64_t)j + (int64_t)g.dims[1] * k;
+            atomicOr((unsigned long long*)(rb.words + row * rb.wr + (i0 >> 6)),
+                     (unsigned long long)(bits << (i0 & 63)));
+            atomicOr((unsigned long long*)&rb.rowmask[row >> 6], 1ull << (row & 63));
+        }
+    }
+}
+
+// The kept boxes (list, *count of them): workgroup w of G carves entries w, w +
+// G, ... with its four waves, one z layer each; any_bits (any_words words)
+// zeroed.
+template <bool kRows>
+__global__ __launch_bounds__(kBlock) void carve_kept_kernel(const CamSet cams,
+                                                            const uint32_t* __restrict__ sils,
+                                                            const fvv_grid g,
+                                                            uint8_t* __restrict__ occ,
+                                                            const RowBits rb,
+                                                            const uint32_t* __restrict__ list,
+                                                            const uint32_t* __restrict__ count,
+                                                            const RejBoxes boxes,
+                                                            uint64_t* __restrict__ any_bits,
+                                                            int64_t any_words) {
+    __shared__ float s_cam[FVV_MAX_CAMS][13];
+    for (int i = threadIdx.x; i < cams.n * 13; i += kBlock) {
+        const int c = i / 13, e = i - 13 * c;
+        s_cam[c][e] = e < 12 ? cams.P[c][e] : cams.pad[c];
+    }
+    // the non-empty blocks, read by the first pass, cleared for the next frame
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < any_words;
+         i += (int64_t)gridDim.x * kBlock)
+        any_bits[i] = 0ull;
+    __syncthreads();
+    const int64_t cam_words = (int64_t)cams.H * cams.wpr;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t n = min(*count, boxes.n);
+    for (uint32_t q = blockIdx.x; q < n; q += gridDim.x) {
+        int i0, j0, k0;
+        rej_box_origin(boxes, list[q], i0, j0, k0);
+        carve_box_layer<kRows>(s_cam, sils, cam_words, cams.n, cams.W, cams.H, cams.wpr, g, i0,
+                               j0, k0 + wave, occ, rb);
+    }
 }
 
 // Camera classification of a whole culled tile (TX x TY x 4 samples from
@@ -1558,7 +1866,8 @@ hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
     X(16, 2) X(16, 4) X(16, 8)
 
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g, TileShape t,
-                        uint8_t* occ, const RowBits* rows, hipStream_t s) {
+                        uint8_t* occ, const RowBits* rows, hipStream_t s,
+                        const CarveReject* rej) {
     const uint64_t tiles = tiles_of_grid(g, t.tx, t.tz);
     if (tiles == 0)
         return hipSuccess;
@@ -1577,6 +1886,36 @@ hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid
         X(16)
 #undef X
         return hipErrorInvalidValue;
+    }
+    const uint64_t V = (uint64_t)g.dims[0] * (uint64_t)g.dims[1] * (uint64_t)g.dims[2];
+    if (rej && V >= kRejectMinSamples) {
+        RejBoxes boxes;
+        boxes.nbx = (uint32_t)((g.dims[0] + 7) / 8);
+        boxes.nby = (uint32_t)((g.dims[1] + 7) / 8);
+        const uint64_t nb = (uint64_t)boxes.nbx * boxes.nby * (uint64_t)((g.dims[2] + 3) / 4);
+        if (nb > 0x7fffffffull)
+            return hipErrorInvalidValue;
+        boxes.n = (uint32_t)nb;
+        boxes.by_nbx = divu32_magic(boxes.nbx);
+        boxes.by_nby = divu32_magic(boxes.nby);
+        const int per_wg = kBlock / cams.n < kWave ? kBlock / cams.n : kWave;
+        const unsigned rblocks = (unsigned)((nb + per_wg - 1) / per_wg);
+        hipLaunchKernelGGL(carve_reject_kernel, dim3(rblocks), dim3(kBlock), 0, s, cams, rej->any,
+                           g, occ, boxes, per_wg, divu32_magic((uint32_t)cams.n), rej->list,
+                           rej->count);
+        // four workgroups per CU: every wave of the second pass resident at once
+        const unsigned kblocks = (unsigned)rej->n_cus * 4;
+        uint64_t* const any_bits = const_cast<uint64_t*>(rej->any.bits);
+        const int64_t any_words = (int64_t)cams.n * rej->any.tph * rej->any.bw;
+        if (rows)
+            hipLaunchKernelGGL(carve_kept_kernel<true>, dim3(kblocks), dim3(kBlock), 0, s, cams,
+                               sils, g, occ, rb, rej->list, rej->count, boxes, any_bits,
+                               any_words);
+        else
+            hipLaunchKernelGGL(carve_kept_kernel<false>, dim3(kblocks), dim3(kBlock), 0, s, cams,
+                               sils, g, occ, rb, rej->list, rej->count, boxes, any_bits,
+                               any_words);
+        return hipGetLastError();
     }
 #define X(TXV, TZV)                                                                           \
     if (t.tx == TXV && t.tz == TZV) {                                                         \

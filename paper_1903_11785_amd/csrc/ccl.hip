@@ -29,7 +29,7 @@
 
 namespace fvv {
 
-constexpr int kLabelThreads = 512;
+constexpr int kLabelThreads = 1024;
 constexpr int kRowCap = 4096;    // listed rows held in LDS
 constexpr int kRunCap = 6144;    // runs held in LDS
 constexpr int kRootCap = 1024;   // components whose stats are held in LDS
@@ -97,10 +97,11 @@ __device__ __forceinline__ void unite(int32_t* P, int32_t a, int32_t b) {
 // Measurement builds (FVV_LABEL_PHASES defined) record, from thread 0 of the
 // labelling workgroup, the real-time clock (100 MHz) at the end of each phase
 // of the last labelling into label_phase_stamps: [0] entry, [1] row mask
-// counted, [2] rows listed, [3] runs cut, [4] runs united, [5] forest
-// flattened and roots numbered, [6] stats, filter and ROI table, [7] labels
-// written and the bitmap cleared, [8] the fine jobs laid out, [9] their radii.
-constexpr int kLabelPhases = 10;
+// counted, [2] rows listed, [3] runs cut, [4] adjacent run pairs listed, [5]
+// runs united, [6] forest flattened and roots numbered, [7] stats, filter and
+// ROI table, [8] labels written and the bitmap cleared, [9] the fine jobs laid
+// out, [10] their radii.
+constexpr int kLabelPhases = 11;
 #ifdef FVV_LABEL_PHASES
 __device__ uint64_t label_phase_stamps[kLabelPhases];
 __device__ __forceinline__ void label_stamp(int i) {
@@ -247,6 +248,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         counter[0] = 0;
         counter[1] = grab_size(tiles, fj.blocks);
         counter[2] = n;
+        counter[kCounterBoxes] = 0;   // for the next frame's two-pass coarse carve
         if (n < K_all)
             atomicOr(status, kFlagCapacity);
     };
@@ -288,7 +290,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
                 finish(n, vox, all_t, all_i);
         }
         __syncthreads();
-        label_stamp(8);
+        label_stamp(9);
         fine_job_radii<NT>(fj, counter);
         return;
     }
@@ -345,7 +347,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
     if (threadIdx.x == 0)
         finish(carried, e_vox, e_tiles, e_items);
     __syncthreads();
-    label_stamp(8);
+    label_stamp(9);
     fine_job_radii<NT>(fj, counter);
 }
 
@@ -363,7 +365,7 @@ struct RunArrays {
     int32_t* x0;       // run extents (global twin) ...
     int32_t* x1;
     uint32_t* xx;      // ... or packed x0 | x1 << 16 (LDS)
-    int32_t* rrow;     // listed row of each run
+    int32_t* rrow;     // row (y + ny z) of each run
     int32_t* P;        // union-find parent; after ranking, -1 - rank at roots
 };
 
@@ -456,7 +458,7 @@ __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunAr
     }
     __syncthreads();
     for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
-        const int32_t r = m.rows[m.rrow[k]];
+        const int32_t r = m.rrow[k];
         const int32_t y = r % a.ny, z = r / a.ny;
         const int2 x = get_run<kLds>(m, k);
         int32_t* s = stats + (int64_t)kStatsRow * rank_of<kLds>(m.P, k);
@@ -507,9 +509,11 @@ __device__ __forceinline__ void stats_and_select(const LabelArgs& a, const RunAr
 template <bool kLds, typename F>
 __device__ __forceinline__ void for_each_earlier_adjacent(const LabelArgs& a, const RunArrays& m,
                                                           int32_t k, F f) {
-    const int32_t r = m.rows[m.rrow[k]];
+    const int32_t r = m.rrow[k];
     const int32_t y = r % a.ny, z = r / a.ny;
     const int2 xk = get_run<kLds>(m, k);
+    // the four rows' list indices, their run ranges and their first runs, each
+    // step's loads issued together
     int32_t jn[4];
     jn[0] = y > 0 ? row_index(m, r - 1) : -1;
 #pragma unroll
@@ -517,17 +521,23 @@ __device__ __forceinline__ void for_each_earlier_adjacent(const LabelArgs& a, co
         const int32_t yy = y - 1 + d;
         jn[1 + d] = (z > 0 && yy >= 0 && yy < a.ny) ? row_index(m, r - a.ny - 1 + d) : -1;
     }
+    int32_t b[4], be[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (jn[q] < 0)
-            continue;
-        const int32_t be = m.rs[jn[q] + 1];
-        for (int32_t b = m.rs[jn[q]]; b < be; ++b) {
-            const int2 xb = get_run<kLds>(m, b);
-            if (xb.x > xk.y + 1)
-                break;
-            if (xb.y + 1 >= xk.x)
-                f(b);
+        b[q] = jn[q] >= 0 ? m.rs[jn[q]] : 0;
+        be[q] = jn[q] >= 0 ? m.rs[jn[q] + 1] : 0;
+    }
+    int2 xb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        xb[q] = b[q] < be[q] ? get_run<kLds>(m, b[q]) : make_int2(0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        while (b[q] < be[q] && xb[q].x <= xk.y + 1) {
+            if (xb[q].y + 1 >= xk.x)
+                f(b[q]);
+            if (++b[q] < be[q])
+                xb[q] = get_run<kLds>(m, b[q]);
         }
     }
 }
@@ -573,7 +583,8 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     for (int32_t base = 0; base < n_rows; base += NT) {
         const int32_t i = base + threadIdx.x;
         const bool act = i < n_rows;
-        const uint64_t* rw = a.rb.words + (act ? (int64_t)m.rows[i] * wr : 0);
+        const int32_t r_i = act ? m.rows[i] : 0;
+        const uint64_t* rw = a.rb.words + (int64_t)r_i * wr;
         uint64_t cw[kRowWords + 1];
 #pragma unroll
         for (int q = 0; q <= kRowWords; ++q)
@@ -608,7 +619,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
                         x_start = x;
                     if ((en >> bit) & 1u) {
                         put_run<kLds>(m, k, x_start, x);
-                        m.rrow[k] = i;
+                        m.rrow[k] = r_i;
                         m.P[k] = k;
                         ++k;
                     }
@@ -658,17 +669,19 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
                     unite<kLds>(m.P, k, b);
             });
         __syncthreads();
+        label_stamp(4);
         const uint32_t np = min(*n_pairs, (uint32_t)kPairCap);
         for (uint32_t q = threadIdx.x; q < np; q += NT) {
             const uint32_t v = pairs[q];
             unite<kLds>(m.P, (int32_t)(v >> 16), (int32_t)(v & 0xffffu));
         }
     } else {
+        label_stamp(4);
         for (int32_t k = threadIdx.x; k < n_runs; k += NT)
             for_each_earlier_adjacent<kLds>(a, m, k, [&](int32_t b) { unite<kLds>(m.P, k, b); });
     }
     __syncthreads();
-    label_stamp(4);
+    label_stamp(5);
     // 4. flatten, then number the roots in ascending run id.  The walk only
     //    reads: the sole writes now set a node to its root, which keeps every
     //    concurrent walk on course (path halving here could store a
@@ -691,7 +704,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         K_all += (int32_t)total;
     }
     __syncthreads();
-    label_stamp(5);
+    label_stamp(6);
     // 5. stats, filter, ROI table (stats rows in LDS while the components fit;
     //    the label of each rank follows the rows)
     uint32_t K = 0;
@@ -703,10 +716,10 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         stats_and_select<kLds, false>(a, m, n_runs, K_all, a.gstats,
                                       a.gstats + (int64_t)kStatsRow * K_all, a.g.rs, scan, &K);
     __syncthreads();
-    label_stamp(6);
+    label_stamp(7);
     // 6. labels of the occupied samples; the bitmap cleared for the next call
     for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
-        const int64_t row_lin = (int64_t)a.nx * m.rows[m.rrow[k]];
+        const int64_t row_lin = (int64_t)a.nx * m.rrow[k];
         const int32_t rk = rank_of<kLds>(m.P, k);
         const int32_t l = lds_stats_ok ? ld<true>(lds_stats + (int64_t)kStatsRow * kRootCap + rk)
                                        : ld<false>(a.gstats + (int64_t)kStatsRow * K_all + rk);
@@ -728,7 +741,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
     }
     if (kJobs) {
         __syncthreads();
-        label_stamp(7);
+        label_stamp(8);
         auto box = [&](uint32_t t, int32_t* lo, int32_t* hi) {
             if (lds_stats_ok) {
                 const int32_t* s = lds_stats + (int64_t)kStatsRow * m.rs[t];
@@ -747,7 +760,7 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
             }
         };
         build_fine_jobs<NT>(fj, box, K, a.max_rois, a.pre, a.counter, a.dcams, a.status);
-        label_stamp_sync(9);
+        label_stamp_sync(10);
     }
     return true;
 }

@@ -17,9 +17,11 @@ constexpr int kEdgeWords = 256;          // fine-bitmap words per crossing-edge 
 constexpr uint32_t kFlagCapacity = 1u;   // sticky device status bits: an output capacity
 constexpr uint32_t kFlagJob = 2u;        // was exceeded; a batched job was out of range
 // Work counters of a context: [0] next work item, [1] tiles per item, [2] jobs
-// (persistent carve); [kCounterMesh] workgroups of the triangle count done.
+// (persistent carve); [kCounterMesh] workgroups of the triangle count done;
+// [kCounterBoxes] boxes kept by a frame's two-pass coarse carve.
 constexpr int kCounters = 8;
 constexpr int kCounterMesh = 4;
+constexpr int kCounterBoxes = 5;
 
 // Projections of a camera rig passed by value in the kernel arguments.
 // pad[c] bounds, for every point of the lattice box the call works in, how far
@@ -423,6 +425,33 @@ struct RowBits {
     int32_t wr;          // words per row, ceil(nx / 64)
 };
 
+// Which 8 x 8-pixel blocks of each camera's silhouette hold a foreground
+// pixel: bit bx % 64 of word (c * tph + by) * bw + bx / 64 for block (bx, by),
+// tph = ceil(H / 8) block rows of bw = ceil(ceil(W / 8) / 64) words.  The
+// packing kernels OR the bits into all-zero words; the two-pass carve's second
+// pass zeroes them again.
+struct SilAny {
+    const uint64_t* bits;
+    int32_t bw, tph;
+};
+inline int32_t sil_any_bw(int W) { return ((W + 7) / 8 + 63) / 64; }
+inline int64_t sil_any_words(int n, int W, int H) {
+    return (int64_t)n * ((H + 7) / 8) * sil_any_bw(W);
+}
+
+// The two-pass carve of a lattice of at least kRejectMinSamples samples: the
+// silhouettes' non-empty blocks (zeroed by the second pass), a list of up to
+// one entry per box of 8 x 8 x 4 samples and its count (0 before the carve;
+// the frame's labelling clears it again), and the CU count for the second
+// pass.
+struct CarveReject {
+    SilAny any;
+    uint32_t* list;
+    uint32_t* count;
+    int n_cus;
+};
+constexpr uint64_t kRejectMinSamples = (uint64_t)1 << 21;
+
 constexpr int kStatsRow = 8;   // per component: count, lo[3], hi[3], smallest linear index
 
 // ------------------------------------------------------------------ device-side job prefix data
@@ -564,6 +593,7 @@ struct fvv_ctx {
     fvv_camera* d_cams;          // camera table of fvv_frame
     uint64_t* d_finebits;        // fine bitmaps of the jobs (bit_cap words)
     uint64_t* d_tsils;           // a frame's silhouettes in 8 x 8-pixel blocks
+    uint64_t* d_sany;            // their non-empty blocks (SilAny layout)
     float* d_rho;                // a frame's radii per (job, camera), kRhoPer floats each
     uint32_t* d_item_cnt;        // crossing edges per work item
     fvv::WordEdges* d_word_edges;  // per fine-bitmap word (bit_cap), for the mesh
@@ -624,8 +654,13 @@ __device__ __forceinline__ void label_write_sample(const LabelWrite& lw, int64_t
 
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_pack(int n, int W, int H, const uint8_t* masks, uint32_t* sils, hipStream_t s);
+// rej: for lattices of at least kRejectMinSamples samples carved with plain
+// (depth 1, 2 or 8) tiles, the two-pass carve that first rejects whole boxes
+// from the silhouettes' non-empty blocks (null: one pass; t does not apply to
+// the two passes).
 hipError_t launch_carve(const CamSet& cams, const uint32_t* sils, const fvv_grid& g,
-                        TileShape t, uint8_t* occ, const RowBits* rows, hipStream_t s);
+                        TileShape t, uint8_t* occ, const RowBits* rows, hipStream_t s,
+                        const CarveReject* rej = nullptr);
 // finebits: NULL, or where each job's fine bitmap goes (at its bit_off).
 hipError_t launch_carve_batched(fvv_ctx* ctx, const fvv_job* jobs, uint32_t n_jobs,
                                 const fvv_camera* cams, const uint32_t* sils, uint8_t* out,
@@ -753,13 +788,15 @@ hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
                               hipStream_t s, hipEvent_t k_start = nullptr,
                               hipEvent_t k_stop = nullptr);
 // The silhouettes in 8 x 8-pixel blocks (tile_sils_kernel's layout), from the
-// packed rows.
+// packed rows; any (may be null): the non-empty blocks ORed into SilAny's
+// layout (all-zero before).
 hipError_t launch_tile_sils(int n, int W, int H, const uint32_t* sils, uint64_t* tiles,
-                            hipStream_t s);
+                            uint64_t* any, hipStream_t s);
 // Pack the masks into both forms (packed rows and 8 x 8-pixel blocks) in one
-// pass where the width is a multiple of 8, else by the two kernels in turn.
+// pass where the width is a multiple of 8, else by the two kernels in turn;
+// any as for launch_tile_sils.
 hipError_t launch_pack_tiled(int n, int W, int H, const uint8_t* masks, uint32_t* sils,
-                             uint64_t* tiles, hipStream_t s);
+                             uint64_t* tiles, uint64_t* any, hipStream_t s);
 // Words of the tiled silhouettes of n cameras of W x H pixels.
 inline int64_t tiled_sil_words(int n, int W, int H) {
     return (int64_t)n * ((W + 7) / 8) * ((H + 7) / 8);

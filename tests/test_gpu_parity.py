@@ -500,7 +500,7 @@ def compare_frame(fvv, sc, bufs, res):
         assert err <= 1e-4 * float(lat.h)
 
 
-@pytest.mark.parametrize("cfg,frame", [(1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (3, 0)])
+@pytest.mark.parametrize("cfg,frame", [(1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (3, 0), (3, 1)])
 def test_frame_against_oracle(fvv, ctx, scene_cache, cfg, frame):
     sc = scene_cache(cfg, frame)
     res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
@@ -607,9 +607,13 @@ def test_frame_dense_coarse_hull(fvv, ctx, scene_cache):
     compare_frame(fvv, sc, bufs, res)
 
 
-def test_frame_graph_replays(fvv, ctx, scene_cache):
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_frame_graph_replays(fvv, ctx, scene_cache, cfg):
+    """Replays of a captured frame, eager work between them; the judo frame's
+    coarse lattice (18900 tiles) takes the two-pass coarse carve, whose tile
+    count the labelling and whose block bits the second pass clear again."""
     import torch
-    sc = scene_cache(2, 0)
+    sc = scene_cache(cfg, 0)
     res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims)
     g, bufs, sils = run_frame(fvv, ctx, sc, graph=True)
     for rep in range(4):
@@ -666,13 +670,30 @@ def test_invalid_arguments_are_rejected(fvv, ctx, scene_cache):
         ctx.label(good, dev(np.zeros((4, 4, 4), np.uint8)), t_np=9, t_nb=8)
 
 
+def test_frame_two_pass_few_cameras(fvv, ctx, scene_cache):
+    """The judo frame seen by 3 of its 24 cameras: the two-pass coarse carve's
+    rejection pass with one workgroup's box count capped by the wave (64 boxes of
+    3 cameras each), a wider hull and more kept boxes, against the oracle."""
+    import copy
+    sc = copy.copy(scene_cache(3, 0))
+    idx = [0, 8, 16]
+    sc.masks = sc.masks[idx]
+    sc.cams = [sc.cams[i] for i in idx]
+    assert int(np.prod(sc.coarse_dims)) >= 1 << 21
+    res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims, sc.t_np,
+                       sc.t_nb, sc.n_steps)
+    _, bufs, _ = run_frame(fvv, ctx, sc)
+    assert ctx.check() == fvv.FVV_OK
+    compare_frame(fvv, sc, bufs, res)
+
+
 # ------------------------------------------------------------------ paper-shaped frames
 @pytest.mark.parametrize("cfg", [scenes.CFG_PAPER_V, scenes.CFG_JUDO_FINE])
 def test_frame_paper_shapes(fvv, scene_cache, cfg):
     """The paper's volleyball shape (10 cameras 3840x2160, an 18 x 18 x 9 m volume at
-    50 mm: 360 x 360 x 180 coarse samples, more rows than the labelling keeps in
-    LDS; 20 mm fine) and a judo frame at 2 mm (~1.9e8 fine samples in 6 ROIs, fine
-    bitmaps and job tables at that size) against the oracle, element by element."""
+    50 mm: 360 x 360 x 180 coarse samples, carved in two passes; 20 mm fine) and a
+    judo frame at 2 mm (~1.9e8 fine samples in 6 ROIs, fine bitmaps and job tables
+    at that size) against the oracle, element by element."""
     sc = scene_cache(cfg, 0)
     res = oracle_frame(sc, cfg, 0)
     c = fvv.Context(max_cams=sc.P32.shape[0], max_w=sc.W, max_h=sc.H,
