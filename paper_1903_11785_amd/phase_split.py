@@ -28,7 +28,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 MEASURE_LIB = os.path.join(HERE, "libfvv_measure.so")
 DEFINES = ("FVV_LABEL_PHASES", "FVV_CARVE_PROBE")
-LABEL_PHASES = ["row mask", "rows listed", "runs cut", "unions", "flatten + root numbers",
+LABEL_PHASES = ["row mask", "rows listed", "runs cut", "pairs listed", "unions",
+                "flatten + root numbers",
                 "stats + Eq. (1) filter + ROIs", "labels + bitmap clear", "fine jobs laid out",
                 "fine job radii"]
 N_STAMPS = len(LABEL_PHASES) + 1
