@@ -1588,12 +1588,14 @@ __global__ __launch_bounds__(kBlock, 7) void carve_frame_kernel(const fvv_job* _
                                                              uint64_t* __restrict__ finebits,
                                                              int job_lds, LabelWrite lw) {
     // the workgroups past the carve's write the coarse labels and filtered
-    // occupancy (they start as the carve's tail frees the CUs)
+    // occupancy and clear the labelling's row bitmap (they start as the
+    // carve's tail frees the CUs)
     if (blockIdx.x >= lw.carve_blocks) {
         const int64_t stride = (int64_t)(gridDim.x - lw.carve_blocks) * kBlock;
-        for (int64_t v = (int64_t)(blockIdx.x - lw.carve_blocks) * kBlock + threadIdx.x; v < lw.V;
-             v += stride)
+        const int64_t t0 = (int64_t)(blockIdx.x - lw.carve_blocks) * kBlock + threadIdx.x;
+        for (int64_t v = t0; v < lw.V; v += stride)
             label_write_sample(lw, v);
+        label_write_clear(lw, t0, stride);
         return;
     }
 #ifdef FVV_CARVE_PROBE
@@ -1837,11 +1839,7 @@ hipError_t launch_carve_frame(fvv_ctx* ctx, const fvv_job* jobs, int max_jobs,
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;
     // the coarse labels' write pass rides in the same launch, about eight
     // samples per thread in workgroups after the carve's
-    LabelWrite lw;
-    lw.sample_label = ctx->d_sample_label;
-    lw.occ = occ_coarse;
-    lw.labels = labels;
-    lw.V = (int64_t)coarse.dims[0] * coarse.dims[1] * coarse.dims[2];
+    LabelWrite lw = label_write_args(ctx, coarse, occ_coarse, labels);
     lw.carve_blocks = (uint32_t)blocks;
     const int64_t lw_blocks = (lw.V + 8 * kBlock - 1) / (8 * kBlock);
     const int extra = (int)(lw_blocks < 1 ? 1 : (lw_blocks > 4 * ctx->n_cus ? 4 * ctx->n_cus

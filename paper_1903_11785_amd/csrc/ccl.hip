@@ -99,8 +99,8 @@ __device__ __forceinline__ void unite(int32_t* P, int32_t a, int32_t b) {
 // of the last labelling into label_phase_stamps: [0] entry, [1] row mask
 // counted, [2] rows listed, [3] runs cut, [4] adjacent run pairs listed, [5]
 // runs united, [6] forest flattened and roots numbered, [7] stats, filter and
-// ROI table, [8] labels written and the bitmap cleared, [9] the fine jobs laid
-// out, [10] their radii.
+// ROI table, [8] labels written, [9] the fine jobs laid out, [10] their
+// radii.
 constexpr int kLabelPhases = 11;
 #ifdef FVV_LABEL_PHASES
 __device__ uint64_t label_phase_stamps[kLabelPhases];
@@ -717,7 +717,8 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
                                       a.gstats + (int64_t)kStatsRow * K_all, a.g.rs, scan, &K);
     __syncthreads();
     label_stamp(7);
-    // 6. labels of the occupied samples; the bitmap cleared for the next call
+    // 6. labels of the occupied samples (the write pass that follows clears the
+    //    bitmap for the next call)
     for (int32_t k = threadIdx.x; k < n_runs; k += NT) {
         const int64_t row_lin = (int64_t)a.nx * m.rrow[k];
         const int32_t rk = rank_of<kLds>(m.P, k);
@@ -727,13 +728,6 @@ __device__ __forceinline__ bool label_body(const LabelArgs& a, const FrameJobs& 
         for (int32_t xi = x.x; xi <= x.y; ++xi)
             a.sample_label[row_lin + xi] = l;
     }
-    for (int32_t i = threadIdx.x; i < n_rows; i += NT) {
-        uint64_t* rw = a.rb.words + (int64_t)m.rows[i] * wr;
-        for (int32_t q = 0; q < wr; ++q)
-            rw[q] = 0;
-    }
-    for (int32_t w = threadIdx.x; w < n_rm; w += NT)
-        a.rb.rowmask[w] = 0;
     if (threadIdx.x == 0) {
         *a.n_rois = K;
         if (K > a.max_rois)
@@ -826,14 +820,26 @@ __global__ __launch_bounds__(kBlock) void label_bitmap_kernel(const uint8_t* __r
     }
 }
 
-__global__ __launch_bounds__(kBlock) void label_write_kernel(const int32_t* __restrict__ sample_label,
-                                                             uint8_t* __restrict__ occ,
-                                                             int32_t* __restrict__ labels,
-                                                             int32_t V) {
+__global__ __launch_bounds__(kBlock) void label_write_kernel(const LabelWrite lw) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (v >= V)
-        return;
-    label_write_sample(LabelWrite{sample_label, occ, labels, V, 0u}, v);
+    label_write_clear(lw, v, (int64_t)gridDim.x * kBlock);
+    if (v < lw.V)
+        label_write_sample(lw, v);
+}
+
+LabelWrite label_write_args(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels) {
+    LabelWrite lw;
+    lw.sample_label = ctx->d_sample_label;
+    lw.occ = occ;
+    lw.labels = labels;
+    lw.V = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+    lw.carve_blocks = 0u;
+    const int64_t R = (int64_t)g.dims[1] * g.dims[2];
+    lw.rb_words = ctx->d_rowbits;
+    lw.rb_n = R * ((g.dims[0] + 63) / 64);
+    lw.rowmask = ctx->d_rowmask;
+    lw.rm_n = (R + 63) / 64;
+    return lw;
 }
 
 RowBits row_bits(fvv_ctx* ctx, const fvv_grid& g) {
@@ -880,10 +886,9 @@ hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* 
 // Labels and filtered occupancy of every sample (after launch_label).
 hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                               hipStream_t s) {
-    const int32_t V = g.dims[0] * g.dims[1] * g.dims[2];
-    const unsigned vblocks = (unsigned)((V + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(label_write_kernel, dim3(vblocks), dim3(kBlock), 0, s,
-                       ctx->d_sample_label, occ, labels, V);
+    const LabelWrite lw = label_write_args(ctx, g, occ, labels);
+    const unsigned vblocks = (unsigned)((lw.V + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(label_write_kernel, dim3(vblocks), dim3(kBlock), 0, s, lw);
     return hipGetLastError();
 }
 

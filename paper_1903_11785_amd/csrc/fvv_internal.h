@@ -417,8 +417,8 @@ __host__ __device__ inline uint32_t grab_size(uint64_t total_tiles, uint32_t blo
 // Row bitmap of a coarse occupancy, the labelling's input: bit x of row
 // r = j + ny*k lies in word r*wr + x/64 (each row padded to whole words, the
 // bits past nx clear) and bit r of `rowmask` flags a row with a set bit.  Both
-// are all-zero between calls: producers OR bits in, the labelling clears what
-// it read.
+// are all-zero between calls: producers OR bits in, the labels' write pass
+// after the labelling clears them.
 struct RowBits {
     uint64_t* words;
     uint64_t* rowmask;
@@ -639,7 +639,21 @@ struct LabelWrite {
     int32_t* labels;
     int64_t V;
     uint32_t carve_blocks;
+    // the labelling's row bitmap (rb_n words) and row mask (rm_n words),
+    // cleared by the same pass for the next call
+    uint64_t* rb_words;
+    int64_t rb_n;
+    uint64_t* rowmask;
+    int64_t rm_n;
 };
+
+// Thread t of nth of the write pass: its share of the bitmap clear.
+__device__ __forceinline__ void label_write_clear(const LabelWrite& lw, int64_t t, int64_t nth) {
+    for (int64_t w = t; w < lw.rb_n; w += nth)
+        lw.rb_words[w] = 0ull;
+    for (int64_t w = t; w < lw.rm_n; w += nth)
+        lw.rowmask[w] = 0ull;
+}
 
 __device__ __forceinline__ void label_write_sample(const LabelWrite& lw, int64_t v) {
     if (lw.occ[v]) {
@@ -672,6 +686,8 @@ RowBits row_bits(fvv_ctx* ctx, const fvv_grid& g);
 hipError_t launch_label(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                         uint32_t t_np, uint32_t t_nb, fvv_roi* rois, uint32_t max_rois,
                         uint32_t* n_rois, bool seeded, const FrameJobs* frame, hipStream_t s);
+// The write pass's arguments for lattice g (carve_blocks 0).
+LabelWrite label_write_args(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels);
 hipError_t launch_label_write(fvv_ctx* ctx, const fvv_grid& g, uint8_t* occ, int32_t* labels,
                               hipStream_t s);
 // Soft hull: one camera as the kernels use it (intrinsics and the perturbed

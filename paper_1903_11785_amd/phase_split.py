@@ -30,7 +30,7 @@ MEASURE_LIB = os.path.join(HERE, "libfvv_measure.so")
 DEFINES = ("FVV_LABEL_PHASES", "FVV_CARVE_PROBE")
 LABEL_PHASES = ["row mask", "rows listed", "runs cut", "pairs listed", "unions",
                 "flatten + root numbers",
-                "stats + Eq. (1) filter + ROIs", "labels + bitmap clear", "fine jobs laid out",
+                "stats + Eq. (1) filter + ROIs", "labels", "fine jobs laid out",
                 "fine job radii"]
 N_STAMPS = len(LABEL_PHASES) + 1
 PROBE_WAVES, PROBE_ITERS = 16384, 4       # the probe tables of the measurement build
