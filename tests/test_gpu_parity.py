@@ -192,6 +192,29 @@ def test_label_adversarial_shapes(fvv, ctx):
         check_label(fvv, ctx, g)
 
 
+def test_label_repeated_merge_orders(fvv, ctx):
+    """Shapes whose unions race: a comb (teeth joining one spine in parallel), a
+    rake (separate columns joined only by their last row), 3-D staircases with
+    vertex contacts, and dense random fields in LDS and past it (global forest);
+    each labelled 12 times, every run byte-identical to the oracle."""
+    comb = np.zeros((24, 8, 120), np.uint8)
+    comb[0, 4, :] = 1
+    comb[:, 4, 0::2] = 1
+    rake = np.zeros((30, 6, 96), np.uint8)
+    rake[:, 2, 0::3] = 1
+    rake[29, 2, :] = 1
+    stairs = np.zeros((40, 40, 40), np.uint8)
+    for t in range(40):
+        stairs[t, t, (t * 7) % 40] = 1
+        stairs[t, 39 - t, t] = 1
+    rng = np.random.default_rng(7)
+    dense = (rng.uniform(size=(12, 32, 48)) < 0.5).astype(np.uint8)   # ~4.6e3 runs: LDS
+    big = (rng.uniform(size=(48, 64, 96)) < 0.45).astype(np.uint8)    # ~7.4e4 runs: global
+    for g in (comb, rake, stairs, dense, big):
+        for _ in range(12):
+            check_label(fvv, ctx, g)
+
+
 def test_label_filter_bounds(fvv, ctx):
     occ = np.zeros((10, 10, 30), np.uint8)
     occ[1, 1, 0:3] = 1
