@@ -145,16 +145,17 @@ constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
 // longest prefix that fits both), and build the tile and work-item prefixes of
 // the batched carve and the surface passes.  box(t, lo, hi) gives ROI t's
 // coarse box.  counts: [0] K, [1] fine samples, [3] ROIs carried.
-// The radii of every carried job and camera (FrameJobs::rho), one pair per
-// thread, once the jobs are written (counter[2] = carried jobs).
-template <int NT>
-__device__ __forceinline__ void fine_job_radii(const FrameJobs& fj, const uint32_t* counter) {
-    const uint32_t n = counter[2];
+// The radii of jobs 0 .. n-1 and every camera (FrameJobs::rho), one pair per
+// thread.
+// grid_of(t) gives job t's lattice; threads first .. NT - 1 share the pairs.
+template <int NT, typename GridOf>
+__device__ __forceinline__ void fine_job_radii(const FrameJobs& fj, uint32_t n, int first,
+                                               GridOf grid_of) {
     const int nc = fj.cams.n;
-    for (uint32_t p = threadIdx.x; p < n * (uint32_t)nc; p += NT) {
+    for (uint32_t p = threadIdx.x - first; p < n * (uint32_t)nc; p += NT - first) {
         const uint32_t t = p / (uint32_t)nc;
         const int c = (int)(p - t * (uint32_t)nc);
-        const fvv_grid g = fj.jobs[t].grid;
+        const fvv_grid g = grid_of(t);
         double lo[3], hi[3];
         grid_box(g, lo, hi);
         const float pad = fj.cams.pad[c];
@@ -254,7 +255,15 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
     };
     if (K <= (uint32_t)kWave) {
         // one wave's worth of ROIs (a frame's usual case): the layout in the
-        // first wave with wave scans, no workgroup barriers
+        // first wave with wave scans, no workgroup barriers, and meanwhile the
+        // radii of every ROI's fine lattice by the other threads (those of ROIs
+        // past the carried ones are computed too and never read)
+        if (threadIdx.x >= kWave)
+            fine_job_radii<NT>(fj, K, kWave, [&](uint32_t t) {
+                fvv_grid fg{};
+                fine_lattice(t, fg);
+                return fg;
+            });
         if (threadIdx.x < kWave) {
             const uint32_t t = threadIdx.x;
             fvv_grid fg{};
@@ -288,10 +297,8 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
             const uint64_t all_t = lane64(inc_t, kWave - 1), all_i = lane64(inc_i, kWave - 1);
             if (t == 0)
                 finish(n, vox, all_t, all_i);
+            label_stamp(9);
         }
-        __syncthreads();
-        label_stamp(9);
-        fine_job_radii<NT>(fj, counter);
         return;
     }
     if (threadIdx.x == 0) {
@@ -348,7 +355,7 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         finish(carried, e_vox, e_tiles, e_items);
     __syncthreads();
     label_stamp(9);
-    fine_job_radii<NT>(fj, counter);
+    fine_job_radii<NT>(fj, carried, 0, [&](uint32_t t) { return fj.jobs[t].grid; });
 }
 
 // ------------------------------------------------------------------ run labelling
