@@ -69,10 +69,11 @@ def parse():
     ap.add_argument("--coarse-tile", default="64x1",
                     help="TXxTZ of the coarse carve (depth 4 culls cameras per tile, which at "
                          "coarse spacings costs more than it saves)")
-    ap.add_argument("--in-flight", type=int, default=6,
+    ap.add_argument("--in-flight", type=int, default=4,
                     help="frames in flight for the throughput figure (one context, buffer set "
-                         "and stream each; even counts map evenly onto the process's 4 hardware "
-                         "queues); latency is measured one frame at a time")
+                         "and stream each, one per hardware queue of the process: 4; measured "
+                         "2, 4, 6, 8, 12: 2.5, 4.8, 4.5, 4.8, 4.7e10 fine voxels/s); latency is "
+                         "measured one frame at a time")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-carve leg")
     ap.add_argument("--no-soft", action="store_true", help="skip the soft-hull leg")
     ap.add_argument("--no-mesh", action="store_true", help="skip the marching-cubes leg")
