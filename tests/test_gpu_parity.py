@@ -710,6 +710,25 @@ def test_frame_two_pass_few_cameras(fvv, ctx, scene_cache):
     compare_frame(fvv, sc, bufs, res)
 
 
+def test_frame_two_pass_empty_and_refilled(fvv, ctx, scene_cache):
+    """The two-pass coarse carve with nothing to keep (all-background silhouettes:
+    every box rejected, no ROI), then the same context on the real frame (the
+    kept-box count and the block bits cleared in between), both against the
+    oracle."""
+    import copy
+    sc0 = scene_cache(3, 0)
+    empty = copy.copy(sc0)
+    empty.masks = np.zeros_like(sc0.masks)
+    for sc in (empty, sc0):
+        res = oracle.frame(sc.masks, sc.P32, sc.origin, sc.hc_um, sc.hf_um, sc.coarse_dims,
+                           sc.t_np, sc.t_nb, sc.n_steps)
+        _, bufs, _ = run_frame(fvv, ctx, sc)
+        assert ctx.check() == fvv.FVV_OK
+        compare_frame(fvv, sc, bufs, res)
+        if sc is empty:
+            assert len(res.rois) == 0 and int(host(bufs.occ_coarse).sum()) == 0
+
+
 # ------------------------------------------------------------------ paper-shaped frames
 @pytest.mark.parametrize("cfg", [scenes.CFG_PAPER_V, scenes.CFG_JUDO_FINE])
 def test_frame_paper_shapes(fvv, scene_cache, cfg):
