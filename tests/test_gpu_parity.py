@@ -693,13 +693,16 @@ def test_invalid_arguments_are_rejected(fvv, ctx, scene_cache):
         ctx.label(good, dev(np.zeros((4, 4, 4), np.uint8)), t_np=9, t_nb=8)
 
 
-def test_frame_two_pass_few_cameras(fvv, ctx, scene_cache):
-    """The judo frame seen by 3 of its 24 cameras: the two-pass coarse carve's
-    rejection pass with one workgroup's box count capped by the wave (64 boxes of
-    3 cameras each), a wider hull and more kept boxes, against the oracle."""
+@pytest.mark.parametrize("idx", [[0, 8, 16], list(range(17)), list(range(24)) + list(range(8))],
+                         ids=["3cams", "17cams", "32cams"])
+def test_frame_two_pass_camera_counts(fvv, ctx, scene_cache, idx):
+    """The judo frame seen by 3, 17 and 32 cameras (the last repeating 8 of its
+    24): the two-pass coarse carve's rejection pass with its box count per
+    workgroup capped by the wave (64 boxes of 3 cameras), uneven (15 boxes of 17
+    cameras) and at the camera limit (8 boxes of 32; two 16-camera groups per
+    kept box), against the oracle."""
     import copy
     sc = copy.copy(scene_cache(3, 0))
-    idx = [0, 8, 16]
     sc.masks = sc.masks[idx]
     sc.cams = [sc.cams[i] for i in idx]
     assert int(np.prod(sc.coarse_dims)) >= 1 << 21
