@@ -78,10 +78,14 @@ def _eroded_inside(sc, X):
     f = np.array([c.K[0, 0] for c in sc.cams]).reshape((-1,) + (1,) * (X.ndim - 1))
     r = (0.71 * depth / f).max(axis=0) + 1e-4
     out = np.zeros(X.shape[:-1], bool)
+    Xf, rf, of = X.reshape(-1, 3), r.reshape(-1), out.reshape(-1)
     for e in sc.ellipsoids:
-        s = np.clip(1.0 - r / e.axes.min(), 0.0, None)
-        d = X - e.center
-        out |= np.einsum('...i,ij,...j->...', d, e.M, d) <= s * s
+        # only the points of the ellipsoid's bounding cube can lie inside it
+        near = np.all(np.abs(Xf - e.center) <= e.axes.max(), axis=1)
+        idx = np.nonzero(near)[0]
+        s = np.clip(1.0 - rf[idx] / e.axes.min(), 0.0, None)
+        d = Xf[idx] - e.center
+        of[idx] |= np.einsum('ni,ij,nj->n', d, e.M, d) <= s * s
     return out
 
 
