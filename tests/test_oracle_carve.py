@@ -73,19 +73,26 @@ def test_pc1_analytic_agreement_fine_roi(scene_cache, frame):
 
 def _eroded_inside(sc, X):
     """Points whose distance to every ellipsoid's surface exceeds the pixel
-    footprint r = max_c 0.71 z_c / f_c + 1e-4 m (scaled-ellipsoid erosion)."""
-    depth = np.stack([scenes.project64(c, X)[2] for c in sc.cams])
-    f = np.array([c.K[0, 0] for c in sc.cams]).reshape((-1,) + (1,) * (X.ndim - 1))
-    r = (0.71 * depth / f).max(axis=0) + 1e-4
+    footprint r = max_c 0.71 z_c / f_c + 1e-4 m (scaled-ellipsoid erosion).  X is
+    a lattice ([nz][ny][nx][3], ascending coordinates): each ellipsoid is
+    evaluated on the lattice points of its bounding cube only."""
     out = np.zeros(X.shape[:-1], bool)
-    Xf, rf, of = X.reshape(-1, 3), r.reshape(-1), out.reshape(-1)
+    axes = (X[0, 0, :, 0], X[0, :, 0, 1], X[:, 0, 0, 2])
+    f = np.array([c.K[0, 0] for c in sc.cams]).reshape(-1, 1, 1, 1)
     for e in sc.ellipsoids:
-        # only the points of the ellipsoid's bounding cube can lie inside it
-        near = np.all(np.abs(Xf - e.center) <= e.axes.max(), axis=1)
-        idx = np.nonzero(near)[0]
-        s = np.clip(1.0 - rf[idx] / e.axes.min(), 0.0, None)
-        d = Xf[idx] - e.center
-        of[idx] |= np.einsum('ni,ij,nj->n', d, e.M, d) <= s * s
+        a = float(e.axes.max())
+        (i0, i1), (j0, j1), (k0, k1) = (
+            (int(np.searchsorted(v, e.center[t] - a)),
+             int(np.searchsorted(v, e.center[t] + a, side="right")))
+            for t, v in enumerate(axes))
+        if i0 >= i1 or j0 >= j1 or k0 >= k1:
+            continue
+        Xs = X[k0:k1, j0:j1, i0:i1]
+        depth = np.stack([scenes.project64(c, Xs)[2] for c in sc.cams])
+        r = (0.71 * depth / f).max(axis=0) + 1e-4
+        s = np.clip(1.0 - r / e.axes.min(), 0.0, None)
+        d = Xs - e.center
+        out[k0:k1, j0:j1, i0:i1] |= np.einsum('...i,ij,...j->...', d, e.M, d) <= s * s
     return out
 
 
