@@ -119,22 +119,12 @@ __device__ __forceinline__ void label_stamp_sync(int) {}
 #endif
 
 // ------------------------------------------------------------------ fine jobs of a frame
-// floor(a / b) for b > 0 and |a| <= 2^53, from binv = 1.0 / b: the double
-// estimate a * binv (two roundings) is within two of the quotient, and two
-// steps of integer residual correction make it exact.
-__device__ __forceinline__ int64_t floor_div_pos(int64_t a, int64_t b, double binv) {
-    int64_t q = (int64_t)__builtin_floor((double)a * binv);
-#pragma unroll
-    for (int step = 0; step < 2; ++step) {
-        const int64_t r = a - q * b;
-        q -= (r < 0) ? 1 : 0;
-        q += (r >= b) ? 1 : 0;
-    }
-    return q;
-}
-
-__device__ __forceinline__ int64_t ceil_div_pos(int64_t a, int64_t b, double binv) {
-    return -floor_div_pos(-a, b, binv);
+// floor(a / b) for integers a, b held exactly in doubles, |a| < 2^53, b > 0:
+// the correctly rounded quotient never rounds up to the next integer n (a
+// non-integer a / b lies at least 1 / b below n, more than its rounding error
+// |a / b| 2^-53), so its floor is exact.
+__device__ __forceinline__ double floor_div_exact(double a, double b) {
+    return __builtin_floor(a / b);
 }
 
 constexpr int64_t kMaxKeyedSamples = 1431655765;  // 3*lin+axis must fit 32 bits
@@ -189,10 +179,6 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
                                                 uint32_t* __restrict__ counter,
                                                 fvv_camera* __restrict__ dcams,
                                                 uint32_t* __restrict__ status) {
-    __shared__ uint64_t scratch[NT / kWave];
-    __shared__ uint64_t c_vox, c_bits, c_tiles, c_items;   // running totals over whole chunks
-    __shared__ uint64_t e_vox, e_tiles, e_items;           // totals over the carried ROIs
-    __shared__ uint32_t carried;
     // the device camera table, by the threads past the first wave (which lays
     // out the jobs meanwhile)
     for (int c = (int)threadIdx.x - kWave; c >= 0 && c < fj.cams.n; c += NT - kWave) {
@@ -204,27 +190,28 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         dcams[c] = cam;
     }
     const uint32_t K = K_all < max_rois ? K_all : max_rois;
-    const double hf_inv = 1.0 / (double)fj.hf_um;
+    // spacings and coarse indices are integers whose products stay below 2^52
+    // (the frame's argument checks), exact in doubles
+    const double hc = (double)fj.hc_um, hf = (double)fj.hf_um;
     auto fine_lattice = [&](uint32_t t, fvv_grid& fg) -> int64_t {
         int32_t lo[3], hi[3];
         box(t, lo, hi);
         int64_t V = 1;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int64_t A = (int64_t)fj.coarse.lo[a] + lo[a] - 1;
-            const int64_t B = (int64_t)fj.coarse.lo[a] + hi[a] + 1;
-            int64_t f0 = floor_div_pos(A * fj.hc_um, fj.hf_um, hf_inv);
-            int64_t f1 = ceil_div_pos(B * fj.hc_um, fj.hf_um, hf_inv);
-            const int64_t fmin =
-                ceil_div_pos((int64_t)fj.coarse.lo[a] * fj.hc_um, fj.hf_um, hf_inv);
-            const int64_t fmax = floor_div_pos(
-                ((int64_t)fj.coarse.lo[a] + fj.coarse.dims[a] - 1) * fj.hc_um, fj.hf_um, hf_inv);
+            const double c0 = (double)fj.coarse.lo[a];
+            const double A = c0 + (double)(lo[a] - 1);
+            const double B = c0 + (double)(hi[a] + 1);
+            double f0 = floor_div_exact(A * hc, hf);
+            double f1 = -floor_div_exact(-B * hc, hf);
+            const double fmin = -floor_div_exact(-c0 * hc, hf);
+            const double fmax = floor_div_exact((c0 + (double)(fj.coarse.dims[a] - 1)) * hc, hf);
             f0 = f0 < fmin ? fmin : f0;
             f1 = f1 > fmax ? fmax : f1;
             fg.origin[a] = fj.coarse.origin[a];
             fg.lo[a] = (int32_t)f0;
-            fg.dims[a] = (int32_t)(f1 - f0 + 1);
-            V *= (f1 - f0 + 1);
+            fg.dims[a] = (int32_t)(f1 - f0 + 1.0);
+            V *= (int64_t)fg.dims[a];
         }
         fg.h = fj.h_fine;
         return V;
@@ -253,109 +240,63 @@ __device__ __forceinline__ void build_fine_jobs(const FrameJobs& fj, Box box, ui
         if (n < K_all)
             atomicOr(status, kFlagCapacity);
     };
-    if (K <= (uint32_t)kWave) {
-        // one wave's worth of ROIs (a frame's usual case): the layout in the
-        // first wave with wave scans, no workgroup barriers, and meanwhile the
-        // radii of every ROI's fine lattice by the other threads (those of ROIs
-        // past the carried ones are computed too and never read)
-        if (threadIdx.x >= kWave)
-            fine_job_radii<NT>(fj, K, kWave, [&](uint32_t t) {
-                fvv_grid fg{};
-                fine_lattice(t, fg);
-                return fg;
-            });
-        if (threadIdx.x < kWave) {
-            const uint32_t t = threadIdx.x;
+    // the layout in the first wave, 64 ROIs at a time with wave scans and no
+    // workgroup barrier, and meanwhile the radii of every ROI's fine lattice
+    // by the other threads (those of ROIs past the carried ones are computed
+    // too and never read)
+    if (threadIdx.x >= kWave) {
+        fine_job_radii<NT>(fj, K, kWave, [&](uint32_t t) {
             fvv_grid fg{};
-            const int64_t V = t < K ? fine_lattice(t, fg) : 0;
-            const uint64_t words = t < K ? (uint64_t)fine_bitmap_words(fg) : 0;
-            const uint64_t inc_v = wave_inclusive_sum64((uint64_t)V);
-            const uint64_t inc_b = wave_inclusive_sum64(words);
-            const uint64_t off = inc_v - (uint64_t)V, boff = inc_b - words;
-            // the carried ROIs are the prefix before the first one that does not fit
-            const bool bad = t < K && (off + (uint64_t)V > (uint64_t)fj.max_fine ||
-                                       V > kMaxKeyedSamples || boff + words > (uint64_t)fj.bit_cap);
-            const uint64_t bad_lanes = __ballot(bad);
-            const uint32_t n = bad_lanes ? (uint32_t)(__ffsll((unsigned long long)bad_lanes) - 1) : K;
-            const bool fits = t < n;
-            const uint64_t tiles = fits ? tiles_of_grid(fg, fj.tile_x, fj.tile_z) : 0;
-            const uint64_t items = fits ? (words + kEdgeWords - 1) / kEdgeWords : 0;
-            const uint64_t inc_t = wave_inclusive_sum64(tiles);
-            const uint64_t inc_i = wave_inclusive_sum64(items);
-            if (fits) {
-                write_job(t, fg, off);
-                pre[t].tile_off = inc_t - tiles;
-                pre[t].bit_off = boff;
-                pre[t].item_off = (uint32_t)(inc_i - items);
-            }
-            auto lane64 = [](uint64_t v, int l) {
-                return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l)
-                        << 32) |
-                       (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-            };
-            const uint64_t vox = n ? lane64(inc_v, (int)n - 1) : 0;
-            const uint64_t all_t = lane64(inc_t, kWave - 1), all_i = lane64(inc_i, kWave - 1);
-            if (t == 0)
-                finish(n, vox, all_t, all_i);
-            label_stamp(9);
-        }
+            fine_lattice(t, fg);
+            return fg;
+        });
         return;
     }
-    if (threadIdx.x == 0) {
-        c_vox = c_bits = c_tiles = c_items = 0;
-        e_vox = e_tiles = e_items = 0;
-        carried = K;
-    }
-    __syncthreads();
-    for (uint32_t base = 0; base < K; base += NT) {
+    auto lane64 = [](uint64_t v, int l) {
+        return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32) |
+               (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    };
+    // running totals over the chunks before (wave-uniform)
+    uint64_t c_vox = 0, c_bits = 0, c_tiles = 0, c_items = 0;
+    uint32_t n = K;
+    for (uint32_t base = 0; base < K; base += kWave) {
         const uint32_t t = base + threadIdx.x;
         fvv_grid fg{};
         const int64_t V = t < K ? fine_lattice(t, fg) : 0;
         const uint64_t words = t < K ? (uint64_t)fine_bitmap_words(fg) : 0;
-        uint64_t tot_v, tot_b;
-        const uint64_t ex_v = block_exclusive_sum64<NT>((uint64_t)V, scratch, &tot_v);
-        const uint64_t ex_b = block_exclusive_sum64<NT>(words, scratch, &tot_b);
-        const uint64_t off = c_vox + ex_v;
-        const uint64_t boff = c_bits + ex_b;
+        const uint64_t inc_v = wave_inclusive_sum64((uint64_t)V);
+        const uint64_t inc_b = wave_inclusive_sum64(words);
+        const uint64_t off = c_vox + inc_v - (uint64_t)V, boff = c_bits + inc_b - words;
         // the carried ROIs are the prefix before the first one that does not fit
-        if (t < K && (off + (uint64_t)V > (uint64_t)fj.max_fine || V > kMaxKeyedSamples ||
-                      boff + words > (uint64_t)fj.bit_cap))
-            atomicMin(&carried, t);
-        __syncthreads();
-        const uint32_t n = carried;
-        const bool fits = t < n;
+        const bool bad = t < K && (off + (uint64_t)V > (uint64_t)fj.max_fine ||
+                                   V > kMaxKeyedSamples || boff + words > (uint64_t)fj.bit_cap);
+        const uint64_t bad_lanes = __ballot(bad);
+        const uint32_t end = bad_lanes ? base + (uint32_t)(__ffsll((unsigned long long)bad_lanes) - 1)
+                                       : (K < base + kWave ? K : base + kWave);
+        const bool fits = t < end;
         const uint64_t tiles = fits ? tiles_of_grid(fg, fj.tile_x, fj.tile_z) : 0;
         const uint64_t items = fits ? (words + kEdgeWords - 1) / kEdgeWords : 0;
-        uint64_t tot_t, tot_i;
-        const uint64_t ex_t = block_exclusive_sum64<NT>(tiles, scratch, &tot_t);
-        const uint64_t ex_i = block_exclusive_sum64<NT>(items, scratch, &tot_i);
+        const uint64_t inc_t = wave_inclusive_sum64(tiles);
+        const uint64_t inc_i = wave_inclusive_sum64(items);
         if (fits) {
             write_job(t, fg, off);
-            pre[t].tile_off = c_tiles + ex_t;
+            pre[t].tile_off = c_tiles + inc_t - tiles;
             pre[t].bit_off = boff;
-            pre[t].item_off = (uint32_t)(c_items + ex_i);
-            if (t + 1 == n) {
-                e_vox = off + (uint64_t)V;
-                e_tiles = c_tiles + ex_t + tiles;
-                e_items = c_items + ex_i + items;
-            }
+            pre[t].item_off = (uint32_t)(c_items + inc_i - items);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            c_vox += tot_v;
-            c_bits += tot_b;
-            c_tiles += tot_t;
-            c_items += tot_i;
-        }
-        __syncthreads();
-        if (n < base + NT)
+        // lanes past `end` add no tiles or items, and no voxels or words past K
+        c_vox += end > base ? lane64(inc_v, (int)(end - base) - 1) : 0;
+        c_bits += lane64(inc_b, kWave - 1);
+        c_tiles += lane64(inc_t, kWave - 1);
+        c_items += lane64(inc_i, kWave - 1);
+        if (bad_lanes) {
+            n = end;
             break;
+        }
     }
     if (threadIdx.x == 0)
-        finish(carried, e_vox, e_tiles, e_items);
-    __syncthreads();
+        finish(n, c_vox, c_tiles, c_items);
     label_stamp(9);
-    fine_job_radii<NT>(fj, carried, 0, [&](uint32_t t) { return fj.jobs[t].grid; });
 }
 
 // ------------------------------------------------------------------ run labelling

@@ -588,6 +588,17 @@ def test_frame_with_more_rois_than_a_wave(fvv, ctx):
     for t in range(60):
         assert tuple(jobs[t]["lo"]) == res.fine[t].lo and tuple(jobs[t]["dims"]) == res.fine[t].dims
     assert ctx.check() == fvv.FVV_ECAPACITY
+    # fine room for 66 ROIs: the layout stops inside its second run of 64
+    sizes = [l.size for l in res.fine]
+    _, bufs, _ = run_frame(fvv, ctx, sc, max_fine=sum(sizes[:66]) + sizes[66] // 2)
+    counts = host(bufs.counts)
+    assert int(counts[0]) == 72 and int(counts[3]) == 66
+    assert int(counts[1]) == sum(sizes[:66])
+    jobs = bufs.jobs_host(66)
+    for t in range(66):
+        assert tuple(jobs[t]["lo"]) == res.fine[t].lo and tuple(jobs[t]["dims"]) == res.fine[t].dims
+        assert int(jobs[t]["out_offset"]) == sum(sizes[:t])
+    assert ctx.check() == fvv.FVV_ECAPACITY
 
 
 _frame_oracle = {}
